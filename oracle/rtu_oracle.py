@@ -1,0 +1,469 @@
+"""FP64 CPU oracle of the RTU-grid lens likelihood and its gradient.
+
+TEST INFRASTRUCTURE ONLY.  Tests, the smoke check and the CPU-baseline leg of
+the benchmark call this module; the GPU library never does, and this module
+imports nothing from the GPU package.  It is written for a reader to check by
+eye against the paper (Enzi et al., "Gaussian processes on ray-guided
+transformed uniform grids"): plain float64 tensor operations in the order the
+paper gives them, library primitives (sort, FFT, conv2d) as single steps, and
+the gradient as reverse-mode differentiation of this forward definition (the
+paper's model is differentiated the same way, by automatic differentiation).
+
+Where the paper is silent or ambiguous, the reading taken is stated at the
+function that implements it.  Status bits follow the GPU library's contract:
+1 non-finite result, 2 non-monotone smoothed CDF (slopes clamped),
+4 fewer masked pixels than nodes + 1, 8 parameter outside its domain.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+DT = torch.float64
+S0 = 0.01            # softplus scale s_0 (Sec. 2.1, eq. 3)
+K_NODES = 22         # Chebyshev nodes = degree 21 + 1 (App. C, step iii; Fig. C1)
+N_LENS_BASE = 7
+N_PER_SUB = 4
+
+ST_NONFINITE = 1
+ST_NONMONOTONE = 2
+ST_MASK_SMALL = 4
+ST_DOMAIN = 8
+
+
+def _t(a) -> torch.Tensor:
+    return torch.as_tensor(np.asarray(a), dtype=DT)
+
+
+# ------------------------------------------------------------------ image plane
+def pixel_centres(n_img: int, pix: float):
+    """Pixel (i, j) centre: theta = ((j - (N-1)/2) pix, (i - (N-1)/2) pix);
+    row i <-> y, column j <-> x.  Returns x, y of shape [N*N] (row-major)."""
+    c = (torch.arange(n_img, dtype=DT) - 0.5 * (n_img - 1)) * pix
+    y, x = torch.meshgrid(c, c, indexing="ij")
+    return x.reshape(-1), y.reshape(-1)
+
+
+def subray_positions(n_img: int, pix: float, ss: int):
+    """Sub-ray (a, b) of pixel p sits at the pixel centre plus
+    (((b + 1/2)/ss - 1/2) pix, ((a + 1/2)/ss - 1/2) pix)  (Sec. 2.3 sub-sampling;
+    a regular ss x ss lattice centred in the pixel).  Shape [N*N, ss*ss]."""
+    xc, yc = pixel_centres(n_img, pix)
+    off = ((torch.arange(ss, dtype=DT) + 0.5) / ss - 0.5) * pix
+    oy, ox = torch.meshgrid(off, off, indexing="ij")
+    return xc[:, None] + ox.reshape(1, -1), yc[:, None] + oy.reshape(1, -1)
+
+
+# ------------------------------------------------------------------ lens mass
+def q_phi_from_e(e1, e2):
+    """Ellipticity components -> axis ratio and angle:
+    e = |(e1, e2)|, q = (1 - e)/(1 + e), phi = atan2(e2, e1)/2 (App. A.1 infers
+    ellipticities; this is the usual convention)."""
+    e = torch.sqrt(e1 * e1 + e2 * e2)
+    return (1.0 - e) / (1.0 + e), 0.5 * torch.atan2(e2, e1), e
+
+
+def sie_deflection(x, y, theta_e, e1, e2, x0, y0):
+    """Deflection of the EPL of App. A.1, eq. (A1), at slope gamma = 2 (singular
+    isothermal ellipsoid): kappa = (theta_E / 2) / rho, rho^2 = q x'^2 + y'^2 / q in
+    the frame rotated by phi about (x0, y0).  Closed form with f = sqrt(1 - q^2),
+    psi = sqrt(q^2 x'^2 + y'^2):
+        a'_x = theta_E sqrt(q)/f atan(f x'/psi),  a'_y = theta_E sqrt(q)/f atanh(f y'/psi),
+    rotated back by phi."""
+    q, phi, e = q_phi_from_e(e1, e2)
+    c, s = torch.cos(phi), torch.sin(phi)
+    dx, dy = x - x0, y - y0
+    xp = c * dx + s * dy
+    yp = -s * dx + c * dy
+    f = 2.0 * torch.sqrt(e) / (1.0 + e)          # = sqrt(1 - q^2) without cancellation
+    psi = torch.sqrt(q * q * xp * xp + yp * yp)
+    pref = theta_e * torch.sqrt(q) / f
+    axp = pref * torch.atan(f * xp / psi)
+    ayp = pref * torch.atanh(f * yp / psi)
+    return c * axp - s * ayp, s * axp + c * ayp
+
+
+def shear_deflection(x, y, g1, g2):
+    """External shear about the origin, potential (g1 (x^2 - y^2) + 2 g2 x y)/2."""
+    return g1 * x + g2 * y, g2 * x - g1 * y
+
+
+def _nfw_T(v):
+    """T(v) = atanh(sqrt v)/sqrt v for v > 0, atan(sqrt(-v))/sqrt(-v) for v < 0,
+    T(0) = 1; the power series 1 + v/3 + v^2/5 + ... near v = 0."""
+    small = v.abs() < 1e-3
+    vs = torch.where(small, torch.full_like(v, 0.5), v)
+    pos = vs > 0
+    sp = torch.sqrt(torch.where(pos, vs, torch.ones_like(vs)))
+    sn = torch.sqrt(torch.where(pos, torch.ones_like(vs), -vs))
+    direct = torch.where(pos, torch.atanh(sp) / sp, torch.atan(sn) / sn)
+    series = 1.0 + v / 3.0 + v * v / 5.0 + v ** 3 / 7.0 + v ** 4 / 9.0
+    return torch.where(small, series, direct)
+
+
+def nfw_h(x):
+    """Projected-mass function of the NFW profile (App. A.2, eqs. A2-A3):
+    h(x) = ln(x/2) + 2/sqrt(1-x^2) atanh(sqrt((1-x)/(1+x))) for x < 1,
+           ln(x/2) + 2/sqrt(x^2-1) atan(sqrt((x-1)/(x+1)))  for x > 1.
+    For x >= 1/2 it is evaluated as ln(x/2) + 2 T(v)/(1+x), v = (1-x)/(1+x), which
+    covers both branches and gives h(1) = 1 + ln 1/2.  Below x = 1/2 the two
+    logarithms cancel; there the same function is written, with c = sqrt(1-x^2)
+    and using 2 atanh(sqrt((1-x)/(1+x))) = ln((1+c)/x), as
+        h = ln(2/x) x^2 / ((1+c) c) + log1p(-x^2 / (2(1+c))) / c."""
+    lo = x < 0.5
+    xl = torch.where(lo, x, torch.full_like(x, 0.25))
+    c = torch.sqrt(1.0 - xl * xl)
+    h_lo = torch.log(2.0 / xl) * xl * xl / ((1.0 + c) * c) + torch.log1p(-xl * xl / (2.0 * (1.0 + c))) / c
+    xh = torch.where(lo, torch.ones_like(x), x)
+    v = (1.0 - xh) / (1.0 + xh)
+    h_hi = torch.log(0.5 * xh) + 2.0 * _nfw_T(v) / (1.0 + xh)
+    return torch.where(lo, h_lo, h_hi)
+
+
+def nfw_deflection(x, y, ks, rs, xs, ys, tau: float = 0.0):
+    """Radial deflection of the projected NFW of eq. (A3):
+    alpha = 4 kappa_s r_s h(X)/X along d/|d|, d = theta - centre, X = |d|/r_s.
+    With tau > 0 the projected mass is frozen beyond X = tau (hard truncation:
+    h(min(X, tau)))."""
+    dx, dy = x - xs, y - ys
+    r = torch.sqrt(dx * dx + dy * dy)
+    X = r / rs
+    Xh = torch.clamp(X, max=tau) if tau > 0 else X
+    Xs = torch.clamp(X, min=1e-300)
+    # alpha_vec = 4 ks rs h(X)/X * d/|d| = 4 ks rs^2 h(X) d / r^2
+    fac = 4.0 * ks * rs * nfw_h(torch.clamp(Xh, min=1e-300)) / (Xs * torch.clamp(r, min=1e-300))
+    return fac * dx, fac * dy
+
+
+def deflection(x, y, lens, n_sub: int = 0, tau: float = 0.0):
+    """Total deflection: SIE + external shear + n_sub NFW subhaloes."""
+    ax, ay = sie_deflection(x, y, lens[0], lens[1], lens[2], lens[3], lens[4])
+    sx, sy = shear_deflection(x, y, lens[5], lens[6])
+    ax, ay = ax + sx, ay + sy
+    for j in range(n_sub):
+        b = N_LENS_BASE + N_PER_SUB * j
+        nx, ny = nfw_deflection(x, y, lens[b], lens[b + 1], lens[b + 2], lens[b + 3], tau)
+        ax, ay = ax + nx, ay + ny
+    return ax, ay
+
+
+def ray_shoot(x, y, lens, n_sub=0, tau=0.0):
+    """Lens equation beta = theta - alpha(theta)."""
+    ax, ay = deflection(x, y, lens, n_sub, tau)
+    return x - ax, y - ay
+
+
+# ------------------------------------------------------------------ RTU transform
+def chebyshev_nodes(K: int = K_NODES):
+    """Chebyshev nodes mapped to (0, 1): u_k = (1 - cos((2k - 1) pi / (2K)))/2."""
+    k = torch.arange(1, K + 1, dtype=DT)
+    return 0.5 * (1.0 - torch.cos((2.0 * k - 1.0) * math.pi / (2.0 * K)))
+
+
+def standardise(bx, by):
+    """App. C step (i): subtract the mean per axis and divide by the smaller of
+    the two (population) standard deviations."""
+    mx, my = bx.mean(), by.mean()
+    sx = torch.sqrt(((bx - mx) ** 2).mean())
+    sy = torch.sqrt(((by - my) ** 2).mean())
+    s = torch.minimum(sx, sy)
+    return mx, my, s
+
+
+def quantiles_type7(z, u):
+    """App. C step (ii): the eCDF by sorting, and its inverse between the sorted
+    positions by linear interpolation (Sec. 2.2, App. C first paragraph):
+    h = (M-1) u, j = floor h, Q(u) = (1 - (h-j)) z_(j) + (h-j) z_(j+1).
+    Ties are ordered by ray index (stable sort).  Returns Q and the sorted
+    positions' original indices at j and j+1."""
+    M = z.shape[0]
+    zs, order = torch.sort(z, stable=True)
+    h = (M - 1) * u
+    j = torch.floor(h).long()
+    t = h - j.to(DT)
+    j1 = torch.clamp(j + 1, max=M - 1)
+    q = (1.0 - t) * zs[j] + t * zs[j1]
+    return q, order[j], order[j1]
+
+
+def chebyshev_T_U(tn, D: int):
+    """T_0..T_D and U_0..U_D at points tn by their three-term recurrences."""
+    T = [torch.ones_like(tn), tn]
+    U = [torch.ones_like(tn), 2.0 * tn]
+    for _ in range(2, D + 1):
+        T.append(2.0 * tn * T[-1] - T[-2])
+        U.append(2.0 * tn * U[-1] - U[-2])
+    return torch.stack(T[:D + 1]), torch.stack(U[:D + 1])
+
+
+def qf_polynomial(q, u):
+    """App. C step (iii): polynomial of degree K-1 (21 for K = 22) through the
+    quantile function at the K Chebyshev nodes.  With as many nodes as
+    coefficients the weighted fit interpolates the nodes exactly, so the node
+    weights do not change it.  In t = 2u - 1:
+        c_j = (2 - delta_j0)/K sum_k q_k T_j(t_k),
+        p'(u) = dp/du = 2 sum_j j c_j U_{j-1}(t).
+    Returns the slope p'(u_k) at every node."""
+    K = q.shape[0]
+    tn = 2.0 * u - 1.0
+    T, U = chebyshev_T_U(tn, K - 1)
+    c = (T @ q) * (2.0 / K)
+    c = torch.cat([c[:1] * 0.5, c[1:]])
+    j = torch.arange(1, K, dtype=DT)
+    dp = 2.0 * ((j[:, None] * c[1:, None]) * U[:K - 1]).sum(0)
+    return dp
+
+
+def cdf_spline(z, X, S, u):
+    """App. C step (iv): the smoothed CDF as the cubic Hermite spline through
+    (X_k, u_k) with slopes S_k = 1/p'(u_k); linear continuation with the end
+    slopes outside [X_1, X_K].  The interval of z is the largest k with
+    X_k <= z (so zero-width intervals are never used)."""
+    K = X.shape[0]
+    k = torch.searchsorted(X.detach().contiguous(), z.detach().contiguous(), right=True)  # #knots <= z
+    inner = (k >= 1) & (k <= K - 1)
+    kl = torch.clamp(k - 1, 0, K - 2)
+    Xl, Xr = X[kl], X[kl + 1]
+    h = torch.where(inner, Xr - Xl, torch.ones_like(Xl))
+    t = (z - Xl) / h
+    t2, t3 = t * t, t * t * t
+    h00 = 2 * t3 - 3 * t2 + 1
+    h10 = t3 - 2 * t2 + t
+    h01 = -2 * t3 + 3 * t2
+    h11 = t3 - t2
+    g_in = h00 * u[kl] + h10 * h * S[kl] + h01 * u[kl + 1] + h11 * h * S[kl + 1]
+    g_lo = u[0] + S[0] * (z - X[0])
+    g_hi = u[K - 1] + S[K - 1] * (z - X[K - 1])
+    return torch.where(k == 0, g_lo, torch.where(k >= K, g_hi, g_in))
+
+
+def build_transform(bxm, bym, K: int = K_NODES):
+    """RTU transform from the masked rays (Sec. 2.2; App. C steps i-iv).
+    Returns a dict with mu, s, knots X[2][K], slopes S[2][K], nodes u, the
+    selected ray indices and the status bits."""
+    u = chebyshev_nodes(K)
+    mx, my, s = standardise(bxm, bym)
+    out = {"u": u, "mu": (mx, my), "s": s, "status": 0}
+    X, S, idx = [], [], []
+    for zc in ((bxm - mx) / s, (bym - my) / s):
+        q, i0, i1 = quantiles_type7(zc, u)
+        dp = qf_polynomial(q, u)
+        # X_k = p(u_k) equals q_k exactly (interpolation); q_k is used directly.
+        eps = 1e-6 * (q[-1] - q[0]).detach()
+        bad = bool((dp.detach() <= eps).any()) or bool((q[1:] <= q[:-1]).any())
+        if bad:
+            out["status"] |= ST_NONMONOTONE
+        dp = torch.where(dp > eps, dp, eps.expand_as(dp))
+        X.append(q)
+        S.append(1.0 / dp)
+        idx.append((i0, i1))
+    out["X"], out["S"], out["idx"] = X, S, idx
+    return out
+
+
+def rtu_transform(bx, by, tr):
+    """Eq. (5): y = g(x) = (CDF_1(x_1), CDF_2(x_2)) on standardised coordinates."""
+    zx = (bx - tr["mu"][0]) / tr["s"]
+    zy = (by - tr["mu"][1]) / tr["s"]
+    return (cdf_spline(zx, tr["X"][0], tr["S"][0], tr["u"]),
+            cdf_spline(zy, tr["X"][1], tr["S"][1], tr["u"]))
+
+
+# ------------------------------------------------------------------ GP source
+def fft_freqs(n: int):
+    """Signed integer FFT frequencies (cycles per unit-square side)."""
+    k = torch.arange(n, dtype=DT)
+    return torch.where(k < n / 2, k, k - n)
+
+
+def matern_sqrtP(n: int, ps):
+    """Square root of the Matern spectrum of eq. (4) on the n x n FFT grid:
+    P(k) = sigma^2 4 pi n_s (2 n_s/zeta^2)^n_s (2 n_s/zeta^2 + k^2)^-(n_s + 1)."""
+    sig, ns, zeta = ps[0], ps[1], ps[2]
+    fk = fft_freqs(n)
+    k2 = fk[:, None] ** 2 + fk[None, :] ** 2
+    a = 2.0 * ns / (zeta * zeta)
+    P = sig * sig * 4.0 * math.pi * ns * a ** ns * (a + k2) ** (-(ns + 1.0))
+    return torch.sqrt(P)
+
+
+def softplus(x):
+    """Eq. (2), log(1 + e^x), evaluated as max(x, 0) + log1p(e^-|x|)."""
+    return torch.clamp(x, min=0.0) + torch.log1p(torch.exp(-x.abs()))
+
+
+def gp_field(w, sqrtP):
+    """Eq. (1): f = Re IDFT(sqrt(P) * DFT(w)), forward DFT unnormalised and the
+    inverse divided by n^2.  The latent is the real white-noise field w."""
+    F = torch.fft.fft2(w.to(torch.complex128))
+    return torch.fft.ifft2(sqrtP * F).real
+
+
+def positive_source(f, alpha):
+    """Eqs. (2)-(3): s = (s0 softplus(f/s0))^alpha_src."""
+    return (S0 * softplus(f / S0)) ** alpha
+
+
+def gp_source(w, ps):
+    """Source grid from the latent and the spectrum parameters, eqs. (1)-(4)."""
+    f = gp_field(w, matern_sqrtP(w.shape[0], ps))
+    return positive_source(f, ps[3]), f
+
+
+def bilinear(s, yx, yy):
+    """Bilinear interpolation of the grid s (Sec. 2.1) at unit-square positions.
+    Node (i, j) sits at ((j + 1/2)/n, (i + 1/2)/n); values outside the grid are
+    zero."""
+    n = s.shape[0]
+    tx = yx * n - 0.5
+    ty = yy * n - 0.5
+    j0 = torch.floor(tx.detach())
+    i0 = torch.floor(ty.detach())
+    fx = tx - j0
+    fy = ty - i0
+    j0 = j0.long()
+    i0 = i0.long()
+    sflat = s.reshape(-1)
+
+    def at(i, j):
+        ok = (i >= 0) & (i < n) & (j >= 0) & (j < n)
+        ii = torch.where(ok, i * n + j, torch.zeros_like(i))
+        return torch.where(ok, sflat[ii], torch.zeros_like(fx))
+
+    return ((1 - fx) * (1 - fy) * at(i0, j0) + fx * (1 - fy) * at(i0, j0 + 1)
+            + (1 - fx) * fy * at(i0 + 1, j0) + fx * fy * at(i0 + 1, j0 + 1))
+
+
+# ------------------------------------------------------------------ image and loss
+def psf_convolve(u, psf):
+    """Zero-padded 'same' convolution of the image with the PSF (kernel flipped,
+    not renormalised)."""
+    k = psf.shape[0]
+    kern = torch.flip(psf, dims=(0, 1))[None, None]
+    return torch.nn.functional.conv2d(u[None, None], kern, padding=k // 2)[0, 0]
+
+
+def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=False):
+    """One evaluation of the lens model.
+
+    obs: dict with n_img, pix, ss, image[N,N], sigma[N,N], psf[K,K], mask[N,N].
+    uniform_box: if given as (x_lo, y_lo, side), the RTU transform is replaced by
+    the plain affine map of that box onto the unit square (the paper's uniform
+    grid, Sec. 2.1)."""
+    N, pix, ss = obs["n_img"], obs["pix"], obs["ss"]
+    status = 0
+    lv, pv = lens.detach(), ps.detach()
+    if float(lv[0]) <= 0 or float(torch.hypot(lv[1], lv[2])) >= 1 or \
+            any(float(lv[N_LENS_BASE + N_PER_SUB * j + 1]) <= 0 for j in range(n_sub)) or \
+            bool((pv[:3] <= 0).any()) or bool((obs["sigma"] <= 0).any()):
+        status |= ST_DOMAIN
+    xr, yr = subray_positions(N, pix, ss)
+    bx, by = ray_shoot(xr, yr, lens, n_sub, tau)
+    mflat = obs["mask"].reshape(-1).bool()
+    xc, yc = pixel_centres(N, pix)
+    M = int(mflat.sum())
+    if M < K_NODES + 1:
+        status |= ST_MASK_SMALL
+    tr = None
+    if uniform_box is None:
+        bxm, bym = ray_shoot(xc[mflat], yc[mflat], lens, n_sub, tau)
+        tr = build_transform(bxm, bym)
+        status |= tr["status"]
+        gx, gy = rtu_transform(bx, by, tr)
+    else:
+        x_lo, y_lo, side = uniform_box
+        gx, gy = (bx - x_lo) / side, (by - y_lo) / side
+    s_grid, f = gp_source(w, ps)
+    v = bilinear(s_grid, gx, gy)
+    u_img = v.mean(dim=1).reshape(N, N)
+    m = psf_convolve(u_img, obs["psf"])
+    res = (m - obs["image"]) / obs["sigma"]
+    chi2 = (res ** 2).sum()
+    loss = 0.5 * chi2 + 0.5 * (w ** 2).sum()
+    chi2_mask = (res.reshape(-1)[mflat] ** 2).mean() if M > 0 else torch.zeros((), dtype=DT)
+    if not bool(torch.isfinite(loss)):
+        status |= ST_NONFINITE
+    out = {"loss": loss, "chi2": chi2, "chi2_mask": chi2_mask, "model": m, "status": status}
+    if return_all:
+        out.update({"bx": bx, "by": by, "gx": gx, "gy": gy, "src": s_grid, "f": f,
+                    "u": u_img, "transform": tr})
+    return out
+
+
+def obs_from_problem(p) -> dict:
+    """Observation dict from a problem produced by the seeded input generator."""
+    g = p.geom
+    return {"n_img": g.n_img, "pix": float(np.float32(g.pixel_scale)), "ss": g.supersample,
+            "image": _t(p.image), "sigma": _t(p.noise_sigma), "psf": _t(p.psf),
+            "mask": torch.as_tensor(p.mask.astype(np.int64)), "tau": g.tnfw_tau}
+
+
+def loss_grad(lens, ps, w, obs, n_sub=0, tau=0.0, want_grad=True, return_all=False):
+    """Loss = chi^2/2 + |w|^2/2 (Gaussian likelihood over all pixels, N(0,1)
+    prior on the latent) and its exact gradient with respect to the lens
+    parameters, the power-spectrum parameters and the latent field."""
+    lens = _t(lens).clone().requires_grad_(want_grad)
+    ps = _t(ps).clone().requires_grad_(want_grad)
+    w = _t(w).clone().requires_grad_(want_grad)
+    out = forward(lens, ps, w, obs, n_sub, tau, return_all=return_all)
+    res = {k: v for k, v in out.items()}
+    if want_grad:
+        gl, gp, gw = torch.autograd.grad(out["loss"], (lens, ps, w), allow_unused=True)
+        res["grad_lens"] = gl if gl is not None else torch.zeros_like(lens)
+        res["grad_ps"] = gp
+        res["grad_latent"] = gw
+        for g in (res["grad_lens"], gp, gw):
+            if not bool(torch.isfinite(g).all()):
+                res["status"] |= ST_NONFINITE
+    return res
+
+
+def loss_grad_problem(p, b: int, want_grad=True, return_all=False):
+    """loss_grad for sample b of a problem from the seeded input generator."""
+    obs = obs_from_problem(p)
+    ns = int(p.n_sub[b])
+    return loss_grad(p.lens[b].astype(np.float64), p.ps[b].astype(np.float64),
+                     p.latent[b].astype(np.float64), obs, ns, p.geom.tnfw_tau,
+                     want_grad=want_grad, return_all=return_all)
+
+
+# ------------------------------------------------------------------ ELBO (Sec. 4)
+def elbo_and_grad(mu, rho, eps, obs, n_lens: int, n_sub=0, tau=0.0):
+    """Stochastic ELBO of a mean-field Gaussian guide over z = (lens, ps, w)
+    with location mu and scale exp(rho), estimated with the given standard-normal
+    draws eps[S, dim]:  z_s = mu + exp(rho) eps_s,
+        ELBO = -mean_s loss(z_s) - sum_p ln(sigma_p sqrt(2 pi)) - (n^2/2) ln 2 pi
+               + sum(rho) + (dim/2)(1 + ln 2 pi),
+    i.e. Gaussian likelihood, flat priors on lens and spectrum parameters, a
+    unit normal prior on the latent, and the guide entropy.  Returns the ELBO
+    and its gradient with respect to mu and rho."""
+    mu = _t(mu).clone().requires_grad_(True)
+    rho = _t(rho).clone().requires_grad_(True)
+    eps = _t(eps)
+    S, dim = eps.shape
+    nsrc2 = dim - n_lens - 4
+    n = int(round(math.sqrt(nsrc2)))
+    total = torch.zeros((), dtype=DT)
+    for s in range(S):
+        z = mu + torch.exp(rho) * eps[s]
+        out = forward(z[:n_lens], z[n_lens:n_lens + 4], z[n_lens + 4:].reshape(n, n),
+                      obs, n_sub, tau)
+        total = total + out["loss"]
+    sig = obs["sigma"]
+    const = -torch.log(sig * math.sqrt(2 * math.pi)).sum() - 0.5 * nsrc2 * math.log(2 * math.pi)
+    elbo = -total / S + const + rho.sum() + 0.5 * dim * (1.0 + math.log(2 * math.pi))
+    gmu, grho = torch.autograd.grad(elbo, (mu, rho))
+    return elbo.detach(), gmu, grho
+
+
+def adam_step(param, grad, m, v, step: int, lr=1e-2, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba 2015, Algorithm 1) minimising along -grad's
+    ascent direction as given (grad is the gradient of the quantity minimised)."""
+    m = b1 * m + (1 - b1) * grad
+    v = b2 * v + (1 - b2) * grad * grad
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return param - lr * mh / (torch.sqrt(vh) + eps), m, v
