@@ -1,0 +1,160 @@
+/*
+ * rtu.h -- C ABI of the MI355X (gfx950) library for the ray-guided
+ * transformed uniform (RTU) grid lens likelihood and its gradient.
+ *
+ * The method (Enzi et al., "Gaussian processes on ray-guided transformed
+ * uniform grids"): supersampled image-plane rays are traced through a lens
+ * (SIE + external shear + optional NFW subhaloes, App. A eqs. A1-A3), the
+ * source-plane coordinates are mapped through a smoothed marginal CDF built
+ * from the arc-masked rays (Sec. 2.2 eq. 5, App. C), the source is a
+ * Gaussian process drawn in Fourier space on a uniform grid (Sec. 2.1,
+ * eqs. 1-4) and evaluated by bilinear interpolation, the sub-rays of each
+ * pixel are averaged, the image is convolved with the PSF and compared to the
+ * data with a Gaussian likelihood (Sec. 3.1, Sec. 4).
+ *
+ * Conventions used by every entry point:
+ *  - Return value: 0 on success, a negative RTU_E* code on misuse detected
+ *    on the host.  No entry point synchronises the device unless its comment
+ *    says so.  Numerical conditions of a sample are reported in its device
+ *    status word (RTU_ST_* bits), never as a return code.
+ *  - "device" pointers are allocations on the plan's device (hipMalloc or a
+ *    torch CUDA tensor), contiguous, row-major, owned by the caller, and
+ *    must stay valid until the work queued on the stream has finished.
+ *  - "host" pointers are read during the call only.
+ *  - stream is a hipStream_t passed as void*; NULL means the null stream.
+ *  - A plan is not thread-safe: use one plan per stream.
+ *
+ * Image pixel (i, j) (row i <-> y, column j <-> x) is centred at
+ * ((j - (N-1)/2) d, (i - (N-1)/2) d) arcsec, d = pixel_scale; its ss x ss
+ * sub-rays sit on a regular lattice centred in the pixel.  Source grid node
+ * (i, j) sits at ((j + 1/2)/n, (i + 1/2)/n) of the unit square of the
+ * transformed coordinates; brightness outside the grid is zero (Sec. 2.1).
+ */
+#ifndef RTU_H
+#define RTU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define RTU_OK        0
+#define RTU_EINVAL   -1   /* bad geometry or argument                         */
+#define RTU_ENOMEM   -2   /* device allocation failed / budget exceeded       */
+#define RTU_EBATCH   -3   /* batch larger than the plan's max_batch           */
+#define RTU_EHIP     -4   /* a HIP runtime call or kernel launch failed        */
+#define RTU_ESTATE   -5   /* call out of order (e.g. no observation set)      */
+#define RTU_ENOTFOUND -6  /* unknown fit id                                   */
+
+/* ---- per-sample status bits (device uint32 words) -------------------- */
+#define RTU_ST_NONFINITE    1u  /* loss or a gradient is not finite                    */
+#define RTU_ST_NONMONOTONE  2u  /* QF slope p'(u_k) <= eps or tied knots: slopes clamped */
+#define RTU_ST_MASK_SMALL   4u  /* fewer masked pixels than nodes + 1                  */
+#define RTU_ST_DOMAIN       8u  /* theta_E <= 0, |e| >= 1, r_s <= 0 or spectrum <= 0   */
+#define RTU_ST_SELECT_SLOW 16u  /* quantile selection took its slow path (many ties)   */
+
+/* Number of Chebyshev nodes of the quantile-function fit: degree 21 + 1
+ * (App. C step iii and Fig. C1). */
+#define RTU_K_NODES 22
+/* Lens parameters: theta_E, e1, e2, x0, y0, gamma1, gamma2, then per
+ * subhalo kappa_s, r_s, x_s, y_s (App. A).  Power-spectrum parameters:
+ * sigma_src, n_src, zeta_src, alpha_src (eqs. 3-4). */
+#define RTU_N_LENS_BASE 7
+#define RTU_N_PER_SUB   4
+#define RTU_N_PS        4
+#define RTU_MAX_SUB    10
+
+typedef struct rtu_plan_s* rtu_plan;
+
+typedef struct {
+  int32_t  n_img;        /* image pixels per side, 8..1024                          */
+  int32_t  supersample;  /* sub-rays per pixel per axis, 1..8                        */
+  int32_t  n_src;        /* source grid pixels per side: power of two, 8..256        */
+  int32_t  psf_size;     /* odd PSF width, 1..63                                    */
+  int32_t  n_sub_max;    /* NFW subhalo slots per sample, 0..RTU_MAX_SUB            */
+  int32_t  k_nodes;      /* must be RTU_K_NODES                                     */
+  float    pixel_scale;  /* arcsec per image pixel, > 0                             */
+  float    tnfw_tau;     /* subhalo projected-mass truncation in units of r_s;
+                            0 = untruncated NFW                                     */
+  uint32_t flags;        /* reserved, must be 0                                     */
+} rtu_geometry;
+
+/* Number of lens parameters per sample: 7 + 4 n_sub_max. */
+int32_t rtu_n_lens(const rtu_geometry* g);
+
+/* Device memory (bytes) a plan of this geometry and batch allocates; a
+ * serving layer uses it for admission.  0 if the geometry is invalid. */
+size_t rtu_workspace_bytes(const rtu_geometry* g, int32_t max_batch);
+
+/* Creates a plan on `device` for batches of up to max_batch samples and
+ * allocates all of its device memory once.  Returns RTU_EINVAL for a bad
+ * geometry, RTU_ENOMEM if the allocation fails.  *out is set on success. */
+int rtu_plan_create(const rtu_geometry* g, int32_t max_batch, int32_t device, rtu_plan* out);
+
+/* Frees the plan and its device memory (synchronises the plan's device). */
+int rtu_plan_destroy(rtu_plan p);
+
+/* Observation of one lens system (host arrays, copied into the plan):
+ * image[N*N] and noise_sigma[N*N] (sigma > 0) in data units, psf[K*K]
+ * (applied as given, not renormalised), arc_mask[N*N] (nonzero = pixel
+ * used to build the RTU grid; Sec. 2.2, the rays are traced from the
+ * observed pixel centres, not supersampled).  Builds the masked pixel list
+ * and the quantile ranks (h = (M-1) u_k, in FP64).  Synchronous.
+ * RTU_EINVAL if a pointer is NULL. */
+int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma,
+                        const float* psf, const uint8_t* arc_mask);
+
+/* Number of masked pixels M of the current observation (-1 if none). */
+int32_t rtu_masked_count(rtu_plan p);
+
+/* One loss evaluation per sample, and its gradient, for `batch` samples.
+ *   lens_params [B][7 + 4 n_sub_max]  device, see RTU_N_LENS_BASE
+ *   n_sub       [B] device int32, number of active subhaloes (<= n_sub_max),
+ *               or NULL for none
+ *   ps_params   [B][4]                device
+ *   latent      [B][n_src][n_src]     device, the white-noise field w of eq. 1
+ * Outputs (device; any may be NULL except loss and status):
+ *   loss        [B] double: chi^2/2 + |w|^2/2, chi^2 over all pixels
+ *   chi2_mask   [B] double: mean of ((m - d)/sigma)^2 over the masked pixels
+ *   grad_lens   [B][7 + 4 n_sub_max], grad_ps [B][4], grad_latent [B][n_src^2]
+ *               d loss / d parameters; if all three are NULL only the forward
+ *               pass runs.  Gradient slots of inactive subhaloes are zero.
+ *   model_image [B][n_img][n_img]: PSF-convolved model
+ *   status      [B] uint32 RTU_ST_* bits of each sample
+ * Asynchronous on `stream`.  RTU_ESTATE without an observation, RTU_EBATCH
+ * if batch > max_batch, RTU_EINVAL for NULL required pointers. */
+int rtu_loss_grad(rtu_plan p, int32_t batch,
+                  const float* lens_params, const int32_t* n_sub,
+                  const float* ps_params, const float* latent,
+                  double* loss, double* chi2_mask,
+                  float* grad_lens, float* grad_ps, float* grad_latent,
+                  float* model_image, uint32_t* status, void* stream);
+
+/* Intermediates of the last rtu_loss_grad call, copied to host memory for
+ * inspection (synchronises `stream`).  `what` selects:
+ *   RTU_DBG_KNOTS   float[2][2][K]: per axis, knots X_k then slopes S_k of the
+ *                   smoothed CDF in standardised units (App. C steps i-iv)
+ *   RTU_DBG_SELECT  int32[2][2][K]: per axis, masked-ray index of the order
+ *                   statistics at floor(h_k) and floor(h_k)+1
+ *   RTU_DBG_STD     double[3]: mean x, mean y, scale s of the masked rays
+ *   RTU_DBG_SOURCE  float[n_src^2]: source grid s (eq. 3)
+ *   RTU_DBG_PREPSF  float[N^2]: sub-ray mean image before the PSF
+ * RTU_EINVAL if `bytes` is smaller than the item. */
+#define RTU_DBG_KNOTS  1
+#define RTU_DBG_SELECT 2
+#define RTU_DBG_STD    3
+#define RTU_DBG_SOURCE 4
+#define RTU_DBG_PREPSF 5
+int rtu_debug_fetch(rtu_plan p, int32_t what, int32_t sample, void* host_dst, size_t bytes,
+                    void* stream);
+
+/* Human-readable text of a return code. */
+const char* rtu_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTU_H */

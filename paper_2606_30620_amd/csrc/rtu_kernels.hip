@@ -1,0 +1,999 @@
+// gfx950 kernels of one RTU-grid likelihood evaluation and its adjoint.
+//
+// Stage order on the caller's stream:
+//   k_prep      per sample: arc-masked ray shooting, standardisation, exact
+//               quantile selection (histogram + scan + in-bin ranking), the
+//               Chebyshev slope fit -> smoothed-CDF knots (App. C i-iv); and,
+//               in a third workgroup role, the FFT Gaussian-process source
+//               (eqs. 1-4).
+//   k_rays_fwd  per 16x16 pixel tile: sub-rays -> lens equation -> RTU
+//               transform (eq. 5) -> bilinear source value -> pixel mean.
+//   k_psf       PSF correlation through an LDS tile; the forward variant also
+//               forms the residual and the chi^2 partial sums (FP64).
+//   k_rays_adj  per tile: the same rays again, scattering d loss/d s into an
+//               LDS copy of the grid and accumulating d loss/d knots and
+//               d loss/d lens parameters.
+//   k_post      per sample: knot adjoint back to the selected masked rays,
+//               final reductions, GP adjoint through the FFT, status.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "rtu_device.h"
+#include "rtu_internal.h"
+
+namespace rtu {
+
+__constant__ float c_u[K];
+__constant__ double c_D[K * K];
+__constant__ float2 c_tw[128];
+
+// ====================================================================== helpers
+__device__ __forceinline__ void pixel_xy(const SysDev& S, int i, int j, int a, int b, float& x, float& y) {
+  // pixel centre ((j - (N-1)/2) d, (i - (N-1)/2) d) plus the sub-ray offset
+  // (((b + 1/2)/ss - 1/2) d, ((a + 1/2)/ss - 1/2) d)
+  const float inv = 1.f / (float)S.ss;
+  x = ((float)j + ((float)b + 0.5f) * inv - 0.5f * (float)S.n_img) * S.pix;
+  y = ((float)i + ((float)a + 0.5f) * inv - 0.5f * (float)S.n_img) * S.pix;
+}
+
+__device__ __forceinline__ int n_sub_of(const SysDev& S, int b) {
+  if (!S.n_sub || S.n_sub_max == 0) return 0;
+  const int v = S.n_sub[b];
+  return v < 0 ? 0 : (v > S.n_sub_max ? S.n_sub_max : v);
+}
+
+// beta = theta - alpha(theta) for SIE + shear + subhaloes
+__device__ __forceinline__ void shoot(const SysDev& S, const Sie& L, const float* lensp, int nsub,
+                                      float x, float y, float& bx, float& by) {
+  float ax, ay;
+  sie_shear_alpha(L, x, y, ax, ay);
+  for (int j = 0; j < nsub; ++j) {
+    const Nfw N = make_nfw(lensp + RTU_N_LENS_BASE + RTU_N_PER_SUB * j, S.tau);
+    nfw_alpha(N, S.tau, x, y, ax, ay);
+  }
+  bx = x - ax;
+  by = y - ay;
+}
+
+__device__ __forceinline__ unsigned long long sel_key(float v, int m) {
+  unsigned u = __float_as_uint(v + 0.0f);      // -0 -> +0
+  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((unsigned long long)u << 32) | (unsigned)m;
+}
+__device__ __forceinline__ float key_value(unsigned long long k) {
+  unsigned u = (unsigned)(k >> 32);
+  u = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+  return __uint_as_float(u);
+}
+
+// ====================================================================== k_prep
+// LDS layout of the selection role
+struct SelLds {
+  int hist[HIST_BINS];
+  unsigned long long cand[SEL_LDS_CAP];
+  double red[8 * 16];
+  float fred[2 * 16];
+  int tbin[2 * K], tcum[2 * K], trank[2 * K];
+  int seg_bin[2 * K], seg_start[2 * K], seg_count[2 * K], seg_fill[2 * K];
+  int nseg, total;
+  float tval[2 * K];
+  int tidx[2 * K];
+  double q[K];
+  uint32_t stat;
+};
+
+__device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* smem) {
+  SelLds& L = *reinterpret_cast<SelLds*>(smem);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int M = S.M;
+  const float* lensp = S.lens + (size_t)b * S.n_lens;
+  const int nsub = n_sub_of(S, b);
+  const Sie sie = make_sie(lensp);
+  float* zb = S.zbuf + ((size_t)b * 2 + axis) * M;
+  uint32_t st = 0;
+  if (M < K + 1) st |= RTU_ST_MASK_SMALL;
+  if (tid == 0) L.stat = 0;
+  if (tid < 2 * K) { L.tval[tid] = 0.f; L.tidx[tid] = 0; }
+
+  // ---- masked rays at the observed pixel centres (not supersampled)
+  double sx = 0, sy = 0, sxx = 0, syy = 0;
+  float vmin = INFINITY, vmax = -INFINITY;
+  for (int m = tid; m < M; m += nt) {
+    const int p = S.mask_idx[m];
+    const int i = p / S.n_img, j = p - i * S.n_img;
+    const float x = ((float)j - 0.5f * (float)(S.n_img - 1)) * S.pix;
+    const float y = ((float)i - 0.5f * (float)(S.n_img - 1)) * S.pix;
+    float bx, by;
+    shoot(S, sie, lensp, nsub, x, y, bx, by);
+    sx += bx; sy += by; sxx += (double)bx * bx; syy += (double)by * by;
+    const float v = (axis == 0 ? bx : by) + 0.0f;
+    zb[m] = v;
+    vmin = fminf(vmin, v);
+    vmax = fmaxf(vmax, v);
+  }
+  {
+    double v4[4] = {sx, sy, sxx, syy};
+    block_sum<4>(v4, L.red);
+    sx = v4[0]; sy = v4[1]; sxx = v4[2]; syy = v4[3];
+    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    float a = wave_min(vmin), c = wave_max(vmax);
+    if (lane == 0) { L.fred[wv] = a; L.fred[16 + wv] = c; }
+    __syncthreads();
+    vmin = INFINITY; vmax = -INFINITY;
+    for (int w = 0; w < nw; ++w) { vmin = fminf(vmin, L.fred[w]); vmax = fmaxf(vmax, L.fred[16 + w]); }
+    __syncthreads();
+  }
+  const double Md = (double)(M > 0 ? M : 1);
+  const double mux = sx / Md, muy = sy / Md;
+  const double sdx = sqrt(fmax(sxx / Md - mux * mux, 0.0));
+  const double sdy = sqrt(fmax(syy / Md - muy * muy, 0.0));
+  const double sc = fmin(sdx, sdy);
+  const double mu = axis == 0 ? mux : muy;
+
+  // ---- level-1 histogram over [vmin, vmax] (monotone bin map)
+  for (int i = tid; i < HIST_BINS; i += nt) L.hist[i] = 0;
+  __syncthreads();
+  const float scale = (vmax > vmin) ? (float)HIST_BINS / (vmax - vmin) : 0.f;
+  auto bin_of = [&](float v) {
+    int bb = (int)((v - vmin) * scale);
+    return bb < 0 ? 0 : (bb >= HIST_BINS ? HIST_BINS - 1 : bb);
+  };
+  for (int m = tid; m < M; m += nt) atomicAdd(&L.hist[bin_of(zb[m])], 1);
+  __syncthreads();
+  // exclusive scan: thread t owns bins [4t, 4t + 4)
+  {
+    const int per = HIST_BINS / PREP_THREADS;  // 4
+    int loc[HIST_BINS / PREP_THREADS];
+    int s = 0;
+    for (int k = 0; k < per; ++k) { loc[k] = L.hist[tid * per + k]; s += loc[k]; }
+    // block exclusive scan of s
+    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    int incl = s;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    int* wsum = reinterpret_cast<int*>(L.red);
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wv; ++w) off += wsum[w];
+    int run = off + incl - s;
+    __syncthreads();
+    for (int k = 0; k < per; ++k) { L.hist[tid * per + k] = run; run += loc[k]; }
+    (void)nw;
+  }
+  __syncthreads();
+  auto cum = [&](int bb) { return bb < HIST_BINS ? L.hist[bb] : M; };
+
+  // ---- target ranks: floor(h_k) and floor(h_k) + 1, h_k = (M-1) u_k
+  if (tid < 2 * K) {
+    int r = S.rank_j[tid >> 1] + (tid & 1);
+    r = r < 0 ? 0 : (r > M - 1 ? M - 1 : r);
+    int lo = 0, hi = HIST_BINS - 1;   // largest bin with cum <= r
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L.hist[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    L.tbin[tid] = lo;
+    L.tcum[tid] = L.hist[lo];
+    L.trank[tid] = r - L.hist[lo];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int ns = 0, tot = 0;
+    for (int t = 0; t < 2 * K; ++t) {
+      const int bb = L.tbin[t];
+      if (ns == 0 || L.seg_bin[ns - 1] != bb) {
+        L.seg_bin[ns] = bb;
+        L.seg_start[ns] = tot;
+        L.seg_count[ns] = cum(bb + 1) - cum(bb);
+        L.seg_fill[ns] = 0;
+        tot += L.seg_count[ns];
+        ++ns;
+      }
+    }
+    L.nseg = ns;
+    L.total = tot;
+  }
+  __syncthreads();
+  const int nseg = L.nseg, total = L.total;
+  // map bin -> segment (reuse the histogram array)
+  for (int i = tid; i < HIST_BINS; i += nt) L.hist[i] = -1;
+  __syncthreads();
+  if (tid < nseg) L.hist[L.seg_bin[tid]] = tid;
+  __syncthreads();
+  const bool slow = total > SEL_LDS_CAP;
+  unsigned long long* cand = slow ? S.cand + ((size_t)b * 2 + axis) * M : L.cand;
+  if (slow) st |= RTU_ST_SELECT_SLOW;
+  for (int m = tid; m < M; m += nt) {
+    const float v = zb[m];
+    const int sg = L.hist[bin_of(v)];
+    if (sg >= 0) {
+      const int pos = atomicAdd(&L.seg_fill[sg], 1);
+      cand[L.seg_start[sg] + pos] = sel_key(v, m);
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  // ---- rank inside each segment by counting
+  for (int sg = 0; sg < nseg; ++sg) {
+    const int st0 = L.seg_start[sg], cnt = L.seg_count[sg], bb = L.seg_bin[sg];
+    for (int c = tid; c < cnt; c += nt) {
+      const unsigned long long kc = cand[st0 + c];
+      int rk = 0;
+      for (int c2 = 0; c2 < cnt; ++c2) rk += cand[st0 + c2] < kc;
+      for (int t = 0; t < 2 * K; ++t) {
+        if (L.tbin[t] == bb && L.trank[t] == rk) {
+          L.tval[t] = key_value(kc);
+          L.tidx[t] = (int)(kc & 0xffffffffu);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- Chebyshev slopes and knots (FP64), App. C steps iii-iv
+  float* kn = S.knots + ((size_t)b * 2 + axis) * 2 * K;
+  float* kd = S.kdbg + ((size_t)b * 2 + axis) * 2 * K;
+  float* dpo = S.dp + ((size_t)b * 2 + axis) * K;
+  int* sel = S.sel + ((size_t)b * 2 + axis) * 2 * K;
+  const bool degenerate = !(sc > 0.0) || M < 2;
+  if (tid < K) {
+    double qb;
+    if (M > 0) {
+      const double t = (double)S.rank_t[tid];
+      qb = (1.0 - t) * (double)L.tval[2 * tid] + t * (double)L.tval[2 * tid + 1];
+    } else {
+      qb = 0.0;
+    }
+    L.q[tid] = degenerate ? (double)c_u[tid] : (qb - mu) / sc;  // standardised quantile
+    sel[2 * tid] = M > 0 ? L.tidx[2 * tid] : 0;
+    sel[2 * tid + 1] = M > 0 ? L.tidx[2 * tid + 1] : 0;
+  }
+  __syncthreads();
+  if (tid < K) {
+    const double* q = L.q;
+    double dpz = 0.0;
+    for (int l = 0; l < K; ++l) dpz += c_D[tid * K + l] * q[l];
+    const double eps = 1e-6 * (q[K - 1] - q[0]);
+    bool bad = !(dpz > eps);
+    if (tid < K - 1 && !(q[tid + 1] > q[tid])) bad = true;
+    const bool clamp = !(dpz > eps);
+    if (bad || degenerate) atomicOr(&L.stat, RTU_ST_NONMONOTONE);
+    const double dpc = clamp ? (eps > 0 ? eps : 1.0) : dpz;
+    const double scd = degenerate ? 1.0 : sc;
+    const double mud = degenerate ? 0.0 : mu;
+    kd[tid] = (float)q[tid];
+    kd[K + tid] = (float)(1.0 / dpc);
+    kn[tid] = (float)(mud + scd * q[tid]);
+    kn[K + tid] = (float)(1.0 / (scd * dpc));
+    dpo[tid] = clamp ? -1.f : (float)(scd * dpc);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (axis == 0) {
+      double* sd = S.stdv + (size_t)b * 4;
+      sd[0] = mux; sd[1] = muy; sd[2] = sc; sd[3] = (double)M;
+    }
+    S.st[b * 4 + axis] = st | L.stat;
+  }
+}
+
+// GP source (eqs. 1-4): F = DFT(w); f = Re IDFT(sqrt(P) F)/n^2; s = (s0 softplus(f/s0))^alpha
+__device__ void prep_gp(const SysDev& S, int b, unsigned char* smem) {
+  float2* lds = reinterpret_cast<float2*>(smem);
+  const int n = S.n_src, logn = S.log2_src, n2 = n * n;
+  const float* w = S.latent + (size_t)b * n2;
+  float2* F = S.F + (size_t)b * n2;
+  float2* T = S.tmp + (size_t)b * n2;
+  float* fo = S.fld + (size_t)b * n2;
+  float* so = S.src + (size_t)b * n2;
+  const float* ps = S.ps + (size_t)b * 4;
+  // zero the adjoint accumulator of this sample for the ray adjoint
+  if (S.want_grad) {
+    float* sb = S.sbar + (size_t)b * n2;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) sb[i] = 0.f;
+  }
+  // parameter domain
+  if (threadIdx.x == 0) {
+    const float* L = S.lens + (size_t)b * S.n_lens;
+    uint32_t st = 0;
+    if (!(L[0] > 0.f) || !(L[1] * L[1] + L[2] * L[2] < 1.f)) st |= RTU_ST_DOMAIN;
+    const int ns = n_sub_of(S, b);
+    for (int j = 0; j < ns; ++j)
+      if (!(L[RTU_N_LENS_BASE + RTU_N_PER_SUB * j + 1] > 0.f)) st |= RTU_ST_DOMAIN;
+    if (!(ps[0] > 0.f) || !(ps[1] > 0.f) || !(ps[2] > 0.f)) st |= RTU_ST_DOMAIN;
+    S.st[b * 4 + 2] = st;
+  }
+  const Matern mt = make_matern(ps);
+  const float alpha = ps[3];
+  const float inv_n2 = 1.f / (float)n2;
+  // rows: forward transform of the real latent
+  fft_pass(lds, n, logn, false, -1.f, false, 0.f,
+           [&](int r, int c) { return make_float2(w[r * n + c], 0.f); },
+           [&](int, int, float2 v) { return v; },
+           [&](int r, int c, float2 v) { T[r * n + c] = v; });
+  // columns: forward, keep F, multiply by sqrt(P), inverse
+  fft_pass(lds, n, logn, true, -1.f, true, 1.f,
+           [&](int r, int c) { return T[r * n + c]; },
+           [&](int r, int c, float2 v) {
+             F[r * n + c] = v;
+             const float kx = fft_freq(c, n), ky = fft_freq(r, n);
+             const float sp = matern_sqrtP(mt, kx * kx + ky * ky);
+             return make_float2(v.x * sp, v.y * sp);
+           },
+           [&](int r, int c, float2 v) { T[r * n + c] = v; });
+  // rows: inverse, real part / n^2, positivity transform
+  fft_pass(lds, n, logn, false, 1.f, false, 0.f,
+           [&](int r, int c) { return T[r * n + c]; },
+           [&](int, int, float2 v) { return v; },
+           [&](int r, int c, float2 v) {
+             const float f = v.x * inv_n2;
+             fo[r * n + c] = f;
+             const float x = f * 100.f;   // f / s0, s0 = 0.01
+             so[r * n + c] = __expf(alpha * (-4.605170186f + log_softplus_f(x)));
+           });
+}
+
+constexpr size_t PREP_LDS = sizeof(SelLds) > FFT_LDS_FLOAT2 * 8 ? sizeof(SelLds) : FFT_LDS_FLOAT2 * 8;
+
+__global__ void __launch_bounds__(PREP_THREADS) k_prep(SysDev S) {
+  __shared__ __align__(16) unsigned char smem[PREP_LDS];
+  const int b = blockIdx.x, role = blockIdx.y;
+  if (role < 2) prep_select(S, b, role, smem);
+  else prep_gp(S, b, smem);
+}
+
+// ====================================================================== ray tiles
+// Source grid staged in LDS with a one-cell zero border:
+// padded index (i + 1) * (n + 2) + (j + 1) for i, j in [-1, n].
+struct RayLdsHead {
+  float X[2][K], Sl[2][K], dp[2][K];
+  float kb[4 * K];   // dX (x), dS (x), dX (y), dS (y)
+};
+
+__device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H) {
+  const float* kn = S.knots + (size_t)b * 4 * K;
+  const float* dp = S.dp + (size_t)b * 2 * K;
+  for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
+    const int ax = i / K, k = i - ax * K;
+    H.X[ax][k] = kn[ax * 2 * K + k];
+    H.Sl[ax][k] = kn[ax * 2 * K + K + k];
+    H.dp[ax][k] = dp[i];
+  }
+  for (int i = threadIdx.x; i < 4 * K; i += blockDim.x) H.kb[i] = 0.f;
+}
+
+template <bool LDSGRID>
+__device__ __forceinline__ void load_grid(const SysDev& S, int b, float* g) {
+  if (!LDSGRID) return;
+  const int n = S.n_src, np = n + 2;
+  const float* src = S.src + (size_t)b * n * n;
+  for (int i = threadIdx.x; i < np * np; i += blockDim.x) {
+    const int r = i / np - 1, c = i - (i / np) * np - 1;
+    g[i] = (r >= 0 && r < n && c >= 0 && c < n) ? src[r * n + c] : 0.f;
+  }
+}
+
+// bilinear weights of y on the n-grid (nodes at (j + 1/2)/n); returns false if
+// all four corners lie outside the zero-padded grid.
+struct Bil {
+  int i0, j0;
+  float fx, fy;
+};
+__device__ __forceinline__ bool bil_setup(float yx, float yy, int n, Bil& o) {
+  const float tx = yx * (float)n - 0.5f, ty = yy * (float)n - 0.5f;
+  if (!(tx >= -1.f && tx < (float)n && ty >= -1.f && ty < (float)n)) return false;
+  const float fj = floorf(tx), fi = floorf(ty);
+  o.j0 = (int)fj; o.i0 = (int)fi;
+  o.fx = tx - fj; o.fy = ty - fi;
+  return true;
+}
+
+template <bool LDSGRID>
+__device__ __forceinline__ void bil_corners(const float* g, const float* gsrc, int n, const Bil& B,
+                                            float& s00, float& s01, float& s10, float& s11) {
+  if (LDSGRID) {
+    const int np = n + 2;
+    const int p = (B.i0 + 1) * np + (B.j0 + 1);
+    s00 = g[p]; s01 = g[p + 1]; s10 = g[p + np]; s11 = g[p + np + 1];
+  } else {
+    auto at = [&](int i, int j) { return (i >= 0 && i < n && j >= 0 && j < n) ? gsrc[i * n + j] : 0.f; };
+    s00 = at(B.i0, B.j0); s01 = at(B.i0, B.j0 + 1); s10 = at(B.i0 + 1, B.j0); s11 = at(B.i0 + 1, B.j0 + 1);
+  }
+}
+
+template <bool LDSGRID>
+__device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* smem) {
+  RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
+  float* g = reinterpret_cast<float*>(smem + sizeof(RayLdsHead));
+  const int ti = tile / S.ray_tx, tj = tile - ti * S.ray_tx;
+  const int i = ti * RAY_TILE + (threadIdx.x >> 4), j = tj * RAY_TILE + (threadIdx.x & 15);
+  load_knots(S, b, H);
+  load_grid<LDSGRID>(S, b, g);
+  __syncthreads();
+  if (i >= S.n_img || j >= S.n_img) return;
+  const float* lensp = S.lens + (size_t)b * S.n_lens;
+  const int nsub = n_sub_of(S, b);
+  const Sie L = make_sie(lensp);
+  const int n = S.n_src;
+  const float* gsrc = S.src + (size_t)b * n * n;
+  float acc = 0.f;
+  for (int a = 0; a < S.ss; ++a) {
+    for (int c = 0; c < S.ss; ++c) {
+      float x, y, bx, by;
+      pixel_xy(S, i, j, a, c, x, y);
+      shoot(S, L, lensp, nsub, x, y, bx, by);
+      float dgx, dgy;
+      const float yx = cdf_eval(H.X[0], H.Sl[0], bx, knot_count(H.X[0], bx), dgx);
+      const float yy = cdf_eval(H.X[1], H.Sl[1], by, knot_count(H.X[1], by), dgy);
+      Bil B;
+      if (bil_setup(yx, yy, n, B)) {
+        float s00, s01, s10, s11;
+        bil_corners<LDSGRID>(g, gsrc, n, B, s00, s01, s10, s11);
+        acc += (1.f - B.fy) * ((1.f - B.fx) * s00 + B.fx * s01) + B.fy * ((1.f - B.fx) * s10 + B.fx * s11);
+      }
+    }
+  }
+  S.u[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] = acc * S.inv_ss2;
+}
+
+template <bool LDSGRID>
+__global__ void __launch_bounds__(RAY_THREADS) k_rays_fwd(SysDev S) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x / S.ray_tiles;
+  rays_fwd_body<LDSGRID>(S, b, blockIdx.x - b * S.ray_tiles, smem);
+}
+
+// register cache of the knot-adjoint accumulation for one axis: the current
+// interval code k (0..K) and the four partial sums of its end knots
+struct KnotCache {
+  int k;
+  float xl, xr, sl, sr;
+};
+__device__ __forceinline__ void kc_flush(KnotCache& c, float* kb /* dX[K], dS[K] */) {
+  if (c.k < 0) return;
+  if (c.k == 0) {
+    atomicAdd(&kb[0], c.xl); atomicAdd(&kb[K], c.sl);
+  } else if (c.k >= K) {
+    atomicAdd(&kb[K - 1], c.xl); atomicAdd(&kb[K + K - 1], c.sl);
+  } else {
+    const int l = c.k - 1;
+    atomicAdd(&kb[l], c.xl); atomicAdd(&kb[l + 1], c.xr);
+    atomicAdd(&kb[K + l], c.sl); atomicAdd(&kb[K + l + 1], c.sr);
+  }
+  c.xl = c.xr = c.sl = c.sr = 0.f;
+}
+
+template <bool LDSGRID>
+__device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* smem) {
+  RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
+  const int n = S.n_src, np = n + 2;
+  float* g = reinterpret_cast<float*>(smem + sizeof(RayLdsHead));
+  float* gb = g + (LDSGRID ? np * np : 0);                 // d loss / d s (padded)
+  float* subacc = gb + (LDSGRID ? np * np : 0);            // [4 n_sub_max][256] per-thread
+  size_t off = sizeof(RayLdsHead) + (size_t)(LDSGRID ? 2 * np * np : 0) * 4 +
+               (size_t)4 * S.n_sub_max * RAY_THREADS * 4;
+  off = (off + 15) & ~(size_t)15;
+  double* red = reinterpret_cast<double*>(smem + off);     // [8 * 4]
+  int* bbox = reinterpret_cast<int*>(red + 8 * 4);
+  const int ti = tile / S.ray_tx, tj = tile - ti * S.ray_tx;
+  const int i = ti * RAY_TILE + (threadIdx.x >> 4), j = tj * RAY_TILE + (threadIdx.x & 15);
+  load_knots(S, b, H);
+  load_grid<LDSGRID>(S, b, g);
+  if (LDSGRID)
+    for (int q = threadIdx.x; q < np * np; q += blockDim.x) gb[q] = 0.f;
+  for (int q = threadIdx.x; q < 4 * S.n_sub_max * RAY_THREADS; q += blockDim.x) subacc[q] = 0.f;
+  if (threadIdx.x == 0) { bbox[0] = bbox[1] = 1 << 30; bbox[2] = bbox[3] = -(1 << 30); }
+  __syncthreads();
+  const float* lensp = S.lens + (size_t)b * S.n_lens;
+  const int nsub = n_sub_of(S, b);
+  const Sie L = make_sie(lensp);
+  const float* gsrc = S.src + (size_t)b * n * n;
+  float* gsb = S.sbar + (size_t)b * n * n;
+  SieAcc acc;
+  acc.zero();
+  int bi0 = 1 << 30, bj0 = 1 << 30, bi1 = -(1 << 30), bj1 = -(1 << 30);
+  if (i < S.n_img && j < S.n_img) {
+    const float vb = S.ubar[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] * S.inv_ss2;
+    KnotCache cx{-1, 0.f, 0.f, 0.f, 0.f}, cy{-1, 0.f, 0.f, 0.f, 0.f};
+    for (int a = 0; a < S.ss; ++a) {
+      for (int c = 0; c < S.ss; ++c) {
+        float x, y, bx, by;
+        pixel_xy(S, i, j, a, c, x, y);
+        shoot(S, L, lensp, nsub, x, y, bx, by);
+        const int kx = knot_count(H.X[0], bx), ky = knot_count(H.X[1], by);
+        float dgx, dgy;
+        const float yx = cdf_eval(H.X[0], H.Sl[0], bx, kx, dgx);
+        const float yy = cdf_eval(H.X[1], H.Sl[1], by, ky, dgy);
+        Bil B;
+        if (!bil_setup(yx, yy, n, B)) continue;
+        float s00, s01, s10, s11;
+        bil_corners<LDSGRID>(g, gsrc, n, B, s00, s01, s10, s11);
+        // d loss / d s at the four corners
+        const float w00 = (1.f - B.fx) * (1.f - B.fy), w01 = B.fx * (1.f - B.fy);
+        const float w10 = (1.f - B.fx) * B.fy, w11 = B.fx * B.fy;
+        if (LDSGRID) {
+          const int p = (B.i0 + 1) * np + (B.j0 + 1);
+          atomicAdd(&gb[p], vb * w00);
+          atomicAdd(&gb[p + 1], vb * w01);
+          atomicAdd(&gb[p + np], vb * w10);
+          atomicAdd(&gb[p + np + 1], vb * w11);
+          bi0 = min(bi0, B.i0); bj0 = min(bj0, B.j0); bi1 = max(bi1, B.i0 + 1); bj1 = max(bj1, B.j0 + 1);
+        } else {
+          auto add = [&](int ii, int jj, float v) {
+            if (ii >= 0 && ii < n && jj >= 0 && jj < n) atomicAdd(&gsb[ii * n + jj], v);
+          };
+          add(B.i0, B.j0, vb * w00); add(B.i0, B.j0 + 1, vb * w01);
+          add(B.i0 + 1, B.j0, vb * w10); add(B.i0 + 1, B.j0 + 1, vb * w11);
+        }
+        // d loss / d y
+        const float fn = (float)n;
+        const float ybx = vb * fn * ((1.f - B.fy) * (s01 - s00) + B.fy * (s11 - s10));
+        const float yby = vb * fn * ((1.f - B.fx) * (s10 - s00) + B.fx * (s11 - s01));
+        // knots and slopes of the CDF splines
+        {
+          float gXl, gXr, gSl, gSr;
+          cdf_knot_partials(H.X[0], H.Sl[0], bx, kx, gXl, gXr, gSl, gSr);
+          if (kx != cx.k) { kc_flush(cx, H.kb); cx.k = kx; }
+          cx.xl += ybx * gXl; cx.xr += ybx * gXr; cx.sl += ybx * gSl; cx.sr += ybx * gSr;
+          cdf_knot_partials(H.X[1], H.Sl[1], by, ky, gXl, gXr, gSl, gSr);
+          if (ky != cy.k) { kc_flush(cy, H.kb + 2 * K); cy.k = ky; }
+          cy.xl += yby * gXl; cy.xr += yby * gXr; cy.sl += yby * gSl; cy.sr += yby * gSr;
+        }
+        // d loss / d beta -> d loss / d alpha = -d loss / d beta
+        const float abx = -ybx * dgx, aby = -yby * dgy;
+        sie_shear_vjp(L, x, y, abx, aby, acc);
+        for (int q = 0; q < nsub; ++q) {
+          const Nfw N = make_nfw(lensp + RTU_N_LENS_BASE + RTU_N_PER_SUB * q, S.tau);
+          float* sa = subacc + (4 * q) * RAY_THREADS + threadIdx.x;
+          float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+          nfw_vjp(N, S.tau, x, y, abx, aby, g0, g1, g2, g3);
+          sa[0] += g0; sa[RAY_THREADS] += g1; sa[2 * RAY_THREADS] += g2; sa[3 * RAY_THREADS] += g3;
+        }
+      }
+    }
+    kc_flush(cx, H.kb);
+    kc_flush(cy, H.kb + 2 * K);
+  }
+  if (LDSGRID) {
+    atomicMin(&bbox[0], bi0); atomicMin(&bbox[1], bj0);
+    atomicMax(&bbox[2], bi1); atomicMax(&bbox[3], bj1);
+  }
+  // ---- lens-gradient partials of this tile (FP64 block sums)
+  double* lp = S.lpart + ((size_t)b * S.ray_tiles + tile) * S.n_lens;
+  {
+    double v[8] = {acc.P, acc.q, acc.f, acc.phi, acc.x0, acc.y0, acc.g1, acc.g2};
+    block_sum<8>(v, red);
+    if (threadIdx.x == 0) {
+      double gl[7];
+      sie_grad(L, v, gl);
+      for (int k = 0; k < 7; ++k) lp[k] = gl[k];
+    }
+  }
+  // subhaloes: 4 n_sub_max columns of per-thread sums
+  for (int q = threadIdx.x >> 6; q < 4 * S.n_sub_max; q += RAY_THREADS / 64) {
+    float s = 0.f;
+    for (int t = threadIdx.x & 63; t < RAY_THREADS; t += 64) s += subacc[q * RAY_THREADS + t];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) lp[RTU_N_LENS_BASE + q] = (double)s;
+  }
+  // knot partials of this tile
+  float* kbo = S.kbar + ((size_t)b * S.ray_tiles + tile) * 4 * K;
+  for (int q = threadIdx.x; q < 4 * K; q += blockDim.x) kbo[q] = H.kb[q];
+  // d loss / d s: add the touched window of the LDS grid to the sample's grid
+  if (LDSGRID) {
+    const int i0 = max(bbox[0], 0), j0 = max(bbox[1], 0), i1 = min(bbox[2], n - 1), j1 = min(bbox[3], n - 1);
+    const int wj = j1 - j0 + 1, wi = i1 - i0 + 1;
+    if (wj > 0 && wi > 0) {
+      for (int q = threadIdx.x; q < wi * wj; q += blockDim.x) {
+        const int ii = i0 + q / wj, jj = j0 + q % wj;
+        const float v = gb[(ii + 1) * np + jj + 1];
+        if (v != 0.f) atomicAdd(&gsb[ii * n + jj], v);
+      }
+    }
+  }
+}
+
+template <bool LDSGRID>
+__global__ void __launch_bounds__(RAY_THREADS) k_rays_adj(SysDev S) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x / S.ray_tiles;
+  rays_adj_body<LDSGRID>(S, b, blockIdx.x - b * S.ray_tiles, smem);
+}
+
+// ====================================================================== PSF
+// out[i, j] = sum_{a,b} W[a, b] in[i + a - h, j + b - h] (zero outside), h = (KP-1)/2.
+// Forward: in = u, W = flipped PSF (a convolution), also r = (m - d)/sigma^2 and
+// chi^2 partials.  Adjoint: in = r, W = PSF (the transpose of the convolution).
+template <int KP>
+__global__ void __launch_bounds__(PSF_THREADS) k_psf(SysDev S, int adjoint) {
+  constexpr int HW = PSF_TW + KP - 1;
+  constexpr int LS = (HW + 3) & ~3;              // row stride, multiple of 4 floats
+  constexpr int HH = PSF_TH + KP - 1;
+  __shared__ __align__(16) float tilein[HH * LS];
+  __shared__ double red[2 * 4];
+  const int N = S.n_img, h = KP / 2;
+  const int b = blockIdx.x / S.psf_tiles, tile = blockIdx.x - b * S.psf_tiles;
+  const int ty0 = (tile / S.psf_tx) * PSF_TH, tx0 = (tile % S.psf_tx) * PSF_TW;
+  const float* in = (adjoint ? S.r : S.u) + (size_t)b * N * N;
+  const float* W = adjoint ? S.psf : S.psf_flip;
+  for (int q = threadIdx.x; q < HH * LS; q += blockDim.x) {
+    const int rr = q / LS, cc = q - rr * LS;
+    const int gi = ty0 + rr - h, gj = tx0 + cc - h;
+    tilein[q] = (cc < HW && gi >= 0 && gi < N && gj >= 0 && gj < N) ? in[gi * N + gj] : 0.f;
+  }
+  __syncthreads();
+  const int ly = threadIdx.x >> 4, lx = (threadIdx.x & 15) * 4;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int a = 0; a < KP; ++a) {
+    const float* row = tilein + (ly + a) * LS + lx;
+    float win[KP + 3];
+#pragma unroll
+    for (int q = 0; q < KP + 3; ++q) win[q] = row[q];
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+      const float wv = W[a * KP + c];
+      acc[0] = fmaf(wv, win[c], acc[0]);
+      acc[1] = fmaf(wv, win[c + 1], acc[1]);
+      acc[2] = fmaf(wv, win[c + 2], acc[2]);
+      acc[3] = fmaf(wv, win[c + 3], acc[3]);
+    }
+  }
+  const int gi = ty0 + ly;
+  double c2 = 0.0, c2m = 0.0;
+  if (gi < N) {
+    for (int q = 0; q < 4; ++q) {
+      const int gj = tx0 + lx + q;
+      if (gj >= N) break;
+      const size_t p = (size_t)b * N * N + gi * N + gj;
+      if (adjoint) {
+        S.ubar[p] = acc[q];
+      } else {
+        const int pi = gi * N + gj;
+        const float res = acc[q] - S.image[pi];
+        const float iv = S.inv_var[pi];
+        S.r[p] = res * iv;
+        if (S.model) S.model[p] = acc[q];
+        const double e = (double)res * (double)res * (double)iv;
+        c2 += e;
+        if (S.mask[pi]) c2m += e;
+      }
+    }
+  }
+  if (!adjoint) {
+    double v[2] = {c2, c2m};
+    block_sum<2>(v, red);
+    if (threadIdx.x == 0) {
+      double* o = S.c2part + ((size_t)b * S.psf_tiles + tile) * 2;
+      o[0] = v[0];
+      o[1] = v[1];
+    }
+  }
+}
+
+// generic PSF size: direct LDS reads
+__global__ void __launch_bounds__(PSF_THREADS) k_psf_any(SysDev S, int adjoint) {
+  extern __shared__ __align__(16) float tilein[];
+  __shared__ double red[2 * 4];
+  const int N = S.n_img, KP = S.psf_k, h = KP / 2;
+  const int HW = PSF_TW + KP - 1, LS = (HW + 3) & ~3, HH = PSF_TH + KP - 1;
+  const int b = blockIdx.x / S.psf_tiles, tile = blockIdx.x - b * S.psf_tiles;
+  const int ty0 = (tile / S.psf_tx) * PSF_TH, tx0 = (tile % S.psf_tx) * PSF_TW;
+  const float* in = (adjoint ? S.r : S.u) + (size_t)b * N * N;
+  const float* W = adjoint ? S.psf : S.psf_flip;
+  for (int q = threadIdx.x; q < HH * LS; q += blockDim.x) {
+    const int rr = q / LS, cc = q - rr * LS;
+    const int gi = ty0 + rr - h, gj = tx0 + cc - h;
+    tilein[q] = (cc < HW && gi >= 0 && gi < N && gj >= 0 && gj < N) ? in[gi * N + gj] : 0.f;
+  }
+  __syncthreads();
+  const int ly = threadIdx.x >> 4, lx = (threadIdx.x & 15) * 4;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int a = 0; a < KP; ++a) {
+    const float* row = tilein + (ly + a) * LS + lx;
+    for (int c = 0; c < KP; ++c) {
+      const float wv = W[a * KP + c];
+      acc[0] = fmaf(wv, row[c], acc[0]);
+      acc[1] = fmaf(wv, row[c + 1], acc[1]);
+      acc[2] = fmaf(wv, row[c + 2], acc[2]);
+      acc[3] = fmaf(wv, row[c + 3], acc[3]);
+    }
+  }
+  const int gi = ty0 + ly;
+  double c2 = 0.0, c2m = 0.0;
+  if (gi < N) {
+    for (int q = 0; q < 4; ++q) {
+      const int gj = tx0 + lx + q;
+      if (gj >= N) break;
+      const size_t p = (size_t)b * N * N + gi * N + gj;
+      if (adjoint) {
+        S.ubar[p] = acc[q];
+      } else {
+        const int pi = gi * N + gj;
+        const float res = acc[q] - S.image[pi];
+        const float iv = S.inv_var[pi];
+        S.r[p] = res * iv;
+        if (S.model) S.model[p] = acc[q];
+        const double e = (double)res * (double)res * (double)iv;
+        c2 += e;
+        if (S.mask[pi]) c2m += e;
+      }
+    }
+  }
+  if (!adjoint) {
+    double v[2] = {c2, c2m};
+    block_sum<2>(v, red);
+    if (threadIdx.x == 0) {
+      double* o = S.c2part + ((size_t)b * S.psf_tiles + tile) * 2;
+      o[0] = v[0];
+      o[1] = v[1];
+    }
+  }
+}
+
+// ====================================================================== k_post
+struct PostLds {
+  double red[16 * 16];
+  double xbar[2][K];      // d loss / d X (beta units), after the slope chain
+  uint32_t stat;
+};
+
+__global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S) {
+  __shared__ __align__(16) unsigned char fft_smem[FFT_LDS_FLOAT2 * 8];
+  __shared__ PostLds P;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int n = S.n_src, n2 = n * n, logn = S.log2_src;
+  const int nl = S.n_lens;
+  if (tid == 0) P.stat = 0;
+  __syncthreads();
+  // ---- loss and chi^2 in the mask
+  {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = tid; t < S.psf_tiles; t += blockDim.x) {
+      const double* o = S.c2part + ((size_t)b * S.psf_tiles + t) * 2;
+      v[0] += o[0];
+      v[1] += o[1];
+    }
+    const float* w = S.latent + (size_t)b * n2;
+    for (int q = tid; q < n2; q += blockDim.x) v[2] += (double)w[q] * w[q];
+    block_sum<3>(v, P.red);
+    if (tid == 0) {
+      const double loss = 0.5 * v[0] + 0.5 * v[2];
+      S.loss[b] = loss;
+      if (S.chi2m) S.chi2m[b] = S.M > 0 ? v[1] / (double)S.M : 0.0;
+      if (!isfinite(loss)) P.stat |= RTU_ST_NONFINITE;
+    }
+  }
+  if (S.want_grad) {
+    const float* lensp = S.lens + (size_t)b * nl;
+    const int nsub = n_sub_of(S, b);
+    const Sie L = make_sie(lensp);
+    // ---- knot adjoint: sum the tile partials, then S_k = 1/p'_k with
+    //      p'_k = sum_l D_kl X_l  ->  dX_l += sum_k (-S_k^2 dS_k) D_kl
+    if (tid < 4 * K) {
+      double s = 0.0;
+      for (int t = 0; t < S.ray_tiles; ++t) s += S.kbar[((size_t)b * S.ray_tiles + t) * 4 * K + tid];
+      P.red[tid] = s;
+    }
+    __syncthreads();
+    if (tid < 2 * K) {
+      const int ax = tid / K, l = tid - ax * K;
+      const float* dp = S.dp + ((size_t)b * 2 + ax) * K;
+      double xb = P.red[ax * 2 * K + l];
+      for (int k = 0; k < K; ++k) {
+        const double d = dp[k];
+        if (d > 0.0) xb += -P.red[ax * 2 * K + K + k] / (d * d) * c_D[k * K + l];
+      }
+      P.xbar[ax][l] = xb;
+    }
+    __syncthreads();
+    // ---- selected masked rays: X_k = (1-t_k) beta_(j) + t_k beta_(j+1); each of
+    //      the 4K (axis, rank) items writes its lens-gradient row into LDS
+    double* mp = reinterpret_cast<double*>(fft_smem);   // [4K][nl]
+    if (tid < 4 * K) {
+      double* row = mp + tid * nl;
+      for (int q = 0; q < nl; ++q) row[q] = 0.0;
+      const int ax = tid / (2 * K), r = tid - ax * 2 * K, k = r >> 1;
+      const double t = S.rank_t[k];
+      const double wgt = (r & 1) ? t : 1.0 - t;
+      int m = S.sel[((size_t)b * 2 + ax) * 2 * K + r];
+      m = m < 0 ? 0 : (m >= S.M ? S.M - 1 : m);
+      const double bb = wgt * P.xbar[ax][k];
+      if (bb != 0.0 && S.M > 0) {
+        const int p = S.mask_idx[m];
+        const int i = p / S.n_img, j = p - i * S.n_img;
+        const float x = ((float)j - 0.5f * (float)(S.n_img - 1)) * S.pix;
+        const float y = ((float)i - 0.5f * (float)(S.n_img - 1)) * S.pix;
+        const float abx = ax == 0 ? -(float)bb : 0.f, aby = ax == 1 ? -(float)bb : 0.f;
+        SieAcc a;
+        a.zero();
+        sie_shear_vjp(L, x, y, abx, aby, a);
+        double av[8] = {a.P, a.q, a.f, a.phi, a.x0, a.y0, a.g1, a.g2};
+        double gl[7];
+        sie_grad(L, av, gl);
+        for (int q = 0; q < 7; ++q) row[q] = gl[q];
+        for (int q = 0; q < nsub; ++q) {
+          const Nfw N = make_nfw(lensp + RTU_N_LENS_BASE + RTU_N_PER_SUB * q, S.tau);
+          float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+          nfw_vjp(N, S.tau, x, y, abx, aby, g0, g1, g2, g3);
+          row[7 + 4 * q] = g0; row[8 + 4 * q] = g1; row[9 + 4 * q] = g2; row[10 + 4 * q] = g3;
+        }
+      }
+    }
+    __syncthreads();
+    // tile partials then masked-ray rows, summed in a fixed order
+    if (tid < nl) {
+      double v = 0.0;
+      const double* lp = S.lpart + (size_t)b * S.ray_tiles * nl + tid;
+      for (int t = 0; t < S.ray_tiles; ++t) v += lp[(size_t)t * nl];
+      for (int it = 0; it < 4 * K; ++it) v += mp[it * nl + tid];
+      if (S.g_lens) S.g_lens[(size_t)b * nl + tid] = (float)v;
+      if (!isfinite(v)) atomicOr(&P.stat, RTU_ST_NONFINITE);
+    }
+    __syncthreads();
+    // ---- GP adjoint
+    const float* ps = S.ps + (size_t)b * 4;
+    const Matern mt = make_matern(ps);
+    const float alpha = ps[3];
+    const float* sb = S.sbar + (size_t)b * n2;
+    const float* fo = S.fld + (size_t)b * n2;
+    const float* so = S.src + (size_t)b * n2;
+    const float2* F = S.F + (size_t)b * n2;
+    float2* T = S.tmp + (size_t)b * n2;
+    const float* w = S.latent + (size_t)b * n2;
+    float2* lds = reinterpret_cast<float2*>(fft_smem);
+    double pacc[4] = {0.0, 0.0, 0.0, 0.0};   // sigma, n, zeta, alpha
+    const float inv_n2 = 1.f / (float)n2;
+    // rows: fbar = sbar ds/df, ds/df = alpha s sigmoid(x)/(s0 softplus(x)), x = f/s0
+    fft_pass(lds, n, logn, false, -1.f, false, 0.f,
+             [&](int r, int c) {
+               const int q = r * n + c;
+               const float x = fo[q] * 100.f;
+               const float s = so[q];
+               const float lsp = log_softplus_f(x);
+               const float ratio = __expf(-softplus_f(-x) - lsp);   // sigmoid/softplus
+               pacc[3] += (double)sb[q] * s * (-4.605170186f + lsp);
+               return make_float2(sb[q] * alpha * s * ratio * 100.f, 0.f);
+             },
+             [&](int, int, float2 v) { return v; },
+             [&](int r, int c, float2 v) { T[r * n + c] = v; });
+    // columns: forward -> Fbar; spectrum gradient; multiply by sqrt(P); inverse
+    fft_pass(lds, n, logn, true, -1.f, true, 1.f,
+             [&](int r, int c) { return T[r * n + c]; },
+             [&](int r, int c, float2 v) {
+               const float kx = fft_freq(c, n), ky = fft_freq(r, n);
+               const float k2 = kx * kx + ky * ky;
+               const float sp = matern_sqrtP(mt, k2);
+               const float2 f0 = F[r * n + c];
+               // Re(F conj(Fbar)) / n^2
+               const double re = ((double)f0.x * v.x + (double)f0.y * v.y) * (double)inv_n2 * sp;
+               const float apk = mt.a + k2;
+               pacc[0] += re / ps[0];
+               pacc[1] += re * (0.5 / mt.n + 0.5 * log((double)mt.a / apk) + 0.5 -
+                                (mt.n + 1.0) * mt.a / (2.0 * mt.n * apk));
+               pacc[2] += re * (-mt.n / mt.zeta + (mt.n + 1.0) * mt.a / (mt.zeta * apk));
+               return make_float2(v.x * sp, v.y * sp);
+             },
+             [&](int r, int c, float2 v) { T[r * n + c] = v; });
+    uint32_t bad = 0;
+    fft_pass(lds, n, logn, false, 1.f, false, 0.f,
+             [&](int r, int c) { return T[r * n + c]; },
+             [&](int, int, float2 v) { return v; },
+             [&](int r, int c, float2 v) {
+               const float g = v.x * inv_n2 + w[r * n + c];
+               if (S.g_lat) S.g_lat[(size_t)b * n2 + r * n + c] = g;
+               if (!isfinite(g)) bad = 1;
+             });
+    if (bad) atomicOr(&P.stat, RTU_ST_NONFINITE);
+    block_sum<4>(pacc, P.red);
+    if (tid < 4 && S.g_ps) {
+      S.g_ps[(size_t)b * 4 + tid] = (float)pacc[tid];
+      if (!isfinite(pacc[tid])) atomicOr(&P.stat, RTU_ST_NONFINITE);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) S.status[b] = P.stat | S.st[b * 4 + 0] | S.st[b * 4 + 1] | S.st[b * 4 + 2];
+}
+
+// ====================================================================== launchers
+hipError_t upload_constants() {
+  double u[K], tn[K];
+  for (int k = 0; k < K; ++k) {
+    u[k] = 0.5 * (1.0 - cos((2.0 * (k + 1) - 1.0) * M_PI / (2.0 * K)));
+    tn[k] = 2.0 * u[k] - 1.0;
+  }
+  // T_j(t_l) and U_j(t_k) by recurrence
+  double T[K][K], U[K][K];
+  for (int k = 0; k < K; ++k) {
+    T[0][k] = 1.0; T[1][k] = tn[k];
+    U[0][k] = 1.0; U[1][k] = 2.0 * tn[k];
+    for (int j = 2; j < K; ++j) {
+      T[j][k] = 2.0 * tn[k] * T[j - 1][k] - T[j - 2][k];
+      U[j][k] = 2.0 * tn[k] * U[j - 1][k] - U[j - 2][k];
+    }
+  }
+  // p'(u_k) = 2 sum_{j>=1} j c_j U_{j-1}(t_k),  c_j = (2/K) sum_l q_l T_j(t_l)
+  double D[K * K];
+  for (int k = 0; k < K; ++k)
+    for (int l = 0; l < K; ++l) {
+      double s = 0.0;
+      for (int j = 1; j < K; ++j) s += 2.0 * j * U[j - 1][k] * (2.0 / K) * T[j][l];
+      D[k * K + l] = s;
+    }
+  float uf[K];
+  for (int k = 0; k < K; ++k) uf[k] = (float)u[k];
+  float2 tw[128];
+  for (int k = 0; k < 128; ++k) tw[k] = make_float2((float)cos(2.0 * M_PI * k / 256.0), (float)-sin(2.0 * M_PI * k / 256.0));
+  hipError_t e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_u), uf, sizeof(uf))) != hipSuccess) return e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_D), D, sizeof(D))) != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_tw), tw, sizeof(tw));
+}
+
+hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep, dim3(batch, 3), dim3(PREP_THREADS), 0, s, h);
+  return hipGetLastError();
+}
+
+// The source grid (and its adjoint) are staged in LDS when the grid is at most
+// GRID_LDS_MAX per side and the workgroup's LDS stays within 64 KB.
+static size_t ray_lds_bytes(const SysDev& h, bool adjoint, bool lds_grid) {
+  const size_t np = (size_t)(h.n_src + 2);
+  size_t bytes = sizeof(RayLdsHead) + (lds_grid ? np * np * 4 : 0);
+  if (adjoint) {
+    bytes += (lds_grid ? np * np * 4 : 0) + (size_t)4 * h.n_sub_max * RAY_THREADS * 4;
+    bytes = (bytes + 15) & ~(size_t)15;
+    bytes += 8 * 4 * 8 + 16;
+  }
+  return bytes;
+}
+static bool ray_lds_grid(const SysDev& h, bool adjoint) {
+  return h.n_src <= GRID_LDS_MAX && ray_lds_bytes(h, adjoint, true) <= 65536;
+}
+
+hipError_t launch_rays_fwd(const SysDev& h, int batch, hipStream_t s) {
+  const bool lg = ray_lds_grid(h, false);
+  const size_t lds = ray_lds_bytes(h, false, lg);
+  if (lg)
+    hipLaunchKernelGGL(k_rays_fwd<true>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), lds, s, h);
+  else
+    hipLaunchKernelGGL(k_rays_fwd<false>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), lds, s, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_rays_adj(const SysDev& h, int batch, hipStream_t s) {
+  const bool lg = ray_lds_grid(h, true);
+  const size_t lds = ray_lds_bytes(h, true, lg);
+  if (lg)
+    hipLaunchKernelGGL(k_rays_adj<true>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), lds, s, h);
+  else
+    hipLaunchKernelGGL(k_rays_adj<false>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), lds, s, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_psf(const SysDev& h, int batch, bool adjoint, hipStream_t s) {
+  const dim3 g(batch * h.psf_tiles), blk(PSF_THREADS);
+  const int adj = adjoint ? 1 : 0;
+  switch (h.psf_k) {
+    case 15: hipLaunchKernelGGL(k_psf<15>, g, blk, 0, s, h, adj); break;
+    case 21: hipLaunchKernelGGL(k_psf<21>, g, blk, 0, s, h, adj); break;
+    case 31: hipLaunchKernelGGL(k_psf<31>, g, blk, 0, s, h, adj); break;
+    default: {
+      const int HW = PSF_TW + h.psf_k - 1, LS = (HW + 3) & ~3, HH = PSF_TH + h.psf_k - 1;
+      hipLaunchKernelGGL(k_psf_any, g, blk, (size_t)HH * LS * 4, s, h, adj);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_post(const SysDev& h, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_post, dim3(batch), dim3(PREP_THREADS), 0, s, h);
+  return hipGetLastError();
+}
+
+
+}  // namespace rtu
