@@ -1,0 +1,170 @@
+"""Throughput of the RTU-grid ELBO step on one MI355X.
+
+Workload (default): a 200x200 image with 4x4 sub-rays per pixel (640k rays),
+a 64x64 RTU source grid, a 21x21 PSF and 32 reparameterised latent samples per
+ELBO step; lens drawn uniformly (theta_E in [0.6, 1.6]", q in [0.5, 0.95],
+phi in [0, pi), |gamma| < 0.08); synthetic arc-like data (see
+paper_2606_30620_amd/synth.py).
+
+One step = one whole ELBO step of the variational fit on the device: draw the
+32 samples z = mu + exp(rho) eps (Philox), evaluate each sample's loss and its
+gradient (masked-ray quantiles and CDF knots, GP source by FFT, ray shooting
+and transform, bilinear interpolation, sub-ray sum, PSF, chi^2, and the full
+adjoint chain), then the ELBO value and the Adam update.
+
+value = fwd+adjoint sample evaluations per second (32 per step).
+
+    python bench.py [--gpus 1] [--steps 40] [--warmup 5]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ELBO fwd+adjoint evals/s (200^2 img, 64^2 src); served fits/s + p99 latency"
+
+# Algorithmic FP32 operations per sub-ray (SIE + external shear, no
+# subhaloes), counted from the formulas each kernel evaluates: add, sub, mul
+# = 1, fused multiply-add = 2, compare = 1, and each of sqrt, reciprocal,
+# atan, atanh counted as one operation.  Breakdown in the design doc.
+FLOP_PER_RAY_FWD = 126
+FLOP_PER_RAY_ADJ = 365
+# MI355X peaks (AMD published): FP32 vector 157.3 TFLOP/s, HBM3E 8 TB/s
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+KERNEL_OF_STAGE = {"rays_adj": "k_rays_adj", "rays_fwd": "k_rays_fwd", "psf_fwd": "k_psf",
+                   "psf_adj": "k_psf", "prep": "k_prep", "post": "k_post", "sample": "k_sample",
+                   "adam": "k_elbo+k_adam"}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2606_30620_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if there is none for this kernel and workload or the kernels changed
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get(kernel + "|" + workload)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(problem, budget_s: float):
+    """The FP64 oracle on the host: fwd + gradient of as many of the workload's
+    samples as fit in about budget_s seconds."""
+    import torch
+
+    from oracle import rtu_oracle as O
+    t0 = time.perf_counter()
+    n = 0
+    while n < problem.batch:
+        O.loss_grad_problem(problem, n)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "evals/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{n} of the {problem.batch} samples of one step (fwd + gradient each, FP64), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+              "the path shards by samples or fits with one gradient all-reduce per step, "
+              "which is not built here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2606_30620_amd import _lib, api, synth
+
+    S = 32
+    problem = synth.make_problem("C2", batch=S)
+    g = problem.geom
+    rays = g.n_img ** 2 * g.supersample ** 2
+    plan = api.plan_for_problem(problem, max_batch=S)
+    mu = np.concatenate([problem.lens[0], problem.ps[0], problem.latent[0].reshape(-1)]).astype(np.float32)
+    rho = np.full(mu.size, math.log(0.1), np.float32)
+    rho[:7] = math.log(0.01)          # keep sampled lenses physical (|e| < 1, theta_E > 0)
+    rho[7:11] = math.log(0.02)
+    fit = _lib.Fit(plan, S, mu, rho, lr=1e-2, seed=202, max_steps=args.warmup + args.steps + 1)
+    stream = torch.cuda.current_stream()
+    fit.step(args.warmup)
+    torch.cuda.synchronize()
+
+    plan.profile_begin(args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fit.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    stages = plan.profile_end()
+    ms_step = ms / args.steps
+    value = S * args.steps / (ms / 1e3)
+
+    # dominant kernel and its roofline (ALU-bound: see the design doc)
+    per_launch = {k: v[0] / v[1] for k, v in stages.items() if v[1] > 0}
+    dom = max(per_launch, key=per_launch.get)
+    flops = {"rays_adj": FLOP_PER_RAY_ADJ, "rays_fwd": FLOP_PER_RAY_FWD}.get(dom)
+    workload = "C2"
+    roof = None
+    if flops:
+        achieved = flops * rays * S / (per_launch[dom] * 1e-3) / 1e12
+        traffic = measured_traffic(KERNEL_OF_STAGE[dom], workload)
+        roof = {"bound": "alu", "kernel": KERNEL_OF_STAGE[dom], "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": traffic, "avg_launch_ms": round(per_launch[dom], 4),
+                "flop_per_launch": flops * rays * S}
+    _, _, trace = fit.read()
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "C2: 200x200 image, 4x4 sub-rays (640k rays/sample), 64x64 RTU source, "
+                               "21x21 PSF, 32 latent samples per ELBO step, SIE+shear",
+                   "samples_per_step": S, "rays_per_sample": rays, "elbo_steps_per_s": round(1e3 / ms_step, 2),
+                   "stage_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
+                   "elbo_last": float(trace[-1]) if trace.size else None},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(problem, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

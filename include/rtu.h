@@ -151,6 +151,71 @@ int rtu_loss_grad(rtu_plan p, int32_t batch,
 int rtu_debug_fetch(rtu_plan p, int32_t what, int32_t sample, void* host_dst, size_t bytes,
                     void* stream);
 
+/* ---- stage timing ------------------------------------------------------
+ * Stages of one evaluation / fit step, in launch order. */
+#define RTU_STAGE_PREP      0   /* masked rays, quantiles, CDF knots; GP source   */
+#define RTU_STAGE_RAYS_FWD  1   /* supersampled rays -> pre-PSF image             */
+#define RTU_STAGE_PSF_FWD   2   /* PSF, residual, chi^2 partials                  */
+#define RTU_STAGE_PSF_ADJ   3   /* PSF adjoint                                    */
+#define RTU_STAGE_RAYS_ADJ  4   /* ray adjoint: source, knot, lens gradients      */
+#define RTU_STAGE_POST      5   /* knot adjoint, reductions, GP adjoint           */
+#define RTU_STAGE_SAMPLE    6   /* fit: draw z = mu + exp(rho) eps                */
+#define RTU_STAGE_ADAM      7   /* fit: ELBO value and Adam update                */
+#define RTU_N_STAGES        8
+
+/* Start recording HIP events around every stage of the next max_calls
+ * evaluations (rtu_loss_grad or fit steps) of this plan, on the stream each
+ * evaluation runs on.  Recording adds no synchronisation. */
+int rtu_profile_begin(rtu_plan p, int32_t max_calls);
+/* Stop recording; wait for the recorded events and return, per stage, the
+ * summed GPU time in milliseconds (stage_ms[RTU_N_STAGES], host) and the
+ * number of recorded launches of each stage (launches[RTU_N_STAGES], host,
+ * may be NULL).  Synchronises the recorded events. */
+int rtu_profile_end(rtu_plan p, double* stage_ms, int32_t* launches);
+
+/* ---- stochastic variational fit (Sec. 4) -------------------------------
+ * A mean-field Gaussian guide over z = (lens[n_lens], ps[4], latent[n_src^2])
+ * with location mu and scale exp(rho).  One step draws S samples
+ * z_s = mu + exp(rho) eps_s (eps from a counter-based Philox4x32-10 stream
+ * keyed by the seed, or given), evaluates the loss and gradient of every
+ * sample on the plan, records the ELBO estimate
+ *   -mean_s loss_s - sum_p ln(sigma_p sqrt(2 pi)) - (n_src^2/2) ln 2 pi
+ *   + sum(rho) + (dim/2)(1 + ln 2 pi)
+ * (Gaussian likelihood, flat priors on lens and spectrum parameters, unit
+ * normal prior on the latent) and takes one Adam step (beta 0.9, 0.999,
+ * epsilon 1e-8) on (mu, rho) to maximise it.  State stays on the device. */
+typedef struct rtu_fit_s* rtu_fit;
+
+/* Creates a fit on plan p (which must hold an observation) with S samples per
+ * step (S <= the plan's max_batch), initial guide mu0, rho0 (host, [dim]),
+ * learning rate lr, Philox seed, room for max_steps ELBO values, and n_sub
+ * active subhaloes.  dim = n_lens + 4 + n_src^2. */
+int rtu_fit_create(rtu_plan p, int32_t samples, const float* mu0, const float* rho0, float lr,
+                   uint64_t seed, int32_t max_steps, int32_t n_sub, rtu_fit* out);
+int rtu_fit_destroy(rtu_fit f);
+int32_t rtu_fit_dim(rtu_fit f);
+/* Queues n_steps fit steps on `stream`.  eps (device, [n_steps][S][dim]) or
+ * NULL to draw from Philox.  RTU_EINVAL if the trace would overflow. */
+int rtu_fit_step(rtu_fit f, int32_t n_steps, const float* eps, void* stream);
+/* Copies the guide (host mu[dim], rho[dim], either may be NULL) and the ELBO
+ * trace (host elbo[max_trace]) out; *n_trace = steps taken.  Synchronises
+ * `stream`. */
+int rtu_fit_read(rtu_fit f, float* mu, float* rho, double* elbo, int32_t max_trace,
+                 int32_t* n_trace, void* stream);
+/* Checkpoint / resume: the full optimiser state as host float[6][dim] in the
+ * order mu, rho, Adam m(mu), v(mu), m(rho), v(rho), plus the number of steps
+ * taken (the Philox counter and Adam's bias correction continue from it).
+ * get synchronises `stream`; set is synchronous. */
+int rtu_fit_get_state(rtu_fit f, float* state, int32_t* steps, void* stream);
+int rtu_fit_set_state(rtu_fit f, const float* state, int32_t steps);
+
+/* Copies the last step's samples z_s to host z[S][dim] (synchronises `stream`). */
+int rtu_fit_samples(rtu_fit f, float* z, void* stream);
+
+/* Device pointers of the last step's per-sample loss [S] (double) and status
+ * [S] (uint32), valid until the fit is destroyed. */
+int rtu_fit_last_outputs(rtu_fit f, const double** loss, const uint32_t** status);
+
 /* Human-readable text of a return code. */
 const char* rtu_strerror(int code);
 

@@ -22,6 +22,7 @@ ST_NONFINITE, ST_NONMONOTONE, ST_MASK_SMALL, ST_DOMAIN, ST_SELECT_SLOW = 1, 2, 4
 K_NODES = 22
 N_LENS_BASE, N_PER_SUB, N_PS, MAX_SUB = 7, 4, 4, 10
 DBG_KNOTS, DBG_SELECT, DBG_STD, DBG_SOURCE, DBG_PREPSF = 1, 2, 3, 4, 5
+STAGES = ("prep", "rays_fwd", "psf_fwd", "psf_adj", "rays_adj", "post", "sample", "adam")
 
 
 class Geometry(C.Structure):
@@ -51,10 +52,24 @@ def _load():
     lib.rtu_masked_count.restype = I32
     lib.rtu_loss_grad.argtypes = [P, I32] + [VP] * 11 + [VP]
     lib.rtu_debug_fetch.argtypes = [P, I32, I32, VP, SZ, VP]
+    lib.rtu_profile_begin.argtypes = [P, I32]
+    lib.rtu_profile_end.argtypes = [P, VP, VP]
+    lib.rtu_fit_create.argtypes = [P, I32, VP, VP, C.c_float, C.c_uint64, I32, I32, C.POINTER(P)]
+    lib.rtu_fit_destroy.argtypes = [P]
+    lib.rtu_fit_dim.argtypes = [P]
+    lib.rtu_fit_dim.restype = I32
+    lib.rtu_fit_step.argtypes = [P, I32, VP, VP]
+    lib.rtu_fit_read.argtypes = [P, VP, VP, VP, I32, C.POINTER(I32), VP]
+    lib.rtu_fit_last_outputs.argtypes = [P, C.POINTER(VP), C.POINTER(VP)]
+    lib.rtu_fit_get_state.argtypes = [P, VP, C.POINTER(I32), VP]
+    lib.rtu_fit_samples.argtypes = [P, VP, VP]
+    lib.rtu_fit_set_state.argtypes = [P, VP, I32]
     lib.rtu_strerror.argtypes = [C.c_int]
     lib.rtu_strerror.restype = C.c_char_p
     for fn in ("rtu_plan_create", "rtu_plan_destroy", "rtu_set_observation", "rtu_loss_grad",
-               "rtu_debug_fetch"):
+               "rtu_debug_fetch", "rtu_profile_begin", "rtu_profile_end", "rtu_fit_create",
+               "rtu_fit_destroy", "rtu_fit_step", "rtu_fit_read", "rtu_fit_last_outputs",
+               "rtu_fit_get_state", "rtu_fit_set_state", "rtu_fit_samples"):
         getattr(lib, fn).restype = C.c_int
     return lib
 
@@ -150,8 +165,82 @@ class Plan:
         return out
 
 
+    def profile_begin(self, max_calls: int) -> None:
+        check(LIB.rtu_profile_begin(self._h, int(max_calls)), "rtu_profile_begin")
+
+    def profile_end(self):
+        """{stage: (total_ms, launches)} of the recorded evaluations."""
+        ms = np.zeros(len(STAGES), np.float64)
+        n = np.zeros(len(STAGES), np.int32)
+        check(LIB.rtu_profile_end(self._h, ms.ctypes.data, n.ctypes.data), "rtu_profile_end")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(STAGES)}
+
+
+class Fit:
+    """An rtu_fit: Gaussian guide over (lens, ps, latent) with Adam, on a plan."""
+
+    def __init__(self, plan: Plan, samples: int, mu0, rho0, lr=1e-2, seed=0, max_steps=1000, n_sub=0):
+        self.plan = plan
+        mu0 = np.ascontiguousarray(mu0, dtype=np.float32)
+        rho0 = np.ascontiguousarray(rho0, dtype=np.float32)
+        h = C.c_void_p()
+        check(LIB.rtu_fit_create(plan._h, int(samples), mu0.ctypes.data, rho0.ctypes.data, float(lr),
+                                 int(seed), int(max_steps), int(n_sub), C.byref(h)), "rtu_fit_create")
+        self._h = h
+        self.dim = LIB.rtu_fit_dim(h)
+        assert self.dim == mu0.size
+        self.S = int(samples)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            LIB.rtu_fit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n_steps: int = 1, eps=None, stream=None) -> None:
+        check(LIB.rtu_fit_step(self._h, int(n_steps), _ptr(eps), _stream_ptr(stream)), "rtu_fit_step")
+
+    def read(self, stream=None):
+        mu = np.zeros(self.dim, np.float32)
+        rho = np.zeros(self.dim, np.float32)
+        n = C.c_int32()
+        check(LIB.rtu_fit_read(self._h, mu.ctypes.data, rho.ctypes.data, None, 0, C.byref(n),
+                               _stream_ptr(stream)), "rtu_fit_read")
+        tr = np.zeros(max(n.value, 1), np.float64)
+        check(LIB.rtu_fit_read(self._h, None, None, tr.ctypes.data, n.value, C.byref(n),
+                               _stream_ptr(stream)), "rtu_fit_read")
+        return mu, rho, tr[:n.value]
+
+    def get_state(self, stream=None):
+        """(state[6, dim]: mu, rho, m_mu, v_mu, m_rho, v_rho; steps taken)."""
+        st = np.zeros((6, self.dim), np.float32)
+        n = C.c_int32()
+        check(LIB.rtu_fit_get_state(self._h, st.ctypes.data, C.byref(n), _stream_ptr(stream)),
+              "rtu_fit_get_state")
+        return st, n.value
+
+    def samples(self, stream=None):
+        """The last step's samples z[S, dim] (host copy)."""
+        z = np.zeros((self.S, self.dim), np.float32)
+        check(LIB.rtu_fit_samples(self._h, z.ctypes.data, _stream_ptr(stream)), "rtu_fit_samples")
+        return z
+
+    def set_state(self, state, steps: int) -> None:
+        st = np.ascontiguousarray(state, dtype=np.float32)
+        assert st.shape == (6, self.dim)
+        check(LIB.rtu_fit_set_state(self._h, st.ctypes.data, int(steps)), "rtu_fit_set_state")
+
+
 def exported_symbols():
     """Names declared in include/rtu.h that the loaded library exports."""
     return [n for n in ("rtu_n_lens", "rtu_workspace_bytes", "rtu_plan_create", "rtu_plan_destroy",
                         "rtu_set_observation", "rtu_masked_count", "rtu_loss_grad", "rtu_debug_fetch",
+                        "rtu_profile_begin", "rtu_profile_end", "rtu_fit_create", "rtu_fit_destroy",
+                        "rtu_fit_dim", "rtu_fit_step", "rtu_fit_read", "rtu_fit_last_outputs",
+                        "rtu_fit_get_state", "rtu_fit_set_state", "rtu_fit_samples",
                         "rtu_strerror") if hasattr(LIB, n)]

@@ -1,0 +1,118 @@
+// gfx950 kernels of the stochastic variational fit (Sec. 4): reparameterised
+// sampling of the guide, the ELBO estimate, and the Adam update.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "rtu_internal.h"
+
+namespace rtu {
+
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw 2011): 10 rounds of the
+// multiply-xor bijection on a 128-bit counter under a 64-bit key.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+    const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    k.x += W0;
+    k.y += W1;
+  }
+  return c;
+}
+
+// Standard normal draw for (step, sample, parameter) by Box-Muller on two
+// 32-bit uniforms of one Philox block.
+__device__ __forceinline__ float normal_draw(const FitDev& F, int step, int s, int i) {
+  const uint4 r = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)s, (uint32_t)step, 0x52545547u),
+                                make_uint2(F.seed_lo, F.seed_hi));
+  const float u1 = ((float)r.x + 0.5f) * 2.3283064365386963e-10f;   // (0, 1)
+  const float u2 = (float)r.y * 2.3283064365386963e-10f;
+  return sqrtf(-2.f * __logf(u1)) * __cosf(6.283185307179586f * u2);
+}
+
+__device__ __forceinline__ float eps_at(const FitDev& F, const float* eps, int step, int s, int i) {
+  return eps ? eps[(size_t)s * F.dim + i] : normal_draw(F, step, s, i);
+}
+
+// z_s = mu + exp(rho) eps_s, scattered into the plan's per-sample inputs
+__global__ void k_sample(FitDev F, const float* eps, int step) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (i >= F.dim) return;
+  const float z = F.mu[i] + __expf(F.rho[i]) * eps_at(F, eps, step, s, i);
+  if (i < F.n_lens) F.z_lens[(size_t)s * F.n_lens + i] = z;
+  else if (i < F.n_lens + 4) F.z_ps[(size_t)s * 4 + (i - F.n_lens)] = z;
+  else F.z_lat[(size_t)s * F.n_src2 + (i - F.n_lens - 4)] = z;
+}
+
+__device__ __forceinline__ float grad_at(const FitDev& F, int s, int i) {
+  if (i < F.n_lens) return F.g_lens[(size_t)s * F.n_lens + i];
+  if (i < F.n_lens + 4) return F.g_ps[(size_t)s * 4 + (i - F.n_lens)];
+  return F.g_lat[(size_t)s * F.n_src2 + (i - F.n_lens - 4)];
+}
+
+// ELBO of this step (before the update): one workgroup
+__global__ void __launch_bounds__(1024) k_elbo(FitDev F, int step) {
+  __shared__ double red[32];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < F.dim; i += blockDim.x) acc += (double)F.rho[i];
+  double ls = 0.0;
+  for (int s = threadIdx.x; s < F.S; s += blockDim.x) ls += F.loss[s];
+  for (int o = 32; o >= 1; o >>= 1) {
+    acc += __shfl_xor(acc, o, 64);
+    ls += __shfl_xor(ls, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { red[wv] = acc; red[16 + wv] = ls; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, l = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += red[w]; l += red[16 + w]; }
+    F.trace[step] = -l / (double)F.S + F.elbo_const + a;
+  }
+}
+
+// Adam on (mu, rho) with the gradient of -ELBO:
+//   d/dmu_i  = mean_s g_si,   d/drho_i = mean_s g_si exp(rho_i) eps_si - 1
+__global__ void k_adam(FitDev F, const float* eps, int step, int t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= F.dim) return;
+  const float sig = __expf(F.rho[i]);
+  float gm = 0.f, gr = 0.f;
+  for (int s = 0; s < F.S; ++s) {
+    const float g = grad_at(F, s, i);
+    gm += g;
+    gr += g * eps_at(F, eps, step, s, i);
+  }
+  const float invS = 1.f / (float)F.S;
+  gm *= invS;
+  gr = gr * invS * sig - 1.f;
+  const float b1 = 0.9f, b2 = 0.999f, e = 1e-8f;
+  const float c1 = 1.f / (1.f - powf(b1, (float)t)), c2 = 1.f / (1.f - powf(b2, (float)t));
+  float m = b1 * F.m_mu[i] + (1.f - b1) * gm;
+  float v = b2 * F.v_mu[i] + (1.f - b2) * gm * gm;
+  F.m_mu[i] = m;
+  F.v_mu[i] = v;
+  F.mu[i] -= F.lr * (m * c1) / (sqrtf(v * c2) + e);
+  m = b1 * F.m_rho[i] + (1.f - b1) * gr;
+  v = b2 * F.v_rho[i] + (1.f - b2) * gr * gr;
+  F.m_rho[i] = m;
+  F.v_rho[i] = v;
+  F.rho[i] -= F.lr * (m * c1) / (sqrtf(v * c2) + e);
+}
+
+hipError_t launch_sample(const FitDev& F, const float* eps, int step, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample, dim3((F.dim + 255) / 256, F.S), dim3(256), 0, s, F, eps, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(const FitDev& F, const float* eps, int step, int t, hipStream_t s) {
+  hipLaunchKernelGGL(k_elbo, dim3(1), dim3(1024), 0, s, F, step);
+  hipLaunchKernelGGL(k_adam, dim3((F.dim + 255) / 256), dim3(256), 0, s, F, eps, step, t);
+  return hipGetLastError();
+}
+
+}  // namespace rtu

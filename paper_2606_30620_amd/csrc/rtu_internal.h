@@ -70,7 +70,23 @@ struct SysDev {
   float* kbar;                // [B][ray_tiles][4K] per-tile dX, dS partials
   double* lpart;              // [B][ray_tiles][n_lens] per-tile lens-gradient partials
   double* c2part;             // [B][psf_tiles][2] per-tile chi^2 partials (all, mask)
-  uint32_t* st;               // [B] internal status bits
+  uint32_t* st;               // [B][4] status words of the stages
+};
+
+// One stochastic variational fit: guide, Adam state and per-sample buffers.
+struct FitDev {
+  int S, dim, n_lens, n_src2;
+  float lr;
+  uint32_t seed_lo, seed_hi;
+  double elbo_const;          // data and prior normalisation + guide entropy constant
+  float *mu, *rho, *m_mu, *v_mu, *m_rho, *v_rho;   // [dim]
+  float *z_lens, *z_ps, *z_lat;                    // [S][...] samples (evaluation inputs)
+  float *g_lens, *g_ps, *g_lat;                    // [S][...] gradients (evaluation outputs)
+  double* loss;               // [S]
+  double* chi2m;              // [S]
+  uint32_t* status;           // [S]
+  int* n_sub;                 // [S]
+  double* trace;              // [max_steps] ELBO per step
 };
 
 // kernel launchers (rtu_kernels.hip)
@@ -80,5 +96,8 @@ hipError_t launch_rays_fwd(const SysDev& h, int batch, hipStream_t s);
 hipError_t launch_psf(const SysDev& h, int batch, bool adjoint, hipStream_t s);
 hipError_t launch_rays_adj(const SysDev& h, int batch, hipStream_t s);
 hipError_t launch_post(const SysDev& h, int batch, hipStream_t s);
+// fit kernels (rtu_fit.hip)
+hipError_t launch_sample(const FitDev& F, const float* eps, int step, hipStream_t s);
+hipError_t launch_adam(const FitDev& F, const float* eps, int step, int t, hipStream_t s);
 
 }  // namespace rtu

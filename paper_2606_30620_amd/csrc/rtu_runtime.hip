@@ -12,6 +12,14 @@
 
 using namespace rtu;
 
+// HIP events around the stages of up to max_calls evaluations
+struct Prof {
+  bool on = false;
+  int max_calls = 0, calls = 0, cur = -1;
+  std::vector<hipEvent_t> ev;      // [max_calls][RTU_N_STAGES][2]
+  std::vector<uint8_t> used;       // [max_calls][RTU_N_STAGES]
+};
+
 struct rtu_plan_s {
   rtu_geometry g;
   int max_batch = 0;
@@ -23,6 +31,15 @@ struct rtu_plan_s {
   int M = -1;
   SysDev last;                    // descriptor of the last evaluation (debug fetch)
   bool have_last = false;
+  Prof prof;
+};
+
+struct rtu_fit_s {
+  rtu_plan plan = nullptr;
+  FitDev F;
+  char* pool = nullptr;
+  int max_steps = 0, steps = 0;
+  int n_sub = 0;
 };
 
 namespace {
@@ -125,6 +142,45 @@ size_t carve_observation(SysDev& h, int B, int M, char* base) {
   return c.off + 256;
 }
 
+void prof_call_begin(rtu_plan p) {
+  Prof& P = p->prof;
+  P.cur = (P.on && P.calls < P.max_calls) ? P.calls++ : -1;
+}
+void prof_stage(rtu_plan p, int stage, bool end, hipStream_t s) {
+  Prof& P = p->prof;
+  if (P.cur < 0) return;
+  const size_t q = (size_t)P.cur * RTU_N_STAGES + stage;
+  (void)hipEventRecord(P.ev[q * 2 + (end ? 1 : 0)], s);
+  if (end) P.used[q] = 1;
+}
+
+// The launch sequence of one evaluation of `batch` samples.
+int run_eval(rtu_plan p, const SysDev& h, int batch, hipStream_t s) {
+  prof_stage(p, RTU_STAGE_PREP, false, s);
+  if (launch_prep(h, batch, s) != hipSuccess) return RTU_EHIP;
+  prof_stage(p, RTU_STAGE_PREP, true, s);
+  prof_stage(p, RTU_STAGE_RAYS_FWD, false, s);
+  if (launch_rays_fwd(h, batch, s) != hipSuccess) return RTU_EHIP;
+  prof_stage(p, RTU_STAGE_RAYS_FWD, true, s);
+  prof_stage(p, RTU_STAGE_PSF_FWD, false, s);
+  if (launch_psf(h, batch, false, s) != hipSuccess) return RTU_EHIP;
+  prof_stage(p, RTU_STAGE_PSF_FWD, true, s);
+  if (h.want_grad) {
+    prof_stage(p, RTU_STAGE_PSF_ADJ, false, s);
+    if (launch_psf(h, batch, true, s) != hipSuccess) return RTU_EHIP;
+    prof_stage(p, RTU_STAGE_PSF_ADJ, true, s);
+    prof_stage(p, RTU_STAGE_RAYS_ADJ, false, s);
+    if (launch_rays_adj(h, batch, s) != hipSuccess) return RTU_EHIP;
+    prof_stage(p, RTU_STAGE_RAYS_ADJ, true, s);
+  }
+  prof_stage(p, RTU_STAGE_POST, false, s);
+  if (launch_post(h, batch, s) != hipSuccess) return RTU_EHIP;
+  prof_stage(p, RTU_STAGE_POST, true, s);
+  p->last = h;
+  p->have_last = true;
+  return RTU_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -164,10 +220,11 @@ int rtu_plan_create(const rtu_geometry* g, int32_t max_batch, int32_t device, rt
 
 int rtu_plan_destroy(rtu_plan p) {
   if (!p) return RTU_EINVAL;
-  hipSetDevice(p->device);
-  hipDeviceSynchronize();
-  if (p->pool) hipFree(p->pool);
-  if (p->obs_pool) hipFree(p->obs_pool);
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  if (p->pool) (void)hipFree(p->pool);
+  if (p->obs_pool) (void)hipFree(p->obs_pool);
+  for (hipEvent_t e : p->prof.ev) (void)hipEventDestroy(e);
   delete p;
   return RTU_OK;
 }
@@ -199,8 +256,8 @@ int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma
   SysDev h = p->h;
   const size_t bytes = carve_observation(h, p->max_batch, M, nullptr);
   if (bytes > p->obs_bytes) {
-    hipDeviceSynchronize();
-    if (p->obs_pool) hipFree(p->obs_pool);
+    (void)hipDeviceSynchronize();
+    if (p->obs_pool) (void)hipFree(p->obs_pool);
     p->obs_pool = nullptr;
     p->obs_bytes = 0;
     if (hipMalloc(&p->obs_pool, bytes) != hipSuccess) return RTU_ENOMEM;
@@ -253,17 +310,8 @@ int rtu_loss_grad(rtu_plan p, int32_t batch, const float* lens_params, const int
   h.model = model_image;
   h.status = status;
   h.want_grad = (grad_lens || grad_ps || grad_latent) ? 1 : 0;
-  if (launch_prep(h, batch, s) != hipSuccess) return RTU_EHIP;
-  if (launch_rays_fwd(h, batch, s) != hipSuccess) return RTU_EHIP;
-  if (launch_psf(h, batch, false, s) != hipSuccess) return RTU_EHIP;
-  if (h.want_grad) {
-    if (launch_psf(h, batch, true, s) != hipSuccess) return RTU_EHIP;
-    if (launch_rays_adj(h, batch, s) != hipSuccess) return RTU_EHIP;
-  }
-  if (launch_post(h, batch, s) != hipSuccess) return RTU_EHIP;
-  p->last = h;
-  p->have_last = true;
-  return RTU_OK;
+  prof_call_begin(p);
+  return run_eval(p, h, batch, s);
 }
 
 int rtu_debug_fetch(rtu_plan p, int32_t what, int32_t sample, void* host_dst, size_t bytes, void* stream) {
@@ -285,6 +333,223 @@ int rtu_debug_fetch(rtu_plan p, int32_t what, int32_t sample, void* host_dst, si
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (hipStreamSynchronize(s) != hipSuccess) return RTU_EHIP;
   if (hipMemcpy(host_dst, src, need, hipMemcpyDeviceToHost) != hipSuccess) return RTU_EHIP;
+  return RTU_OK;
+}
+
+int rtu_profile_begin(rtu_plan p, int32_t max_calls) {
+  if (!p || max_calls < 1) return RTU_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return RTU_EHIP;
+  Prof& P = p->prof;
+  for (hipEvent_t e : P.ev) (void)hipEventDestroy(e);
+  P.ev.assign((size_t)max_calls * RTU_N_STAGES * 2, nullptr);
+  P.used.assign((size_t)max_calls * RTU_N_STAGES, 0);
+  for (auto& e : P.ev)
+    if (hipEventCreate(&e) != hipSuccess) return RTU_EHIP;
+  P.on = true;
+  P.max_calls = max_calls;
+  P.calls = 0;
+  P.cur = -1;
+  return RTU_OK;
+}
+
+int rtu_profile_end(rtu_plan p, double* stage_ms, int32_t* launches) {
+  if (!p || !stage_ms) return RTU_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return RTU_EHIP;
+  Prof& P = p->prof;
+  for (int k = 0; k < RTU_N_STAGES; ++k) {
+    stage_ms[k] = 0.0;
+    if (launches) launches[k] = 0;
+  }
+  for (int c = 0; c < P.calls; ++c)
+    for (int k = 0; k < RTU_N_STAGES; ++k) {
+      const size_t q = (size_t)c * RTU_N_STAGES + k;
+      if (!P.used[q]) continue;
+      if (hipEventSynchronize(P.ev[q * 2 + 1]) != hipSuccess) return RTU_EHIP;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, P.ev[q * 2], P.ev[q * 2 + 1]) != hipSuccess) return RTU_EHIP;
+      stage_ms[k] += ms;
+      if (launches) launches[k] += 1;
+    }
+  for (hipEvent_t e : P.ev) (void)hipEventDestroy(e);
+  P.ev.clear();
+  P.used.clear();
+  P.on = false;
+  P.calls = 0;
+  P.cur = -1;
+  return RTU_OK;
+}
+
+int rtu_fit_create(rtu_plan p, int32_t samples, const float* mu0, const float* rho0, float lr,
+                   uint64_t seed, int32_t max_steps, int32_t n_sub, rtu_fit* out) {
+  if (!p || !out || !mu0 || !rho0 || samples < 1 || max_steps < 1) return RTU_EINVAL;
+  if (samples > p->max_batch) return RTU_EBATCH;
+  if (p->M < 0) return RTU_ESTATE;
+  if (n_sub < 0 || n_sub > p->g.n_sub_max) return RTU_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return RTU_EHIP;
+  rtu_fit f = new rtu_fit_s();
+  f->plan = p;
+  f->max_steps = max_steps;
+  f->n_sub = n_sub;
+  FitDev& F = f->F;
+  memset(&F, 0, sizeof(F));
+  const int S = samples, nl = p->h.n_lens, n2 = p->h.n_src * p->h.n_src;
+  F.S = S;
+  F.n_lens = nl;
+  F.n_src2 = n2;
+  F.dim = nl + 4 + n2;
+  F.lr = lr;
+  F.seed_lo = (uint32_t)seed;
+  F.seed_hi = (uint32_t)(seed >> 32);
+  // -sum_p ln(sigma_p sqrt(2 pi)) - (n^2/2) ln 2 pi + (dim/2)(1 + ln 2 pi)
+  std::vector<float> iv((size_t)p->g.n_img * p->g.n_img);
+  if (hipMemcpy(iv.data(), p->h.inv_var, iv.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+    delete f;
+    return RTU_EHIP;
+  }
+  double c = 0.0;
+  for (float v : iv) c += 0.5 * log((double)v) - 0.5 * log(2.0 * M_PI);
+  c += -0.5 * n2 * log(2.0 * M_PI) + 0.5 * F.dim * (1.0 + log(2.0 * M_PI));
+  F.elbo_const = c;
+  Carve cv{nullptr};
+  for (int pass = 0; pass < 2; ++pass) {
+    cv.off = 0;
+    F.mu = cv.take<float>(F.dim); F.rho = cv.take<float>(F.dim);
+    F.m_mu = cv.take<float>(F.dim); F.v_mu = cv.take<float>(F.dim);
+    F.m_rho = cv.take<float>(F.dim); F.v_rho = cv.take<float>(F.dim);
+    F.z_lens = cv.take<float>((size_t)S * nl); F.z_ps = cv.take<float>((size_t)S * 4);
+    F.z_lat = cv.take<float>((size_t)S * n2);
+    F.g_lens = cv.take<float>((size_t)S * nl); F.g_ps = cv.take<float>((size_t)S * 4);
+    F.g_lat = cv.take<float>((size_t)S * n2);
+    F.loss = cv.take<double>(S); F.chi2m = cv.take<double>(S);
+    F.status = cv.take<uint32_t>(S); F.n_sub = cv.take<int>(S);
+    F.trace = cv.take<double>(max_steps);
+    if (pass == 0) {
+      if (hipMalloc(&f->pool, cv.off + 256) != hipSuccess) {
+        delete f;
+        return RTU_ENOMEM;
+      }
+      cv.base = f->pool;
+    }
+  }
+  std::vector<int> ns(S, n_sub);
+  hipError_t e = hipMemcpy(F.mu, mu0, (size_t)F.dim * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(F.rho, rho0, (size_t)F.dim * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(F.m_mu, 0, (size_t)F.dim * 4);
+  if (e == hipSuccess) e = hipMemset(F.v_mu, 0, (size_t)F.dim * 4);
+  if (e == hipSuccess) e = hipMemset(F.m_rho, 0, (size_t)F.dim * 4);
+  if (e == hipSuccess) e = hipMemset(F.v_rho, 0, (size_t)F.dim * 4);
+  if (e == hipSuccess) e = hipMemcpy(F.n_sub, ns.data(), (size_t)S * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(f->pool);
+    delete f;
+    return RTU_EHIP;
+  }
+  *out = f;
+  return RTU_OK;
+}
+
+int rtu_fit_destroy(rtu_fit f) {
+  if (!f) return RTU_EINVAL;
+  (void)hipSetDevice(f->plan->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(f->pool);
+  delete f;
+  return RTU_OK;
+}
+
+int32_t rtu_fit_dim(rtu_fit f) { return f ? f->F.dim : -1; }
+
+int rtu_fit_step(rtu_fit f, int32_t n_steps, const float* eps, void* stream) {
+  if (!f || n_steps < 0) return RTU_EINVAL;
+  if (f->steps + n_steps > f->max_steps) return RTU_EINVAL;
+  rtu_plan p = f->plan;
+  if (p->M < 0) return RTU_ESTATE;
+  if (hipSetDevice(p->device) != hipSuccess) return RTU_EHIP;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const FitDev& F = f->F;
+  SysDev h = p->h;
+  h.batch = F.S;
+  h.lens = F.z_lens; h.n_sub = F.n_sub; h.ps = F.z_ps; h.latent = F.z_lat;
+  h.loss = F.loss; h.chi2m = F.chi2m; h.g_lens = F.g_lens; h.g_ps = F.g_ps; h.g_lat = F.g_lat;
+  h.model = nullptr; h.status = F.status; h.want_grad = 1;
+  for (int k = 0; k < n_steps; ++k) {
+    const int step = f->steps;
+    const float* ek = eps ? eps + (size_t)k * F.S * F.dim : nullptr;
+    prof_call_begin(p);
+    prof_stage(p, RTU_STAGE_SAMPLE, false, s);
+    if (launch_sample(F, ek, step, s) != hipSuccess) return RTU_EHIP;
+    prof_stage(p, RTU_STAGE_SAMPLE, true, s);
+    int rc = run_eval(p, h, F.S, s);
+    if (rc) return rc;
+    prof_stage(p, RTU_STAGE_ADAM, false, s);
+    if (launch_adam(F, ek, step, step + 1, s) != hipSuccess) return RTU_EHIP;
+    prof_stage(p, RTU_STAGE_ADAM, true, s);
+    f->steps++;
+  }
+  return RTU_OK;
+}
+
+int rtu_fit_read(rtu_fit f, float* mu, float* rho, double* elbo, int32_t max_trace, int32_t* n_trace,
+                 void* stream) {
+  if (!f) return RTU_EINVAL;
+  if (hipSetDevice(f->plan->device) != hipSuccess) return RTU_EHIP;
+  if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return RTU_EHIP;
+  const FitDev& F = f->F;
+  hipError_t e = hipSuccess;
+  if (mu) e = hipMemcpy(mu, F.mu, (size_t)F.dim * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && rho) e = hipMemcpy(rho, F.rho, (size_t)F.dim * 4, hipMemcpyDeviceToHost);
+  const int nt = f->steps < max_trace ? f->steps : max_trace;
+  if (e == hipSuccess && elbo && nt > 0) e = hipMemcpy(elbo, F.trace, (size_t)nt * 8, hipMemcpyDeviceToHost);
+  if (n_trace) *n_trace = f->steps;
+  return e == hipSuccess ? RTU_OK : RTU_EHIP;
+}
+
+int rtu_fit_get_state(rtu_fit f, float* state, int32_t* steps, void* stream) {
+  if (!f || !state) return RTU_EINVAL;
+  if (hipSetDevice(f->plan->device) != hipSuccess) return RTU_EHIP;
+  if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return RTU_EHIP;
+  const FitDev& F = f->F;
+  float* src[6] = {F.mu, F.rho, F.m_mu, F.v_mu, F.m_rho, F.v_rho};
+  for (int k = 0; k < 6; ++k)
+    if (hipMemcpy(state + (size_t)k * F.dim, src[k], (size_t)F.dim * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return RTU_EHIP;
+  if (steps) *steps = f->steps;
+  return RTU_OK;
+}
+
+int rtu_fit_set_state(rtu_fit f, const float* state, int32_t steps) {
+  if (!f || !state || steps < 0 || steps > f->max_steps) return RTU_EINVAL;
+  if (hipSetDevice(f->plan->device) != hipSuccess) return RTU_EHIP;
+  const FitDev& F = f->F;
+  float* dst[6] = {F.mu, F.rho, F.m_mu, F.v_mu, F.m_rho, F.v_rho};
+  if (hipDeviceSynchronize() != hipSuccess) return RTU_EHIP;
+  for (int k = 0; k < 6; ++k)
+    if (hipMemcpy(dst[k], state + (size_t)k * F.dim, (size_t)F.dim * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return RTU_EHIP;
+  f->steps = steps;
+  return RTU_OK;
+}
+
+int rtu_fit_samples(rtu_fit f, float* z, void* stream) {
+  if (!f || !z) return RTU_EINVAL;
+  if (hipSetDevice(f->plan->device) != hipSuccess) return RTU_EHIP;
+  if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return RTU_EHIP;
+  const FitDev& F = f->F;
+  for (int s = 0; s < F.S; ++s) {
+    float* row = z + (size_t)s * F.dim;
+    if (hipMemcpy(row, F.z_lens + (size_t)s * F.n_lens, (size_t)F.n_lens * 4, hipMemcpyDeviceToHost) ||
+        hipMemcpy(row + F.n_lens, F.z_ps + (size_t)s * 4, 16, hipMemcpyDeviceToHost) ||
+        hipMemcpy(row + F.n_lens + 4, F.z_lat + (size_t)s * F.n_src2, (size_t)F.n_src2 * 4,
+                  hipMemcpyDeviceToHost))
+      return RTU_EHIP;
+  }
+  return RTU_OK;
+}
+
+int rtu_fit_last_outputs(rtu_fit f, const double** loss, const uint32_t** status) {
+  if (!f) return RTU_EINVAL;
+  if (loss) *loss = f->F.loss;
+  if (status) *status = f->F.status;
   return RTU_OK;
 }
 
