@@ -14,7 +14,8 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librtu.so")
+# RTU_LIB may point at another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("RTU_LIB") or os.path.join(HERE, "librtu.so")
 
 RTU_OK = 0
 RTU_EINVAL, RTU_ENOMEM, RTU_EBATCH, RTU_EHIP, RTU_ESTATE, RTU_ENOTFOUND = -1, -2, -3, -4, -5, -6

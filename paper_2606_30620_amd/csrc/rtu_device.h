@@ -35,6 +35,7 @@ struct Sie {
   float the, x0, y0, g1, g2;
   float c, s;        // cos, sin of the position angle phi = atan2(e2, e1)/2
   float q, f, P;     // axis ratio, f = sqrt(1-q^2), P = theta_E sqrt(q)
+  float invf;        // 1/f
   float e1, e2, e;
 };
 
@@ -47,53 +48,110 @@ __device__ __forceinline__ Sie make_sie(const float* L) {
   sincosf(phi, &o.s, &o.c);
   o.f = 2.f * sqrtf(o.e) / (1.f + o.e);   // sqrt(1 - q^2) without cancellation
   o.P = o.the * sqrtf(o.q);
+  o.invf = o.f > 0.f ? 1.f / o.f : 0.f;
   return o;
 }
 
-// atan(f a)/f and its partial derivatives in a and f (series for small f).
-__device__ __forceinline__ void atan_over_f(float f, float a, float& v, float& da, float& df) {
-  const float fa = f * a;
-  const float den = 1.f / (1.f + fa * fa);
-  da = den;
-  if (f < 1e-3f) {
-    v = a * (1.f - fa * fa * (1.f / 3.f));
-    df = -(2.f / 3.f) * f * a * a * a;
+// ------------------------------------------------------------------ fast math
+// Hardware reciprocal, square root and base-2 logarithm (about 1 ulp each).
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fln(float x) { return 0.69314718055994531f * __builtin_amdgcn_logf(x); }
+
+// atan(x)/x = P(x^2) and atanh(x)/x = Q(x^2): least-squares fits made by
+// csrc/gen_poly.py (max relative error of the FP32 evaluation 1.4e-7 on
+// [0, 1] and 1.2e-7 on [0, 1/2]).
+__device__ __forceinline__ float poly_atan(float t) {
+  float p = 0.0028340642f;
+  p = fmaf(p, t, -0.01600503f); p = fmaf(p, t, 0.042587608f); p = fmaf(p, t, -0.07495446f);
+  p = fmaf(p, t, 0.10636754f);  p = fmaf(p, t, -0.14202571f); p = fmaf(p, t, 0.19992484f);
+  p = fmaf(p, t, -0.33333066f); p = fmaf(p, t, 1.0f);
+  return p;
+}
+__device__ __forceinline__ float poly_atan_d(float t) {   // d P / d t
+  float p = 8.f * 0.0028340642f;
+  p = fmaf(p, t, 7.f * -0.01600503f); p = fmaf(p, t, 6.f * 0.042587608f); p = fmaf(p, t, 5.f * -0.07495446f);
+  p = fmaf(p, t, 4.f * 0.10636754f);  p = fmaf(p, t, 3.f * -0.14202571f); p = fmaf(p, t, 2.f * 0.19992484f);
+  p = fmaf(p, t, -0.33333066f);
+  return p;
+}
+__device__ __forceinline__ float poly_atanh(float t) {
+  float p = 0.1783732f;
+  p = fmaf(p, t, 0.04998629f); p = fmaf(p, t, 0.11866759f); p = fmaf(p, t, 0.14216292f);
+  p = fmaf(p, t, 0.2000299f);  p = fmaf(p, t, 0.33333287f); p = fmaf(p, t, 1.0f);
+  return p;
+}
+__device__ __forceinline__ float poly_atanh_d(float t) {
+  float p = 6.f * 0.1783732f;
+  p = fmaf(p, t, 5.f * 0.04998629f); p = fmaf(p, t, 4.f * 0.11866759f); p = fmaf(p, t, 3.f * 0.14216292f);
+  p = fmaf(p, t, 2.f * 0.2000299f);  p = fmaf(p, t, 0.33333287f);
+  return p;
+}
+
+// atan(f a)/f with d/da and d/df (computed without cancellation for |f a| <= 1).
+template <bool D>
+__device__ __forceinline__ void atan_over_f(float f, float invf, float a, float& v, float& da, float& df) {
+  const float fa = f * a, t = fa * fa;
+  if (D) da = rcp(1.f + t);
+  if (t <= 1.f) {
+    v = a * poly_atan(t);
+    if (D) df = 2.f * f * a * a * a * poly_atan_d(t);
   } else {
-    v = atanf(fa) / f;
-    df = (a * den - v) / f;
+    const float r = rcp(fabsf(fa));
+    const float at = copysignf(1.5707963267948966f - r * poly_atan(r * r), fa);
+    v = at * invf;
+    if (D) df = (a * da - v) * invf;
   }
 }
-// atanh(f b)/f and its partial derivatives in b and f (|f b| < 1).
-__device__ __forceinline__ void atanh_over_f(float f, float b, float& v, float& db, float& df) {
-  const float fb = f * b;
-  const float den = 1.f / (1.f - fb * fb);
-  db = den;
-  if (f < 1e-3f) {
-    v = b * (1.f + fb * fb * (1.f / 3.f));
-    df = (2.f / 3.f) * f * b * b * b;
+// atanh(f b)/f with d/db and d/df (|f b| < 1).
+template <bool D>
+__device__ __forceinline__ void atanh_over_f(float f, float invf, float b, float& v, float& db, float& df) {
+  const float fb = f * b, t = fb * fb;
+  if (D) db = rcp(1.f - t);
+  if (t <= 0.25f) {
+    v = b * poly_atanh(t);
+    if (D) df = 2.f * f * b * b * b * poly_atanh_d(t);
   } else {
-    v = atanhf(fb) / f;
-    df = (b * den - v) / f;
+    v = 0.5f * fln((1.f + fb) * rcp(1.f - fb)) * invf;
+    if (D) df = (b * db - v) * invf;
   }
 }
 
-// Deflection of SIE + shear at (x, y).
-__device__ __forceinline__ void sie_shear_alpha(const Sie& L, float x, float y, float& ax, float& ay) {
+// Per-ray intermediates of the SIE deflection, kept for the VJP.
+struct SieRay {
+  float xp, yp, ip, a, b, A, dA, fA, B, dB, fB;
+  bool ok;
+};
+
+// Deflection of SIE + shear at (x, y); with D the partial derivatives needed by
+// sie_shear_vjp are kept in E.
+template <bool D>
+__device__ __forceinline__ void sie_shear_alpha(const Sie& L, float x, float y, float& ax, float& ay,
+                                                SieRay& E) {
   const float dx = x - L.x0, dy = y - L.y0;
-  const float xp = L.c * dx + L.s * dy;
-  const float yp = -L.s * dx + L.c * dy;
-  const float psi = sqrtf(L.q * L.q * xp * xp + yp * yp);
+  E.xp = L.c * dx + L.s * dy;
+  E.yp = -L.s * dx + L.c * dy;
+  const float qx = L.q * E.xp;
+  const float psi2 = qx * qx + E.yp * E.yp;
   float axp = 0.f, ayp = 0.f;
-  if (psi > 1e-20f) {
-    const float ip = 1.f / psi;
-    float A, dA, fA, B, dB, fB;
-    atan_over_f(L.f, xp * ip, A, dA, fA);
-    atanh_over_f(L.f, yp * ip, B, dB, fB);
-    axp = L.P * A;
-    ayp = L.P * B;
+  E.ok = psi2 > 1e-30f;
+  if (E.ok) {
+    const float psi = fsqrt(psi2);
+    E.ip = rcp(psi);
+    E.a = E.xp * E.ip;
+    E.b = E.yp * E.ip;
+    atan_over_f<D>(L.f, L.invf, E.a, E.A, E.dA, E.fA);
+    atanh_over_f<D>(L.f, L.invf, E.b, E.B, E.dB, E.fB);
+    axp = L.P * E.A;
+    ayp = L.P * E.B;
   }
   ax = L.c * axp - L.s * ayp + L.g1 * x + L.g2 * y;
   ay = L.s * axp + L.c * ayp + L.g2 * x - L.g1 * y;
+}
+
+__device__ __forceinline__ void sie_shear_alpha(const Sie& L, float x, float y, float& ax, float& ay) {
+  SieRay E;
+  sie_shear_alpha<false>(L, x, y, ax, ay, E);
 }
 
 // Accumulators of the SIE + shear vector-Jacobian product; converted to
@@ -103,43 +161,31 @@ struct SieAcc {
   __device__ __forceinline__ void zero() { P = q = f = phi = x0 = y0 = g1 = g2 = 0.f; }
 };
 
-// Given d loss / d alpha at (x, y), accumulate d loss / d (internal SIE
-// quantities) and the shear gradient.
-__device__ __forceinline__ void sie_shear_vjp(const Sie& L, float x, float y, float abx, float aby,
-                                              SieAcc& acc) {
+// Given d loss / d alpha at (x, y) and the ray's SIE intermediates, accumulate
+// d loss / d (internal SIE quantities) and the shear gradient.
+__device__ __forceinline__ void sie_shear_vjp(const Sie& L, const SieRay& E, float x, float y, float abx,
+                                              float aby, SieAcc& acc) {
   acc.g1 += abx * x - aby * y;
   acc.g2 += abx * y + aby * x;
-  const float dx = x - L.x0, dy = y - L.y0;
-  const float xp = L.c * dx + L.s * dy;
-  const float yp = -L.s * dx + L.c * dy;
-  const float psi = sqrtf(L.q * L.q * xp * xp + yp * yp);
-  if (!(psi > 1e-20f)) return;
-  const float ip = 1.f / psi;
-  const float a = xp * ip, b = yp * ip;
-  float A, dA, fA, B, dB, fB;
-  atan_over_f(L.f, a, A, dA, fA);
-  atanh_over_f(L.f, b, B, dB, fB);
-  const float axp = L.P * A, ayp = L.P * B;
-  // rotation alpha = R(phi) alpha': d/dphi R(phi) alpha' = (-alpha'_y rot, alpha'_x rot)
+  if (!E.ok) return;
+  const float axp = L.P * E.A, ayp = L.P * E.B;
+  // rotation alpha = R(phi) alpha': d/dphi R(phi) alpha' = (-alpha_y, alpha_x) of the SIE part
   const float rx = L.c * axp - L.s * ayp, ry = L.s * axp + L.c * ayp;
-  float phib = abx * (-ry) + aby * rx;
+  float phib = aby * rx - abx * ry;
   const float axpb = L.c * abx + L.s * aby;
   const float aypb = -L.s * abx + L.c * aby;
-  acc.P += axpb * A + aypb * B;
-  const float ab = axpb * L.P * dA;
-  const float bb = aypb * L.P * dB;
-  acc.f += axpb * L.P * fA + aypb * L.P * fB;
-  float xpb = ab * ip, ypb = bb * ip;
-  const float psib = -(ab * a + bb * b) * ip;
-  acc.q += psib * L.q * xp * xp * ip;
-  xpb += psib * L.q * L.q * xp * ip;
-  ypb += psib * yp * ip;
-  phib += xpb * yp - ypb * xp;
+  acc.P += axpb * E.A + aypb * E.B;
+  const float ab = axpb * L.P * E.dA;
+  const float bb = aypb * L.P * E.dB;
+  acc.f += L.P * (axpb * E.fA + aypb * E.fB);
+  const float psib = -(ab * E.a + bb * E.b) * E.ip;
+  acc.q += psib * L.q * E.xp * E.a;
+  const float xpb = (ab + psib * L.q * L.q * E.xp) * E.ip;
+  const float ypb = (bb + psib * E.yp) * E.ip;
+  phib += xpb * E.yp - ypb * E.xp;
   acc.phi += phib;
-  const float dxb = L.c * xpb - L.s * ypb;
-  const float dyb = L.s * xpb + L.c * ypb;
-  acc.x0 -= dxb;
-  acc.y0 -= dyb;
+  acc.x0 -= L.c * xpb - L.s * ypb;
+  acc.y0 -= L.s * xpb + L.c * ypb;
 }
 
 // Convert summed accumulators (double) to d loss / d (theta_E, e1, e2, x0, y0, g1, g2).
@@ -162,39 +208,40 @@ __device__ __forceinline__ void sie_grad(const Sie& L, const double* a, double* 
 }
 
 // ------------------------------------------------------------------ NFW (App. A.2)
-// T(v) = atanh(sqrt v)/sqrt v (v > 0), atan(sqrt(-v))/sqrt(-v) (v < 0), 1 at 0.
+// T(v) = atanh(sqrt v)/sqrt v (v > 0), atan(sqrt(-v))/sqrt(-v) (v < 0), 1 at 0:
+// Q(v) and P(-v) of the polynomials above where they apply.
 __device__ __forceinline__ float nfw_T(float v) {
-  if (fabsf(v) < 0.1f) {
-    float r = 1.f / 17.f;
-    r = fmaf(r, v, 1.f / 15.f); r = fmaf(r, v, 1.f / 13.f); r = fmaf(r, v, 1.f / 11.f);
-    r = fmaf(r, v, 1.f / 9.f);  r = fmaf(r, v, 1.f / 7.f);  r = fmaf(r, v, 1.f / 5.f);
-    r = fmaf(r, v, 1.f / 3.f);  r = fmaf(r, v, 1.f);
-    return r;
+  if (v >= 0.f) {
+    if (v <= 0.25f) return poly_atanh(v);
+    const float sq = fsqrt(v);
+    return 0.5f * fln((1.f + sq) * rcp(1.f - sq)) * rcp(sq);
   }
-  if (v > 0.f) { const float s = sqrtf(v); return atanhf(s) / s; }
-  const float s = sqrtf(-v);
-  return atanf(s) / s;
+  if (v >= -1.f) return poly_atan(-v);
+  const float sq = fsqrt(-v), r = rcp(sq);
+  return (1.5707963267948966f - r * poly_atan(r * r)) * r;
 }
 
 // Projected-mass function h(X) of the NFW convergence (eq. A3) and h'(X) = X G(X),
 // G = (1 - F(X))/(X^2 - 1) = kappa/(2 kappa_s).
 __device__ __forceinline__ void nfw_h_dh(float X, float& h, float& dh) {
   if (X < 1e-6f) {
-    const float L = __logf(2.f / X);
+    const float L = fln(2.f * rcp(X));
     h = X * X * (0.5f * L - 0.25f);
     dh = X * (L - 1.f);
     return;
   }
   if (X < 0.5f) {
+    // c = sqrt(1 - X^2); 2 atanh(sqrt((1-X)/(1+X))) = ln((1+c)/X)
     const float X2 = X * X;
-    const float c = sqrtf(1.f - X2);
-    h = __logf(2.f / X) * X2 / ((1.f + c) * c) + log1pf(-X2 / (2.f * (1.f + c))) / c;
-    const float F = atanhf(c) / c;
-    dh = X * (F - 1.f) / (c * c);
+    const float c = fsqrt(1.f - X2), ic = rcp(c), i1c = rcp(1.f + c);
+    h = fln(2.f * rcp(X)) * X2 * i1c * ic + log1pf(-0.5f * X2 * i1c) * ic;
+    const float F = 0.5f * fln((1.f + c) * (1.f + c) * rcp(X2)) * ic;   // atanh(c)/c
+    dh = X * (F - 1.f) * ic * ic;
     return;
   }
-  const float v = (1.f - X) / (1.f + X);
-  h = __logf(0.5f * X) + 2.f * nfw_T(v) / (1.f + X);
+  const float ix1 = rcp(1.f + X);
+  const float v = (1.f - X) * ix1;
+  h = fln(0.5f * X) + 2.f * nfw_T(v) * ix1;
   const float vp = (1.f - X) * (1.f + X);
   float G;
   if (fabsf(vp) < 0.2f) {
@@ -205,18 +252,19 @@ __device__ __forceinline__ void nfw_h_dh(float X, float& h, float& dh) {
     r = fmaf(r, vp, 1.f / 5.f);  r = fmaf(r, vp, 1.f / 3.f);
     G = r;
   } else {
-    G = (nfw_T(vp) - 1.f) / vp;
+    G = (nfw_T(vp) - 1.f) * rcp(vp);
   }
   dh = X * G;
 }
 
 struct Nfw {
-  float ks, rs, xs, ys, htau;  // htau = h(tau) (tau > 0)
+  float ks, rs, xs, ys, irs, htau;  // htau = h(tau) (tau > 0)
 };
 
 __device__ __forceinline__ Nfw make_nfw(const float* p, float tau) {
   Nfw o;
   o.ks = p[0]; o.rs = p[1]; o.xs = p[2]; o.ys = p[3];
+  o.irs = 1.f / o.rs;
   o.htau = 0.f;
   if (tau > 0.f) { float d; nfw_h_dh(tau, o.htau, d); }
   return o;
@@ -227,11 +275,11 @@ __device__ __forceinline__ void nfw_alpha(const Nfw& N, float tau, float x, floa
   const float dx = x - N.xs, dy = y - N.ys;
   const float r2 = dx * dx + dy * dy;
   if (!(r2 > 1e-30f)) return;
-  const float r = sqrtf(r2);
-  const float X = r / N.rs;
+  const float ir2 = rcp(r2);
+  const float X = fsqrt(r2) * N.irs;
   float H, dH;
   if (tau > 0.f && X > tau) { H = N.htau; } else { nfw_h_dh(X, H, dH); }
-  const float C = 4.f * N.ks * N.rs * N.rs * H / r2;
+  const float C = 4.f * N.ks * N.rs * N.rs * H * ir2;
   ax += C * dx;
   ay += C * dy;
 }
@@ -242,22 +290,19 @@ __device__ __forceinline__ void nfw_vjp(const Nfw& N, float tau, float x, float 
   const float dx = x - N.xs, dy = y - N.ys;
   const float r2 = dx * dx + dy * dy;
   if (!(r2 > 1e-30f)) return;
-  const float r = sqrtf(r2);
-  const float X = r / N.rs;
+  const float r = fsqrt(r2), ir = rcp(r), ir2 = ir * ir;
+  const float X = r * N.irs;
   float H, dH;
   if (tau > 0.f && X > tau) { H = N.htau; dH = 0.f; } else { nfw_h_dh(X, H, dH); }
   const float Y = abx * dx + aby * dy;
-  const float ir2 = 1.f / r2;
   const float rs = N.rs;
   gks += 4.f * rs * rs * H * Y * ir2;
   grs += Y * 4.f * N.ks * (2.f * rs * H - r * dH) * ir2;
   const float C = 4.f * N.ks * rs * rs * H * ir2;
   // C'(r)/r = 4 ks (rs H'/r^3 - 2 rs^2 H / r^4)
-  const float Cpr = 4.f * N.ks * (rs * dH / r - 2.f * rs * rs * H * ir2) * ir2;
-  const float dxb = C * abx + Y * Cpr * dx;
-  const float dyb = C * aby + Y * Cpr * dy;
-  gxs -= dxb;
-  gys -= dyb;
+  const float Cpr = 4.f * N.ks * (rs * dH * ir - 2.f * rs * rs * H * ir2) * ir2;
+  gxs -= C * abx + Y * Cpr * dx;
+  gys -= C * aby + Y * Cpr * dy;
 }
 
 // ------------------------------------------------------------------ CDF spline
@@ -270,48 +315,69 @@ __device__ __forceinline__ int knot_count(const float* X, float z) {
   }
   return k;
 }
+// The same, trying the interval of the previous sub-ray first.
+__device__ __forceinline__ int knot_count_from(const float* X, float z, int k) {
+  const bool ok = (k == 0 || X[k - 1] <= z) && (k == K || z < X[k]);
+  return ok ? k : knot_count(X, z);
+}
 
-// Cubic Hermite spline through (X_k, u_k) with slopes S_k, linear outside.
-// Returns g(z); dg = dg/dz.
-__device__ __forceinline__ float cdf_eval(const float* X, const float* S, float z, int k, float& dg) {
-  if (k == 0) { dg = S[0]; return c_u[0] + S[0] * (z - X[0]); }
-  if (k >= K) { dg = S[K - 1]; return c_u[K - 1] + S[K - 1] * (z - X[K - 1]); }
+// Cubic Hermite spline through (X_k, u_k) with slopes S_k, linear outside
+// (App. C step iv).  ih[l] = 1/(X_{l+1} - X_l).  Returns g(z) and dg = dg/dz;
+// tt = t in [0, 1) inside an interval, z - X_end on the linear continuations.
+__device__ __forceinline__ float cdf_eval(const float* X, const float* S, const float* ih, float z, int k,
+                                          float& dg, float& tt) {
+  if (k == 0) { tt = z - X[0]; dg = S[0]; return c_u[0] + S[0] * tt; }
+  if (k >= K) { tt = z - X[K - 1]; dg = S[K - 1]; return c_u[K - 1] + S[K - 1] * tt; }
   const int l = k - 1;
   const float Xl = X[l];
   const float h = X[l + 1] - Xl;
-  const float ih = 1.f / h;
-  const float t = (z - Xl) * ih;
+  const float ihh = ih[l];
+  const float t = (z - Xl) * ihh;
+  tt = t;
   const float t2 = t * t, t3 = t2 * t;
-  const float u0 = c_u[l], u1 = c_u[l + 1];
+  const float u0 = c_u[l], du = c_u[l + 1] - u0;
   const float hs0 = h * S[l], hs1 = h * S[l + 1];
-  const float g = u0 + (u1 - u0) * (3.f * t2 - 2.f * t3) + hs0 * (t3 - 2.f * t2 + t) + hs1 * (t3 - t2);
-  const float dgdt = (u1 - u0) * (6.f * t - 6.f * t2) + hs0 * (3.f * t2 - 4.f * t + 1.f) + hs1 * (3.f * t2 - 2.f * t);
-  dg = dgdt * ih;
+  const float g = u0 + du * (3.f * t2 - 2.f * t3) + hs0 * (t3 - 2.f * t2 + t) + hs1 * (t3 - t2);
+  const float dgdt = du * (6.f * t - 6.f * t2) + hs0 * (3.f * t2 - 4.f * t + 1.f) + hs1 * (3.f * t2 - 2.f * t);
+  dg = dgdt * ihh;
   return g;
 }
 
-// Partial derivatives of g(z) with respect to the knots and slopes of its
-// interval: gXl, gXr (d g/d X_l, X_{l+1}) and gSl, gSr.  For the linear
-// continuations only the end knot is involved (returned in the *l slots).
-__device__ __forceinline__ void cdf_knot_partials(const float* X, const float* S, float z, int k,
-                                                  float& gXl, float& gXr, float& gSl, float& gSr) {
-  if (k == 0) { gXl = -S[0]; gSl = z - X[0]; gXr = gSr = 0.f; return; }
-  if (k >= K) { gXl = -S[K - 1]; gSl = z - X[K - 1]; gXr = gSr = 0.f; return; }
-  const int l = k - 1;
-  const float Xl = X[l];
-  const float h = X[l + 1] - Xl;
-  const float ih = 1.f / h;
-  const float t = (z - Xl) * ih;
-  const float t2 = t * t, t3 = t2 * t;
-  const float u0 = c_u[l], u1 = c_u[l + 1];
-  const float h10 = t3 - 2.f * t2 + t, h11 = t3 - t2;
-  const float dgdt = (u1 - u0) * (6.f * t - 6.f * t2) + h * S[l] * (3.f * t2 - 4.f * t + 1.f) +
-                     h * S[l + 1] * (3.f * t2 - 2.f * t);
-  const float gh = h10 * S[l] + h11 * S[l + 1];
-  gSl = h * h10;
-  gSr = h * h11;
-  gXl = dgdt * (t - 1.f) * ih - gh;
-  gXr = -dgdt * t * ih + gh;
+// Knot adjoint of one axis, accumulated per interval as moments
+// m_j = sum ybar t^j of the rays in it; kb_flush turns them into
+// d loss / d X_l, X_{l+1}, S_l, S_{l+1} (every partial derivative of the
+// Hermite form is a cubic in t with interval-constant coefficients).
+struct KnotMom {
+  int k;
+  float m0, m1, m2, m3;
+};
+__device__ __forceinline__ void km_add(KnotMom& c, float yb, float t) {
+  const float yt = yb * t, yt2 = yt * t;
+  c.m0 += yb; c.m1 += yt; c.m2 += yt2; c.m3 = fmaf(yt2, t, c.m3);
+}
+__device__ __forceinline__ void km_flush(KnotMom& c, const float* X, const float* S, const float* ih,
+                                         float* kb /* dX[K], dS[K] */) {
+  if (c.k < 0) return;
+  if (c.k == 0) {
+    atomicAdd(&kb[0], -S[0] * c.m0); atomicAdd(&kb[K], c.m1);
+  } else if (c.k >= K) {
+    atomicAdd(&kb[K - 1], -S[K - 1] * c.m0); atomicAdd(&kb[2 * K - 1], c.m1);
+  } else {
+    const int l = c.k - 1;
+    const float h = X[l + 1] - X[l], ihh = ih[l], Sl = S[l], Sr = S[l + 1];
+    const float du = c_u[l + 1] - c_u[l];
+    const float G10 = c.m3 - 2.f * c.m2 + c.m1;     // sum ybar (t^3 - 2t^2 + t)
+    const float G11 = c.m3 - c.m2;                  // sum ybar (t^3 - t^2)
+    const float gh = Sl * G10 + Sr * G11;           // sum ybar dg/dh at fixed t
+    const float a0 = h * Sl, a1 = 6.f * du - 4.f * h * Sl - 2.f * h * Sr, a2 = -6.f * du + 3.f * h * (Sl + Sr);
+    const float Atm1 = -a0 * c.m0 + (a0 - a1) * c.m1 + (a1 - a2) * c.m2 + a2 * c.m3;  // sum ybar dg/dt (t-1)
+    const float At = a0 * c.m1 + a1 * c.m2 + a2 * c.m3;                              // sum ybar dg/dt t
+    atomicAdd(&kb[l], Atm1 * ihh - gh);
+    atomicAdd(&kb[l + 1], gh - At * ihh);
+    atomicAdd(&kb[K + l], h * G10);
+    atomicAdd(&kb[K + l + 1], h * G11);
+  }
+  c.m0 = c.m1 = c.m2 = c.m3 = 0.f;
 }
 
 // ------------------------------------------------------------------ reductions
@@ -355,6 +421,20 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
     v[i] = s;
   }
   __syncthreads();
+}
+
+// Column sums of a row-major [rows][cols] array with row stride ld: wave w
+// reduces columns w, w + nw, ... in a fixed order (deterministic); emit(c, sum)
+// runs on lane 0 of the owning wave.
+template <class T, class EMIT>
+__device__ __forceinline__ void reduce_columns(const T* a, int rows, int cols, int ld, EMIT emit) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = wv; c < cols; c += nw) {
+    double s = 0.0;
+    for (int r = lane; r < rows; r += 64) s += (double)a[(size_t)r * ld + c];
+    s = wave_sum(s);
+    if (lane == 0) emit(c, s);
+  }
 }
 
 // ------------------------------------------------------------------ FFT

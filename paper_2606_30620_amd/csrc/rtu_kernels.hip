@@ -55,6 +55,14 @@ __device__ __forceinline__ void shoot(const SysDev& S, const Sie& L, const float
   bx = x - ax;
   by = y - ay;
 }
+__device__ __forceinline__ void shoot(const SysDev& S, const Sie& L, const Nfw* nf, int nsub,
+                                      float x, float y, float& bx, float& by) {
+  float ax, ay;
+  sie_shear_alpha(L, x, y, ax, ay);
+  for (int j = 0; j < nsub; ++j) nfw_alpha(nf[j], S.tau, x, y, ax, ay);
+  bx = x - ax;
+  by = y - ay;
+}
 
 __device__ __forceinline__ unsigned long long sel_key(float v, int m) {
   unsigned u = __float_as_uint(v + 0.0f);      // -0 -> +0
@@ -75,7 +83,7 @@ struct SelLds {
   double red[8 * 16];
   float fred[2 * 16];
   int tbin[2 * K], tcum[2 * K], trank[2 * K];
-  int seg_bin[2 * K], seg_start[2 * K], seg_count[2 * K], seg_fill[2 * K];
+  int seg_bin[2 * K], seg_start[2 * K], seg_count[2 * K], seg_fill[2 * K], seg_t0[2 * K];
   int nseg, total;
   float tval[2 * K];
   int tidx[2 * K];
@@ -187,6 +195,7 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
       const int bb = L.tbin[t];
       if (ns == 0 || L.seg_bin[ns - 1] != bb) {
         L.seg_bin[ns] = bb;
+        L.seg_t0[ns] = t;
         L.seg_start[ns] = tot;
         L.seg_count[ns] = cum(bb + 1) - cum(bb);
         L.seg_fill[ns] = 0;
@@ -217,18 +226,22 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
   }
   __threadfence_block();
   __syncthreads();
-  // ---- rank inside each segment by counting
-  for (int sg = 0; sg < nseg; ++sg) {
-    const int st0 = L.seg_start[sg], cnt = L.seg_count[sg], bb = L.seg_bin[sg];
-    for (int c = tid; c < cnt; c += nt) {
-      const unsigned long long kc = cand[st0 + c];
-      int rk = 0;
-      for (int c2 = 0; c2 < cnt; ++c2) rk += cand[st0 + c2] < kc;
-      for (int t = 0; t < 2 * K; ++t) {
-        if (L.tbin[t] == bb && L.trank[t] == rk) {
-          L.tval[t] = key_value(kc);
-          L.tidx[t] = (int)(kc & 0xffffffffu);
-        }
+  // ---- rank inside each segment by counting, all candidates in parallel; the
+  //      targets of a segment are a contiguous range of t (ranks are sorted)
+  for (int idx = tid; idx < total; idx += nt) {
+    int lo = 0, hi = nseg - 1;      // segment holding position idx
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L.seg_start[mid] <= idx) lo = mid; else hi = mid - 1;
+    }
+    const int st0 = L.seg_start[lo], cnt = L.seg_count[lo], bb = L.seg_bin[lo];
+    const unsigned long long kc = cand[idx];
+    int rk = 0;
+    for (int c2 = 0; c2 < cnt; ++c2) rk += cand[st0 + c2] < kc;
+    for (int t = L.seg_t0[lo]; t < 2 * K && L.tbin[t] == bb; ++t) {
+      if (L.trank[t] == rk) {
+        L.tval[t] = key_value(kc);
+        L.tidx[t] = (int)(kc & 0xffffffffu);
       }
     }
   }
@@ -350,11 +363,17 @@ __global__ void __launch_bounds__(PREP_THREADS) k_prep(SysDev S) {
 // Source grid staged in LDS with a one-cell zero border:
 // padded index (i + 1) * (n + 2) + (j + 1) for i, j in [-1, n].
 struct RayLdsHead {
-  float X[2][K], Sl[2][K], dp[2][K];
+  float X[2][K], Sl[2][K], ih[2][K], dp[2][K];
   float kb[4 * K];   // dX (x), dS (x), dX (y), dS (y)
+  Nfw nfw[RTU_MAX_SUB];
 };
 
 __device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H) {
+  {
+    const int ns = n_sub_of(S, b);
+    const float* lensp = S.lens + (size_t)b * S.n_lens;
+    if ((int)threadIdx.x < ns) H.nfw[threadIdx.x] = make_nfw(lensp + RTU_N_LENS_BASE + RTU_N_PER_SUB * threadIdx.x, S.tau);
+  }
   const float* kn = S.knots + (size_t)b * 4 * K;
   const float* dp = S.dp + (size_t)b * 2 * K;
   for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
@@ -364,6 +383,10 @@ __device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H
     H.dp[ax][k] = dp[i];
   }
   for (int i = threadIdx.x; i < 4 * K; i += blockDim.x) H.kb[i] = 0.f;
+  for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
+    const int ax = i / K, k = i - ax * K;
+    H.ih[ax][k] = k < K - 1 ? 1.f / (kn[ax * 2 * K + k + 1] - kn[ax * 2 * K + k]) : 0.f;
+  }
 }
 
 template <bool LDSGRID>
@@ -421,14 +444,18 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
   const int n = S.n_src;
   const float* gsrc = S.src + (size_t)b * n * n;
   float acc = 0.f;
+  int kx = 0, ky = 0;
   for (int a = 0; a < S.ss; ++a) {
-    for (int c = 0; c < S.ss; ++c) {
+    for (int cc = 0; cc < S.ss; ++cc) {
+      const int c = (a & 1) ? S.ss - 1 - cc : cc;   // serpentine: neighbouring sub-rays in turn
       float x, y, bx, by;
       pixel_xy(S, i, j, a, c, x, y);
-      shoot(S, L, lensp, nsub, x, y, bx, by);
-      float dgx, dgy;
-      const float yx = cdf_eval(H.X[0], H.Sl[0], bx, knot_count(H.X[0], bx), dgx);
-      const float yy = cdf_eval(H.X[1], H.Sl[1], by, knot_count(H.X[1], by), dgy);
+      shoot(S, L, H.nfw, nsub, x, y, bx, by);
+      kx = knot_count_from(H.X[0], bx, kx);
+      ky = knot_count_from(H.X[1], by, ky);
+      float dgx, dgy, tx, ty;
+      const float yx = cdf_eval(H.X[0], H.Sl[0], H.ih[0], bx, kx, dgx, tx);
+      const float yy = cdf_eval(H.X[1], H.Sl[1], H.ih[1], by, ky, dgy, ty);
       Bil B;
       if (bil_setup(yx, yy, n, B)) {
         float s00, s01, s10, s11;
@@ -447,34 +474,15 @@ __global__ void __launch_bounds__(RAY_THREADS) k_rays_fwd(SysDev S) {
   rays_fwd_body<LDSGRID>(S, b, blockIdx.x - b * S.ray_tiles, smem);
 }
 
-// register cache of the knot-adjoint accumulation for one axis: the current
-// interval code k (0..K) and the four partial sums of its end knots
-struct KnotCache {
-  int k;
-  float xl, xr, sl, sr;
-};
-__device__ __forceinline__ void kc_flush(KnotCache& c, float* kb /* dX[K], dS[K] */) {
-  if (c.k < 0) return;
-  if (c.k == 0) {
-    atomicAdd(&kb[0], c.xl); atomicAdd(&kb[K], c.sl);
-  } else if (c.k >= K) {
-    atomicAdd(&kb[K - 1], c.xl); atomicAdd(&kb[K + K - 1], c.sl);
-  } else {
-    const int l = c.k - 1;
-    atomicAdd(&kb[l], c.xl); atomicAdd(&kb[l + 1], c.xr);
-    atomicAdd(&kb[K + l], c.sl); atomicAdd(&kb[K + l + 1], c.sr);
-  }
-  c.xl = c.xr = c.sl = c.sr = 0.f;
-}
-
 template <bool LDSGRID>
 __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* smem) {
   RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
   const int n = S.n_src, np = n + 2;
+  // the source grid is read through L1/L2 here; only d loss / d s lives in LDS
   float* g = reinterpret_cast<float*>(smem + sizeof(RayLdsHead));
-  float* gb = g + (LDSGRID ? np * np : 0);                 // d loss / d s (padded)
+  float* gb = g;                                           // d loss / d s (padded)
   float* subacc = gb + (LDSGRID ? np * np : 0);            // [4 n_sub_max][256] per-thread
-  size_t off = sizeof(RayLdsHead) + (size_t)(LDSGRID ? 2 * np * np : 0) * 4 +
+  size_t off = sizeof(RayLdsHead) + (size_t)(LDSGRID ? 1 * np * np : 0) * 4 +
                (size_t)4 * S.n_sub_max * RAY_THREADS * 4;
   off = (off + 15) & ~(size_t)15;
   double* red = reinterpret_cast<double*>(smem + off);     // [8 * 4]
@@ -482,7 +490,6 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   const int ti = tile / S.ray_tx, tj = tile - ti * S.ray_tx;
   const int i = ti * RAY_TILE + (threadIdx.x >> 4), j = tj * RAY_TILE + (threadIdx.x & 15);
   load_knots(S, b, H);
-  load_grid<LDSGRID>(S, b, g);
   if (LDSGRID)
     for (int q = threadIdx.x; q < np * np; q += blockDim.x) gb[q] = 0.f;
   for (int q = threadIdx.x; q < 4 * S.n_sub_max * RAY_THREADS; q += blockDim.x) subacc[q] = 0.f;
@@ -498,65 +505,79 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   int bi0 = 1 << 30, bj0 = 1 << 30, bi1 = -(1 << 30), bj1 = -(1 << 30);
   if (i < S.n_img && j < S.n_img) {
     const float vb = S.ubar[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] * S.inv_ss2;
-    KnotCache cx{-1, 0.f, 0.f, 0.f, 0.f}, cy{-1, 0.f, 0.f, 0.f, 0.f};
+    KnotMom cx{-1, 0.f, 0.f, 0.f, 0.f}, cy{-1, 0.f, 0.f, 0.f, 0.f};
+    int kx = 0, ky = 0;
+    // d loss / d s of the cell the last sub-rays fell in, kept in registers
+    // and added to the grid when the cell changes (sub-rays of one pixel
+    // mostly share a cell)
+    int ci = -1000, cj = -1000;
+    float c00 = 0.f, c01 = 0.f, c10 = 0.f, c11 = 0.f;
+    auto flush_cell = [&]() {
+      if (ci < -1) return;
+      if (LDSGRID) {
+        const int p = (ci + 1) * np + (cj + 1);
+        atomicAdd(&gb[p], c00);
+        atomicAdd(&gb[p + 1], c01);
+        atomicAdd(&gb[p + np], c10);
+        atomicAdd(&gb[p + np + 1], c11);
+        bi0 = min(bi0, ci); bj0 = min(bj0, cj); bi1 = max(bi1, ci + 1); bj1 = max(bj1, cj + 1);
+      } else {
+        auto add = [&](int ii, int jj, float v) {
+          if (ii >= 0 && ii < n && jj >= 0 && jj < n) atomicAdd(&gsb[ii * n + jj], v);
+        };
+        add(ci, cj, c00); add(ci, cj + 1, c01); add(ci + 1, cj, c10); add(ci + 1, cj + 1, c11);
+      }
+      c00 = c01 = c10 = c11 = 0.f;
+    };
     for (int a = 0; a < S.ss; ++a) {
-      for (int c = 0; c < S.ss; ++c) {
-        float x, y, bx, by;
+      for (int cc = 0; cc < S.ss; ++cc) {
+        const int c = (a & 1) ? S.ss - 1 - cc : cc;   // serpentine order
+        float x, y;
         pixel_xy(S, i, j, a, c, x, y);
-        shoot(S, L, lensp, nsub, x, y, bx, by);
-        const int kx = knot_count(H.X[0], bx), ky = knot_count(H.X[1], by);
-        float dgx, dgy;
-        const float yx = cdf_eval(H.X[0], H.Sl[0], bx, kx, dgx);
-        const float yy = cdf_eval(H.X[1], H.Sl[1], by, ky, dgy);
+        SieRay E;
+        float ax, ay;
+        sie_shear_alpha<true>(L, x, y, ax, ay, E);
+        for (int q = 0; q < nsub; ++q) nfw_alpha(H.nfw[q], S.tau, x, y, ax, ay);
+        const float bx = x - ax, by = y - ay;
+        kx = knot_count_from(H.X[0], bx, kx);
+        ky = knot_count_from(H.X[1], by, ky);
+        float dgx, dgy, tx, ty;
+        const float yx = cdf_eval(H.X[0], H.Sl[0], H.ih[0], bx, kx, dgx, tx);
+        const float yy = cdf_eval(H.X[1], H.Sl[1], H.ih[1], by, ky, dgy, ty);
         Bil B;
         if (!bil_setup(yx, yy, n, B)) continue;
         float s00, s01, s10, s11;
-        bil_corners<LDSGRID>(g, gsrc, n, B, s00, s01, s10, s11);
+        bil_corners<false>(g, gsrc, n, B, s00, s01, s10, s11);
         // d loss / d s at the four corners
-        const float w00 = (1.f - B.fx) * (1.f - B.fy), w01 = B.fx * (1.f - B.fy);
-        const float w10 = (1.f - B.fx) * B.fy, w11 = B.fx * B.fy;
-        if (LDSGRID) {
-          const int p = (B.i0 + 1) * np + (B.j0 + 1);
-          atomicAdd(&gb[p], vb * w00);
-          atomicAdd(&gb[p + 1], vb * w01);
-          atomicAdd(&gb[p + np], vb * w10);
-          atomicAdd(&gb[p + np + 1], vb * w11);
-          bi0 = min(bi0, B.i0); bj0 = min(bj0, B.j0); bi1 = max(bi1, B.i0 + 1); bj1 = max(bj1, B.j0 + 1);
-        } else {
-          auto add = [&](int ii, int jj, float v) {
-            if (ii >= 0 && ii < n && jj >= 0 && jj < n) atomicAdd(&gsb[ii * n + jj], v);
-          };
-          add(B.i0, B.j0, vb * w00); add(B.i0, B.j0 + 1, vb * w01);
-          add(B.i0 + 1, B.j0, vb * w10); add(B.i0 + 1, B.j0 + 1, vb * w11);
-        }
+        if (B.i0 != ci || B.j0 != cj) { flush_cell(); ci = B.i0; cj = B.j0; }
+        const float w01 = B.fx * (1.f - B.fy), w11 = B.fx * B.fy;
+        c00 += vb * ((1.f - B.fy) - w01);
+        c01 += vb * w01;
+        c10 += vb * (B.fy - w11);
+        c11 += vb * w11;
         // d loss / d y
-        const float fn = (float)n;
-        const float ybx = vb * fn * ((1.f - B.fy) * (s01 - s00) + B.fy * (s11 - s10));
-        const float yby = vb * fn * ((1.f - B.fx) * (s10 - s00) + B.fx * (s11 - s01));
-        // knots and slopes of the CDF splines
-        {
-          float gXl, gXr, gSl, gSr;
-          cdf_knot_partials(H.X[0], H.Sl[0], bx, kx, gXl, gXr, gSl, gSr);
-          if (kx != cx.k) { kc_flush(cx, H.kb); cx.k = kx; }
-          cx.xl += ybx * gXl; cx.xr += ybx * gXr; cx.sl += ybx * gSl; cx.sr += ybx * gSr;
-          cdf_knot_partials(H.X[1], H.Sl[1], by, ky, gXl, gXr, gSl, gSr);
-          if (ky != cy.k) { kc_flush(cy, H.kb + 2 * K); cy.k = ky; }
-          cy.xl += yby * gXl; cy.xr += yby * gXr; cy.sl += yby * gSl; cy.sr += yby * gSr;
-        }
+        const float vn = vb * (float)n;
+        const float ybx = vn * ((1.f - B.fy) * (s01 - s00) + B.fy * (s11 - s10));
+        const float yby = vn * ((1.f - B.fx) * (s10 - s00) + B.fx * (s11 - s01));
+        // knots and slopes of the CDF splines (moments per interval)
+        if (kx != cx.k) { km_flush(cx, H.X[0], H.Sl[0], H.ih[0], H.kb); cx.k = kx; }
+        km_add(cx, ybx, tx);
+        if (ky != cy.k) { km_flush(cy, H.X[1], H.Sl[1], H.ih[1], H.kb + 2 * K); cy.k = ky; }
+        km_add(cy, yby, ty);
         // d loss / d beta -> d loss / d alpha = -d loss / d beta
         const float abx = -ybx * dgx, aby = -yby * dgy;
-        sie_shear_vjp(L, x, y, abx, aby, acc);
+        sie_shear_vjp(L, E, x, y, abx, aby, acc);
         for (int q = 0; q < nsub; ++q) {
-          const Nfw N = make_nfw(lensp + RTU_N_LENS_BASE + RTU_N_PER_SUB * q, S.tau);
           float* sa = subacc + (4 * q) * RAY_THREADS + threadIdx.x;
           float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
-          nfw_vjp(N, S.tau, x, y, abx, aby, g0, g1, g2, g3);
+          nfw_vjp(H.nfw[q], S.tau, x, y, abx, aby, g0, g1, g2, g3);
           sa[0] += g0; sa[RAY_THREADS] += g1; sa[2 * RAY_THREADS] += g2; sa[3 * RAY_THREADS] += g3;
         }
       }
     }
-    kc_flush(cx, H.kb);
-    kc_flush(cy, H.kb + 2 * K);
+    flush_cell();
+    km_flush(cx, H.X[0], H.Sl[0], H.ih[0], H.kb);
+    km_flush(cy, H.X[1], H.Sl[1], H.ih[1], H.kb + 2 * K);
   }
   if (LDSGRID) {
     atomicMin(&bbox[0], bi0); atomicMin(&bbox[1], bj0);
@@ -739,6 +760,7 @@ __global__ void __launch_bounds__(PSF_THREADS) k_psf_any(SysDev S, int adjoint) 
 struct PostLds {
   double red[16 * 16];
   double xbar[2][K];      // d loss / d X (beta units), after the slope chain
+  double lsum[RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB];
   uint32_t stat;
 };
 
@@ -774,11 +796,8 @@ __global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S) {
     const Sie L = make_sie(lensp);
     // ---- knot adjoint: sum the tile partials, then S_k = 1/p'_k with
     //      p'_k = sum_l D_kl X_l  ->  dX_l += sum_k (-S_k^2 dS_k) D_kl
-    if (tid < 4 * K) {
-      double s = 0.0;
-      for (int t = 0; t < S.ray_tiles; ++t) s += S.kbar[((size_t)b * S.ray_tiles + t) * 4 * K + tid];
-      P.red[tid] = s;
-    }
+    reduce_columns(S.kbar + (size_t)b * S.ray_tiles * 4 * K, S.ray_tiles, 4 * K, 4 * K,
+                   [&](int c, double v) { P.red[c] = v; });
     __syncthreads();
     if (tid < 2 * K) {
       const int ax = tid / K, l = tid - ax * K;
@@ -811,7 +830,10 @@ __global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S) {
         const float abx = ax == 0 ? -(float)bb : 0.f, aby = ax == 1 ? -(float)bb : 0.f;
         SieAcc a;
         a.zero();
-        sie_shear_vjp(L, x, y, abx, aby, a);
+        SieRay E;
+        float ax_, ay_;
+        sie_shear_alpha<true>(L, x, y, ax_, ay_, E);
+        sie_shear_vjp(L, E, x, y, abx, aby, a);
         double av[8] = {a.P, a.q, a.f, a.phi, a.x0, a.y0, a.g1, a.g2};
         double gl[7];
         sie_grad(L, av, gl);
@@ -825,12 +847,14 @@ __global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S) {
       }
     }
     __syncthreads();
-    // tile partials then masked-ray rows, summed in a fixed order
+    // tile partials, then the masked-ray rows, each summed in a fixed order
+    reduce_columns(S.lpart + (size_t)b * S.ray_tiles * nl, S.ray_tiles, nl, nl,
+                   [&](int c, double v) { P.lsum[c] = v; });
+    __syncthreads();
+    reduce_columns(mp, 4 * K, nl, nl, [&](int c, double v) { P.lsum[c] += v; });
+    __syncthreads();
     if (tid < nl) {
-      double v = 0.0;
-      const double* lp = S.lpart + (size_t)b * S.ray_tiles * nl + tid;
-      for (int t = 0; t < S.ray_tiles; ++t) v += lp[(size_t)t * nl];
-      for (int it = 0; it < 4 * K; ++it) v += mp[it * nl + tid];
+      const double v = P.lsum[tid];
       if (S.g_lens) S.g_lens[(size_t)b * nl + tid] = (float)v;
       if (!isfinite(v)) atomicOr(&P.stat, RTU_ST_NONFINITE);
     }
@@ -945,7 +969,8 @@ static size_t ray_lds_bytes(const SysDev& h, bool adjoint, bool lds_grid) {
   const size_t np = (size_t)(h.n_src + 2);
   size_t bytes = sizeof(RayLdsHead) + (lds_grid ? np * np * 4 : 0);
   if (adjoint) {
-    bytes += (lds_grid ? np * np * 4 : 0) + (size_t)4 * h.n_sub_max * RAY_THREADS * 4;
+    // the adjoint keeps d loss / d s (not the source grid) in LDS
+    bytes += (size_t)4 * h.n_sub_max * RAY_THREADS * 4;
     bytes = (bytes + 15) & ~(size_t)15;
     bytes += 8 * 4 * 8 + 16;
   }
