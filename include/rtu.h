@@ -216,6 +216,59 @@ int rtu_fit_samples(rtu_fit f, float* z, void* stream);
  * [S] (uint32), valid until the fit is destroyed. */
 int rtu_fit_last_outputs(rtu_fit f, const double** loss, const uint32_t** status);
 
+/* ---- serving: many fits in shared launches ------------------------------
+ * A fleet owns one HBM arena of a fixed budget.  Requests (a lens system and
+ * the settings of its variational fit) queue in arrival order and are
+ * admitted, first come first served, whenever the arena and a slot have room
+ * for the head of the queue.  Every round advances every admitted fit by one
+ * ELBO + Adam step (rtu_fit_* semantics) in one set of kernel launches shared
+ * by all of them, whatever their image, source or PSF sizes; each fit keeps its
+ * optimiser state on the device.  A fit that has taken its steps is retired at
+ * the next sync point (results copied to the host, memory returned), and
+ * queued requests are admitted there.  Sync points happen at most every
+ * sync_every rounds, or whenever no admitted fit has steps left. */
+typedef struct rtu_fleet_s* rtu_fleet;
+
+typedef struct {
+  rtu_geometry geom;
+  const float* image;        /* host [N*N] */
+  const float* noise_sigma;  /* host [N*N] */
+  const float* psf;          /* host [K*K] */
+  const uint8_t* arc_mask;   /* host [N*N] */
+  const float* mu0;          /* host [dim], dim = n_lens + 4 + n_src^2 */
+  const float* rho0;         /* host [dim] */
+  int32_t samples;           /* S per step */
+  int32_t steps;             /* ELBO steps of the fit */
+  int32_t n_sub;             /* active subhaloes (<= geom.n_sub_max) */
+  float lr;
+  uint64_t seed;             /* Philox key of the fit's draws */
+} rtu_fit_request;
+
+/* Creates a fleet on `device` with an arena of hbm_budget bytes and at most
+ * max_fits fits admitted at once. */
+int rtu_fleet_create(int32_t device, size_t hbm_budget, int32_t max_fits, int32_t sync_every, rtu_fleet* out);
+int rtu_fleet_destroy(rtu_fleet f);
+/* Arena bytes the request needs once admitted (0 if it is invalid). */
+size_t rtu_fleet_request_bytes(const rtu_fit_request* r);
+/* Queues a request; its host arrays are copied.  *ticket identifies it.
+ * RTU_EINVAL for a bad request, RTU_ENOMEM if it can never fit the budget. */
+int rtu_fleet_submit(rtu_fleet f, const rtu_fit_request* r, int64_t* ticket);
+/* Queues up to `rounds` rounds on `stream` (sync points, which wait for the
+ * stream, happen inside as described above).  Returns early when no fit has
+ * steps left and none can be admitted. */
+int rtu_fleet_run(rtu_fleet f, int32_t rounds, void* stream);
+/* Forces a sync point now: waits for `stream`, retires finished fits, admits. */
+int rtu_fleet_sync(rtu_fleet f, void* stream);
+/* Tickets of fits retired since the last poll (host, up to max). */
+int rtu_fleet_poll(rtu_fleet f, int64_t* tickets, int32_t max, int32_t* n);
+/* Result of a retired fit (host copies; any pointer may be NULL), then forgets
+ * it: guide mu[dim], rho[dim], ELBO per step elbo[max_trace] (*n_trace = steps),
+ * and the OR of all its samples' status words.  RTU_ENOTFOUND if unknown. */
+int rtu_fleet_result(rtu_fleet f, int64_t ticket, float* mu, float* rho, double* elbo, int32_t max_trace,
+                     int32_t* n_trace, uint32_t* status);
+/* Admitted fits, queued requests, arena bytes in use, rounds run. */
+int rtu_fleet_stats(rtu_fleet f, int32_t* active, int32_t* queued, size_t* bytes_in_use, int64_t* rounds);
+
 /* Human-readable text of a return code. */
 const char* rtu_strerror(int code);
 

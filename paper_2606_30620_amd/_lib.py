@@ -32,6 +32,12 @@ class Geometry(C.Structure):
                 ("pixel_scale", C.c_float), ("tnfw_tau", C.c_float), ("flags", C.c_uint32)]
 
 
+class FitRequest(C.Structure):
+    _fields_ = [("geom", Geometry), ("image", C.c_void_p), ("noise_sigma", C.c_void_p), ("psf", C.c_void_p),
+                ("arc_mask", C.c_void_p), ("mu0", C.c_void_p), ("rho0", C.c_void_p), ("samples", C.c_int32),
+                ("steps", C.c_int32), ("n_sub", C.c_int32), ("lr", C.c_float), ("seed", C.c_uint64)]
+
+
 class RTUError(RuntimeError):
     pass
 
@@ -65,12 +71,24 @@ def _load():
     lib.rtu_fit_get_state.argtypes = [P, VP, C.POINTER(I32), VP]
     lib.rtu_fit_samples.argtypes = [P, VP, VP]
     lib.rtu_fit_set_state.argtypes = [P, VP, I32]
+    lib.rtu_fleet_create.argtypes = [I32, SZ, I32, I32, C.POINTER(P)]
+    lib.rtu_fleet_destroy.argtypes = [P]
+    lib.rtu_fleet_request_bytes.argtypes = [C.POINTER(FitRequest)]
+    lib.rtu_fleet_request_bytes.restype = SZ
+    lib.rtu_fleet_submit.argtypes = [P, C.POINTER(FitRequest), C.POINTER(C.c_int64)]
+    lib.rtu_fleet_run.argtypes = [P, I32, VP]
+    lib.rtu_fleet_sync.argtypes = [P, VP]
+    lib.rtu_fleet_poll.argtypes = [P, VP, I32, C.POINTER(I32)]
+    lib.rtu_fleet_result.argtypes = [P, C.c_int64, VP, VP, VP, I32, C.POINTER(I32), C.POINTER(C.c_uint32)]
+    lib.rtu_fleet_stats.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(SZ), C.POINTER(C.c_int64)]
     lib.rtu_strerror.argtypes = [C.c_int]
     lib.rtu_strerror.restype = C.c_char_p
     for fn in ("rtu_plan_create", "rtu_plan_destroy", "rtu_set_observation", "rtu_loss_grad",
                "rtu_debug_fetch", "rtu_profile_begin", "rtu_profile_end", "rtu_fit_create",
                "rtu_fit_destroy", "rtu_fit_step", "rtu_fit_read", "rtu_fit_last_outputs",
-               "rtu_fit_get_state", "rtu_fit_set_state", "rtu_fit_samples"):
+               "rtu_fit_get_state", "rtu_fit_set_state", "rtu_fit_samples", "rtu_fleet_create",
+               "rtu_fleet_destroy", "rtu_fleet_submit", "rtu_fleet_run", "rtu_fleet_sync", "rtu_fleet_poll",
+               "rtu_fleet_result", "rtu_fleet_stats"):
         getattr(lib, fn).restype = C.c_int
     return lib
 
@@ -237,11 +255,86 @@ class Fit:
         check(LIB.rtu_fit_set_state(self._h, st.ctypes.data, int(steps)), "rtu_fit_set_state")
 
 
+class Fleet:
+    """An rtu_fleet: continuous batching of many fits in shared launches."""
+
+    def __init__(self, hbm_budget: int, max_fits: int = 256, sync_every: int = 4, device: int = 0):
+        h = C.c_void_p()
+        check(LIB.rtu_fleet_create(int(device), int(hbm_budget), int(max_fits), int(sync_every), C.byref(h)),
+              "rtu_fleet_create")
+        self._h = h
+        self._dims = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            LIB.rtu_fleet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _request(geom: Geometry, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub=0, lr=1e-2, seed=0):
+        arrs = [np.ascontiguousarray(image, np.float32), np.ascontiguousarray(sigma, np.float32),
+                np.ascontiguousarray(psf, np.float32), np.ascontiguousarray(mask, np.uint8),
+                np.ascontiguousarray(mu0, np.float32), np.ascontiguousarray(rho0, np.float32)]
+        req = FitRequest(geom, *[a.ctypes.data for a in arrs], int(samples), int(steps), int(n_sub), float(lr),
+                         int(seed))
+        return req, arrs
+
+    @staticmethod
+    def request_bytes(geom, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub=0) -> int:
+        req, keep = Fleet._request(geom, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub)
+        return LIB.rtu_fleet_request_bytes(C.byref(req))
+
+    def submit(self, geom, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub=0, lr=1e-2, seed=0) -> int:
+        req, keep = self._request(geom, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub, lr, seed)
+        t = C.c_int64()
+        check(LIB.rtu_fleet_submit(self._h, C.byref(req), C.byref(t)), "rtu_fleet_submit")
+        self._dims[t.value] = (keep[4].size, int(steps))
+        return t.value
+
+    def run(self, rounds: int, stream=None) -> None:
+        check(LIB.rtu_fleet_run(self._h, int(rounds), _stream_ptr(stream)), "rtu_fleet_run")
+
+    def sync(self, stream=None) -> None:
+        check(LIB.rtu_fleet_sync(self._h, _stream_ptr(stream)), "rtu_fleet_sync")
+
+    def poll(self, max_n: int = 4096):
+        buf = np.zeros(max_n, np.int64)
+        n = C.c_int32()
+        check(LIB.rtu_fleet_poll(self._h, buf.ctypes.data, max_n, C.byref(n)), "rtu_fleet_poll")
+        return buf[:n.value].tolist()
+
+    def result(self, ticket: int):
+        dim, steps = self._dims.pop(ticket)
+        mu = np.zeros(dim, np.float32)
+        rho = np.zeros(dim, np.float32)
+        tr = np.zeros(steps, np.float64)
+        n = C.c_int32()
+        st = C.c_uint32()
+        check(LIB.rtu_fleet_result(self._h, int(ticket), mu.ctypes.data, rho.ctypes.data, tr.ctypes.data, steps,
+                                   C.byref(n), C.byref(st)), "rtu_fleet_result")
+        return mu, rho, tr[:n.value], st.value
+
+    def stats(self):
+        a, q = C.c_int32(), C.c_int32()
+        b = C.c_size_t()
+        r = C.c_int64()
+        check(LIB.rtu_fleet_stats(self._h, C.byref(a), C.byref(q), C.byref(b), C.byref(r)), "rtu_fleet_stats")
+        return {"active": a.value, "queued": q.value, "bytes_in_use": b.value, "rounds": r.value}
+
+
 def exported_symbols():
     """Names declared in include/rtu.h that the loaded library exports."""
     return [n for n in ("rtu_n_lens", "rtu_workspace_bytes", "rtu_plan_create", "rtu_plan_destroy",
                         "rtu_set_observation", "rtu_masked_count", "rtu_loss_grad", "rtu_debug_fetch",
                         "rtu_profile_begin", "rtu_profile_end", "rtu_fit_create", "rtu_fit_destroy",
                         "rtu_fit_dim", "rtu_fit_step", "rtu_fit_read", "rtu_fit_last_outputs",
-                        "rtu_fit_get_state", "rtu_fit_set_state", "rtu_fit_samples",
+                        "rtu_fit_get_state", "rtu_fit_set_state", "rtu_fit_samples", "rtu_fleet_create",
+                        "rtu_fleet_destroy", "rtu_fleet_request_bytes", "rtu_fleet_submit", "rtu_fleet_run",
+                        "rtu_fleet_sync", "rtu_fleet_poll", "rtu_fleet_result", "rtu_fleet_stats",
                         "rtu_strerror") if hasattr(LIB, n)]

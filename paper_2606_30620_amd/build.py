@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librtu.so")
-SOURCES = ["rtu_kernels.hip", "rtu_fit.hip", "rtu_runtime.hip"]
+SOURCES = ["rtu_kernels.hip", "rtu_fit.hip", "rtu_runtime.hip", "rtu_fleet.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

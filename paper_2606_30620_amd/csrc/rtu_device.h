@@ -356,12 +356,12 @@ __device__ __forceinline__ void km_add(KnotMom& c, float yb, float t) {
   c.m0 += yb; c.m1 += yt; c.m2 += yt2; c.m3 = fmaf(yt2, t, c.m3);
 }
 __device__ __forceinline__ void km_flush(KnotMom& c, const float* X, const float* S, const float* ih,
-                                         float* kb /* dX[K], dS[K] */) {
+                                         double* kb /* dX[K], dS[K] */) {
   if (c.k < 0) return;
   if (c.k == 0) {
-    atomicAdd(&kb[0], -S[0] * c.m0); atomicAdd(&kb[K], c.m1);
+    atomicAdd(&kb[0], (double)(-S[0] * c.m0)); atomicAdd(&kb[K], (double)c.m1);
   } else if (c.k >= K) {
-    atomicAdd(&kb[K - 1], -S[K - 1] * c.m0); atomicAdd(&kb[2 * K - 1], c.m1);
+    atomicAdd(&kb[K - 1], (double)(-S[K - 1] * c.m0)); atomicAdd(&kb[2 * K - 1], (double)c.m1);
   } else {
     const int l = c.k - 1;
     const float h = X[l + 1] - X[l], ihh = ih[l], Sl = S[l], Sr = S[l + 1];
@@ -372,10 +372,10 @@ __device__ __forceinline__ void km_flush(KnotMom& c, const float* X, const float
     const float a0 = h * Sl, a1 = 6.f * du - 4.f * h * Sl - 2.f * h * Sr, a2 = -6.f * du + 3.f * h * (Sl + Sr);
     const float Atm1 = -a0 * c.m0 + (a0 - a1) * c.m1 + (a1 - a2) * c.m2 + a2 * c.m3;  // sum ybar dg/dt (t-1)
     const float At = a0 * c.m1 + a1 * c.m2 + a2 * c.m3;                              // sum ybar dg/dt t
-    atomicAdd(&kb[l], Atm1 * ihh - gh);
-    atomicAdd(&kb[l + 1], gh - At * ihh);
-    atomicAdd(&kb[K + l], h * G10);
-    atomicAdd(&kb[K + l + 1], h * G11);
+    atomicAdd(&kb[l], (double)(Atm1 * ihh - gh));
+    atomicAdd(&kb[l + 1], (double)(gh - At * ihh));
+    atomicAdd(&kb[K + l], (double)(h * G10));
+    atomicAdd(&kb[K + l + 1], (double)(h * G11));
   }
   c.m0 = c.m1 = c.m2 = c.m3 = 0.f;
 }

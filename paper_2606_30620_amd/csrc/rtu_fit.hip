@@ -38,14 +38,16 @@ __device__ __forceinline__ float eps_at(const FitDev& F, const float* eps, int s
 }
 
 // z_s = mu + exp(rho) eps_s, scattered into the plan's per-sample inputs
-__global__ void k_sample(FitDev F, const float* eps, int step) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = blockIdx.y;
+__device__ __forceinline__ void sample_body(const FitDev& F, const float* eps, int step, int s, int i) {
   if (i >= F.dim) return;
   const float z = F.mu[i] + __expf(F.rho[i]) * eps_at(F, eps, step, s, i);
   if (i < F.n_lens) F.z_lens[(size_t)s * F.n_lens + i] = z;
   else if (i < F.n_lens + 4) F.z_ps[(size_t)s * 4 + (i - F.n_lens)] = z;
   else F.z_lat[(size_t)s * F.n_src2 + (i - F.n_lens - 4)] = z;
+}
+
+__global__ void k_sample(FitDev F, const float* eps, int step) {
+  sample_body(F, eps, step, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __device__ __forceinline__ float grad_at(const FitDev& F, int s, int i) {
@@ -54,9 +56,9 @@ __device__ __forceinline__ float grad_at(const FitDev& F, int s, int i) {
   return F.g_lat[(size_t)s * F.n_src2 + (i - F.n_lens - 4)];
 }
 
-// ELBO of this step (before the update): one workgroup
-__global__ void __launch_bounds__(1024) k_elbo(FitDev F, int step) {
-  __shared__ double red[32];
+// ELBO of this step (before the update), and the OR of the samples' status
+// words: one workgroup of 1024 threads
+__device__ void elbo_body(const FitDev& F, int step, double* red) {
   double acc = 0.0;
   for (int i = threadIdx.x; i < F.dim; i += blockDim.x) acc += (double)F.rho[i];
   double ls = 0.0;
@@ -72,13 +74,20 @@ __global__ void __launch_bounds__(1024) k_elbo(FitDev F, int step) {
     double a = 0.0, l = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += red[w]; l += red[16 + w]; }
     F.trace[step] = -l / (double)F.S + F.elbo_const + a;
+    uint32_t st = 0;
+    for (int s = 0; s < F.S; ++s) st |= F.status[s];
+    if (F.status_acc) F.status_acc[0] |= st;
   }
+}
+
+__global__ void __launch_bounds__(1024) k_elbo(FitDev F, int step) {
+  __shared__ double red[32];
+  elbo_body(F, step, red);
 }
 
 // Adam on (mu, rho) with the gradient of -ELBO:
 //   d/dmu_i  = mean_s g_si,   d/drho_i = mean_s g_si exp(rho_i) eps_si - 1
-__global__ void k_adam(FitDev F, const float* eps, int step, int t) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void adam_body(const FitDev& F, const float* eps, int step, int t, int i) {
   if (i >= F.dim) return;
   const float sig = __expf(F.rho[i]);
   float gm = 0.f, gr = 0.f;
@@ -102,6 +111,53 @@ __global__ void k_adam(FitDev F, const float* eps, int step, int t) {
   F.m_rho[i] = m;
   F.v_rho[i] = v;
   F.rho[i] -= F.lr * (m * c1) / (sqrtf(v * c2) + e);
+}
+
+__global__ void k_adam(FitDev F, const float* eps, int step, int t) {
+  adam_body(F, eps, step, t, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---- shared launches over many fits (serving); step = round - round0
+__device__ __forceinline__ bool fit_step(const FitDev& F, int round, int& step) {
+  step = round - F.round0;
+  return step >= 0 && step < F.nsteps;
+}
+
+__global__ void kf_sample(const FitDev* __restrict__ fits, const Task* __restrict__ tasks, int round,
+                          const float* eps) {
+  const Task t = tasks[blockIdx.x];      // x fit, y parameter block, z sample
+  const FitDev& F = fits[t.x];
+  int step;
+  if (!fit_step(F, round, step)) return;
+  sample_body(F, eps, step, t.z, t.y * blockDim.x + threadIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) kf_elbo(const FitDev* __restrict__ fits, const Task* __restrict__ tasks,
+                                               int round) {
+  __shared__ double red[32];
+  const FitDev& F = fits[tasks[blockIdx.x].x];
+  int step;
+  if (!fit_step(F, round, step)) return;
+  elbo_body(F, step, red);
+}
+
+__global__ void kf_adam(const FitDev* __restrict__ fits, const Task* __restrict__ tasks, int round,
+                        const float* eps) {
+  const Task t = tasks[blockIdx.x];      // x fit, y parameter block
+  const FitDev& F = fits[t.x];
+  int step;
+  if (!fit_step(F, round, step)) return;
+  adam_body(F, eps, step, step + 1, t.y * blockDim.x + threadIdx.x);
+}
+
+hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, const float* eps, hipStream_t s) {
+  if (stage == RTU_STAGE_SAMPLE) {
+    if (L.n_sample) hipLaunchKernelGGL(kf_sample, dim3(L.n_sample), dim3(256), 0, s, L.fit, L.t_sample, round, eps);
+  } else if (stage == RTU_STAGE_ADAM) {
+    if (L.n_fit) hipLaunchKernelGGL(kf_elbo, dim3(L.n_fit), dim3(1024), 0, s, L.fit, L.t_fit, round);
+    if (L.n_param) hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(256), 0, s, L.fit, L.t_param, round, eps);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_sample(const FitDev& F, const float* eps, int step, hipStream_t s) {

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/rtu.h"
 
 namespace rtu {
@@ -29,6 +31,8 @@ struct SysDev {
   int ray_tx, ray_tiles;      // 16x16 ray tiles per side / per sample
   int psf_tx, psf_tiles;      // 64x16 PSF tiles along x / per sample
   int want_grad, batch;
+  int round0, nsteps;         // serving: rounds [round0, round0 + nsteps) are this system's steps
+  int lds_fwd, lds_adj;       // ray kernels stage the grid / its adjoint in LDS (1) or not (0)
   // observation (owned by the plan)
   const float* image;         // [N*N]
   const float* inv_var;       // [N*N] 1/sigma^2
@@ -66,8 +70,8 @@ struct SysDev {
   float* u;                   // [B][N^2] sub-ray mean image
   float* r;                   // [B][N^2] (m - d)/sigma^2
   float* ubar;                // [B][N^2] d loss / d u
-  float* sbar;                // [B][n^2] d loss / d s
-  float* kbar;                // [B][ray_tiles][4K] per-tile dX, dS partials
+  double* sbar;               // [B][n^2] d loss / d s (FP64 accumulation: order-independent to FP32 rounding)
+  double* kbar;               // [B][ray_tiles][4K] per-tile dX, dS partials
   double* lpart;              // [B][ray_tiles][n_lens] per-tile lens-gradient partials
   double* c2part;             // [B][psf_tiles][2] per-tile chi^2 partials (all, mask)
   uint32_t* st;               // [B][4] status words of the stages
@@ -76,6 +80,7 @@ struct SysDev {
 // One stochastic variational fit: guide, Adam state and per-sample buffers.
 struct FitDev {
   int S, dim, n_lens, n_src2;
+  int round0, nsteps;         // serving: step = round - round0, active while < nsteps
   float lr;
   uint32_t seed_lo, seed_hi;
   double elbo_const;          // data and prior normalisation + guide entropy constant
@@ -87,7 +92,12 @@ struct FitDev {
   uint32_t* status;           // [S]
   int* n_sub;                 // [S]
   double* trace;              // [max_steps] ELBO per step
+  uint32_t* status_acc;       // [1] OR of every sample status over all steps
 };
+
+// One work item of a shared (serving) launch: x = system/fit slot,
+// y = sample (or parameter block), z = tile / role / sample.
+using Task = int4;
 
 // kernel launchers (rtu_kernels.hip)
 hipError_t upload_constants();
@@ -99,5 +109,56 @@ hipError_t launch_post(const SysDev& h, int batch, hipStream_t s);
 // fit kernels (rtu_fit.hip)
 hipError_t launch_sample(const FitDev& F, const float* eps, int step, hipStream_t s);
 hipError_t launch_adam(const FitDev& F, const float* eps, int step, int t, hipStream_t s);
+
+// host helpers shared by plans, fits and the serving fleet (rtu_runtime.hip)
+struct ObsHost {
+  std::vector<int> idx;       // masked pixels, row-major
+  int rank_j[K];
+  double rank_t[K];
+  std::vector<float> inv_var, flip;
+};
+int ensure_constants(int device);
+bool valid_geometry(const rtu_geometry* g);
+void fill_geometry(const rtu_geometry* g, SysDev& h);
+size_t carve_workspace(SysDev& h, int B, char* base);
+size_t carve_observation(SysDev& h, int B, int M, char* base);
+size_t carve_fit(FitDev& F, int S, int max_steps, char* base);
+void prepare_observation(const rtu_geometry* g, const float* noise_sigma, const float* psf,
+                         const uint8_t* arc_mask, ObsHost& o);
+hipError_t upload_observation(const SysDev& h, const float* image, const float* psf, const uint8_t* arc_mask,
+                              const ObsHost& o, hipStream_t s);
+double elbo_constant(const std::vector<float>& inv_var, int n_src2, int dim);
+hipError_t init_fit_state(const FitDev& F, const float* mu0, const float* rho0, int n_sub, hipStream_t s);
+
+// LDS sizing shared by both launch paths
+size_t ray_lds_bytes(const SysDev& h, bool adjoint, bool lds_grid);
+bool ray_lds_grid(const SysDev& h, bool adjoint);
+size_t psf_lds_bytes(int KP);
+
+// shared launches over many systems (serving): one work item per task
+struct FleetLaunch {
+  const SysDev* sys;          // device [n_slots]
+  const FitDev* fit;          // device [n_slots]
+  const Task *t_prep, *t_psf, *t_post, *t_param, *t_sample, *t_fit;
+  int n_prep, n_psf, n_post, n_param, n_sample, n_fit;
+  // ray tiles split by LDS mode: [0] grid in LDS, [1] grid through L1/L2
+  const Task *t_fwd[2], *t_adj[2];
+  int n_fwd[2], n_adj[2];
+  size_t lds_rays_fwd, lds_rays_adj, lds_psf;
+};
+// One stage (RTU_STAGE_*) of a shared launch; eps (device [S][dim] per fit,
+// only for a single-fit table) replaces the Philox draws when not null.
+hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const float* eps, hipStream_t s);
+
+// Device copies of the descriptors and work lists of a set of systems/fits.
+struct DeviceTables {
+  SysDev* d_sys = nullptr;
+  FitDev* d_fit = nullptr;
+  Task* d_tasks = nullptr;
+  size_t cap_slots = 0, cap_tasks = 0;
+  // synchronous upload; the previous tables must no longer be in use
+  int upload(const std::vector<SysDev>& sys, const std::vector<FitDev>& fit, FleetLaunch& L);
+  void release();
+};
 
 }  // namespace rtu

@@ -306,8 +306,8 @@ __device__ void prep_gp(const SysDev& S, int b, unsigned char* smem) {
   const float* ps = S.ps + (size_t)b * 4;
   // zero the adjoint accumulator of this sample for the ray adjoint
   if (S.want_grad) {
-    float* sb = S.sbar + (size_t)b * n2;
-    for (int i = threadIdx.x; i < n2; i += blockDim.x) sb[i] = 0.f;
+    double* sb = S.sbar + (size_t)b * n2;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) sb[i] = 0.0;
   }
   // parameter domain
   if (threadIdx.x == 0) {
@@ -363,9 +363,10 @@ __global__ void __launch_bounds__(PREP_THREADS) k_prep(SysDev S) {
 // Source grid staged in LDS with a one-cell zero border:
 // padded index (i + 1) * (n + 2) + (j + 1) for i, j in [-1, n].
 struct RayLdsHead {
+  double kb[4 * K];  // knot adjoint: dX (x), dS (x), dX (y), dS (y)
   float X[2][K], Sl[2][K], ih[2][K], dp[2][K];
-  float kb[4 * K];   // dX (x), dS (x), dX (y), dS (y)
   Nfw nfw[RTU_MAX_SUB];
+  float pad[2];
 };
 
 __device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H) {
@@ -382,7 +383,7 @@ __device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H
     H.Sl[ax][k] = kn[ax * 2 * K + K + k];
     H.dp[ax][k] = dp[i];
   }
-  for (int i = threadIdx.x; i < 4 * K; i += blockDim.x) H.kb[i] = 0.f;
+  for (int i = threadIdx.x; i < 4 * K; i += blockDim.x) H.kb[i] = 0.0;
   for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
     const int ax = i / K, k = i - ax * K;
     H.ih[ax][k] = k < K - 1 ? 1.f / (kn[ax * 2 * K + k + 1] - kn[ax * 2 * K + k]) : 0.f;
@@ -478,11 +479,13 @@ template <bool LDSGRID>
 __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* smem) {
   RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
   const int n = S.n_src, np = n + 2;
-  // the source grid is read through L1/L2 here; only d loss / d s lives in LDS
-  float* g = reinterpret_cast<float*>(smem + sizeof(RayLdsHead));
-  float* gb = g;                                           // d loss / d s (padded)
-  float* subacc = gb + (LDSGRID ? np * np : 0);            // [4 n_sub_max][256] per-thread
-  size_t off = sizeof(RayLdsHead) + (size_t)(LDSGRID ? 1 * np * np : 0) * 4 +
+  // the source grid is read through L1/L2 here; only d loss / d s lives in LDS,
+  // accumulated in FP64 so that its value does not depend on the order of the
+  // atomic additions (to FP32 rounding)
+  const float* g = nullptr;
+  double* gb = reinterpret_cast<double*>(smem + sizeof(RayLdsHead));          // padded grid
+  float* subacc = reinterpret_cast<float*>(gb + (LDSGRID ? np * np : 0));    // [4 n_sub_max][256]
+  size_t off = sizeof(RayLdsHead) + (size_t)(LDSGRID ? np * np : 0) * 8 +
                (size_t)4 * S.n_sub_max * RAY_THREADS * 4;
   off = (off + 15) & ~(size_t)15;
   double* red = reinterpret_cast<double*>(smem + off);     // [8 * 4]
@@ -491,7 +494,7 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   const int i = ti * RAY_TILE + (threadIdx.x >> 4), j = tj * RAY_TILE + (threadIdx.x & 15);
   load_knots(S, b, H);
   if (LDSGRID)
-    for (int q = threadIdx.x; q < np * np; q += blockDim.x) gb[q] = 0.f;
+    for (int q = threadIdx.x; q < np * np; q += blockDim.x) gb[q] = 0.0;
   for (int q = threadIdx.x; q < 4 * S.n_sub_max * RAY_THREADS; q += blockDim.x) subacc[q] = 0.f;
   if (threadIdx.x == 0) { bbox[0] = bbox[1] = 1 << 30; bbox[2] = bbox[3] = -(1 << 30); }
   __syncthreads();
@@ -499,7 +502,7 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   const int nsub = n_sub_of(S, b);
   const Sie L = make_sie(lensp);
   const float* gsrc = S.src + (size_t)b * n * n;
-  float* gsb = S.sbar + (size_t)b * n * n;
+  double* gsb = S.sbar + (size_t)b * n * n;
   SieAcc acc;
   acc.zero();
   int bi0 = 1 << 30, bj0 = 1 << 30, bi1 = -(1 << 30), bj1 = -(1 << 30);
@@ -516,14 +519,14 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
       if (ci < -1) return;
       if (LDSGRID) {
         const int p = (ci + 1) * np + (cj + 1);
-        atomicAdd(&gb[p], c00);
-        atomicAdd(&gb[p + 1], c01);
-        atomicAdd(&gb[p + np], c10);
-        atomicAdd(&gb[p + np + 1], c11);
+        atomicAdd(&gb[p], (double)c00);
+        atomicAdd(&gb[p + 1], (double)c01);
+        atomicAdd(&gb[p + np], (double)c10);
+        atomicAdd(&gb[p + np + 1], (double)c11);
         bi0 = min(bi0, ci); bj0 = min(bj0, cj); bi1 = max(bi1, ci + 1); bj1 = max(bj1, cj + 1);
       } else {
         auto add = [&](int ii, int jj, float v) {
-          if (ii >= 0 && ii < n && jj >= 0 && jj < n) atomicAdd(&gsb[ii * n + jj], v);
+          if (ii >= 0 && ii < n && jj >= 0 && jj < n) atomicAdd(&gsb[ii * n + jj], (double)v);
         };
         add(ci, cj, c00); add(ci, cj + 1, c01); add(ci + 1, cj, c10); add(ci + 1, cj + 1, c11);
       }
@@ -602,7 +605,7 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
     if ((threadIdx.x & 63) == 0) lp[RTU_N_LENS_BASE + q] = (double)s;
   }
   // knot partials of this tile
-  float* kbo = S.kbar + ((size_t)b * S.ray_tiles + tile) * 4 * K;
+  double* kbo = S.kbar + ((size_t)b * S.ray_tiles + tile) * 4 * K;
   for (int q = threadIdx.x; q < 4 * K; q += blockDim.x) kbo[q] = H.kb[q];
   // d loss / d s: add the touched window of the LDS grid to the sample's grid
   if (LDSGRID) {
@@ -611,8 +614,8 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
     if (wj > 0 && wi > 0) {
       for (int q = threadIdx.x; q < wi * wj; q += blockDim.x) {
         const int ii = i0 + q / wj, jj = j0 + q % wj;
-        const float v = gb[(ii + 1) * np + jj + 1];
-        if (v != 0.f) atomicAdd(&gsb[ii * n + jj], v);
+        const double v = gb[(ii + 1) * np + jj + 1];
+        if (v != 0.0) atomicAdd(&gsb[ii * n + jj], v);
       }
     }
   }
@@ -629,24 +632,67 @@ __global__ void __launch_bounds__(RAY_THREADS) k_rays_adj(SysDev S) {
 // out[i, j] = sum_{a,b} W[a, b] in[i + a - h, j + b - h] (zero outside), h = (KP-1)/2.
 // Forward: in = u, W = flipped PSF (a convolution), also r = (m - d)/sigma^2 and
 // chi^2 partials.  Adjoint: in = r, W = PSF (the transpose of the convolution).
-template <int KP>
-__global__ void __launch_bounds__(PSF_THREADS) k_psf(SysDev S, int adjoint) {
-  constexpr int HW = PSF_TW + KP - 1;
-  constexpr int LS = (HW + 3) & ~3;              // row stride, multiple of 4 floats
-  constexpr int HH = PSF_TH + KP - 1;
-  __shared__ __align__(16) float tilein[HH * LS];
-  __shared__ double red[2 * 4];
+__device__ __forceinline__ int psf_row_stride(int KP) { return (PSF_TW + KP - 1 + 3) & ~3; }
+
+// residual, model and chi^2 partials of 4 output pixels (forward), or the
+// adjoint image (adjoint), then the tile's FP64 chi^2 sums
+__device__ __forceinline__ void psf_epilogue(const SysDev& S, int b, int tile, int adjoint, int ty0, int tx0,
+                                             int ly, int lx, const float (&acc)[4], double* red) {
+  const int N = S.n_img;
+  const int gi = ty0 + ly;
+  double c2 = 0.0, c2m = 0.0;
+  if (gi < N) {
+    for (int q = 0; q < 4; ++q) {
+      const int gj = tx0 + lx + q;
+      if (gj >= N) break;
+      const size_t p = (size_t)b * N * N + gi * N + gj;
+      if (adjoint) {
+        S.ubar[p] = acc[q];
+      } else {
+        const int pi = gi * N + gj;
+        const float res = acc[q] - S.image[pi];
+        const float iv = S.inv_var[pi];
+        S.r[p] = res * iv;
+        if (S.model) S.model[p] = acc[q];
+        const double e = (double)res * (double)res * (double)iv;
+        c2 += e;
+        if (S.mask[pi]) c2m += e;
+      }
+    }
+  }
+  if (!adjoint) {
+    double v[2] = {c2, c2m};
+    block_sum<2>(v, red);
+    if (threadIdx.x == 0) {
+      double* o = S.c2part + ((size_t)b * S.psf_tiles + tile) * 2;
+      o[0] = v[0];
+      o[1] = v[1];
+    }
+  }
+}
+
+__device__ __forceinline__ void psf_load_tile(const SysDev& S, int b, int adjoint, int KP, int ty0, int tx0,
+                                              float* tilein) {
   const int N = S.n_img, h = KP / 2;
-  const int b = blockIdx.x / S.psf_tiles, tile = blockIdx.x - b * S.psf_tiles;
-  const int ty0 = (tile / S.psf_tx) * PSF_TH, tx0 = (tile % S.psf_tx) * PSF_TW;
+  const int HW = PSF_TW + KP - 1, LS = psf_row_stride(KP), HH = PSF_TH + KP - 1;
   const float* in = (adjoint ? S.r : S.u) + (size_t)b * N * N;
-  const float* W = adjoint ? S.psf : S.psf_flip;
   for (int q = threadIdx.x; q < HH * LS; q += blockDim.x) {
     const int rr = q / LS, cc = q - rr * LS;
     const int gi = ty0 + rr - h, gj = tx0 + cc - h;
     tilein[q] = (cc < HW && gi >= 0 && gi < N && gj >= 0 && gj < N) ? in[gi * N + gj] : 0.f;
   }
   __syncthreads();
+}
+
+// out[i, j] = sum_{a,b} W[a, b] in[i + a - h, j + b - h] (zero outside), h = (KP-1)/2.
+// Forward: in = u, W = flipped PSF (a convolution), also r = (m - d)/sigma^2 and
+// chi^2 partials.  Adjoint: in = r, W = PSF (the transpose of the convolution).
+template <int KP>
+__device__ void psf_body(const SysDev& S, int b, int tile, int adjoint, float* tilein, double* red) {
+  constexpr int LS = (PSF_TW + KP - 1 + 3) & ~3;
+  const int ty0 = (tile / S.psf_tx) * PSF_TH, tx0 = (tile % S.psf_tx) * PSF_TW;
+  const float* W = adjoint ? S.psf : S.psf_flip;
+  psf_load_tile(S, b, adjoint, KP, ty0, tx0, tilein);
   const int ly = threadIdx.x >> 4, lx = (threadIdx.x & 15) * 4;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
@@ -664,54 +710,15 @@ __global__ void __launch_bounds__(PSF_THREADS) k_psf(SysDev S, int adjoint) {
       acc[3] = fmaf(wv, win[c + 3], acc[3]);
     }
   }
-  const int gi = ty0 + ly;
-  double c2 = 0.0, c2m = 0.0;
-  if (gi < N) {
-    for (int q = 0; q < 4; ++q) {
-      const int gj = tx0 + lx + q;
-      if (gj >= N) break;
-      const size_t p = (size_t)b * N * N + gi * N + gj;
-      if (adjoint) {
-        S.ubar[p] = acc[q];
-      } else {
-        const int pi = gi * N + gj;
-        const float res = acc[q] - S.image[pi];
-        const float iv = S.inv_var[pi];
-        S.r[p] = res * iv;
-        if (S.model) S.model[p] = acc[q];
-        const double e = (double)res * (double)res * (double)iv;
-        c2 += e;
-        if (S.mask[pi]) c2m += e;
-      }
-    }
-  }
-  if (!adjoint) {
-    double v[2] = {c2, c2m};
-    block_sum<2>(v, red);
-    if (threadIdx.x == 0) {
-      double* o = S.c2part + ((size_t)b * S.psf_tiles + tile) * 2;
-      o[0] = v[0];
-      o[1] = v[1];
-    }
-  }
+  psf_epilogue(S, b, tile, adjoint, ty0, tx0, ly, lx, acc, red);
 }
 
-// generic PSF size: direct LDS reads
-__global__ void __launch_bounds__(PSF_THREADS) k_psf_any(SysDev S, int adjoint) {
-  extern __shared__ __align__(16) float tilein[];
-  __shared__ double red[2 * 4];
-  const int N = S.n_img, KP = S.psf_k, h = KP / 2;
-  const int HW = PSF_TW + KP - 1, LS = (HW + 3) & ~3, HH = PSF_TH + KP - 1;
-  const int b = blockIdx.x / S.psf_tiles, tile = blockIdx.x - b * S.psf_tiles;
+// any PSF size: direct LDS reads
+__device__ void psf_any_body(const SysDev& S, int b, int tile, int adjoint, float* tilein, double* red) {
+  const int KP = S.psf_k, LS = psf_row_stride(KP);
   const int ty0 = (tile / S.psf_tx) * PSF_TH, tx0 = (tile % S.psf_tx) * PSF_TW;
-  const float* in = (adjoint ? S.r : S.u) + (size_t)b * N * N;
   const float* W = adjoint ? S.psf : S.psf_flip;
-  for (int q = threadIdx.x; q < HH * LS; q += blockDim.x) {
-    const int rr = q / LS, cc = q - rr * LS;
-    const int gi = ty0 + rr - h, gj = tx0 + cc - h;
-    tilein[q] = (cc < HW && gi >= 0 && gi < N && gj >= 0 && gj < N) ? in[gi * N + gj] : 0.f;
-  }
-  __syncthreads();
+  psf_load_tile(S, b, adjoint, KP, ty0, tx0, tilein);
   const int ly = threadIdx.x >> 4, lx = (threadIdx.x & 15) * 4;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   for (int a = 0; a < KP; ++a) {
@@ -724,36 +731,24 @@ __global__ void __launch_bounds__(PSF_THREADS) k_psf_any(SysDev S, int adjoint) 
       acc[3] = fmaf(wv, row[c + 3], acc[3]);
     }
   }
-  const int gi = ty0 + ly;
-  double c2 = 0.0, c2m = 0.0;
-  if (gi < N) {
-    for (int q = 0; q < 4; ++q) {
-      const int gj = tx0 + lx + q;
-      if (gj >= N) break;
-      const size_t p = (size_t)b * N * N + gi * N + gj;
-      if (adjoint) {
-        S.ubar[p] = acc[q];
-      } else {
-        const int pi = gi * N + gj;
-        const float res = acc[q] - S.image[pi];
-        const float iv = S.inv_var[pi];
-        S.r[p] = res * iv;
-        if (S.model) S.model[p] = acc[q];
-        const double e = (double)res * (double)res * (double)iv;
-        c2 += e;
-        if (S.mask[pi]) c2m += e;
-      }
-    }
+  psf_epilogue(S, b, tile, adjoint, ty0, tx0, ly, lx, acc, red);
+}
+
+__device__ __forceinline__ void psf_dispatch(const SysDev& S, int b, int tile, int adjoint, float* tilein,
+                                             double* red) {
+  switch (S.psf_k) {
+    case 15: psf_body<15>(S, b, tile, adjoint, tilein, red); break;
+    case 21: psf_body<21>(S, b, tile, adjoint, tilein, red); break;
+    case 31: psf_body<31>(S, b, tile, adjoint, tilein, red); break;
+    default: psf_any_body(S, b, tile, adjoint, tilein, red);
   }
-  if (!adjoint) {
-    double v[2] = {c2, c2m};
-    block_sum<2>(v, red);
-    if (threadIdx.x == 0) {
-      double* o = S.c2part + ((size_t)b * S.psf_tiles + tile) * 2;
-      o[0] = v[0];
-      o[1] = v[1];
-    }
-  }
+}
+
+__global__ void __launch_bounds__(PSF_THREADS) k_psf(SysDev S, int adjoint) {
+  extern __shared__ __align__(16) float tilein[];
+  __shared__ double red[2 * 4];
+  const int b = blockIdx.x / S.psf_tiles;
+  psf_dispatch(S, b, blockIdx.x - b * S.psf_tiles, adjoint, tilein, red);
 }
 
 // ====================================================================== k_post
@@ -764,10 +759,8 @@ struct PostLds {
   uint32_t stat;
 };
 
-__global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S) {
-  __shared__ __align__(16) unsigned char fft_smem[FFT_LDS_FLOAT2 * 8];
-  __shared__ PostLds P;
-  const int b = blockIdx.x, tid = threadIdx.x;
+__device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, PostLds& P) {
+  const int tid = threadIdx.x;
   const int n = S.n_src, n2 = n * n, logn = S.log2_src;
   const int nl = S.n_lens;
   if (tid == 0) P.stat = 0;
@@ -863,7 +856,7 @@ __global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S) {
     const float* ps = S.ps + (size_t)b * 4;
     const Matern mt = make_matern(ps);
     const float alpha = ps[3];
-    const float* sb = S.sbar + (size_t)b * n2;
+    const double* sb = S.sbar + (size_t)b * n2;
     const float* fo = S.fld + (size_t)b * n2;
     const float* so = S.src + (size_t)b * n2;
     const float2* F = S.F + (size_t)b * n2;
@@ -880,8 +873,9 @@ __global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S) {
                const float s = so[q];
                const float lsp = log_softplus_f(x);
                const float ratio = __expf(-softplus_f(-x) - lsp);   // sigmoid/softplus
-               pacc[3] += (double)sb[q] * s * (-4.605170186f + lsp);
-               return make_float2(sb[q] * alpha * s * ratio * 100.f, 0.f);
+               const float sbq = (float)sb[q];
+               pacc[3] += (double)sbq * s * (-4.605170186f + lsp);
+               return make_float2(sbq * alpha * s * ratio * 100.f, 0.f);
              },
              [&](int, int, float2 v) { return v; },
              [&](int r, int c, float2 v) { T[r * n + c] = v; });
@@ -921,6 +915,12 @@ __global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S) {
   }
   __syncthreads();
   if (tid == 0) S.status[b] = P.stat | S.st[b * 4 + 0] | S.st[b * 4 + 1] | S.st[b * 4 + 2];
+}
+
+__global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S) {
+  __shared__ __align__(16) unsigned char fft_smem[FFT_LDS_FLOAT2 * 8];
+  __shared__ PostLds P;
+  post_body(S, blockIdx.x, fft_smem, P);
 }
 
 // ====================================================================== launchers
@@ -965,18 +965,18 @@ hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
 
 // The source grid (and its adjoint) are staged in LDS when the grid is at most
 // GRID_LDS_MAX per side and the workgroup's LDS stays within 64 KB.
-static size_t ray_lds_bytes(const SysDev& h, bool adjoint, bool lds_grid) {
+size_t ray_lds_bytes(const SysDev& h, bool adjoint, bool lds_grid) {
   const size_t np = (size_t)(h.n_src + 2);
   size_t bytes = sizeof(RayLdsHead) + (lds_grid ? np * np * 4 : 0);
   if (adjoint) {
-    // the adjoint keeps d loss / d s (not the source grid) in LDS
-    bytes += (size_t)4 * h.n_sub_max * RAY_THREADS * 4;
+    // the adjoint keeps d loss / d s (FP64, not the source grid) in LDS
+    bytes = sizeof(RayLdsHead) + (lds_grid ? np * np * 8 : 0) + (size_t)4 * h.n_sub_max * RAY_THREADS * 4;
     bytes = (bytes + 15) & ~(size_t)15;
     bytes += 8 * 4 * 8 + 16;
   }
   return bytes;
 }
-static bool ray_lds_grid(const SysDev& h, bool adjoint) {
+bool ray_lds_grid(const SysDev& h, bool adjoint) {
   return h.n_src <= GRID_LDS_MAX && ray_lds_bytes(h, adjoint, true) <= 65536;
 }
 
@@ -1000,18 +1000,14 @@ hipError_t launch_rays_adj(const SysDev& h, int batch, hipStream_t s) {
   return hipGetLastError();
 }
 
+size_t psf_lds_bytes(int KP) {
+  const int HW = PSF_TW + KP - 1, LS = (HW + 3) & ~3, HH = PSF_TH + KP - 1;
+  return (size_t)HH * LS * 4;
+}
+
 hipError_t launch_psf(const SysDev& h, int batch, bool adjoint, hipStream_t s) {
-  const dim3 g(batch * h.psf_tiles), blk(PSF_THREADS);
-  const int adj = adjoint ? 1 : 0;
-  switch (h.psf_k) {
-    case 15: hipLaunchKernelGGL(k_psf<15>, g, blk, 0, s, h, adj); break;
-    case 21: hipLaunchKernelGGL(k_psf<21>, g, blk, 0, s, h, adj); break;
-    case 31: hipLaunchKernelGGL(k_psf<31>, g, blk, 0, s, h, adj); break;
-    default: {
-      const int HW = PSF_TW + h.psf_k - 1, LS = (HW + 3) & ~3, HH = PSF_TH + h.psf_k - 1;
-      hipLaunchKernelGGL(k_psf_any, g, blk, (size_t)HH * LS * 4, s, h, adj);
-    }
-  }
+  hipLaunchKernelGGL(k_psf, dim3(batch * h.psf_tiles), dim3(PSF_THREADS), psf_lds_bytes(h.psf_k), s, h,
+                     adjoint ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -1020,5 +1016,101 @@ hipError_t launch_post(const SysDev& h, int batch, hipStream_t s) {
   return hipGetLastError();
 }
 
+
+// ====================================================================== shared launches
+// Serving: every work item names its system; systems outside their step
+// window skip.  The bodies are the ones of the single-system kernels.
+__device__ __forceinline__ bool sys_active(const SysDev& S, int round) {
+  const int st = round - S.round0;
+  return st >= 0 && st < S.nsteps;
+}
+
+__global__ void __launch_bounds__(PREP_THREADS) kf_prep(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
+                                                      int round) {
+  __shared__ __align__(16) unsigned char smem[PREP_LDS];
+  const Task t = tasks[blockIdx.x];
+  const SysDev S = sys[t.x];
+  if (!sys_active(S, round)) return;
+  if (t.z < 2) prep_select(S, t.y, t.z, smem);
+  else prep_gp(S, t.y, smem);
+}
+
+template <bool LDSGRID>
+__global__ void __launch_bounds__(RAY_THREADS) kf_rays_fwd(const SysDev* __restrict__ sys,
+                                                           const Task* __restrict__ tasks, int round) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Task t = tasks[blockIdx.x];
+  const SysDev S = sys[t.x];
+  if (!sys_active(S, round)) return;
+  rays_fwd_body<LDSGRID>(S, t.y, t.z, smem);
+}
+
+template <bool LDSGRID>
+__global__ void __launch_bounds__(RAY_THREADS) kf_rays_adj(const SysDev* __restrict__ sys,
+                                                           const Task* __restrict__ tasks, int round) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Task t = tasks[blockIdx.x];
+  const SysDev S = sys[t.x];
+  if (!sys_active(S, round)) return;
+  rays_adj_body<LDSGRID>(S, t.y, t.z, smem);
+}
+
+__global__ void __launch_bounds__(PSF_THREADS) kf_psf(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
+                                                    int round, int adjoint) {
+  extern __shared__ __align__(16) float tilein[];
+  __shared__ double red[2 * 4];
+  const Task t = tasks[blockIdx.x];
+  const SysDev S = sys[t.x];
+  if (!sys_active(S, round)) return;
+  psf_dispatch(S, t.y, t.z, adjoint, tilein, red);
+}
+
+__global__ void __launch_bounds__(PREP_THREADS) kf_post(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
+                                                      int round) {
+  __shared__ __align__(16) unsigned char fft_smem[FFT_LDS_FLOAT2 * 8];
+  __shared__ PostLds P;
+  const Task t = tasks[blockIdx.x];
+  const SysDev S = sys[t.x];
+  if (!sys_active(S, round)) return;
+  post_body(S, t.y, fft_smem, P);
+}
+
+hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, const float* eps, hipStream_t s);
+
+hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const float* eps, hipStream_t s) {
+  switch (stage) {
+    case RTU_STAGE_PREP:
+      if (L.n_prep) hipLaunchKernelGGL(kf_prep, dim3(L.n_prep), dim3(PREP_THREADS), 0, s, L.sys, L.t_prep, round);
+      break;
+    case RTU_STAGE_RAYS_FWD:
+      if (L.n_fwd[0])
+        hipLaunchKernelGGL(kf_rays_fwd<true>, dim3(L.n_fwd[0]), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys,
+                           L.t_fwd[0], round);
+      if (L.n_fwd[1])
+        hipLaunchKernelGGL(kf_rays_fwd<false>, dim3(L.n_fwd[1]), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys,
+                           L.t_fwd[1], round);
+      break;
+    case RTU_STAGE_PSF_FWD:
+    case RTU_STAGE_PSF_ADJ:
+      if (L.n_psf)
+        hipLaunchKernelGGL(kf_psf, dim3(L.n_psf), dim3(PSF_THREADS), L.lds_psf, s, L.sys, L.t_psf, round,
+                           stage == RTU_STAGE_PSF_ADJ ? 1 : 0);
+      break;
+    case RTU_STAGE_RAYS_ADJ:
+      if (L.n_adj[0])
+        hipLaunchKernelGGL(kf_rays_adj<true>, dim3(L.n_adj[0]), dim3(RAY_THREADS), L.lds_rays_adj, s, L.sys,
+                           L.t_adj[0], round);
+      if (L.n_adj[1])
+        hipLaunchKernelGGL(kf_rays_adj<false>, dim3(L.n_adj[1]), dim3(RAY_THREADS), L.lds_rays_adj, s, L.sys,
+                           L.t_adj[1], round);
+      break;
+    case RTU_STAGE_POST:
+      if (L.n_post) hipLaunchKernelGGL(kf_post, dim3(L.n_post), dim3(PREP_THREADS), 0, s, L.sys, L.t_post, round);
+      break;
+    default:
+      return launch_fleet_fit_stage(L, stage, round, eps, s);
+  }
+  return hipGetLastError();
+}
 
 }  // namespace rtu

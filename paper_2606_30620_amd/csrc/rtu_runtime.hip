@@ -32,6 +32,7 @@ struct rtu_plan_s {
   SysDev last;                    // descriptor of the last evaluation (debug fetch)
   bool have_last = false;
   Prof prof;
+  std::vector<float> inv_var;     // host copy of 1/sigma^2 (ELBO constant)
 };
 
 struct rtu_fit_s {
@@ -40,9 +41,13 @@ struct rtu_fit_s {
   char* pool = nullptr;
   int max_steps = 0, steps = 0;
   int n_sub = 0;
+  // the fit runs the shared-launch kernels of the serving fleet on a one-fit
+  // table, so a fit alone and a fit in a fleet execute the same code
+  DeviceTables tables;
+  FleetLaunch L{};
 };
 
-namespace {
+namespace rtu {
 
 std::mutex g_const_mu;
 std::vector<int> g_const_done;    // devices whose constant tables are uploaded
@@ -83,6 +88,8 @@ struct Carve {
 
 void fill_geometry(const rtu_geometry* g, SysDev& h) {
   memset(&h, 0, sizeof(h));
+  h.round0 = 0;
+  h.nsteps = 0x7fffffff;
   h.n_img = g->n_img;
   h.ss = g->supersample;
   h.n_src = g->n_src;
@@ -117,8 +124,8 @@ size_t carve_workspace(SysDev& h, int B, char* base) {
   h.u = c.take<float>(B * N2);
   h.r = c.take<float>(B * N2);
   h.ubar = c.take<float>(B * N2);
-  h.sbar = c.take<float>(B * n2);
-  h.kbar = c.take<float>((size_t)B * h.ray_tiles * 4 * K);
+  h.sbar = c.take<double>(B * n2);
+  h.kbar = c.take<double>((size_t)B * h.ray_tiles * 4 * K);
   h.lpart = c.take<double>((size_t)B * h.ray_tiles * h.n_lens);
   h.c2part = c.take<double>((size_t)B * h.psf_tiles * 2);
   h.st = c.take<uint32_t>((size_t)B * 4);
@@ -141,6 +148,89 @@ size_t carve_observation(SysDev& h, int B, int M, char* base) {
   h.cand = c.take<unsigned long long>((size_t)B * 2 * (M > 0 ? M : 1));
   return c.off + 256;
 }
+
+// Host side of an observation: masked pixel list, quantile ranks
+// h_k = (M-1) u_k in FP64, inverse variances and the flipped PSF.
+void prepare_observation(const rtu_geometry* g, const float* noise_sigma, const float* psf,
+                         const uint8_t* arc_mask, ObsHost& o) {
+  const int N = g->n_img, KP = g->psf_size;
+  const size_t N2 = (size_t)N * N;
+  o.idx.clear();
+  for (size_t q = 0; q < N2; ++q)
+    if (arc_mask[q]) o.idx.push_back((int)q);
+  const int M = (int)o.idx.size();
+  for (int k = 0; k < K; ++k) {
+    const double u = 0.5 * (1.0 - cos((2.0 * (k + 1) - 1.0) * M_PI / (2.0 * K)));
+    const double hh = (double)(M > 0 ? M - 1 : 0) * u;
+    const double fl = floor(hh);
+    o.rank_j[k] = (int)fl;
+    o.rank_t[k] = hh - fl;
+  }
+  o.inv_var.resize(N2);
+  for (size_t q = 0; q < N2; ++q) o.inv_var[q] = 1.f / (noise_sigma[q] * noise_sigma[q]);
+  o.flip.resize((size_t)KP * KP);
+  for (int a = 0; a < KP; ++a)
+    for (int b = 0; b < KP; ++b) o.flip[(size_t)a * KP + b] = psf[(size_t)(KP - 1 - a) * KP + (KP - 1 - b)];
+}
+
+hipError_t upload_observation(const SysDev& h, const float* image, const float* psf, const uint8_t* arc_mask,
+                              const ObsHost& o, hipStream_t s) {
+  const size_t N2 = (size_t)h.n_img * h.n_img, k2 = (size_t)h.psf_k * h.psf_k;
+  hipError_t e = hipSuccess;
+  auto cp = [&](const void* dst, const void* src, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpyAsync(const_cast<void*>(dst), src, n, hipMemcpyHostToDevice, s);
+  };
+  cp(h.image, image, N2 * 4);
+  cp(h.inv_var, o.inv_var.data(), N2 * 4);
+  cp(h.psf_flip, o.flip.data(), k2 * 4);
+  cp(h.psf, psf, k2 * 4);
+  cp(h.mask, arc_mask, N2);
+  cp(h.mask_idx, o.idx.data(), o.idx.size() * 4);
+  cp(h.rank_j, o.rank_j, sizeof(o.rank_j));
+  cp(h.rank_t, o.rank_t, sizeof(o.rank_t));
+  return e;
+}
+
+// Fit state of S samples: guide, Adam moments, sample and gradient buffers.
+size_t carve_fit(FitDev& F, int S, int max_steps, char* base) {
+  Carve cv{base};
+  F.mu = cv.take<float>(F.dim); F.rho = cv.take<float>(F.dim);
+  F.m_mu = cv.take<float>(F.dim); F.v_mu = cv.take<float>(F.dim);
+  F.m_rho = cv.take<float>(F.dim); F.v_rho = cv.take<float>(F.dim);
+  F.z_lens = cv.take<float>((size_t)S * F.n_lens); F.z_ps = cv.take<float>((size_t)S * 4);
+  F.z_lat = cv.take<float>((size_t)S * F.n_src2);
+  F.g_lens = cv.take<float>((size_t)S * F.n_lens); F.g_ps = cv.take<float>((size_t)S * 4);
+  F.g_lat = cv.take<float>((size_t)S * F.n_src2);
+  F.loss = cv.take<double>(S); F.chi2m = cv.take<double>(S);
+  F.status = cv.take<uint32_t>(S); F.n_sub = cv.take<int>(S);
+  F.trace = cv.take<double>(max_steps);
+  F.status_acc = cv.take<uint32_t>(1);
+  return cv.off + 256;
+}
+
+// ELBO constant: -sum_p ln(sigma_p sqrt(2 pi)) - (n^2/2) ln 2 pi + (dim/2)(1 + ln 2 pi)
+double elbo_constant(const std::vector<float>& inv_var, int n_src2, int dim) {
+  double c = 0.0;
+  for (float v : inv_var) c += 0.5 * log((double)v) - 0.5 * log(2.0 * M_PI);
+  return c - 0.5 * n_src2 * log(2.0 * M_PI) + 0.5 * dim * (1.0 + log(2.0 * M_PI));
+}
+
+// Initial fit state on the device: mu, rho, zero moments, n_sub per sample.
+hipError_t init_fit_state(const FitDev& F, const float* mu0, const float* rho0, int n_sub, hipStream_t s) {
+  std::vector<int> ns(F.S, n_sub);
+  hipError_t e = hipMemcpyAsync(F.mu, mu0, (size_t)F.dim * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(F.rho, rho0, (size_t)F.dim * 4, hipMemcpyHostToDevice, s);
+  float* z[4] = {F.m_mu, F.v_mu, F.m_rho, F.v_rho};
+  for (int k = 0; k < 4 && e == hipSuccess; ++k) e = hipMemsetAsync(z[k], 0, (size_t)F.dim * 4, s);
+  if (e == hipSuccess && F.status_acc) e = hipMemsetAsync(F.status_acc, 0, 4, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(F.n_sub, ns.data(), (size_t)F.S * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host vector above must outlive the copy
+  return e;
+}
+
+}  // namespace rtu
+
+namespace {
 
 void prof_call_begin(rtu_plan p) {
   Prof& P = p->prof;
@@ -233,26 +323,9 @@ int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma
                         const uint8_t* arc_mask) {
   if (!p || !image || !noise_sigma || !psf || !arc_mask) return RTU_EINVAL;
   if (hipSetDevice(p->device) != hipSuccess) return RTU_EHIP;
-  const int N = p->g.n_img, KP = p->g.psf_size;
-  const size_t N2 = (size_t)N * N;
-  std::vector<int> idx;
-  for (size_t q = 0; q < N2; ++q)
-    if (arc_mask[q]) idx.push_back((int)q);
-  const int M = (int)idx.size();
-  // quantile ranks of the Chebyshev nodes: h_k = (M-1) u_k in FP64
-  int rj[K];
-  double rt[K];
-  for (int k = 0; k < K; ++k) {
-    const double u = 0.5 * (1.0 - cos((2.0 * (k + 1) - 1.0) * M_PI / (2.0 * K)));
-    const double hh = (double)(M > 0 ? M - 1 : 0) * u;
-    const double fl = floor(hh);
-    rj[k] = (int)fl;
-    rt[k] = hh - fl;
-  }
-  std::vector<float> iv(N2), flip((size_t)KP * KP);
-  for (size_t q = 0; q < N2; ++q) iv[q] = 1.f / (noise_sigma[q] * noise_sigma[q]);
-  for (int a = 0; a < KP; ++a)
-    for (int b = 0; b < KP; ++b) flip[(size_t)a * KP + b] = psf[(size_t)(KP - 1 - a) * KP + (KP - 1 - b)];
+  ObsHost o;
+  prepare_observation(&p->g, noise_sigma, psf, arc_mask, o);
+  const int M = (int)o.idx.size();
   SysDev h = p->h;
   const size_t bytes = carve_observation(h, p->max_batch, M, nullptr);
   if (bytes > p->obs_bytes) {
@@ -264,22 +337,12 @@ int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma
     p->obs_bytes = bytes;
   }
   carve_observation(h, p->max_batch, M, p->obs_pool);
-  hipError_t e = hipSuccess;
-  auto cp = [&](const void* dst, const void* src, size_t n) {
-    if (e == hipSuccess && n) e = hipMemcpy(const_cast<void*>(dst), src, n, hipMemcpyHostToDevice);
-  };
-  cp(h.image, image, N2 * 4);
-  cp(h.inv_var, iv.data(), N2 * 4);
-  cp(h.psf_flip, flip.data(), (size_t)KP * KP * 4);
-  cp(h.psf, psf, (size_t)KP * KP * 4);
-  cp(h.mask, arc_mask, N2);
-  cp(h.mask_idx, idx.data(), (size_t)M * 4);
-  cp(h.rank_j, rj, sizeof(rj));
-  cp(h.rank_t, rt, sizeof(rt));
-  if (e != hipSuccess) return RTU_EHIP;
+  if (upload_observation(h, image, psf, arc_mask, o, nullptr) != hipSuccess) return RTU_EHIP;
+  if (hipDeviceSynchronize() != hipSuccess) return RTU_EHIP;
   h.M = M;
   p->h = h;
   p->M = M;
+  p->inv_var = o.inv_var;
   return RTU_OK;
 }
 
@@ -400,50 +463,39 @@ int rtu_fit_create(rtu_plan p, int32_t samples, const float* mu0, const float* r
   F.lr = lr;
   F.seed_lo = (uint32_t)seed;
   F.seed_hi = (uint32_t)(seed >> 32);
-  // -sum_p ln(sigma_p sqrt(2 pi)) - (n^2/2) ln 2 pi + (dim/2)(1 + ln 2 pi)
-  std::vector<float> iv((size_t)p->g.n_img * p->g.n_img);
-  if (hipMemcpy(iv.data(), p->h.inv_var, iv.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+  F.round0 = 0;
+  F.nsteps = max_steps;
+  F.elbo_const = elbo_constant(p->inv_var, n2, F.dim);
+  const size_t bytes = carve_fit(F, S, max_steps, nullptr);
+  if (hipMalloc(&f->pool, bytes) != hipSuccess) {
     delete f;
-    return RTU_EHIP;
+    return RTU_ENOMEM;
   }
-  double c = 0.0;
-  for (float v : iv) c += 0.5 * log((double)v) - 0.5 * log(2.0 * M_PI);
-  c += -0.5 * n2 * log(2.0 * M_PI) + 0.5 * F.dim * (1.0 + log(2.0 * M_PI));
-  F.elbo_const = c;
-  Carve cv{nullptr};
-  for (int pass = 0; pass < 2; ++pass) {
-    cv.off = 0;
-    F.mu = cv.take<float>(F.dim); F.rho = cv.take<float>(F.dim);
-    F.m_mu = cv.take<float>(F.dim); F.v_mu = cv.take<float>(F.dim);
-    F.m_rho = cv.take<float>(F.dim); F.v_rho = cv.take<float>(F.dim);
-    F.z_lens = cv.take<float>((size_t)S * nl); F.z_ps = cv.take<float>((size_t)S * 4);
-    F.z_lat = cv.take<float>((size_t)S * n2);
-    F.g_lens = cv.take<float>((size_t)S * nl); F.g_ps = cv.take<float>((size_t)S * 4);
-    F.g_lat = cv.take<float>((size_t)S * n2);
-    F.loss = cv.take<double>(S); F.chi2m = cv.take<double>(S);
-    F.status = cv.take<uint32_t>(S); F.n_sub = cv.take<int>(S);
-    F.trace = cv.take<double>(max_steps);
-    if (pass == 0) {
-      if (hipMalloc(&f->pool, cv.off + 256) != hipSuccess) {
-        delete f;
-        return RTU_ENOMEM;
-      }
-      cv.base = f->pool;
-    }
-  }
-  std::vector<int> ns(S, n_sub);
-  hipError_t e = hipMemcpy(F.mu, mu0, (size_t)F.dim * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(F.rho, rho0, (size_t)F.dim * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(F.m_mu, 0, (size_t)F.dim * 4);
-  if (e == hipSuccess) e = hipMemset(F.v_mu, 0, (size_t)F.dim * 4);
-  if (e == hipSuccess) e = hipMemset(F.m_rho, 0, (size_t)F.dim * 4);
-  if (e == hipSuccess) e = hipMemset(F.v_rho, 0, (size_t)F.dim * 4);
-  if (e == hipSuccess) e = hipMemcpy(F.n_sub, ns.data(), (size_t)S * 4, hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
+  carve_fit(F, S, max_steps, f->pool);
+  if (init_fit_state(F, mu0, rho0, n_sub, nullptr) != hipSuccess) {
     (void)hipFree(f->pool);
     delete f;
     return RTU_EHIP;
   }
+  SysDev h = p->h;
+  h.batch = S;
+  h.want_grad = 1;
+  h.lens = F.z_lens; h.n_sub = F.n_sub; h.ps = F.z_ps; h.latent = F.z_lat;
+  h.loss = F.loss; h.chi2m = F.chi2m; h.g_lens = F.g_lens; h.g_ps = F.g_ps; h.g_lat = F.g_lat;
+  h.model = nullptr; h.status = F.status;
+  h.lds_fwd = ray_lds_grid(h, false) ? 1 : 0;
+  h.lds_adj = ray_lds_grid(h, true) ? 1 : 0;
+  h.round0 = 0;
+  h.nsteps = max_steps;
+  const int rc = f->tables.upload({h}, {F}, f->L);
+  if (rc) {
+    f->tables.release();
+    (void)hipFree(f->pool);
+    delete f;
+    return rc;
+  }
+  p->last = h;
+  p->have_last = true;
   *out = f;
   return RTU_OK;
 }
@@ -453,6 +505,7 @@ int rtu_fit_destroy(rtu_fit f) {
   (void)hipSetDevice(f->plan->device);
   (void)hipDeviceSynchronize();
   (void)hipFree(f->pool);
+  f->tables.release();
   delete f;
   return RTU_OK;
 }
@@ -467,23 +520,17 @@ int rtu_fit_step(rtu_fit f, int32_t n_steps, const float* eps, void* stream) {
   if (hipSetDevice(p->device) != hipSuccess) return RTU_EHIP;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const FitDev& F = f->F;
-  SysDev h = p->h;
-  h.batch = F.S;
-  h.lens = F.z_lens; h.n_sub = F.n_sub; h.ps = F.z_ps; h.latent = F.z_lat;
-  h.loss = F.loss; h.chi2m = F.chi2m; h.g_lens = F.g_lens; h.g_ps = F.g_ps; h.g_lat = F.g_lat;
-  h.model = nullptr; h.status = F.status; h.want_grad = 1;
+  const int order[] = {RTU_STAGE_SAMPLE, RTU_STAGE_PREP, RTU_STAGE_RAYS_FWD, RTU_STAGE_PSF_FWD,
+                       RTU_STAGE_PSF_ADJ, RTU_STAGE_RAYS_ADJ, RTU_STAGE_POST, RTU_STAGE_ADAM};
   for (int k = 0; k < n_steps; ++k) {
     const int step = f->steps;
     const float* ek = eps ? eps + (size_t)k * F.S * F.dim : nullptr;
     prof_call_begin(p);
-    prof_stage(p, RTU_STAGE_SAMPLE, false, s);
-    if (launch_sample(F, ek, step, s) != hipSuccess) return RTU_EHIP;
-    prof_stage(p, RTU_STAGE_SAMPLE, true, s);
-    int rc = run_eval(p, h, F.S, s);
-    if (rc) return rc;
-    prof_stage(p, RTU_STAGE_ADAM, false, s);
-    if (launch_adam(F, ek, step, step + 1, s) != hipSuccess) return RTU_EHIP;
-    prof_stage(p, RTU_STAGE_ADAM, true, s);
+    for (int st : order) {
+      prof_stage(p, st, false, s);
+      if (launch_fleet_stage(f->L, st, step, ek, s) != hipSuccess) return RTU_EHIP;
+      prof_stage(p, st, true, s);
+    }
     f->steps++;
   }
   return RTU_OK;

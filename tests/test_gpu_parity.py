@@ -129,3 +129,16 @@ def test_autograd_function_scales_gradients():
     assert close(lens.grad[0], 2.0 * r.grad_lens[0]) and close(lens.grad[1], -0.5 * r.grad_lens[1])
     assert close(ps.grad[0], 2.0 * r.grad_ps[0])
     assert close(lat.grad[1], -0.5 * r.grad_latent[1])
+
+
+def test_replay_is_deterministic():
+    say("[gpu] replay: two identical C2 calls (batch 4) give bitwise-equal results")
+    from paper_2606_30620_amd import api
+    p = synth.make_problem("C2", batch=4)
+    plan = api.plan_for_problem(p)
+    lens, ps, lat, nsub = api.device_inputs(p)
+    a = api.evaluate(plan, lens, ps, lat, nsub, want_model=True)
+    b = api.evaluate(plan, lens, ps, lat, nsub, want_model=True)
+    torch.cuda.synchronize()
+    for name in ("loss", "model", "grad_lens", "grad_ps", "grad_latent"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
