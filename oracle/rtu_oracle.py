@@ -313,15 +313,17 @@ def gp_source(w, ps):
     return positive_source(f, ps[3]), f
 
 
-def bilinear(s, yx, yy):
+def bilinear(s, yx, yy, cell_shift: float = 0.0):
     """Bilinear interpolation of the grid s (Sec. 2.1) at unit-square positions.
     Node (i, j) sits at ((j + 1/2)/n, (i + 1/2)/n); values outside the grid are
-    zero."""
+    zero.  The cell of a position t (in node units) is floor(t + cell_shift);
+    the interpolant is continuous, so a small shift changes only which side's
+    derivative a position on a cell edge takes."""
     n = s.shape[0]
     tx = yx * n - 0.5
     ty = yy * n - 0.5
-    j0 = torch.floor(tx.detach())
-    i0 = torch.floor(ty.detach())
+    j0 = torch.floor(tx.detach() + cell_shift)
+    i0 = torch.floor(ty.detach() + cell_shift)
     fx = tx - j0
     fy = ty - i0
     j0 = j0.long()
@@ -346,14 +348,19 @@ def psf_convolve(u, psf):
     return torch.nn.functional.conv2d(u[None, None], kern, padding=k // 2)[0, 0]
 
 
-def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=False):
+def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=False, cell_shift=0.0,
+            round32=False):
     """One evaluation of the lens model.
 
     obs: dict with n_img, pix, ss, image[N,N], sigma[N,N], psf[K,K], mask[N,N].
     uniform_box: if given as (x_lo, y_lo, side), the RTU transform is replaced by
     the plain affine map of that box onto the unit square (the paper's uniform
-    grid, Sec. 2.1)."""
+    grid, Sec. 2.1).
+    round32: round the ray positions, the knots and slopes and the grid
+    positions to binary32 (a model of an evaluation that shoots rays and
+    evaluates the spline in binary32 with the quantile fit in binary64)."""
     N, pix, ss = obs["n_img"], obs["pix"], obs["ss"]
+    r32 = (lambda t: t.float().to(DT)) if round32 else (lambda t: t)
     status = 0
     lv, pv = lens.detach(), ps.detach()
     if float(lv[0]) <= 0 or float(torch.hypot(lv[1], lv[2])) >= 1 or \
@@ -362,6 +369,7 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
         status |= ST_DOMAIN
     xr, yr = subray_positions(N, pix, ss)
     bx, by = ray_shoot(xr, yr, lens, n_sub, tau)
+    bx, by = r32(bx), r32(by)
     mflat = obs["mask"].reshape(-1).bool()
     xc, yc = pixel_centres(N, pix)
     M = int(mflat.sum())
@@ -370,14 +378,18 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
     tr = None
     if uniform_box is None:
         bxm, bym = ray_shoot(xc[mflat], yc[mflat], lens, n_sub, tau)
-        tr = build_transform(bxm, bym)
+        tr = build_transform(r32(bxm), r32(bym))
         status |= tr["status"]
+        if round32:
+            tr["X"] = [r32(x) for x in tr["X"]]
+            tr["S"] = [r32(x) for x in tr["S"]]
         gx, gy = rtu_transform(bx, by, tr)
+        gx, gy = r32(gx), r32(gy)
     else:
         x_lo, y_lo, side = uniform_box
         gx, gy = (bx - x_lo) / side, (by - y_lo) / side
     s_grid, f = gp_source(w, ps)
-    v = bilinear(s_grid, gx, gy)
+    v = bilinear(s_grid, gx, gy, cell_shift)
     u_img = v.mean(dim=1).reshape(N, N)
     m = psf_convolve(u_img, obs["psf"])
     res = (m - obs["image"]) / obs["sigma"]
@@ -401,14 +413,14 @@ def obs_from_problem(p) -> dict:
             "mask": torch.as_tensor(p.mask.astype(np.int64)), "tau": g.tnfw_tau}
 
 
-def loss_grad(lens, ps, w, obs, n_sub=0, tau=0.0, want_grad=True, return_all=False):
+def loss_grad(lens, ps, w, obs, n_sub=0, tau=0.0, want_grad=True, return_all=False, cell_shift=0.0):
     """Loss = chi^2/2 + |w|^2/2 (Gaussian likelihood over all pixels, N(0,1)
     prior on the latent) and its exact gradient with respect to the lens
     parameters, the power-spectrum parameters and the latent field."""
     lens = _t(lens).clone().requires_grad_(want_grad)
     ps = _t(ps).clone().requires_grad_(want_grad)
     w = _t(w).clone().requires_grad_(want_grad)
-    out = forward(lens, ps, w, obs, n_sub, tau, return_all=return_all)
+    out = forward(lens, ps, w, obs, n_sub, tau, return_all=return_all, cell_shift=cell_shift)
     res = {k: v for k, v in out.items()}
     if want_grad:
         gl, gp, gw = torch.autograd.grad(out["loss"], (lens, ps, w), allow_unused=True)
@@ -428,6 +440,101 @@ def loss_grad_problem(p, b: int, want_grad=True, return_all=False):
     return loss_grad(p.lens[b].astype(np.float64), p.ps[b].astype(np.float64),
                      p.latent[b].astype(np.float64), obs, ns, p.geom.tnfw_tau,
                      want_grad=want_grad, return_all=return_all)
+
+
+def position_rounding_bound(lens, ps, w, obs, n_sub=0, tau=0.0):
+    """Largest change, in node spacings, of any sub-ray's grid position between
+    the exact evaluation and the binary32 rounding model of `forward`."""
+    with torch.no_grad():
+        a = forward(_t(lens), _t(ps), _t(w), obs, n_sub, tau, return_all=True)
+        b = forward(_t(lens), _t(ps), _t(w), obs, n_sub, tau, return_all=True, round32=True)
+    n = a["src"].shape[0]
+    d = torch.cat([(a["gx"] - b["gx"]).reshape(-1), (a["gy"] - b["gy"]).reshape(-1)]).abs() * n
+    d = d[torch.isfinite(d)]
+    return float(d.max()) if d.numel() else 0.0
+
+
+def cell_edge_slack(lens, ps, w, obs, n_sub=0, tau=0.0, delta=None, side=0):
+    """How far the lens gradient may move when sub-rays lying within `delta`
+    node spacings of a cell edge of the bilinear interpolation (Sec. 2.1) take
+    the cell on the other side.
+
+    The interpolant is continuous but its derivative jumps across an edge: a
+    position on the edge at column c has d v/d t = s[c] - s[c-1] from the left
+    cell and s[c+1] - s[c] from the right one (mixed along the other axis with
+    that axis's weights).  An evaluation whose positions carry rounding errors
+    of up to `delta` node spacings may therefore give sub-ray r the one-sided
+    derivative of either side, which moves d loss/d lens by
+        c_r J_r,   c_r = d loss/d v_r * (jump of d v_r/d t_r) * n,
+    J_r = d g_r/d lens (through the ray and through the RTU knots).
+    Returns sum_r |c_r| |J_r| per lens parameter, the number of sub-ray axes
+    within delta of an edge, and delta; delta = None takes twice the
+    binary32 rounding model's positional error (position_rounding_bound).
+    side = +1 (-1) instead returns the signed first-order change when every
+    position within delta below (at or above) an edge takes the cell above
+    (below) it: sum of c_r J_r (-c_r J_r) over those sub-rays."""
+    if delta is None:
+        delta = max(2.0 * position_rounding_bound(lens, ps, w, obs, n_sub, tau), 1e-6)
+    lens_t = _t(lens).clone().requires_grad_(False)
+    ps_t, w_t = _t(ps), _t(w)
+    lens_g = lens_t.clone().requires_grad_(True)
+    out = forward(lens_g, ps_t, w_t, obs, n_sub, tau, return_all=True)
+    (dldu,) = torch.autograd.grad(out["loss"], [out["u"]])
+    N, pix, ss = obs["n_img"], obs["pix"], obs["ss"]
+    gx, gy = out["gx"].detach(), out["gy"].detach()
+    src = out["src"].detach()
+    n = src.shape[0]
+    dldv = (dldu.reshape(-1, 1) / (ss * ss)).expand_as(gx)
+
+    def at(i, j):
+        ok = (i >= 0) & (i < n) & (j >= 0) & (j < n)
+        return torch.where(ok, src.reshape(-1)[torch.where(ok, i * n + j, torch.zeros_like(i))],
+                           torch.zeros((), dtype=src.dtype))
+
+    picks = []        # (flat sub-ray index, axis, c_r, below the edge)
+    for axis in (0, 1):
+        t = (gx if axis == 0 else gy) * n - 0.5
+        o = (gy if axis == 0 else gx) * n - 0.5
+        c = torch.round(t)
+        near = (t - c).abs() < delta
+        if not bool(near.any()):
+            continue
+        ce = c[near].long()
+        o0 = torch.floor(o[near])
+        fo = o[near] - o0
+        o0 = o0.long()
+
+        def val(k, m):   # grid value at (along-axis k, other-axis m)
+            return at(m, k) if axis == 0 else at(k, m)
+
+        left = (1 - fo) * (val(ce, o0) - val(ce - 1, o0)) + fo * (val(ce, o0 + 1) - val(ce - 1, o0 + 1))
+        right = (1 - fo) * (val(ce + 1, o0) - val(ce, o0)) + fo * (val(ce + 1, o0 + 1) - val(ce, o0 + 1))
+        cr = dldv[near] * (right - left) * n
+        below = (t - c)[near] < 0
+        idx = torch.nonzero(near.reshape(-1)).reshape(-1)
+        picks += [(int(i), axis, float(v), bool(lo)) for i, v, lo in zip(idx, cr, below)]
+    if not picks:
+        return torch.zeros_like(lens_t), 0, delta
+    xr, yr = subray_positions(N, pix, ss)
+    xr, yr = xr.reshape(-1), yr.reshape(-1)
+    mflat = obs["mask"].reshape(-1).bool()
+    xc, yc = pixel_centres(N, pix)
+    sel = torch.tensor([p[0] for p in picks])
+    axes = torch.tensor([p[1] for p in picks])
+
+    def g_of(lv):
+        bxm, bym = ray_shoot(xc[mflat], yc[mflat], lv, n_sub, tau)
+        tr = build_transform(bxm, bym)
+        bx, by = ray_shoot(xr[sel], yr[sel], lv, n_sub, tau)
+        g1, g2 = rtu_transform(bx, by, tr)
+        return torch.where(axes == 0, g1, g2)
+
+    J = torch.autograd.functional.jacobian(g_of, lens_t, vectorize=True)     # [picks, n_lens]
+    c = torch.tensor([p[2] for p in picks], dtype=DT)
+    if side == 0:
+        return (c.abs()[:, None] * J.abs()).sum(dim=0), len(picks), delta
+    take = torch.tensor([p[3] == (side > 0) for p in picks])
+    return (side * (c * take)[:, None] * J).sum(dim=0), int(take.sum()), delta
 
 
 # ------------------------------------------------------------------ ELBO (Sec. 4)

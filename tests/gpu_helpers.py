@@ -47,6 +47,16 @@ def selection_agrees(gpu_sel, tr, z_axes):
     return same
 
 
+def lens_slack(problem, b):
+    """Oracle bound (per lens parameter) on the lens-gradient change from
+    sub-rays within rounding distance of a bilinear cell edge."""
+    obs = O.obs_from_problem(problem)
+    sl, n, delta = O.cell_edge_slack(problem.lens[b].astype(np.float64), problem.ps[b].astype(np.float64),
+                                     problem.latent[b].astype(np.float64), obs, int(problem.n_sub[b]),
+                                     problem.geom.tnfw_tau)
+    return sl.numpy(), n, delta
+
+
 def compare(plan, problem, b, res, ref, check_stages=True):
     """Compare sample b of a GPU result with the oracle result `ref`
     (from oracle.loss_grad_problem(..., return_all=True))."""
@@ -63,7 +73,7 @@ def compare(plan, problem, b, res, ref, check_stages=True):
     out["chi2_mask"] = abs(float(res.chi2_mask[b]) - cm_r) / max(abs(cm_r), 1e-30)
     assert out["chi2_mask"] <= TOL_IMG
     st = int(res.status[b])
-    assert (st & ~_lib.ST_SELECT_SLOW) == ref["status"], ("status", st, ref["status"])
+    assert st == ref["status"], ("status", st, ref["status"])
     same_sel = True
     if check_stages:
         tr = ref["transform"]
@@ -100,8 +110,15 @@ def compare(plan, problem, b, res, ref, check_stages=True):
         gl = res.grad_lens[b].cpu().numpy()
         assert np.all(gl[nl:] == 0.0), "inactive subhalo gradient slots must be zero"
         if same_sel:
-            out["g_lens"] = relinf(gl[:nl], ref["grad_lens"].numpy()[:nl])
-            assert out["g_lens"] <= TOL_GRAD, ("grad_lens", gl[:nl], ref["grad_lens"].numpy()[:nl])
+            gr = ref["grad_lens"].numpy()[:nl]
+            out["g_lens"] = relinf(gl[:nl], gr)
+            if out["g_lens"] > TOL_GRAD:
+                # sub-rays near a cell edge of the bilinear interpolation may
+                # take the other side's derivative: allow the oracle's bound
+                slack, npk, delta = lens_slack(problem, b)
+                excess = np.abs(gl[:nl] - gr) - TOL_GRAD * np.abs(gr).max() - slack[:nl]
+                out["g_lens_edge"] = f"{npk} sub-ray axes within {delta:.1e} cells of an edge"
+                assert np.all(excess <= 0), ("grad_lens beyond cell-edge slack", gl[:nl], gr, slack[:nl])
         else:
             out["g_lens"] = "skipped: near-tie order statistic"
     return out

@@ -395,3 +395,28 @@ def test_elbo_gradient_and_adam():
         xt.grad = g.clone()
         opt.step()
     assert torch.allclose(x, xt.detach(), atol=1e-15)
+
+
+def test_cell_edge_slack_predicts_one_sided_derivative_flips():
+    """Pin of the oracle's cell-edge bound: moving every sub-ray position that
+    lies within delta below (above) a bilinear cell edge into the cell above
+    (below) changes the lens gradient, computed by autograd through the
+    shifted interpolation, by the signed first-order sum the bound is built
+    from; and the absolute bound dominates both changes."""
+    p = synth.make_problem("C1")
+    obs = O.obs_from_problem(p)
+    args = (p.lens[0].astype(np.float64), p.ps[0].astype(np.float64), p.latent[0].astype(np.float64), obs,
+            int(p.n_sub[0]), p.geom.tnfw_tau)
+    delta = 1e-3
+    g0 = O.loss_grad(*args)["grad_lens"].detach().numpy()
+    bound, n, _ = O.cell_edge_slack(*args, delta=delta)
+    assert n > 0
+    for side in (1, -1):
+        pred, m, _ = O.cell_edge_slack(*args, delta=delta, side=side)
+        got = O.loss_grad(*args, cell_shift=side * delta)["grad_lens"].detach().numpy() - g0
+        assert m > 0
+        np.testing.assert_allclose(pred.numpy(), got, rtol=0, atol=5e-3 * np.abs(got).max())
+        assert np.all(np.abs(got) <= bound.numpy() * 1.01)
+    # the binary32 rounding model moves positions by far less than a cell
+    r = O.position_rounding_bound(*args)
+    assert 0 < r < 1e-3
