@@ -54,7 +54,6 @@ extern "C" {
 #define RTU_ST_NONMONOTONE  2u  /* QF slope p'(u_k) <= eps or tied knots: slopes clamped */
 #define RTU_ST_MASK_SMALL   4u  /* fewer masked pixels than nodes + 1                  */
 #define RTU_ST_DOMAIN       8u  /* theta_E <= 0, |e| >= 1, r_s <= 0 or spectrum <= 0   */
-#define RTU_ST_SELECT_SLOW 16u  /* quantile selection took its slow path (many ties)   */
 
 /* Number of Chebyshev nodes of the quantile-function fit: degree 21 + 1
  * (App. C step iii and Fig. C1). */
@@ -79,8 +78,14 @@ typedef struct {
   float    pixel_scale;  /* arcsec per image pixel, > 0                             */
   float    tnfw_tau;     /* subhalo projected-mass truncation in units of r_s;
                             0 = untruncated NFW                                     */
-  uint32_t flags;        /* reserved, must be 0                                     */
+  uint32_t flags;        /* 0 or RTU_GEOM_RADIX_SELECT                              */
 } rtu_geometry;
+
+/* Geometry flag: select the quantile order statistics with the bounded-pass
+ * radix select for every sample, instead of only where the value-linear
+ * histogram cannot separate the target ranks.  Both selections return the
+ * same rays (ties by index); the flag exists to exercise the fallback. */
+#define RTU_GEOM_RADIX_SELECT 1u
 
 /* Number of lens parameters per sample: 7 + 4 n_sub_max. */
 int32_t rtu_n_lens(const rtu_geometry* g);

@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("RTU_LIB") or os.path.join(HERE, "librtu.so")
 
 RTU_OK = 0
 RTU_EINVAL, RTU_ENOMEM, RTU_EBATCH, RTU_EHIP, RTU_ESTATE, RTU_ENOTFOUND = -1, -2, -3, -4, -5, -6
-ST_NONFINITE, ST_NONMONOTONE, ST_MASK_SMALL, ST_DOMAIN, ST_SELECT_SLOW = 1, 2, 4, 8, 16
+ST_NONFINITE, ST_NONMONOTONE, ST_MASK_SMALL, ST_DOMAIN = 1, 2, 4, 8
 K_NODES = 22
 N_LENS_BASE, N_PER_SUB, N_PS, MAX_SUB = 7, 4, 4, 10
 DBG_KNOTS, DBG_SELECT, DBG_STD, DBG_SOURCE, DBG_PREPSF = 1, 2, 3, 4, 5
@@ -43,6 +43,11 @@ class RTUError(RuntimeError):
 
 
 def _load():
+    # torch ships its own HIP runtime (libamdhip64.so.7, the same soname as
+    # ROCm's).  It must be loaded first so that librtu.so binds to that one copy;
+    # loading librtu.so first would bring in a second runtime that torch's
+    # kernels then cannot use.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_30620_amd.build` "
                           "(the RTU library has no CPU fallback)")
@@ -101,9 +106,13 @@ def check(rc: int, what: str = "") -> None:
         raise RTUError(f"{what}: {LIB.rtu_strerror(rc).decode()} ({rc})")
 
 
-def make_geometry(n_img, supersample, n_src, psf_size, pixel_scale, n_sub_max=0, tnfw_tau=0.0) -> Geometry:
+GEOM_RADIX_SELECT = 1
+
+
+def make_geometry(n_img, supersample, n_src, psf_size, pixel_scale, n_sub_max=0, tnfw_tau=0.0,
+                  flags=0) -> Geometry:
     return Geometry(int(n_img), int(supersample), int(n_src), int(psf_size), int(n_sub_max), K_NODES,
-                    float(pixel_scale), float(tnfw_tau), 0)
+                    float(pixel_scale), float(tnfw_tau), int(flags))
 
 
 def _ptr(t) -> Optional[int]:
@@ -115,6 +124,14 @@ def _ptr(t) -> Optional[int]:
         return t.ctypes.data
     assert t.is_contiguous(), "tensors passed to the RTU library must be contiguous"
     return t.data_ptr()
+
+
+def _ensure_torch_cuda() -> None:
+    """Initialise torch's HIP context before the library's first device call,
+    so both share one runtime state (streams are torch's)."""
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.current_stream()
 
 
 def _stream_ptr(stream) -> Optional[int]:
@@ -132,6 +149,7 @@ class Plan:
         self.max_batch = int(max_batch)
         self.device = int(device)
         self.n_lens = LIB.rtu_n_lens(C.byref(geom))
+        _ensure_torch_cuda()
         h = C.c_void_p()
         check(LIB.rtu_plan_create(C.byref(geom), self.max_batch, self.device, C.byref(h)), "rtu_plan_create")
         self._h = h
@@ -259,6 +277,7 @@ class Fleet:
     """An rtu_fleet: continuous batching of many fits in shared launches."""
 
     def __init__(self, hbm_budget: int, max_fits: int = 256, sync_every: int = 4, device: int = 0):
+        _ensure_torch_cuda()
         h = C.c_void_p()
         check(LIB.rtu_fleet_create(int(device), int(hbm_budget), int(max_fits), int(sync_every), C.byref(h)),
               "rtu_fleet_create")

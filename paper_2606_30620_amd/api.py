@@ -27,11 +27,11 @@ class Result:
     model: Optional[torch.Tensor] = None
 
 
-def plan_for_problem(problem, max_batch: Optional[int] = None, device: int = 0) -> Plan:
+def plan_for_problem(problem, max_batch: Optional[int] = None, device: int = 0, flags: int = 0) -> Plan:
     """Plan + observation for a problem from the seeded input generator."""
     g = problem.geom
     geom = make_geometry(g.n_img, g.supersample, g.n_src, g.psf_size, g.pixel_scale,
-                         g.n_sub_max, g.tnfw_tau)
+                         g.n_sub_max, g.tnfw_tau, flags)
     plan = Plan(geom, max_batch or problem.batch, device)
     plan.set_observation(problem.image, problem.noise_sigma, problem.psf, problem.mask)
     return plan

@@ -478,10 +478,10 @@ __device__ __forceinline__ int bitrev(int i, int logn) {
 // transformed with sign2 if `twice`, and written through `st(row, col, value)`.
 // Lines are processed in chunks that fit the LDS buffer.
 template <class LD, class MID, class ST>
-__device__ void fft_pass(float2* lds, int n, int logn, bool cols, float sign1, bool twice, float sign2,
+__device__ void fft_pass(float2* lds, int cap, int n, int logn, bool cols, float sign1, bool twice, float sign2,
                          LD ld, MID mid, ST st) {
   const int ls = n + 1;
-  int chunk = FFT_LDS_FLOAT2 / ls;
+  int chunk = cap / ls;
   if (chunk > n) chunk = n;
   for (int l0 = 0; l0 < n; l0 += chunk) {
     const int nl = min(chunk, n - l0);

@@ -115,7 +115,7 @@ namespace rtu {
 int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDev>& fit, FleetLaunch& L) {
   const size_t n = sys.size();
   std::vector<Task> prep, psf, post, param, samp, fits, fwd[2], adj[2];
-  size_t lds_f = 0, lds_a = 0, lds_p = 0;
+  size_t lds_f = 0, lds_a = 0, lds_p = 0, lds_pr = 0, lds_po = 0;
   for (size_t i = 0; i < n; ++i) {
     const SysDev& h = sys[i];
     const FitDev& F = fit[i];
@@ -138,6 +138,8 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
     lds_f = std::max(lds_f, ray_lds_bytes(h, false, h.lds_fwd != 0));
     lds_a = std::max(lds_a, ray_lds_bytes(h, true, h.lds_adj != 0));
     lds_p = std::max(lds_p, psf_lds_bytes(h.psf_k));
+    lds_pr = std::max(lds_pr, prep_lds_bytes(h.n_src));
+    lds_po = std::max(lds_po, post_lds_bytes(h.n_src, h.n_lens));
   }
   std::vector<Task> all;
   size_t off[10];
@@ -181,6 +183,8 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
   L.lds_rays_fwd = lds_f;
   L.lds_rays_adj = lds_a;
   L.lds_psf = lds_p;
+  L.lds_prep = lds_pr;
+  L.lds_post = lds_po;
   return RTU_OK;
 }
 

@@ -16,10 +16,8 @@ constexpr int PSF_TW = 64;              // PSF kernels: 64 x 16 output tile,
 constexpr int PSF_TH = 16;              // 256 threads x 4 columns each
 constexpr int PSF_THREADS = 256;
 constexpr int PREP_THREADS = 1024;      // quantile selection and FFT workgroups
-constexpr int HIST_BINS = 4096;         // first-level histogram of the selection
-constexpr int SEL_LDS_CAP = 3072;       // candidates kept in LDS (else global scratch)
 constexpr int GRID_LDS_MAX = 64;        // n_src <= this: source grid staged in LDS
-constexpr int FFT_LDS_FLOAT2 = 4224;    // FFT chunk buffer (float2) = 33 KB
+constexpr int FFT_LDS_MAX = 128 * 129;  // FFT line buffer (float2): 128 lines of 128 + 1 pad = 129 KB
 constexpr int KBAR = 4 * K;             // per axis pair: dX[K], dS[K]  (x: 0..2K, y: 2K..4K)
 
 // Everything a kernel needs about one lens system and the samples of a call.
@@ -33,6 +31,7 @@ struct SysDev {
   int want_grad, batch;
   int round0, nsteps;         // serving: rounds [round0, round0 + nsteps) are this system's steps
   int lds_fwd, lds_adj;       // ray kernels stage the grid / its adjoint in LDS (1) or not (0)
+  int sel_radix;              // quantile selection: always the radix select (1)
   // observation (owned by the plan)
   const float* image;         // [N*N]
   const float* inv_var;       // [N*N] 1/sigma^2
@@ -61,7 +60,6 @@ struct SysDev {
   float2* F;                  // [B][n^2] DFT of the latent
   float2* tmp;                // [B][n^2] FFT scratch
   float* zbuf;                // [B][2][M] masked-ray beta per axis
-  unsigned long long* cand;   // [B][2][M] selection candidates (slow path)
   float* knots;               // [B][2][2][K] per axis: X_k, S_k in beta units
   float* kdbg;                // [B][2][2][K] per axis: X_k, S_k standardised
   int* sel;                   // [B][2][2][K] per axis: ray index at rank j, j+1
@@ -134,6 +132,9 @@ hipError_t init_fit_state(const FitDev& F, const float* mu0, const float* rho0, 
 size_t ray_lds_bytes(const SysDev& h, bool adjoint, bool lds_grid);
 bool ray_lds_grid(const SysDev& h, bool adjoint);
 size_t psf_lds_bytes(int KP);
+int fft_lds_cap(int n_src);          // float2 slots of the FFT line buffer for this grid
+size_t prep_lds_bytes(int n_src);
+size_t post_lds_bytes(int n_src, int n_lens);
 
 // shared launches over many systems (serving): one work item per task
 struct FleetLaunch {
@@ -144,7 +145,7 @@ struct FleetLaunch {
   // ray tiles split by LDS mode: [0] grid in LDS, [1] grid through L1/L2
   const Task *t_fwd[2], *t_adj[2];
   int n_fwd[2], n_adj[2];
-  size_t lds_rays_fwd, lds_rays_adj, lds_psf;
+  size_t lds_rays_fwd, lds_rays_adj, lds_psf, lds_prep, lds_post;
 };
 // One stage (RTU_STAGE_*) of a shared launch; eps (device [S][dim] per fit,
 // only for a single-fit table) replaces the Philox draws when not null.

@@ -64,36 +64,287 @@ __device__ __forceinline__ void shoot(const SysDev& S, const Sie& L, const Nfw* 
   by = y - ay;
 }
 
-__device__ __forceinline__ unsigned long long sel_key(float v, int m) {
-  unsigned u = __float_as_uint(v + 0.0f);      // -0 -> +0
-  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-  return ((unsigned long long)u << 32) | (unsigned)m;
+// Order-preserving map of a float onto uint32 (-0 taken as +0; NaNs sort
+// beyond the infinities, by sign).
+__device__ __forceinline__ unsigned ord_key(float v) {
+  const unsigned u = __float_as_uint(v + 0.0f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
-__device__ __forceinline__ float key_value(unsigned long long k) {
-  unsigned u = (unsigned)(k >> 32);
-  u = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
-  return __uint_as_float(u);
+// Sort key of masked ray m: its value, ties by index.
+__device__ __forceinline__ unsigned long long sel_key(float v, int m) {
+  return ((unsigned long long)ord_key(v) << 32) | (unsigned)m;
 }
 
 // ====================================================================== k_prep
-// LDS layout of the selection role
+// The type-7 quantiles need the masked rays at 2K ranks of their sorted order
+// (ties by ray index).  First a value-linear histogram over the finite range
+// [vmin, vmax] names the bin of every target rank.  When the target bins are
+// small, their rays are gathered into LDS and ranked by counting.  Otherwise
+// (rays clustered far below the histogram's resolution, many ties,
+// non-finite values) a most-significant-digit radix select on the unique keys
+//   key(m) = (ord(v_m) - ord_min) << ib | m   (tb = vb + ib bits)
+// finds them: every pass histograms the next digit of the rays that share an
+// unresolved target's prefix, a target is resolved once its prefix holds one
+// ray, and the number of passes is bounded by the key width whatever the
+// values are.  The digit width adapts to the number of distinct prefixes so
+// that groups x bins fits the LDS histogram.
+constexpr int HIST_BINS = 4096;          // first level: value-linear bins
+constexpr int SEL_LDS_CAP = 3072;        // rays of the target bins ranked by counting
+constexpr int SEL_SEG_MAX = 256;         // largest target bin ranked by counting
+constexpr int SEL_BINS = 11264;          // radix: groups << digit bits <= SEL_BINS
+constexpr int SEL_MAX_DIGIT = 13;
+
 struct SelLds {
-  int hist[HIST_BINS];
-  unsigned long long cand[SEL_LDS_CAP];
+  union {
+    struct {
+      int hist[HIST_BINS];
+      unsigned long long cand[SEL_LDS_CAP];
+    } c;
+    int rhist[SEL_BINS + 1];
+  };
   double red[8 * 16];
   float fred[2 * 16];
-  int tbin[2 * K], tcum[2 * K], trank[2 * K];
+  unsigned ured[2 * 16];
+  int trank[2 * K];
+  // counting path
+  int tbin[2 * K];
   int seg_bin[2 * K], seg_start[2 * K], seg_count[2 * K], seg_fill[2 * K], seg_t0[2 * K];
-  int nseg, total;
+  int nseg, total, maxcnt;
+  // radix path
+  unsigned long long gpre[2 * K];        // prefixes of the active groups (ascending)
+  unsigned long long tpre[2 * K];        // per target: prefix of its consumed bits
+  unsigned long long ulo[2 * K], uhi[2 * K];  // resolved key ranges (ascending, disjoint)
+  int tlen[2 * K], tgrp[2 * K], tres[2 * K];
+  int ut0[2 * K], ut1[2 * K];
+  int ng, nu, consumed, w;
+  // result
   float tval[2 * K];
   int tidx[2 * K];
   double q[K];
   uint32_t stat;
 };
 
+// Exclusive scan of h[0, n) by the whole workgroup; h[n] = total.
+__device__ __forceinline__ void block_exclusive_scan(int* h, int n, int* wsum) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6;
+  const int per = (n + nt - 1) / nt;
+  const int i0 = min(tid * per, n), i1 = min(i0 + per, n);
+  int s = 0;
+  for (int i = i0; i < i1; ++i) s += h[i];
+  int incl = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  int off = 0;
+  for (int q = 0; q < wv; ++q) off += wsum[q];
+  int run = off + incl - s;
+  for (int i = i0; i < i1; ++i) { const int c = h[i]; h[i] = run; run += c; }
+  if (tid == nt - 1) h[n] = off + incl;
+  __syncthreads();
+}
+
+// Targets t in [0, 2K) with ranks L.trank: rank by counting inside the
+// value-linear bins (returns false, having changed nothing but the bin
+// histogram, when a target bin is too large for it).
+__device__ bool select_by_counting(SelLds& L, const float* zb, int M, float vmin, float vmax) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  int* hist = L.c.hist;
+  for (int i = tid; i <= HIST_BINS; i += nt) hist[i] = 0;   // hist[HIST_BINS] aliases cand[0]: rewritten below
+  __syncthreads();
+  const float scale = (vmax > vmin) ? (float)HIST_BINS / (vmax - vmin) : 0.f;
+  // monotone in the key order: -NaN, -inf -> 0; +inf, +NaN -> last
+  auto bin_of = [&](float v) {
+    if (isnan(v)) return signbit(v) ? 0 : HIST_BINS - 1;
+    const float t = (v - vmin) * scale;
+    if (!(t > 0.f)) return isinf(v) && v > 0.f ? HIST_BINS - 1 : 0;
+    return t < (float)HIST_BINS ? (int)t : HIST_BINS - 1;
+  };
+  for (int m = tid; m < M; m += nt) atomicAdd(&hist[bin_of(zb[m])], 1);
+  __syncthreads();
+  block_exclusive_scan(hist, HIST_BINS, reinterpret_cast<int*>(L.red));
+  if (tid < 2 * K) {
+    const int r = L.trank[tid];
+    int lo = 0, hi = HIST_BINS - 1;   // largest bin with cum <= r
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (hist[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    L.tbin[tid] = lo;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int ns = 0, tot = 0, mx = 0;
+    for (int t = 0; t < 2 * K; ++t) {
+      const int bb = L.tbin[t];
+      if (ns == 0 || L.seg_bin[ns - 1] != bb) {
+        L.seg_bin[ns] = bb;
+        L.seg_t0[ns] = t;
+        L.seg_start[ns] = tot;
+        L.seg_count[ns] = hist[bb + 1] - hist[bb];
+        L.seg_fill[ns] = 0;
+        tot += L.seg_count[ns];
+        mx = max(mx, L.seg_count[ns]);
+        ++ns;
+      }
+    }
+    L.nseg = ns;
+    L.total = tot;
+    L.maxcnt = mx;
+  }
+  __syncthreads();
+  const int nseg = L.nseg, total = L.total;
+  if (total > SEL_LDS_CAP || L.maxcnt > SEL_SEG_MAX) return false;
+  if (tid < 2 * K) L.trank[tid] -= hist[L.tbin[tid]];     // rank inside the bin
+  __syncthreads();
+  // map bin -> segment (reuse the histogram)
+  for (int i = tid; i < HIST_BINS; i += nt) hist[i] = -1;
+  __syncthreads();
+  if (tid < nseg) hist[L.seg_bin[tid]] = tid;
+  __syncthreads();
+  for (int m = tid; m < M; m += nt) {
+    const float v = zb[m];
+    const int sg = hist[bin_of(v)];
+    if (sg >= 0) {
+      const int pos = atomicAdd(&L.seg_fill[sg], 1);
+      L.c.cand[L.seg_start[sg] + pos] = sel_key(v, m);
+    }
+  }
+  __syncthreads();
+  // rank inside each segment by counting, all candidates in parallel; the
+  // targets of a segment are a contiguous range of t (ranks are sorted)
+  for (int idx = tid; idx < total; idx += nt) {
+    int lo = 0, hi = nseg - 1;      // segment holding position idx
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L.seg_start[mid] <= idx) lo = mid; else hi = mid - 1;
+    }
+    const int st0 = L.seg_start[lo], cnt = L.seg_count[lo], bb = L.seg_bin[lo];
+    const unsigned long long kc = L.c.cand[idx];
+    int rk = 0;
+    for (int c2 = 0; c2 < cnt; ++c2) rk += L.c.cand[st0 + c2] < kc;
+    for (int t = L.seg_t0[lo]; t < 2 * K && L.tbin[t] == bb; ++t) {
+      if (L.trank[t] == rk) {
+        const int m = (int)(kc & 0xffffffffu);
+        L.tval[t] = zb[m];
+        L.tidx[t] = m;
+      }
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// Targets t in [0, 2K) with ranks L.trank: radix select on the unique keys.
+__device__ void select_by_radix(SelLds& L, const float* zb, int M, unsigned umin, unsigned umax) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  int* hist = L.rhist;
+  const unsigned R = umax - umin;
+  const int vb = R ? 32 - __clz((int)R) : 0;
+  const int ib = M > 1 ? 32 - __clz(M - 1) : 0;
+  const int tb = vb + ib;                       // <= 32 + 31 bits
+  auto key = [&](int m) {
+    return ((unsigned long long)(ord_key(zb[m]) - umin) << ib) | (unsigned)m;
+  };
+  if (tid < 2 * K) {
+    L.tpre[tid] = 0ull;
+    L.tlen[tid] = 0;
+    L.tres[tid] = tb == 0;                      // a single ray
+  }
+  __syncthreads();
+  for (;;) {
+    if (tid == 0) {
+      int ng = 0, consumed = tb;
+      for (int t = 0; t < 2 * K; ++t) {
+        if (L.tres[t]) continue;
+        if (ng == 0 || L.gpre[ng - 1] != L.tpre[t]) L.gpre[ng++] = L.tpre[t];
+        L.tgrp[t] = ng - 1;
+        consumed = L.tlen[t];                   // the same for every unresolved target
+      }
+      int w = 0;
+      if (ng) {
+        w = SEL_MAX_DIGIT;
+        while ((ng << w) > SEL_BINS) --w;
+        if (w > tb - consumed) w = tb - consumed;
+      }
+      L.ng = ng;
+      L.consumed = consumed;
+      L.w = w;
+    }
+    __syncthreads();
+    const int ng = L.ng, w = L.w, sh = tb - L.consumed - w;
+    if (ng == 0) break;
+    const int nb = ng << w;
+    for (int i = tid; i <= nb; i += nt) hist[i] = 0;
+    __syncthreads();
+    const unsigned long long dmask = (1ull << w) - 1ull;
+    for (int m = tid; m < M; m += nt) {
+      const unsigned long long k = key(m);
+      const unsigned long long pre = (k >> sh) >> w;
+      int lo = 0, hi = ng - 1;                  // the group with this prefix, if any
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.gpre[mid] <= pre) lo = mid; else hi = mid - 1;
+      }
+      if (L.gpre[lo] == pre) atomicAdd(&hist[(lo << w) + (int)((k >> sh) & dmask)], 1);
+    }
+    __syncthreads();
+    block_exclusive_scan(hist, nb, reinterpret_cast<int*>(L.red));
+    if (tid < 2 * K && !L.tres[tid]) {
+      const int base = L.tgrp[tid] << w;
+      const int target = hist[base] + L.trank[tid];
+      int lo = 0, hi = (1 << w) - 1;            // largest digit whose start <= target
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (hist[base + mid] <= target) lo = mid; else hi = mid - 1;
+      }
+      const int cnt = hist[base + lo + 1] - hist[base + lo];
+      L.trank[tid] = target - hist[base + lo];
+      L.tpre[tid] = (L.tpre[tid] << w) | (unsigned long long)lo;
+      L.tlen[tid] += w;
+      L.tres[tid] = cnt <= 1 || L.tlen[tid] >= tb;
+    }
+    __syncthreads();
+  }
+  // every target's prefix now holds exactly one ray: fetch it
+  if (tid == 0) {
+    int nu = 0;
+    for (int t = 0; t < 2 * K; ++t) {
+      const int free_bits = tb - L.tlen[t];
+      const unsigned long long lo = L.tpre[t] << free_bits;
+      if (nu == 0 || L.ulo[nu - 1] != lo) {
+        L.ulo[nu] = lo;
+        L.uhi[nu] = lo + (1ull << free_bits);
+        L.ut0[nu] = t;
+        ++nu;
+      }
+      L.ut1[nu - 1] = t;
+    }
+    L.nu = nu;
+  }
+  __syncthreads();
+  const int nu = L.nu;
+  for (int m = tid; m < M; m += nt) {
+    const unsigned long long k = key(m);
+    int lo = 0, hi = nu - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L.ulo[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    if (L.ulo[lo] <= k && k < L.uhi[lo]) {
+      const float v = zb[m];
+      for (int t = L.ut0[lo]; t <= L.ut1[lo]; ++t) { L.tval[t] = v; L.tidx[t] = m; }
+    }
+  }
+  __syncthreads();
+}
+
 __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* smem) {
   SelLds& L = *reinterpret_cast<SelLds*>(smem);
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
   const int M = S.M;
   const float* lensp = S.lens + (size_t)b * S.n_lens;
   const int nsub = n_sub_of(S, b);
@@ -106,7 +357,8 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
 
   // ---- masked rays at the observed pixel centres (not supersampled)
   double sx = 0, sy = 0, sxx = 0, syy = 0;
-  float vmin = INFINITY, vmax = -INFINITY;
+  float vmin = INFINITY, vmax = -INFINITY;      // over the finite values
+  unsigned umin = 0xffffffffu, umax = 0u;       // key range over all values
   for (int m = tid; m < M; m += nt) {
     const int p = S.mask_idx[m];
     const int i = p / S.n_img, j = p - i * S.n_img;
@@ -117,19 +369,32 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
     sx += bx; sy += by; sxx += (double)bx * bx; syy += (double)by * by;
     const float v = (axis == 0 ? bx : by) + 0.0f;
     zb[m] = v;
-    vmin = fminf(vmin, v);
-    vmax = fmaxf(vmax, v);
+    if (isfinite(v)) {
+      vmin = fminf(vmin, v);
+      vmax = fmaxf(vmax, v);
+    }
+    const unsigned u = ord_key(v);
+    umin = min(umin, u);
+    umax = max(umax, u);
   }
   {
     double v4[4] = {sx, sy, sxx, syy};
     block_sum<4>(v4, L.red);
     sx = v4[0]; sy = v4[1]; sxx = v4[2]; syy = v4[3];
-    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     float a = wave_min(vmin), c = wave_max(vmax);
-    if (lane == 0) { L.fred[wv] = a; L.fred[16 + wv] = c; }
+    for (int o = 32; o >= 1; o >>= 1) {
+      umin = min(umin, (unsigned)__shfl_xor((int)umin, o, 64));
+      umax = max(umax, (unsigned)__shfl_xor((int)umax, o, 64));
+    }
+    if (lane == 0) { L.fred[wv] = a; L.fred[16 + wv] = c; L.ured[wv] = umin; L.ured[16 + wv] = umax; }
     __syncthreads();
     vmin = INFINITY; vmax = -INFINITY;
-    for (int w = 0; w < nw; ++w) { vmin = fminf(vmin, L.fred[w]); vmax = fmaxf(vmax, L.fred[16 + w]); }
+    for (int w = 0; w < nw; ++w) {
+      vmin = fminf(vmin, L.fred[w]);
+      vmax = fmaxf(vmax, L.fred[16 + w]);
+      umin = min(umin, L.ured[w]);
+      umax = max(umax, L.ured[16 + w]);
+    }
     __syncthreads();
   }
   const double Md = (double)(M > 0 ? M : 1);
@@ -139,111 +404,14 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
   const double sc = fmin(sdx, sdy);
   const double mu = axis == 0 ? mux : muy;
 
-  // ---- level-1 histogram over [vmin, vmax] (monotone bin map)
-  for (int i = tid; i < HIST_BINS; i += nt) L.hist[i] = 0;
-  __syncthreads();
-  const float scale = (vmax > vmin) ? (float)HIST_BINS / (vmax - vmin) : 0.f;
-  auto bin_of = [&](float v) {
-    int bb = (int)((v - vmin) * scale);
-    return bb < 0 ? 0 : (bb >= HIST_BINS ? HIST_BINS - 1 : bb);
-  };
-  for (int m = tid; m < M; m += nt) atomicAdd(&L.hist[bin_of(zb[m])], 1);
-  __syncthreads();
-  // exclusive scan: thread t owns bins [4t, 4t + 4)
-  {
-    const int per = HIST_BINS / PREP_THREADS;  // 4
-    int loc[HIST_BINS / PREP_THREADS];
-    int s = 0;
-    for (int k = 0; k < per; ++k) { loc[k] = L.hist[tid * per + k]; s += loc[k]; }
-    // block exclusive scan of s
-    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-    int incl = s;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
+  if (M > 0) {
+    // target ranks floor(h_k) and floor(h_k) + 1, h_k = (M-1) u_k (ascending)
+    if (tid < 2 * K) {
+      const int r = S.rank_j[tid >> 1] + (tid & 1);
+      L.trank[tid] = r < 0 ? 0 : (r > M - 1 ? M - 1 : r);
     }
-    int* wsum = reinterpret_cast<int*>(L.red);
-    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    int off = 0;
-    for (int w = 0; w < wv; ++w) off += wsum[w];
-    int run = off + incl - s;
-    __syncthreads();
-    for (int k = 0; k < per; ++k) { L.hist[tid * per + k] = run; run += loc[k]; }
-    (void)nw;
-  }
-  __syncthreads();
-  auto cum = [&](int bb) { return bb < HIST_BINS ? L.hist[bb] : M; };
-
-  // ---- target ranks: floor(h_k) and floor(h_k) + 1, h_k = (M-1) u_k
-  if (tid < 2 * K) {
-    int r = S.rank_j[tid >> 1] + (tid & 1);
-    r = r < 0 ? 0 : (r > M - 1 ? M - 1 : r);
-    int lo = 0, hi = HIST_BINS - 1;   // largest bin with cum <= r
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (L.hist[mid] <= r) lo = mid; else hi = mid - 1;
-    }
-    L.tbin[tid] = lo;
-    L.tcum[tid] = L.hist[lo];
-    L.trank[tid] = r - L.hist[lo];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int ns = 0, tot = 0;
-    for (int t = 0; t < 2 * K; ++t) {
-      const int bb = L.tbin[t];
-      if (ns == 0 || L.seg_bin[ns - 1] != bb) {
-        L.seg_bin[ns] = bb;
-        L.seg_t0[ns] = t;
-        L.seg_start[ns] = tot;
-        L.seg_count[ns] = cum(bb + 1) - cum(bb);
-        L.seg_fill[ns] = 0;
-        tot += L.seg_count[ns];
-        ++ns;
-      }
-    }
-    L.nseg = ns;
-    L.total = tot;
-  }
-  __syncthreads();
-  const int nseg = L.nseg, total = L.total;
-  // map bin -> segment (reuse the histogram array)
-  for (int i = tid; i < HIST_BINS; i += nt) L.hist[i] = -1;
-  __syncthreads();
-  if (tid < nseg) L.hist[L.seg_bin[tid]] = tid;
-  __syncthreads();
-  const bool slow = total > SEL_LDS_CAP;
-  unsigned long long* cand = slow ? S.cand + ((size_t)b * 2 + axis) * M : L.cand;
-  if (slow) st |= RTU_ST_SELECT_SLOW;
-  for (int m = tid; m < M; m += nt) {
-    const float v = zb[m];
-    const int sg = L.hist[bin_of(v)];
-    if (sg >= 0) {
-      const int pos = atomicAdd(&L.seg_fill[sg], 1);
-      cand[L.seg_start[sg] + pos] = sel_key(v, m);
-    }
-  }
-  __threadfence_block();
-  __syncthreads();
-  // ---- rank inside each segment by counting, all candidates in parallel; the
-  //      targets of a segment are a contiguous range of t (ranks are sorted)
-  for (int idx = tid; idx < total; idx += nt) {
-    int lo = 0, hi = nseg - 1;      // segment holding position idx
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (L.seg_start[mid] <= idx) lo = mid; else hi = mid - 1;
-    }
-    const int st0 = L.seg_start[lo], cnt = L.seg_count[lo], bb = L.seg_bin[lo];
-    const unsigned long long kc = cand[idx];
-    int rk = 0;
-    for (int c2 = 0; c2 < cnt; ++c2) rk += cand[st0 + c2] < kc;
-    for (int t = L.seg_t0[lo]; t < 2 * K && L.tbin[t] == bb; ++t) {
-      if (L.trank[t] == rk) {
-        L.tval[t] = key_value(kc);
-        L.tidx[t] = (int)(kc & 0xffffffffu);
-      }
-    }
+    if (S.sel_radix || !select_by_counting(L, zb, M, vmin, vmax)) select_by_radix(L, zb, M, umin, umax);
   }
   __syncthreads();
 
@@ -295,7 +463,7 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
 }
 
 // GP source (eqs. 1-4): F = DFT(w); f = Re IDFT(sqrt(P) F)/n^2; s = (s0 softplus(f/s0))^alpha
-__device__ void prep_gp(const SysDev& S, int b, unsigned char* smem) {
+__device__ void prep_gp(const SysDev& S, int b, unsigned char* smem, int cap) {
   float2* lds = reinterpret_cast<float2*>(smem);
   const int n = S.n_src, logn = S.log2_src, n2 = n * n;
   const float* w = S.latent + (size_t)b * n2;
@@ -324,12 +492,12 @@ __device__ void prep_gp(const SysDev& S, int b, unsigned char* smem) {
   const float alpha = ps[3];
   const float inv_n2 = 1.f / (float)n2;
   // rows: forward transform of the real latent
-  fft_pass(lds, n, logn, false, -1.f, false, 0.f,
+  fft_pass(lds, cap, n, logn, false, -1.f, false, 0.f,
            [&](int r, int c) { return make_float2(w[r * n + c], 0.f); },
            [&](int, int, float2 v) { return v; },
            [&](int r, int c, float2 v) { T[r * n + c] = v; });
   // columns: forward, keep F, multiply by sqrt(P), inverse
-  fft_pass(lds, n, logn, true, -1.f, true, 1.f,
+  fft_pass(lds, cap, n, logn, true, -1.f, true, 1.f,
            [&](int r, int c) { return T[r * n + c]; },
            [&](int r, int c, float2 v) {
              F[r * n + c] = v;
@@ -339,7 +507,7 @@ __device__ void prep_gp(const SysDev& S, int b, unsigned char* smem) {
            },
            [&](int r, int c, float2 v) { T[r * n + c] = v; });
   // rows: inverse, real part / n^2, positivity transform
-  fft_pass(lds, n, logn, false, 1.f, false, 0.f,
+  fft_pass(lds, cap, n, logn, false, 1.f, false, 0.f,
            [&](int r, int c) { return T[r * n + c]; },
            [&](int, int, float2 v) { return v; },
            [&](int r, int c, float2 v) {
@@ -350,13 +518,13 @@ __device__ void prep_gp(const SysDev& S, int b, unsigned char* smem) {
            });
 }
 
-constexpr size_t PREP_LDS = sizeof(SelLds) > FFT_LDS_FLOAT2 * 8 ? sizeof(SelLds) : FFT_LDS_FLOAT2 * 8;
-
-__global__ void __launch_bounds__(PREP_THREADS) k_prep(SysDev S) {
-  __shared__ __align__(16) unsigned char smem[PREP_LDS];
+// Dynamic LDS of the prep kernels: the larger of the selection layout and the
+// FFT line buffer (fft_cap float2 slots).
+__global__ void __launch_bounds__(PREP_THREADS) k_prep(SysDev S, int fft_cap) {
+  extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x, role = blockIdx.y;
   if (role < 2) prep_select(S, b, role, smem);
-  else prep_gp(S, b, smem);
+  else prep_gp(S, b, smem, fft_cap);
 }
 
 // ====================================================================== ray tiles
@@ -759,7 +927,7 @@ struct PostLds {
   uint32_t stat;
 };
 
-__device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, PostLds& P) {
+__device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, int cap, PostLds& P) {
   const int tid = threadIdx.x;
   const int n = S.n_src, n2 = n * n, logn = S.log2_src;
   const int nl = S.n_lens;
@@ -866,7 +1034,7 @@ __device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, PostL
     double pacc[4] = {0.0, 0.0, 0.0, 0.0};   // sigma, n, zeta, alpha
     const float inv_n2 = 1.f / (float)n2;
     // rows: fbar = sbar ds/df, ds/df = alpha s sigmoid(x)/(s0 softplus(x)), x = f/s0
-    fft_pass(lds, n, logn, false, -1.f, false, 0.f,
+    fft_pass(lds, cap, n, logn, false, -1.f, false, 0.f,
              [&](int r, int c) {
                const int q = r * n + c;
                const float x = fo[q] * 100.f;
@@ -880,7 +1048,7 @@ __device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, PostL
              [&](int, int, float2 v) { return v; },
              [&](int r, int c, float2 v) { T[r * n + c] = v; });
     // columns: forward -> Fbar; spectrum gradient; multiply by sqrt(P); inverse
-    fft_pass(lds, n, logn, true, -1.f, true, 1.f,
+    fft_pass(lds, cap, n, logn, true, -1.f, true, 1.f,
              [&](int r, int c) { return T[r * n + c]; },
              [&](int r, int c, float2 v) {
                const float kx = fft_freq(c, n), ky = fft_freq(r, n);
@@ -898,7 +1066,7 @@ __device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, PostL
              },
              [&](int r, int c, float2 v) { T[r * n + c] = v; });
     uint32_t bad = 0;
-    fft_pass(lds, n, logn, false, 1.f, false, 0.f,
+    fft_pass(lds, cap, n, logn, false, 1.f, false, 0.f,
              [&](int r, int c) { return T[r * n + c]; },
              [&](int, int, float2 v) { return v; },
              [&](int r, int c, float2 v) {
@@ -917,13 +1085,15 @@ __device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, PostL
   if (tid == 0) S.status[b] = P.stat | S.st[b * 4 + 0] | S.st[b * 4 + 1] | S.st[b * 4 + 2];
 }
 
-__global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S) {
-  __shared__ __align__(16) unsigned char fft_smem[FFT_LDS_FLOAT2 * 8];
+__global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S, int fft_cap) {
+  extern __shared__ __align__(16) unsigned char fft_smem[];
   __shared__ PostLds P;
-  post_body(S, blockIdx.x, fft_smem, P);
+  post_body(S, blockIdx.x, fft_smem, fft_cap, P);
 }
 
 // ====================================================================== launchers
+hipError_t configure_fft_kernels();
+
 hipError_t upload_constants() {
   double u[K], tn[K];
   for (int k = 0; k < K; ++k) {
@@ -955,11 +1125,28 @@ hipError_t upload_constants() {
   hipError_t e;
   if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_u), uf, sizeof(uf))) != hipSuccess) return e;
   if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_D), D, sizeof(D))) != hipSuccess) return e;
-  return hipMemcpyToSymbol(HIP_SYMBOL(c_tw), tw, sizeof(tw));
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_tw), tw, sizeof(tw))) != hipSuccess) return e;
+  return configure_fft_kernels();
+}
+
+// The FFT keeps min(n, cap / (n + 1)) lines of the grid in LDS at a time:
+// every line of a grid up to 128 per side, 64-line chunks beyond.
+int fft_lds_cap(int n_src) { return n_src <= 128 ? n_src * (n_src + 1) : FFT_LDS_MAX; }
+size_t prep_lds_bytes(int n_src) {
+  const size_t f = (size_t)fft_lds_cap(n_src) * sizeof(float2);
+  return f > sizeof(SelLds) ? f : sizeof(SelLds);
+}
+// k_post shares its dynamic LDS between the FFT lines and the per-node
+// lens-parameter rows of the knot adjoint ([4K][n_lens] doubles).
+size_t post_lds_bytes(int n_src, int n_lens) {
+  const size_t f = (size_t)fft_lds_cap(n_src) * sizeof(float2);
+  const size_t m = (size_t)4 * K * n_lens * sizeof(double);
+  return f > m ? f : m;
 }
 
 hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep, dim3(batch, 3), dim3(PREP_THREADS), 0, s, h);
+  hipLaunchKernelGGL(k_prep, dim3(batch, 3), dim3(PREP_THREADS), prep_lds_bytes(h.n_src), s, h,
+                     (int)(prep_lds_bytes(h.n_src) / sizeof(float2)));
   return hipGetLastError();
 }
 
@@ -1012,7 +1199,8 @@ hipError_t launch_psf(const SysDev& h, int batch, bool adjoint, hipStream_t s) {
 }
 
 hipError_t launch_post(const SysDev& h, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_post, dim3(batch), dim3(PREP_THREADS), 0, s, h);
+  hipLaunchKernelGGL(k_post, dim3(batch), dim3(PREP_THREADS), post_lds_bytes(h.n_src, h.n_lens), s, h,
+                     fft_lds_cap(h.n_src));
   return hipGetLastError();
 }
 
@@ -1026,13 +1214,13 @@ __device__ __forceinline__ bool sys_active(const SysDev& S, int round) {
 }
 
 __global__ void __launch_bounds__(PREP_THREADS) kf_prep(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
-                                                      int round) {
-  __shared__ __align__(16) unsigned char smem[PREP_LDS];
+                                                      int round, int fft_cap) {
+  extern __shared__ __align__(16) unsigned char smem[];
   const Task t = tasks[blockIdx.x];
   const SysDev S = sys[t.x];
   if (!sys_active(S, round)) return;
   if (t.z < 2) prep_select(S, t.y, t.z, smem);
-  else prep_gp(S, t.y, smem);
+  else prep_gp(S, t.y, smem, fft_cap);
 }
 
 template <bool LDSGRID>
@@ -1066,13 +1254,13 @@ __global__ void __launch_bounds__(PSF_THREADS) kf_psf(const SysDev* __restrict__
 }
 
 __global__ void __launch_bounds__(PREP_THREADS) kf_post(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
-                                                      int round) {
-  __shared__ __align__(16) unsigned char fft_smem[FFT_LDS_FLOAT2 * 8];
+                                                      int round, int fft_cap) {
+  extern __shared__ __align__(16) unsigned char fft_smem[];
   __shared__ PostLds P;
   const Task t = tasks[blockIdx.x];
   const SysDev S = sys[t.x];
   if (!sys_active(S, round)) return;
-  post_body(S, t.y, fft_smem, P);
+  post_body(S, t.y, fft_smem, fft_cap, P);
 }
 
 hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, const float* eps, hipStream_t s);
@@ -1080,7 +1268,9 @@ hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, co
 hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const float* eps, hipStream_t s) {
   switch (stage) {
     case RTU_STAGE_PREP:
-      if (L.n_prep) hipLaunchKernelGGL(kf_prep, dim3(L.n_prep), dim3(PREP_THREADS), 0, s, L.sys, L.t_prep, round);
+      if (L.n_prep)
+        hipLaunchKernelGGL(kf_prep, dim3(L.n_prep), dim3(PREP_THREADS), L.lds_prep, s, L.sys, L.t_prep, round,
+                           (int)(L.lds_prep / sizeof(float2)));
       break;
     case RTU_STAGE_RAYS_FWD:
       if (L.n_fwd[0])
@@ -1105,12 +1295,28 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
                            L.t_adj[1], round);
       break;
     case RTU_STAGE_POST:
-      if (L.n_post) hipLaunchKernelGGL(kf_post, dim3(L.n_post), dim3(PREP_THREADS), 0, s, L.sys, L.t_post, round);
+      if (L.n_post)
+        hipLaunchKernelGGL(kf_post, dim3(L.n_post), dim3(PREP_THREADS), L.lds_post, s, L.sys, L.t_post, round,
+                           (int)(L.lds_post / sizeof(float2)));
       break;
     default:
       return launch_fleet_fit_stage(L, stage, round, eps, s);
   }
   return hipGetLastError();
+}
+
+// The FFT kernels may take up to 129 KB of dynamic LDS (plus their static
+// part) of the 160 KB per CU.
+hipError_t configure_fft_kernels() {
+  const int big = (int)(prep_lds_bytes(128) > post_lds_bytes(128, RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB)
+                            ? prep_lds_bytes(128)
+                            : post_lds_bytes(128, RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB));
+  const void* fns[4] = {(const void*)k_prep, (const void*)k_post, (const void*)kf_prep, (const void*)kf_post};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace rtu

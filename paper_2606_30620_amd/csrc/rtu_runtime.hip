@@ -70,7 +70,7 @@ bool valid_geometry(const rtu_geometry* g) {
   if (g->psf_size < 1 || g->psf_size > 63 || !(g->psf_size & 1)) return false;
   if (g->n_sub_max < 0 || g->n_sub_max > RTU_MAX_SUB) return false;
   if (g->k_nodes != RTU_K_NODES) return false;
-  if (!(g->pixel_scale > 0.f) || !(g->tnfw_tau >= 0.f) || g->flags != 0) return false;
+  if (!(g->pixel_scale > 0.f) || !(g->tnfw_tau >= 0.f) || (g->flags & ~RTU_GEOM_RADIX_SELECT) != 0) return false;
   return true;
 }
 
@@ -102,6 +102,7 @@ void fill_geometry(const rtu_geometry* g, SysDev& h) {
   h.pix = g->pixel_scale;
   h.tau = g->tnfw_tau;
   h.inv_ss2 = 1.f / (float)(g->supersample * g->supersample);
+  h.sel_radix = (g->flags & RTU_GEOM_RADIX_SELECT) ? 1 : 0;
   h.ray_tx = (g->n_img + RAY_TILE - 1) / RAY_TILE;
   h.ray_tiles = h.ray_tx * h.ray_tx;
   h.psf_tx = (g->n_img + PSF_TW - 1) / PSF_TW;
@@ -145,7 +146,6 @@ size_t carve_observation(SysDev& h, int B, int M, char* base) {
   h.rank_j = c.take<int>(K);
   h.rank_t = c.take<double>(K);
   h.zbuf = c.take<float>((size_t)B * 2 * (M > 0 ? M : 1));
-  h.cand = c.take<unsigned long long>((size_t)B * 2 * (M > 0 ? M : 1));
   return c.off + 256;
 }
 

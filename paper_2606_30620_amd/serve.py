@@ -48,11 +48,13 @@ def guide_init(problem: synth.Problem):
 
 
 def make_requests(n: int, rate: float, steps: int = 200, samples: int = 1, seed: int = 505,
-                  first_id: int = 0) -> List[Request]:
+                  first_id: int = 0, lr: float = 5e-4) -> List[Request]:
     """n requests of the serving mix with Poisson arrivals at `rate` per second
-    (rate = inf: all at t = 0)."""
+    (rate = inf: all at t = 0).  The step size keeps a fit started at its
+    parameter sample inside the parameter domain (subhalo scale radii are a
+    few hundredths of an arcsecond)."""
     times = np.zeros(n) if math.isinf(rate) else synth.poisson_arrivals(n, rate, seed)
-    return [Request(first_id + i, float(times[i]), synth.serving_request(first_id + i), steps, samples,
+    return [Request(first_id + i, float(times[i]), synth.serving_request(first_id + i), steps, samples, lr=lr,
                     seed=1000 + first_id + i) for i in range(n)]
 
 

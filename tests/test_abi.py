@@ -32,5 +32,9 @@ def test_host_validation_without_gpu():
     assert L.rtu_workspace_bytes(bad, 1) == 0
     bad = _lib.make_geometry(64, 1, 32, 15, 0.05, n_sub_max=_lib.MAX_SUB + 1)
     assert L.rtu_workspace_bytes(bad, 1) == 0
+    ok = _lib.make_geometry(64, 1, 32, 15, 0.05, flags=_lib.GEOM_RADIX_SELECT)
+    assert L.rtu_workspace_bytes(ok, 1) == L.rtu_workspace_bytes(g, 1)
+    bad = _lib.make_geometry(64, 1, 32, 15, 0.05, flags=2)     # unknown flag
+    assert L.rtu_workspace_bytes(bad, 1) == 0
     assert L.rtu_strerror(_lib.RTU_EBATCH).decode().startswith("batch")
     assert L.rtu_loss_grad(None, 1, *([None] * 12)) == _lib.RTU_EINVAL

@@ -18,17 +18,17 @@ from tests.gpu_helpers import compare, say
 pytestmark = pytest.mark.gpu
 
 
-def _run(problem, samples=None, want_grad=True, batch_max=None):
+def _run(problem, samples=None, want_grad=True, batch_max=None, flags=0):
     from paper_2606_30620_amd import api
-    plan = api.plan_for_problem(problem, max_batch=batch_max)
+    plan = api.plan_for_problem(problem, max_batch=batch_max, flags=flags)
     lens, ps, lat, nsub = api.device_inputs(problem)
     res = api.evaluate(plan, lens, ps, lat, nsub, want_grad=want_grad, want_model=True)
     torch.cuda.synchronize()
     return plan, res
 
 
-def _check(problem, samples, want_grad=True, check_stages=True):
-    plan, res = _run(problem, want_grad=want_grad)
+def _check(problem, samples, want_grad=True, check_stages=True, flags=0):
+    plan, res = _run(problem, want_grad=want_grad, flags=flags)
     worst = {}
     for b in samples:
         ref = O.loss_grad_problem(problem, b, want_grad=want_grad, return_all=True)
@@ -142,3 +142,30 @@ def test_replay_is_deterministic():
     torch.cuda.synchronize()
     for name in ("loss", "model", "grad_lens", "grad_ps", "grad_latent"):
         assert torch.equal(getattr(a, name), getattr(b, name)), name
+
+
+@pytest.mark.parametrize("case", ["c2", "subhalo", "ragged"])
+def test_radix_selection_matches_histogram_selection(case):
+    """The bounded-pass radix select (the fallback for clustered or tied
+    masked rays) picks exactly the rays of the histogram + counting select:
+    forcing it for every sample leaves every output bit-identical, and the
+    forced run agrees with the oracle."""
+    from paper_2606_30620_amd import _lib
+    if case == "c2":
+        p = synth.make_problem("C2", batch=2)
+    elif case == "subhalo":
+        p = synth.make_problem("X", batch=2, seed=11,
+                               geom=synth.Geometry(96, 0.05, 2, 64, 15, 1.0, n_sub_max=3, tnfw_tau=10.0))
+    else:
+        p = synth.make_problem("X", batch=2, seed=7, geom=synth.Geometry(72, 0.06, 3, 16, 9, 1.2))
+    say(f"[gpu] radix vs histogram selection: {case}")
+    plan0, r0 = _run(p)
+    plan1, r1 = _run(p, flags=_lib.GEOM_RADIX_SELECT)
+    for name in ("loss", "chi2_mask", "status", "grad_lens", "grad_ps", "grad_latent", "model"):
+        a, b = getattr(r0, name), getattr(r1, name)
+        assert torch.equal(a, b), name
+    for b in range(p.batch):
+        s0 = plan0.debug_fetch(_lib.DBG_SELECT, b)
+        s1 = plan1.debug_fetch(_lib.DBG_SELECT, b)
+        assert np.array_equal(s0, s1)
+    _check(p, [0], flags=_lib.GEOM_RADIX_SELECT)
