@@ -14,6 +14,14 @@ adjoint chain), then the ELBO value and the Adam update.
 
 value = fwd+adjoint sample evaluations per second (32 per step).
 
+Serving (the metric's second part): 64 requests of the serving mix (image
+64..300 px, 2..4 sub-rays, 32..128 source, 0..3 subhaloes; one sample per
+step, 200 ELBO + Adam steps each).  First all requests arrive at once
+(capacity), then Poisson arrivals at 0.8 x that capacity; the fleet
+(continuous batching in shared launches) and sequential plain fits (one at a
+time) serve the same trace; fits/s and p50/p99 latency (completion - arrival)
+of both are reported under "serving".  Progress goes to stderr.
+
     python bench.py [--gpus 1] [--steps 40] [--warmup 5]
 """
 from __future__ import annotations
@@ -79,15 +87,40 @@ def cpu_baseline(problem, budget_s: float):
     from oracle import rtu_oracle as O
     t0 = time.perf_counter()
     n = 0
-    while n < problem.batch:
-        O.loss_grad_problem(problem, n)
+    while time.perf_counter() - t0 < budget_s:
+        O.loss_grad_problem(problem, n % problem.batch)
         n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "evals/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{n} of the {problem.batch} samples of one step (fwd + gradient each, FP64), "
-                      f"{dt:.1f} s"}
+            "sample": f"{n} evaluations (fwd + gradient, FP64) cycling over the {problem.batch} samples of "
+                      f"one ELBO step of the same workload, {dt:.1f} s"}
+
+
+def note(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def serving_bench(n: int, steps: int) -> dict:
+    """Fleet vs sequential plain fits on the serving mix (see module docstring)."""
+    from paper_2606_30620_amd import serve
+
+    # warm-up (kernel loading) on a few short requests
+    serve.serve_fleet(serve.make_requests(8, float("inf"), steps=10, first_id=900000))
+    cap_reqs = serve.make_requests(n, float("inf"), steps=steps, first_id=0)
+    cap = serve.serve_fleet(cap_reqs, keep_results=True)
+    out_of_domain = sum(1 for r in cap.results.values() if r[3] & 8)
+    note(f"serving capacity {cap.summary()}")
+    rate = 0.8 * cap.fits_per_s
+    reqs = serve.make_requests(n, rate, steps=steps, first_id=10000, seed=505)
+    fleet = serve.serve_fleet(reqs)
+    note(f"serving fleet on the Poisson trace {fleet.summary()}")
+    seq = serve.serve_sequential(reqs)
+    note(f"serving sequential on the same trace {seq.summary()}")
+    return {"workload": f"{n} requests of the serving mix, {steps} ELBO + Adam steps each, 1 sample per step",
+            "capacity_fits_per_s": round(cap.fits_per_s, 2), "arrival_rate_per_s": round(rate, 2),
+            "fleet": fleet.summary(), "sequential": seq.summary(),
+            "speedup_fits_per_s": round(fleet.fits_per_s / seq.fits_per_s, 2),
+            "fits_leaving_parameter_domain": out_of_domain}
 
 
 def main():
@@ -97,6 +130,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=200)
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device 3 times (a plain copy "
                          "kernel of known size, to scale the HBM counters)")
@@ -125,6 +161,7 @@ def main():
     stream = torch.cuda.current_stream()
     fit.step(args.warmup)
     torch.cuda.synchronize()
+    note(f"warm-up done ({args.warmup} ELBO steps of {S} samples)")
 
     plan.profile_begin(args.steps)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -136,6 +173,7 @@ def main():
     ms = e0.elapsed_time(e1)
     stages = plan.profile_end()
     ms_step = ms / args.steps
+    note(f"timed {args.steps} ELBO steps: {ms_step:.4f} ms/step")
     value = S * args.steps / (ms / 1e3)
 
     # dominant kernel and its roofline (ALU-bound: see the design doc)
@@ -164,6 +202,8 @@ def main():
                    "elbo_last": float(trace[-1]) if trace.size else None},
         "roofline": roof,
     }
+    if not args.no_serve:
+        line["serving"] = serving_bench(args.serve_requests, args.serve_steps)
     if args.calib_copy:
         src = torch.ones(args.calib_copy // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -172,6 +212,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
     if not args.no_cpu:
+        note("oracle on the host (cpu_baseline)")
         line["cpu_baseline"] = cpu_baseline(problem, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

@@ -444,25 +444,42 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 
 // In-place radix-2 transforms of nl lines of length n = 2^logn held in LDS with
 // line stride ls, input already in bit-reversed order.  sign = -1 forward
-// (e^{-2 pi i k x / n}), +1 inverse; no normalisation.
-__device__ __forceinline__ void fft_lines(float2* buf, int nl, int n, int logn, int ls, float sign) {
+// (e^{-2 pi i k x / n}), +1 inverse; no normalisation.  tw: LDS copy of the
+// 128 twiddles e^{-2 pi i k / 256}.  Each thread takes its butterflies of a
+// stage FFT_U at a time, all loads first, so LDS latency overlaps.
+constexpr int FFT_U = 8;
+__device__ __forceinline__ void fft_lines(float2* buf, const float2* tw, int nl, int n, int logn, int ls,
+                                          float sign) {
   const int half_n = n >> 1;
   const int nb = nl * half_n;
+  const int nt = blockDim.x;
   for (int s = 1; s <= logn; ++s) {
     const int half = 1 << (s - 1);
-    for (int idx = threadIdx.x; idx < nb; idx += blockDim.x) {
-      const int l = idx >> (logn - 1);
-      const int k = idx & (half_n - 1);
-      const int grp = k >> (s - 1);
-      const int pos = k & (half - 1);
-      const int i0 = (grp << s) + pos;
-      float2 w = c_tw[pos << (8 - s)];
-      w.y *= -sign;  // table holds e^{-i}: forward keeps it, inverse conjugates
-      float2* p = buf + l * ls;
-      const float2 a = p[i0];
-      const float2 b = cmul(p[i0 + half], w);
-      p[i0] = make_float2(a.x + b.x, a.y + b.y);
-      p[i0 + half] = make_float2(a.x - b.x, a.y - b.y);
+    for (int base = threadIdx.x; base < nb; base += FFT_U * nt) {
+      float2 a[FFT_U], b[FFT_U], w[FFT_U];
+      int o[FFT_U];
+#pragma unroll
+      for (int j = 0; j < FFT_U; ++j) {
+        const int idx = base + j * nt;
+        if (idx < nb) {
+          const int l = idx >> (logn - 1);
+          const int k = idx & (half_n - 1);
+          const int pos = k & (half - 1);
+          o[j] = l * ls + ((k >> (s - 1)) << s) + pos;
+          w[j] = tw[pos << (8 - s)];
+          a[j] = buf[o[j]];
+          b[j] = buf[o[j] + half];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < FFT_U; ++j) {
+        if (base + j * nt < nb) {
+          const float2 ww = make_float2(w[j].x, -sign * w[j].y);  // table holds e^{-i}: inverse conjugates
+          const float2 t = cmul(b[j], ww);
+          buf[o[j]] = make_float2(a[j].x + t.x, a[j].y + t.y);
+          buf[o[j] + half] = make_float2(a[j].x - t.x, a[j].y - t.y);
+        }
+      }
     }
     __syncthreads();
   }
@@ -476,34 +493,58 @@ __device__ __forceinline__ int bitrev(int i, int logn) {
 // or every column (cols = true) is loaded through `ld(row, col)`, transformed
 // with sign1, handed to `mid(row, col, value)` (which may rescale it), then
 // transformed with sign2 if `twice`, and written through `st(row, col, value)`.
-// Lines are processed in chunks that fit the LDS buffer.
-template <class LD, class MID, class ST>
+// Lines are processed in chunks that fit the cap float2 slots of the LDS
+// buffer, which holds 128 more slots after them for the twiddle table.  The
+// global loads and stores go U per thread at a time.
+template <int U = FFT_U, class LD, class MID, class ST>
 __device__ void fft_pass(float2* lds, int cap, int n, int logn, bool cols, float sign1, bool twice, float sign2,
                          LD ld, MID mid, ST st) {
+  float2* tw = lds + cap;
+  for (int k = threadIdx.x; k < 128; k += blockDim.x) tw[k] = c_tw[k];
   const int ls = n + 1;
+  const int nt = blockDim.x;
   int chunk = cap / ls;
   if (chunk > n) chunk = n;
   for (int l0 = 0; l0 < n; l0 += chunk) {
     const int nl = min(chunk, n - l0);
     const int tot = nl * n;
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-      int l, i;
+    // element idx of the chunk: its line l, its index i along the line, and
+    // its (row, col) in the array
+    auto place = [&](int idx, int& l, int& i, int& row, int& col) {
       if (cols) { l = idx % nl; i = idx / nl; } else { i = idx & (n - 1); l = idx >> logn; }
-      const int row = cols ? i : l0 + l, col = cols ? l0 + l : i;
-      lds[l * ls + bitrev(i, logn)] = ld(row, col);
+      row = cols ? i : l0 + l;
+      col = cols ? l0 + l : i;
+    };
+    for (int base = threadIdx.x; base < tot; base += U * nt) {
+      float2 v[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        int l, i, row, col;
+        if (base + j * nt < tot) {
+          place(base + j * nt, l, i, row, col);
+          v[j] = ld(row, col);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        int l, i, row, col;
+        if (base + j * nt < tot) {
+          place(base + j * nt, l, i, row, col);
+          lds[l * ls + bitrev(i, logn)] = v[j];
+        }
+      }
     }
     __syncthreads();
-    fft_lines(lds, nl, n, logn, ls, sign1);
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-      int l, i;
-      if (cols) { l = idx % nl; i = idx / nl; } else { i = idx & (n - 1); l = idx >> logn; }
-      const int row = cols ? i : l0 + l, col = cols ? l0 + l : i;
+    fft_lines(lds, tw, nl, n, logn, ls, sign1);
+    for (int idx = threadIdx.x; idx < tot; idx += nt) {
+      int l, i, row, col;
+      place(idx, l, i, row, col);
       lds[l * ls + i] = mid(row, col, lds[l * ls + i]);
     }
     __syncthreads();
     if (twice) {
       // bit-reverse in place, then transform again
-      for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+      for (int idx = threadIdx.x; idx < tot; idx += nt) {
         const int l = idx >> logn, i = idx & (n - 1);
         const int j = bitrev(i, logn);
         if (j > i) {
@@ -514,13 +555,26 @@ __device__ void fft_pass(float2* lds, int cap, int n, int logn, bool cols, float
         }
       }
       __syncthreads();
-      fft_lines(lds, nl, n, logn, ls, sign2);
+      fft_lines(lds, tw, nl, n, logn, ls, sign2);
     }
-    for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-      int l, i;
-      if (cols) { l = idx % nl; i = idx / nl; } else { i = idx & (n - 1); l = idx >> logn; }
-      const int row = cols ? i : l0 + l, col = cols ? l0 + l : i;
-      st(row, col, lds[l * ls + i]);
+    for (int base = threadIdx.x; base < tot; base += U * nt) {
+      float2 v[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        int l, i, row, col;
+        if (base + j * nt < tot) {
+          place(base + j * nt, l, i, row, col);
+          v[j] = lds[l * ls + i];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        int l, i, row, col;
+        if (base + j * nt < tot) {
+          place(base + j * nt, l, i, row, col);
+          st(row, col, v[j]);
+        }
+      }
     }
     __syncthreads();
   }

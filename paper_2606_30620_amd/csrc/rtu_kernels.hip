@@ -519,7 +519,7 @@ __device__ void prep_gp(const SysDev& S, int b, unsigned char* smem, int cap) {
 }
 
 // Dynamic LDS of the prep kernels: the larger of the selection layout and the
-// FFT line buffer (fft_cap float2 slots).
+// FFT buffer (fft_cap float2 line slots, then the twiddle table).
 __global__ void __launch_bounds__(PREP_THREADS) k_prep(SysDev S, int fft_cap) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x, role = blockIdx.y;
@@ -1034,7 +1034,7 @@ __device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, int c
     double pacc[4] = {0.0, 0.0, 0.0, 0.0};   // sigma, n, zeta, alpha
     const float inv_n2 = 1.f / (float)n2;
     // rows: fbar = sbar ds/df, ds/df = alpha s sigmoid(x)/(s0 softplus(x)), x = f/s0
-    fft_pass(lds, cap, n, logn, false, -1.f, false, 0.f,
+    fft_pass<2>(lds, cap, n, logn, false, -1.f, false, 0.f,
              [&](int r, int c) {
                const int q = r * n + c;
                const float x = fo[q] * 100.f;
@@ -1048,7 +1048,7 @@ __device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, int c
              [&](int, int, float2 v) { return v; },
              [&](int r, int c, float2 v) { T[r * n + c] = v; });
     // columns: forward -> Fbar; spectrum gradient; multiply by sqrt(P); inverse
-    fft_pass(lds, cap, n, logn, true, -1.f, true, 1.f,
+    fft_pass<2>(lds, cap, n, logn, true, -1.f, true, 1.f,
              [&](int r, int c) { return T[r * n + c]; },
              [&](int r, int c, float2 v) {
                const float kx = fft_freq(c, n), ky = fft_freq(r, n);
@@ -1066,7 +1066,7 @@ __device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, int c
              },
              [&](int r, int c, float2 v) { T[r * n + c] = v; });
     uint32_t bad = 0;
-    fft_pass(lds, cap, n, logn, false, 1.f, false, 0.f,
+    fft_pass<2>(lds, cap, n, logn, false, 1.f, false, 0.f,
              [&](int r, int c) { return T[r * n + c]; },
              [&](int, int, float2 v) { return v; },
              [&](int r, int c, float2 v) {
@@ -1131,22 +1131,23 @@ hipError_t upload_constants() {
 
 // The FFT keeps min(n, cap / (n + 1)) lines of the grid in LDS at a time:
 // every line of a grid up to 128 per side, 64-line chunks beyond.
+// The buffer holds the lines plus the 128-entry twiddle table.
 int fft_lds_cap(int n_src) { return n_src <= 128 ? n_src * (n_src + 1) : FFT_LDS_MAX; }
 size_t prep_lds_bytes(int n_src) {
-  const size_t f = (size_t)fft_lds_cap(n_src) * sizeof(float2);
+  const size_t f = (size_t)(fft_lds_cap(n_src) + 128) * sizeof(float2);
   return f > sizeof(SelLds) ? f : sizeof(SelLds);
 }
 // k_post shares its dynamic LDS between the FFT lines and the per-node
 // lens-parameter rows of the knot adjoint ([4K][n_lens] doubles).
 size_t post_lds_bytes(int n_src, int n_lens) {
-  const size_t f = (size_t)fft_lds_cap(n_src) * sizeof(float2);
+  const size_t f = (size_t)(fft_lds_cap(n_src) + 128) * sizeof(float2);
   const size_t m = (size_t)4 * K * n_lens * sizeof(double);
   return f > m ? f : m;
 }
 
 hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
   hipLaunchKernelGGL(k_prep, dim3(batch, 3), dim3(PREP_THREADS), prep_lds_bytes(h.n_src), s, h,
-                     (int)(prep_lds_bytes(h.n_src) / sizeof(float2)));
+                     fft_lds_cap(h.n_src));
   return hipGetLastError();
 }
 
@@ -1270,7 +1271,7 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
     case RTU_STAGE_PREP:
       if (L.n_prep)
         hipLaunchKernelGGL(kf_prep, dim3(L.n_prep), dim3(PREP_THREADS), L.lds_prep, s, L.sys, L.t_prep, round,
-                           (int)(L.lds_prep / sizeof(float2)));
+                           (int)(L.lds_prep / sizeof(float2)) - 128);
       break;
     case RTU_STAGE_RAYS_FWD:
       if (L.n_fwd[0])
@@ -1297,7 +1298,7 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
     case RTU_STAGE_POST:
       if (L.n_post)
         hipLaunchKernelGGL(kf_post, dim3(L.n_post), dim3(PREP_THREADS), L.lds_post, s, L.sys, L.t_post, round,
-                           (int)(L.lds_post / sizeof(float2)));
+                           (int)(L.lds_post / sizeof(float2)) - 128);
       break;
     default:
       return launch_fleet_fit_stage(L, stage, round, eps, s);
