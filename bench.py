@@ -40,18 +40,25 @@ sys.path.insert(0, ROOT)
 METRIC = "ELBO fwd+adjoint evals/s (200^2 img, 64^2 src); served fits/s + p99 latency"
 
 # Algorithmic FP32 operations per sub-ray (SIE + external shear, no
-# subhaloes), counted from the formulas each kernel evaluates: add, sub, mul
-# = 1, fused multiply-add = 2, compare = 1, and each of sqrt, reciprocal,
-# atan, atanh counted as one operation.  Breakdown in the design doc.
-FLOP_PER_RAY_FWD = 126
-FLOP_PER_RAY_ADJ = 365
-# MI355X peaks (AMD published): FP32 vector 157.3 TFLOP/s, HBM3E 8 TB/s
-PEAK_FP32_TFLOPS = 157.3
+# subhaloes), counted from the formulas of the method: add, sub, mul, compare
+# = 1, fused multiply-add = 2, and each of sqrt, reciprocal, floor, atan,
+# atanh = 1.  The forward is the lens equation (45), the knot interval (4),
+# the Hermite CDF on both axes (42), the bilinear sample (23), the sub-ray sum
+# and position (5); the adjoint recomputes the forward with the derivative
+# factors (118 + 52) and adds the bilinear adjoint with the source scatter
+# (26), the knot moments (16) and the lens vector-Jacobian product (67).
+FLOP_PER_RAY_FWD = 118
+FLOP_PER_RAY_ADJ = 279
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s of
+# unpacked FP32.  The published 157.3 counts packed (2 x FP32) instructions,
+# which this build disables; both are reported.
+PEAK_FP32_TFLOPS = 78.6
+PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
-KERNEL_OF_STAGE = {"rays_adj": "k_rays_adj", "rays_fwd": "k_rays_fwd", "psf_fwd": "k_psf",
-                   "psf_adj": "k_psf", "prep": "k_prep", "post": "k_post", "sample": "k_sample",
-                   "adam": "k_elbo+k_adam"}
+KERNEL_OF_STAGE = {"rays_adj": "kf_rays_adj<true>", "rays_fwd": "kf_rays_fwd<true>", "psf_fwd": "kf_psf",
+                   "psf_adj": "kf_psf", "prep": "kf_prep", "post": "kf_post", "sample": "kf_sample",
+                   "adam": "kf_elbo+kf_adam"}
 
 
 def kernel_source_hash() -> str:
@@ -131,6 +138,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving section (for profiling)")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=200)
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -147,6 +155,10 @@ def main():
     import torch
 
     from paper_2606_30620_amd import _lib, api, synth
+
+    if args.serve_only:
+        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_steps)}), flush=True)
+        return
 
     S = 32
     problem = synth.make_problem("C2", batch=S)
@@ -188,7 +200,8 @@ def main():
         roof = {"bound": "alu", "kernel": KERNEL_OF_STAGE[dom], "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                 "traffic": traffic, "avg_launch_ms": round(per_launch[dom], 4),
-                "flop_per_launch": flops * rays * S}
+                "flop_per_launch": flops * rays * S,
+                "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4)}
     _, _, trace = fit.read()
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "evals/s", "n_gpus": 1,
