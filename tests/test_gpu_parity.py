@@ -169,3 +169,23 @@ def test_radix_selection_matches_histogram_selection(case):
         s1 = plan1.debug_fetch(_lib.DBG_SELECT, b)
         assert np.array_equal(s0, s1)
     _check(p, [0], flags=_lib.GEOM_RADIX_SELECT)
+
+
+@pytest.mark.parametrize("seed", [303, 319, 325])
+def test_c3_full_size_parity(seed):
+    """C3 at full size: 400x400 with 3x3 sub-rays (1.44M rays per sample),
+    128x128 source, 31x31 PSF and truncated-NFW subhaloes (seed 303: 9,
+    319: 10 = the maximum, 325: 1); batch 4 in one launch, first and last
+    samples compared element by element with the oracle."""
+    p = synth.make_problem("C3", batch=4, seed=seed)
+    say(f"[gpu] C3 400x400 ss=3 n_src=128 psf=31, seed {seed}, {int(p.n_sub[0])} truncated NFW, batch 4")
+    _check(p, [0, 3])
+
+
+def test_c4_full_size_parity():
+    """C4 at full size in its launch configuration: 512x512 with 4x4 sub-rays
+    (4.2M rays per sample), 256x256 source (chunked FFT, global source grid),
+    64 samples in one launch; samples 0 and 63 compared with the oracle."""
+    say("[gpu] C4 512x512 ss=4 n_src=256 psf=21, batch 64, samples 0 and 63")
+    p = synth.make_problem("C4", batch=64)
+    _check(p, [0, 63])
