@@ -321,28 +321,6 @@ __device__ __forceinline__ int knot_count_from(const float* X, float z, int k) {
   return ok ? k : knot_count(X, z);
 }
 
-// Cubic Hermite spline through (X_k, u_k) with slopes S_k, linear outside
-// (App. C step iv).  ih[l] = 1/(X_{l+1} - X_l).  Returns g(z) and dg = dg/dz;
-// tt = t in [0, 1) inside an interval, z - X_end on the linear continuations.
-__device__ __forceinline__ float cdf_eval(const float* X, const float* S, const float* ih, float z, int k,
-                                          float& dg, float& tt) {
-  if (k == 0) { tt = z - X[0]; dg = S[0]; return c_u[0] + S[0] * tt; }
-  if (k >= K) { tt = z - X[K - 1]; dg = S[K - 1]; return c_u[K - 1] + S[K - 1] * tt; }
-  const int l = k - 1;
-  const float Xl = X[l];
-  const float h = X[l + 1] - Xl;
-  const float ihh = ih[l];
-  const float t = (z - Xl) * ihh;
-  tt = t;
-  const float t2 = t * t, t3 = t2 * t;
-  const float u0 = c_u[l], du = c_u[l + 1] - u0;
-  const float hs0 = h * S[l], hs1 = h * S[l + 1];
-  const float g = u0 + du * (3.f * t2 - 2.f * t3) + hs0 * (t3 - 2.f * t2 + t) + hs1 * (t3 - t2);
-  const float dgdt = du * (6.f * t - 6.f * t2) + hs0 * (3.f * t2 - 4.f * t + 1.f) + hs1 * (3.f * t2 - 2.f * t);
-  dg = dgdt * ihh;
-  return g;
-}
-
 // Knot adjoint of one axis, accumulated per interval as moments
 // m_j = sum ybar t^j of the rays in it; kb_flush turns them into
 // d loss / d X_l, X_{l+1}, S_l, S_{l+1} (every partial derivative of the

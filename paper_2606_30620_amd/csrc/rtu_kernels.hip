@@ -29,12 +29,14 @@ __constant__ double c_D[K * K];
 __constant__ float2 c_tw[128];
 
 // ====================================================================== helpers
-__device__ __forceinline__ void pixel_xy(const SysDev& S, int i, int j, int a, int b, float& x, float& y) {
-  // pixel centre ((j - (N-1)/2) d, (i - (N-1)/2) d) plus the sub-ray offset
-  // (((b + 1/2)/ss - 1/2) d, ((a + 1/2)/ss - 1/2) d)
+// Sub-ray (a, b) of pixel (i, j) sits at the pixel centre
+// ((j - (N-1)/2) d, (i - (N-1)/2) d) plus (((b + 1/2)/ss - 1/2) d,
+// ((a + 1/2)/ss - 1/2) d), i.e. at (x0 + b dxs, y0 + a dxs).
+__device__ __forceinline__ void subray_origin(const SysDev& S, int i, int j, float& x0, float& y0, float& dxs) {
   const float inv = 1.f / (float)S.ss;
-  x = ((float)j + ((float)b + 0.5f) * inv - 0.5f * (float)S.n_img) * S.pix;
-  y = ((float)i + ((float)a + 0.5f) * inv - 0.5f * (float)S.n_img) * S.pix;
+  x0 = ((float)j + 0.5f * inv - 0.5f * (float)S.n_img) * S.pix;
+  y0 = ((float)i + 0.5f * inv - 0.5f * (float)S.n_img) * S.pix;
+  dxs = inv * S.pix;
 }
 
 __device__ __forceinline__ int n_sub_of(const SysDev& S, int b) {
@@ -532,6 +534,11 @@ __global__ void __launch_bounds__(PREP_THREADS) k_prep(SysDev S, int fft_cap) {
 // padded index (i + 1) * (n + 2) + (j + 1) for i, j in [-1, n].
 struct RayLdsHead {
   double kb[4 * K];  // knot adjoint: dX (x), dS (x), dX (y), dS (y)
+  // per axis and interval k (0: below the first knot, K: above the last; else
+  // [X_{k-1}, X_k)): the local coordinate t = (z - ct.x) * ct.y and the grid
+  // coordinate T = n g - 1/2 = ((cq.w t + cq.z) t + cq.y) t + cq.x
+  float4 cq[2][K + 1];
+  float2 ct[2][K + 1];
   float X[2][K], Sl[2][K], ih[2][K], dp[2][K];
   Nfw nfw[RTU_MAX_SUB];
   float pad[2];
@@ -556,6 +563,37 @@ __device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H
     const int ax = i / K, k = i - ax * K;
     H.ih[ax][k] = k < K - 1 ? 1.f / (kn[ax * 2 * K + k + 1] - kn[ax * 2 * K + k]) : 0.f;
   }
+  // the Hermite pieces (App. C iv) as cubics in t, scaled to grid coordinates:
+  // g = u_l + du (3t^2 - 2t^3) + h S_l (t^3 - 2t^2 + t) + h S_r (t^3 - t^2)
+  const float n = (float)S.n_src;
+  for (int i = threadIdx.x; i < 2 * (K + 1); i += blockDim.x) {
+    const int ax = i / (K + 1), k = i - ax * (K + 1);
+    const float* X = kn + ax * 2 * K;
+    const float* Sl = X + K;
+    if (k == 0 || k == K) {          // linear continuation with the end slope
+      const int e = k == 0 ? 0 : K - 1;
+      H.ct[ax][k] = make_float2(X[e], 1.f);
+      H.cq[ax][k] = make_float4(n * c_u[e] - 0.5f, n * Sl[e], 0.f, 0.f);
+    } else {
+      const int l = k - 1;
+      const float h = X[l + 1] - X[l];
+      const float du = c_u[l + 1] - c_u[l], hs0 = h * Sl[l], hs1 = h * Sl[l + 1];
+      H.ct[ax][k] = make_float2(X[l], 1.f / h);
+      H.cq[ax][k] = make_float4(n * c_u[l] - 0.5f, n * hs0, n * (3.f * du - 2.f * hs0 - hs1),
+                                n * (hs0 + hs1 - 2.f * du));
+    }
+  }
+}
+
+// Grid coordinate T = n g(z) - 1/2 of the CDF spline on interval k, its local
+// coordinate t and, with D, dT/dz.
+template <bool D>
+__device__ __forceinline__ float cdf_grid(const RayLdsHead& H, int ax, int k, float z, float& t, float& dT) {
+  const float4 c = H.cq[ax][k];
+  const float2 p = H.ct[ax][k];
+  t = (z - p.x) * p.y;
+  if (D) dT = fmaf(fmaf(3.f * c.w, t, 2.f * c.z), t, c.y) * p.y;
+  return fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
 }
 
 template <bool LDSGRID>
@@ -569,14 +607,14 @@ __device__ __forceinline__ void load_grid(const SysDev& S, int b, float* g) {
   }
 }
 
-// bilinear weights of y on the n-grid (nodes at (j + 1/2)/n); returns false if
-// all four corners lie outside the zero-padded grid.
+// bilinear weights at grid coordinates (tx, ty) = n y - 1/2 (nodes at
+// (j + 1/2)/n); returns false if all four corners lie outside the zero-padded
+// grid.
 struct Bil {
   int i0, j0;
   float fx, fy;
 };
-__device__ __forceinline__ bool bil_setup(float yx, float yy, int n, Bil& o) {
-  const float tx = yx * (float)n - 0.5f, ty = yy * (float)n - 0.5f;
+__device__ __forceinline__ bool bil_setup(float tx, float ty, int n, Bil& o) {
   if (!(tx >= -1.f && tx < (float)n && ty >= -1.f && ty < (float)n)) return false;
   const float fj = floorf(tx), fi = floorf(ty);
   o.j0 = (int)fj; o.i0 = (int)fi;
@@ -614,19 +652,22 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
   const float* gsrc = S.src + (size_t)b * n * n;
   float acc = 0.f;
   int kx = 0, ky = 0;
+  float x0, y0, dxs;
+  subray_origin(S, i, j, x0, y0, dxs);
   for (int a = 0; a < S.ss; ++a) {
+    const float y = fmaf((float)a, dxs, y0);
     for (int cc = 0; cc < S.ss; ++cc) {
       const int c = (a & 1) ? S.ss - 1 - cc : cc;   // serpentine: neighbouring sub-rays in turn
-      float x, y, bx, by;
-      pixel_xy(S, i, j, a, c, x, y);
+      const float x = fmaf((float)c, dxs, x0);
+      float bx, by;
       shoot(S, L, H.nfw, nsub, x, y, bx, by);
       kx = knot_count_from(H.X[0], bx, kx);
       ky = knot_count_from(H.X[1], by, ky);
-      float dgx, dgy, tx, ty;
-      const float yx = cdf_eval(H.X[0], H.Sl[0], H.ih[0], bx, kx, dgx, tx);
-      const float yy = cdf_eval(H.X[1], H.Sl[1], H.ih[1], by, ky, dgy, ty);
+      float tx, ty, dTx, dTy;
+      const float Tx = cdf_grid<false>(H, 0, kx, bx, tx, dTx);
+      const float Ty = cdf_grid<false>(H, 1, ky, by, ty, dTy);
       Bil B;
-      if (bil_setup(yx, yy, n, B)) {
+      if (bil_setup(Tx, Ty, n, B)) {
         float s00, s01, s10, s11;
         bil_corners<LDSGRID>(g, gsrc, n, B, s00, s01, s10, s11);
         acc += (1.f - B.fy) * ((1.f - B.fx) * s00 + B.fx * s01) + B.fy * ((1.f - B.fx) * s10 + B.fx * s11);
@@ -700,11 +741,13 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
       }
       c00 = c01 = c10 = c11 = 0.f;
     };
+    float x0, y0, dxs;
+    subray_origin(S, i, j, x0, y0, dxs);
     for (int a = 0; a < S.ss; ++a) {
+      const float y = fmaf((float)a, dxs, y0);
       for (int cc = 0; cc < S.ss; ++cc) {
         const int c = (a & 1) ? S.ss - 1 - cc : cc;   // serpentine order
-        float x, y;
-        pixel_xy(S, i, j, a, c, x, y);
+        const float x = fmaf((float)c, dxs, x0);
         SieRay E;
         float ax, ay;
         sie_shear_alpha<true>(L, x, y, ax, ay, E);
@@ -712,11 +755,11 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         const float bx = x - ax, by = y - ay;
         kx = knot_count_from(H.X[0], bx, kx);
         ky = knot_count_from(H.X[1], by, ky);
-        float dgx, dgy, tx, ty;
-        const float yx = cdf_eval(H.X[0], H.Sl[0], H.ih[0], bx, kx, dgx, tx);
-        const float yy = cdf_eval(H.X[1], H.Sl[1], H.ih[1], by, ky, dgy, ty);
+        float tx, ty, dTx, dTy;
+        const float Tx = cdf_grid<true>(H, 0, kx, bx, tx, dTx);
+        const float Ty = cdf_grid<true>(H, 1, ky, by, ty, dTy);
         Bil B;
-        if (!bil_setup(yx, yy, n, B)) continue;
+        if (!bil_setup(Tx, Ty, n, B)) continue;
         float s00, s01, s10, s11;
         bil_corners<false>(g, gsrc, n, B, s00, s01, s10, s11);
         // d loss / d s at the four corners
@@ -726,17 +769,17 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         c01 += vb * w01;
         c10 += vb * (B.fy - w11);
         c11 += vb * w11;
-        // d loss / d y
-        const float vn = vb * (float)n;
-        const float ybx = vn * ((1.f - B.fy) * (s01 - s00) + B.fy * (s11 - s10));
-        const float yby = vn * ((1.f - B.fx) * (s10 - s00) + B.fx * (s11 - s01));
+        // d loss / d T (grid coordinates) and d loss / d g = n d loss / d T
+        const float Tbx = vb * ((1.f - B.fy) * (s01 - s00) + B.fy * (s11 - s10));
+        const float Tby = vb * ((1.f - B.fx) * (s10 - s00) + B.fx * (s11 - s01));
+        const float ybx = Tbx * (float)n, yby = Tby * (float)n;
         // knots and slopes of the CDF splines (moments per interval)
         if (kx != cx.k) { km_flush(cx, H.X[0], H.Sl[0], H.ih[0], H.kb); cx.k = kx; }
         km_add(cx, ybx, tx);
         if (ky != cy.k) { km_flush(cy, H.X[1], H.Sl[1], H.ih[1], H.kb + 2 * K); cy.k = ky; }
         km_add(cy, yby, ty);
         // d loss / d beta -> d loss / d alpha = -d loss / d beta
-        const float abx = -ybx * dgx, aby = -yby * dgy;
+        const float abx = -Tbx * dTx, aby = -Tby * dTy;
         sie_shear_vjp(L, E, x, y, abx, aby, acc);
         for (int q = 0; q < nsub; ++q) {
           float* sa = subacc + (4 * q) * RAY_THREADS + threadIdx.x;
