@@ -56,6 +56,7 @@ struct SysDev {
   uint32_t* status;           // [B]
   // workspace (owned by the plan)
   float* src;                 // [B][n^2] source brightness s
+  float* srcp;                // [B][(n+2)^2] s with a one-cell zero border (corner reads need no bounds checks)
   float* fld;                 // [B][n^2] GP field f
   float2* F;                  // [B][n^2] DFT of the latent
   float2* tmp;                // [B][n^2] FFT scratch

@@ -473,7 +473,15 @@ __device__ void prep_gp(const SysDev& S, int b, unsigned char* smem, int cap) {
   float2* T = S.tmp + (size_t)b * n2;
   float* fo = S.fld + (size_t)b * n2;
   float* so = S.src + (size_t)b * n2;
+  float* sp = S.srcp + (size_t)b * (n + 2) * (n + 2);
   const float* ps = S.ps + (size_t)b * 4;
+  // zero border of the padded copy of s
+  for (int q = threadIdx.x; q < 4 * (n + 1); q += blockDim.x) {
+    const int side = q / (n + 1), o = q - side * (n + 1);
+    const int r = side == 0 ? 0 : (side == 1 ? n + 1 : (side == 2 ? o + 1 : o));
+    const int c = side == 0 ? o : (side == 1 ? o + 1 : (side == 2 ? 0 : n + 1));
+    sp[r * (n + 2) + c] = 0.f;
+  }
   // zero the adjoint accumulator of this sample for the ray adjoint
   if (S.want_grad) {
     double* sb = S.sbar + (size_t)b * n2;
@@ -516,7 +524,9 @@ __device__ void prep_gp(const SysDev& S, int b, unsigned char* smem, int cap) {
              const float f = v.x * inv_n2;
              fo[r * n + c] = f;
              const float x = f * 100.f;   // f / s0, s0 = 0.01
-             so[r * n + c] = __expf(alpha * (-4.605170186f + log_softplus_f(x)));
+             const float s = __expf(alpha * (-4.605170186f + log_softplus_f(x)));
+             so[r * n + c] = s;
+             sp[(r + 1) * (n + 2) + c + 1] = s;
            });
 }
 
@@ -599,12 +609,9 @@ __device__ __forceinline__ float cdf_grid(const RayLdsHead& H, int ax, int k, fl
 template <bool LDSGRID>
 __device__ __forceinline__ void load_grid(const SysDev& S, int b, float* g) {
   if (!LDSGRID) return;
-  const int n = S.n_src, np = n + 2;
-  const float* src = S.src + (size_t)b * n * n;
-  for (int i = threadIdx.x; i < np * np; i += blockDim.x) {
-    const int r = i / np - 1, c = i - (i / np) * np - 1;
-    g[i] = (r >= 0 && r < n && c >= 0 && c < n) ? src[r * n + c] : 0.f;
-  }
+  const int np = S.n_src + 2;
+  const float* sp = S.srcp + (size_t)b * np * np;
+  for (int i = threadIdx.x; i < np * np; i += blockDim.x) g[i] = sp[i];
 }
 
 // bilinear weights at grid coordinates (tx, ty) = n y - 1/2 (nodes at
@@ -622,17 +629,13 @@ __device__ __forceinline__ bool bil_setup(float tx, float ty, int n, Bil& o) {
   return true;
 }
 
-template <bool LDSGRID>
-__device__ __forceinline__ void bil_corners(const float* g, const float* gsrc, int n, const Bil& B,
-                                            float& s00, float& s01, float& s10, float& s11) {
-  if (LDSGRID) {
-    const int np = n + 2;
-    const int p = (B.i0 + 1) * np + (B.j0 + 1);
-    s00 = g[p]; s01 = g[p + 1]; s10 = g[p + np]; s11 = g[p + np + 1];
-  } else {
-    auto at = [&](int i, int j) { return (i >= 0 && i < n && j >= 0 && j < n) ? gsrc[i * n + j] : 0.f; };
-    s00 = at(B.i0, B.j0); s01 = at(B.i0, B.j0 + 1); s10 = at(B.i0 + 1, B.j0); s11 = at(B.i0 + 1, B.j0 + 1);
-  }
+// The four corner values from a zero-bordered copy of the grid (in LDS or in
+// global memory), padded index (i + 1) (n + 2) + (j + 1).
+__device__ __forceinline__ void bil_corners(const float* g, int n, const Bil& B, float& s00, float& s01,
+                                            float& s10, float& s11) {
+  const int np = n + 2;
+  const int p = (B.i0 + 1) * np + (B.j0 + 1);
+  s00 = g[p]; s01 = g[p + 1]; s10 = g[p + np]; s11 = g[p + np + 1];
 }
 
 template <bool LDSGRID>
@@ -649,7 +652,7 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
   const int nsub = n_sub_of(S, b);
   const Sie L = make_sie(lensp);
   const int n = S.n_src;
-  const float* gsrc = S.src + (size_t)b * n * n;
+  const float* gsrc = LDSGRID ? g : S.srcp + (size_t)b * (n + 2) * (n + 2);
   float acc = 0.f;
   int kx = 0, ky = 0;
   float x0, y0, dxs;
@@ -669,7 +672,7 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
       Bil B;
       if (bil_setup(Tx, Ty, n, B)) {
         float s00, s01, s10, s11;
-        bil_corners<LDSGRID>(g, gsrc, n, B, s00, s01, s10, s11);
+        bil_corners(gsrc, n, B, s00, s01, s10, s11);
         acc += (1.f - B.fy) * ((1.f - B.fx) * s00 + B.fx * s01) + B.fy * ((1.f - B.fx) * s10 + B.fx * s11);
       }
     }
@@ -688,10 +691,9 @@ template <bool LDSGRID>
 __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* smem) {
   RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
   const int n = S.n_src, np = n + 2;
-  // the source grid is read through L1/L2 here; only d loss / d s lives in LDS,
-  // accumulated in FP64 so that its value does not depend on the order of the
-  // atomic additions (to FP32 rounding)
-  const float* g = nullptr;
+  // the source grid is read from its zero-bordered copy through L1/L2 here;
+  // only d loss / d s lives in LDS, accumulated in FP64 so that its value does
+  // not depend on the order of the atomic additions (to FP32 rounding)
   double* gb = reinterpret_cast<double*>(smem + sizeof(RayLdsHead));          // padded grid
   float* subacc = reinterpret_cast<float*>(gb + (LDSGRID ? np * np : 0));    // [4 n_sub_max][256]
   size_t off = sizeof(RayLdsHead) + (size_t)(LDSGRID ? np * np : 0) * 8 +
@@ -710,7 +712,7 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   const float* lensp = S.lens + (size_t)b * S.n_lens;
   const int nsub = n_sub_of(S, b);
   const Sie L = make_sie(lensp);
-  const float* gsrc = S.src + (size_t)b * n * n;
+  const float* gsrc = S.srcp + (size_t)b * np * np;
   double* gsb = S.sbar + (size_t)b * n * n;
   SieAcc acc;
   acc.zero();
@@ -761,7 +763,7 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         Bil B;
         if (!bil_setup(Tx, Ty, n, B)) continue;
         float s00, s01, s10, s11;
-        bil_corners<false>(g, gsrc, n, B, s00, s01, s10, s11);
+        bil_corners(gsrc, n, B, s00, s01, s10, s11);
         // d loss / d s at the four corners
         if (B.i0 != ci || B.j0 != cj) { flush_cell(); ci = B.i0; cj = B.j0; }
         const float w01 = B.fx * (1.f - B.fy), w11 = B.fx * B.fy;

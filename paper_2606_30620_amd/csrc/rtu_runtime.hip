@@ -114,6 +114,7 @@ size_t carve_workspace(SysDev& h, int B, char* base) {
   Carve c{base};
   const size_t n2 = (size_t)h.n_src * h.n_src, N2 = (size_t)h.n_img * h.n_img;
   h.src = c.take<float>(B * n2);
+  h.srcp = c.take<float>((size_t)B * (h.n_src + 2) * (h.n_src + 2));
   h.fld = c.take<float>(B * n2);
   h.F = c.take<float2>(B * n2);
   h.tmp = c.take<float2>(B * n2);
