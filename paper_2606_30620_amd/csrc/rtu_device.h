@@ -307,20 +307,6 @@ __device__ __forceinline__ void nfw_vjp(const Nfw& N, float tau, float x, float 
 
 // ------------------------------------------------------------------ CDF spline
 // Number of knots <= z (0..K): the spline interval of z.
-__device__ __forceinline__ int knot_count(const float* X, float z) {
-  int k = 0;
-#pragma unroll
-  for (int step = 16; step >= 1; step >>= 1) {
-    if (k + step <= K && X[k + step - 1] <= z) k += step;
-  }
-  return k;
-}
-// The same, trying the interval of the previous sub-ray first.
-__device__ __forceinline__ int knot_count_from(const float* X, float z, int k) {
-  const bool ok = (k == 0 || X[k - 1] <= z) && (k == K || z < X[k]);
-  return ok ? k : knot_count(X, z);
-}
-
 // Knot adjoint of one axis, accumulated per interval as moments
 // m_j = sum ybar t^j of the rays in it; kb_flush turns them into
 // d loss / d X_l, X_{l+1}, S_l, S_{l+1} (every partial derivative of the
@@ -333,28 +319,31 @@ __device__ __forceinline__ void km_add(KnotMom& c, float yb, float t) {
   const float yt = yb * t, yt2 = yt * t;
   c.m0 += yb; c.m1 += yt; c.m2 += yt2; c.m3 = fmaf(yt2, t, c.m3);
 }
+// One code path for the Hermite intervals and the two linear continuations
+// (interval 0: g = u_0 + S_0 (z - X_0); interval K: the same at X_{K-1}), so
+// that lanes flushing different kinds of interval do not diverge.  du[l] =
+// u_{l+1} - u_l.
 __device__ __forceinline__ void km_flush(KnotMom& c, const float* X, const float* S, const float* ih,
-                                         double* kb /* dX[K], dS[K] */) {
+                                         const float* du_tab, double* kb /* dX[K], dS[K] */) {
   if (c.k < 0) return;
-  if (c.k == 0) {
-    atomicAdd(&kb[0], (double)(-S[0] * c.m0)); atomicAdd(&kb[K], (double)c.m1);
-  } else if (c.k >= K) {
-    atomicAdd(&kb[K - 1], (double)(-S[K - 1] * c.m0)); atomicAdd(&kb[2 * K - 1], (double)c.m1);
-  } else {
-    const int l = c.k - 1;
-    const float h = X[l + 1] - X[l], ihh = ih[l], Sl = S[l], Sr = S[l + 1];
-    const float du = c_u[l + 1] - c_u[l];
-    const float G10 = c.m3 - 2.f * c.m2 + c.m1;     // sum ybar (t^3 - 2t^2 + t)
-    const float G11 = c.m3 - c.m2;                  // sum ybar (t^3 - t^2)
-    const float gh = Sl * G10 + Sr * G11;           // sum ybar dg/dh at fixed t
-    const float a0 = h * Sl, a1 = 6.f * du - 4.f * h * Sl - 2.f * h * Sr, a2 = -6.f * du + 3.f * h * (Sl + Sr);
-    const float Atm1 = -a0 * c.m0 + (a0 - a1) * c.m1 + (a1 - a2) * c.m2 + a2 * c.m3;  // sum ybar dg/dt (t-1)
-    const float At = a0 * c.m1 + a1 * c.m2 + a2 * c.m3;                              // sum ybar dg/dt t
-    atomicAdd(&kb[l], (double)(Atm1 * ihh - gh));
-    atomicAdd(&kb[l + 1], (double)(gh - At * ihh));
-    atomicAdd(&kb[K + l], (double)(h * G10));
-    atomicAdd(&kb[K + l + 1], (double)(h * G11));
-  }
+  const bool lin = c.k == 0 || c.k >= K;
+  const int l = lin ? (c.k == 0 ? 0 : K - 1) : c.k - 1;
+  const int r = min(l + 1, K - 1);
+  const float h = X[r] - X[l], ihh = ih[l], Sl = S[l], Sr = S[r], du = du_tab[l];
+  const float G10 = c.m3 - 2.f * c.m2 + c.m1;     // sum ybar (t^3 - 2t^2 + t)
+  const float G11 = c.m3 - c.m2;                  // sum ybar (t^3 - t^2)
+  const float gh = Sl * G10 + Sr * G11;           // sum ybar dg/dh at fixed t
+  const float a0 = h * Sl, a1 = 6.f * du - 4.f * h * Sl - 2.f * h * Sr, a2 = -6.f * du + 3.f * h * (Sl + Sr);
+  const float Atm1 = -a0 * c.m0 + (a0 - a1) * c.m1 + (a1 - a2) * c.m2 + a2 * c.m3;  // sum ybar dg/dt (t-1)
+  const float At = a0 * c.m1 + a1 * c.m2 + a2 * c.m3;                              // sum ybar dg/dt t
+  const float v0 = lin ? -Sl * c.m0 : Atm1 * ihh - gh;
+  const float v1 = lin ? 0.f : gh - At * ihh;
+  const float v2 = lin ? c.m1 : h * G10;
+  const float v3 = lin ? 0.f : h * G11;
+  atomicAdd(&kb[l], (double)v0);
+  atomicAdd(&kb[r], (double)v1);
+  atomicAdd(&kb[K + l], (double)v2);
+  atomicAdd(&kb[K + r], (double)v3);
   c.m0 = c.m1 = c.m2 = c.m3 = 0.f;
 }
 

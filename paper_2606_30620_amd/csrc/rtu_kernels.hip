@@ -549,6 +549,9 @@ struct RayLdsHead {
   // coordinate T = n g - 1/2 = ((cq.w t + cq.z) t + cq.y) t + cq.x
   float4 cq[2][K + 1];
   float2 ct[2][K + 1];
+  float2 kr[2][K + 1];  // interval k as [kr.x, kr.y), with -inf / +inf at the ends
+  float xs[2][32];      // knots, then +inf (branch-free search)
+  float du[K];          // u_{l+1} - u_l (0 for l = K-1)
   float X[2][K], Sl[2][K], ih[2][K], dp[2][K];
   Nfw nfw[RTU_MAX_SUB];
   float pad[2];
@@ -573,6 +576,13 @@ __device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H
     const int ax = i / K, k = i - ax * K;
     H.ih[ax][k] = k < K - 1 ? 1.f / (kn[ax * 2 * K + k + 1] - kn[ax * 2 * K + k]) : 0.f;
   }
+  for (int i = threadIdx.x; i < 2 * 32; i += blockDim.x) {
+    const int ax = i >> 5, k = i & 31;
+    H.xs[ax][k] = k < K ? kn[ax * 2 * K + k] : INFINITY;
+    if (k <= K)
+      H.kr[ax][k] = make_float2(k == 0 ? -INFINITY : kn[ax * 2 * K + k - 1], k == K ? INFINITY : kn[ax * 2 * K + k]);
+  }
+  for (int i = threadIdx.x; i < K; i += blockDim.x) H.du[i] = i < K - 1 ? c_u[i + 1] - c_u[i] : 0.f;
   // the Hermite pieces (App. C iv) as cubics in t, scaled to grid coordinates:
   // g = u_l + du (3t^2 - 2t^3) + h S_l (t^3 - 2t^2 + t) + h S_r (t^3 - t^2)
   const float n = (float)S.n_src;
@@ -593,6 +603,21 @@ __device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H
                                 n * (hs0 + hs1 - 2.f * du));
     }
   }
+}
+
+// Interval of z on axis ax (the number of knots <= z), trying the previous
+// sub-ray's interval k first; the wave searches only if one of its lanes
+// missed, and then without branches.
+__device__ __forceinline__ int knot_find(const RayLdsHead& H, int ax, float z, int k) {
+  const float2 r = H.kr[ax][k];
+  const bool ok = r.x <= z && z < r.y;
+  if (__any(!ok)) {
+    int s = 0;
+#pragma unroll
+    for (int step = 16; step >= 1; step >>= 1) s = H.xs[ax][s + step - 1] <= z ? s + step : s;
+    k = ok ? k : min(s, K);
+  }
+  return k;
 }
 
 // Grid coordinate T = n g(z) - 1/2 of the CDF spline on interval k, its local
@@ -664,8 +689,8 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
       const float x = fmaf((float)c, dxs, x0);
       float bx, by;
       shoot(S, L, H.nfw, nsub, x, y, bx, by);
-      kx = knot_count_from(H.X[0], bx, kx);
-      ky = knot_count_from(H.X[1], by, ky);
+      kx = knot_find(H, 0, bx, kx);
+      ky = knot_find(H, 1, by, ky);
       float tx, ty, dTx, dTy;
       const float Tx = cdf_grid<false>(H, 0, kx, bx, tx, dTx);
       const float Ty = cdf_grid<false>(H, 1, ky, by, ty, dTy);
@@ -755,8 +780,8 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         sie_shear_alpha<true>(L, x, y, ax, ay, E);
         for (int q = 0; q < nsub; ++q) nfw_alpha(H.nfw[q], S.tau, x, y, ax, ay);
         const float bx = x - ax, by = y - ay;
-        kx = knot_count_from(H.X[0], bx, kx);
-        ky = knot_count_from(H.X[1], by, ky);
+        kx = knot_find(H, 0, bx, kx);
+        ky = knot_find(H, 1, by, ky);
         float tx, ty, dTx, dTy;
         const float Tx = cdf_grid<true>(H, 0, kx, bx, tx, dTx);
         const float Ty = cdf_grid<true>(H, 1, ky, by, ty, dTy);
@@ -776,9 +801,9 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         const float Tby = vb * ((1.f - B.fx) * (s10 - s00) + B.fx * (s11 - s01));
         const float ybx = Tbx * (float)n, yby = Tby * (float)n;
         // knots and slopes of the CDF splines (moments per interval)
-        if (kx != cx.k) { km_flush(cx, H.X[0], H.Sl[0], H.ih[0], H.kb); cx.k = kx; }
+        if (kx != cx.k) { km_flush(cx, H.X[0], H.Sl[0], H.ih[0], H.du, H.kb); cx.k = kx; }
         km_add(cx, ybx, tx);
-        if (ky != cy.k) { km_flush(cy, H.X[1], H.Sl[1], H.ih[1], H.kb + 2 * K); cy.k = ky; }
+        if (ky != cy.k) { km_flush(cy, H.X[1], H.Sl[1], H.ih[1], H.du, H.kb + 2 * K); cy.k = ky; }
         km_add(cy, yby, ty);
         // d loss / d beta -> d loss / d alpha = -d loss / d beta
         const float abx = -Tbx * dTx, aby = -Tby * dTy;
@@ -792,8 +817,8 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
       }
     }
     flush_cell();
-    km_flush(cx, H.X[0], H.Sl[0], H.ih[0], H.kb);
-    km_flush(cy, H.X[1], H.Sl[1], H.ih[1], H.kb + 2 * K);
+    km_flush(cx, H.X[0], H.Sl[0], H.ih[0], H.du, H.kb);
+    km_flush(cy, H.X[1], H.Sl[1], H.ih[1], H.du, H.kb + 2 * K);
   }
   if (LDSGRID) {
     atomicMin(&bbox[0], bi0); atomicMin(&bbox[1], bj0);
