@@ -88,32 +88,47 @@ __device__ __forceinline__ float poly_atanh_d(float t) {
   return p;
 }
 
-// atan(f a)/f with d/da and d/df (computed without cancellation for |f a| <= 1).
+// atan(f a)/f with d/da and d/df: the polynomial in (f a)^2 for |f a| <= 1,
+// else pi/2 - atan(1/|f a|) with the same polynomial.  The second form is
+// evaluated only when a lane of the wave needs it (a wave-uniform branch),
+// and then selected per lane.
 template <bool D>
 __device__ __forceinline__ void atan_over_f(float f, float invf, float a, float& v, float& da, float& df) {
   const float fa = f * a, t = fa * fa;
-  if (D) da = rcp(1.f + t);
-  if (t <= 1.f) {
-    v = a * poly_atan(t);
-    if (D) df = 2.f * f * a * a * a * poly_atan_d(t);
-  } else {
-    const float r = rcp(fabsf(fa));
-    const float at = copysignf(1.5707963267948966f - r * poly_atan(r * r), fa);
-    v = at * invf;
-    if (D) df = (a * da - v) * invf;
+  const bool big = t > 1.f;
+  const bool any_big = __any(big);
+  float r = 0.f, arg = t;
+  if (any_big) {
+    r = rcp(fabsf(fa));
+    arg = big ? r * r : t;
+  }
+  const float p = poly_atan(arg);
+  v = a * p;
+  if (D) {
+    da = rcp(1.f + t);
+    df = 2.f * f * a * a * a * poly_atan_d(arg);
+  }
+  if (any_big) {
+    const float vb = copysignf(1.5707963267948966f - r * p, fa) * invf;
+    v = big ? vb : v;
+    if (D) df = big ? (a * da - vb) * invf : df;
   }
 }
-// atanh(f b)/f with d/db and d/df (|f b| < 1).
+// atanh(f b)/f with d/db and d/df (|f b| < 1): the polynomial in (f b)^2 for
+// (f b)^2 <= 1/4, else the logarithm, evaluated when a lane of the wave needs it.
 template <bool D>
 __device__ __forceinline__ void atanh_over_f(float f, float invf, float b, float& v, float& db, float& df) {
   const float fb = f * b, t = fb * fb;
-  if (D) db = rcp(1.f - t);
-  if (t <= 0.25f) {
-    v = b * poly_atanh(t);
-    if (D) df = 2.f * f * b * b * b * poly_atanh_d(t);
-  } else {
-    v = 0.5f * fln((1.f + fb) * rcp(1.f - fb)) * invf;
-    if (D) df = (b * db - v) * invf;
+  const bool big = t > 0.25f;
+  v = b * poly_atanh(t);
+  if (D) {
+    db = rcp(1.f - t);
+    df = 2.f * f * b * b * b * poly_atanh_d(t);
+  }
+  if (__any(big)) {
+    const float vl = 0.5f * fln((1.f + fb) * rcp(1.f - fb)) * invf;
+    v = big ? vl : v;
+    if (D) df = big ? (b * db - vl) * invf : df;
   }
 }
 
@@ -133,18 +148,16 @@ __device__ __forceinline__ void sie_shear_alpha(const Sie& L, float x, float y, 
   E.yp = -L.s * dx + L.c * dy;
   const float qx = L.q * E.xp;
   const float psi2 = qx * qx + E.yp * E.yp;
-  float axp = 0.f, ayp = 0.f;
+  // a ray at the lens centre (psi = 0) is not deflected by the SIE; it takes
+  // the same arithmetic on a clamped psi and its result is selected away
   E.ok = psi2 > 1e-30f;
-  if (E.ok) {
-    const float psi = fsqrt(psi2);
-    E.ip = rcp(psi);
-    E.a = E.xp * E.ip;
-    E.b = E.yp * E.ip;
-    atan_over_f<D>(L.f, L.invf, E.a, E.A, E.dA, E.fA);
-    atanh_over_f<D>(L.f, L.invf, E.b, E.B, E.dB, E.fB);
-    axp = L.P * E.A;
-    ayp = L.P * E.B;
-  }
+  E.ip = __builtin_amdgcn_rsqf(fmaxf(psi2, 1e-30f));
+  E.a = E.xp * E.ip;
+  E.b = E.yp * E.ip;
+  atan_over_f<D>(L.f, L.invf, E.a, E.A, E.dA, E.fA);
+  atanh_over_f<D>(L.f, L.invf, E.b, E.B, E.dB, E.fB);
+  const float axp = E.ok ? L.P * E.A : 0.f;
+  const float ayp = E.ok ? L.P * E.B : 0.f;
   ax = L.c * axp - L.s * ayp + L.g1 * x + L.g2 * y;
   ay = L.s * axp + L.c * ayp + L.g2 * x - L.g1 * y;
 }
@@ -167,7 +180,10 @@ __device__ __forceinline__ void sie_shear_vjp(const Sie& L, const SieRay& E, flo
                                               float aby, SieAcc& acc) {
   acc.g1 += abx * x - aby * y;
   acc.g2 += abx * y + aby * x;
-  if (!E.ok) return;
+  // the SIE part contributes nothing for a ray at the lens centre
+  const float m = E.ok ? 1.f : 0.f;
+  abx *= m;
+  aby *= m;
   const float axp = L.P * E.A, ayp = L.P * E.B;
   // rotation alpha = R(phi) alpha': d/dphi R(phi) alpha' = (-alpha_y, alpha_x) of the SIE part
   const float rx = L.c * axp - L.s * ayp, ry = L.s * axp + L.c * ayp;
