@@ -37,17 +37,16 @@ __device__ __forceinline__ float eps_at(const FitDev& F, const float* eps, int s
   return eps ? eps[(size_t)s * F.dim + i] : normal_draw(F, step, s, i);
 }
 
-// z_s = mu + exp(rho) eps_s, scattered into the plan's per-sample inputs
+// z_s = mu + exp(rho) eps_s, scattered into the plan's per-sample inputs; the
+// draw is kept for the Adam update of rho
 __device__ __forceinline__ void sample_body(const FitDev& F, const float* eps, int step, int s, int i) {
   if (i >= F.dim) return;
-  const float z = F.mu[i] + __expf(F.rho[i]) * eps_at(F, eps, step, s, i);
+  const float e = eps_at(F, eps, step, s, i);
+  F.eps_s[(size_t)s * F.dim + i] = e;
+  const float z = F.mu[i] + __expf(F.rho[i]) * e;
   if (i < F.n_lens) F.z_lens[(size_t)s * F.n_lens + i] = z;
   else if (i < F.n_lens + 4) F.z_ps[(size_t)s * 4 + (i - F.n_lens)] = z;
   else F.z_lat[(size_t)s * F.n_src2 + (i - F.n_lens - 4)] = z;
-}
-
-__global__ void k_sample(FitDev F, const float* eps, int step) {
-  sample_body(F, eps, step, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __device__ __forceinline__ float grad_at(const FitDev& F, int s, int i) {
@@ -74,27 +73,33 @@ __device__ void elbo_body(const FitDev& F, int step, double* red) {
     double a = 0.0, l = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += red[w]; l += red[16 + w]; }
     F.trace[step] = -l / (double)F.S + F.elbo_const + a;
-    uint32_t st = 0;
-    for (int s = 0; s < F.S; ++s) st |= F.status[s];
-    if (F.status_acc) F.status_acc[0] |= st;
   }
-}
-
-__global__ void __launch_bounds__(1024) k_elbo(FitDev F, int step) {
-  __shared__ double red[32];
-  elbo_body(F, step, red);
+  // OR of the samples' status words
+  uint32_t st = 0;
+  for (int s = threadIdx.x; s < F.S; s += blockDim.x) st |= F.status[s];
+  for (int o = 32; o >= 1; o >>= 1) st |= (uint32_t)__shfl_xor((int)st, o, 64);
+  __syncthreads();
+  uint32_t* sred = reinterpret_cast<uint32_t*>(red);
+  if (lane == 0) sred[wv] = st;
+  __syncthreads();
+  if (threadIdx.x == 0 && F.status_acc) {
+    uint32_t all = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) all |= sred[w];
+    F.status_acc[0] |= all;
+  }
 }
 
 // Adam on (mu, rho) with the gradient of -ELBO:
 //   d/dmu_i  = mean_s g_si,   d/drho_i = mean_s g_si exp(rho_i) eps_si - 1
-__device__ __forceinline__ void adam_body(const FitDev& F, const float* eps, int step, int t, int i) {
+__device__ __forceinline__ void adam_body(const FitDev& F, int t, int i) {
   if (i >= F.dim) return;
   const float sig = __expf(F.rho[i]);
   float gm = 0.f, gr = 0.f;
+#pragma unroll 8
   for (int s = 0; s < F.S; ++s) {
     const float g = grad_at(F, s, i);
     gm += g;
-    gr += g * eps_at(F, eps, step, s, i);
+    gr += g * F.eps_s[(size_t)s * F.dim + i];
   }
   const float invS = 1.f / (float)F.S;
   gm *= invS;
@@ -111,10 +116,6 @@ __device__ __forceinline__ void adam_body(const FitDev& F, const float* eps, int
   F.m_rho[i] = m;
   F.v_rho[i] = v;
   F.rho[i] -= F.lr * (m * c1) / (sqrtf(v * c2) + e);
-}
-
-__global__ void k_adam(FitDev F, const float* eps, int step, int t) {
-  adam_body(F, eps, step, t, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---- shared launches over many fits (serving); step = round - round0
@@ -141,13 +142,12 @@ __global__ void __launch_bounds__(1024) kf_elbo(const FitDev* __restrict__ fits,
   elbo_body(F, step, red);
 }
 
-__global__ void kf_adam(const FitDev* __restrict__ fits, const Task* __restrict__ tasks, int round,
-                        const float* eps) {
+__global__ void kf_adam(const FitDev* __restrict__ fits, const Task* __restrict__ tasks, int round) {
   const Task t = tasks[blockIdx.x];      // x fit, y parameter block
   const FitDev& F = fits[t.x];
   int step;
   if (!fit_step(F, round, step)) return;
-  adam_body(F, eps, step, step + 1, t.y * blockDim.x + threadIdx.x);
+  adam_body(F, step + 1, t.y * blockDim.x + threadIdx.x);
 }
 
 hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, const float* eps, hipStream_t s) {
@@ -155,19 +155,8 @@ hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, co
     if (L.n_sample) hipLaunchKernelGGL(kf_sample, dim3(L.n_sample), dim3(256), 0, s, L.fit, L.t_sample, round, eps);
   } else if (stage == RTU_STAGE_ADAM) {
     if (L.n_fit) hipLaunchKernelGGL(kf_elbo, dim3(L.n_fit), dim3(1024), 0, s, L.fit, L.t_fit, round);
-    if (L.n_param) hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(256), 0, s, L.fit, L.t_param, round, eps);
+    if (L.n_param) hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(256), 0, s, L.fit, L.t_param, round);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_sample(const FitDev& F, const float* eps, int step, hipStream_t s) {
-  hipLaunchKernelGGL(k_sample, dim3((F.dim + 255) / 256, F.S), dim3(256), 0, s, F, eps, step);
-  return hipGetLastError();
-}
-
-hipError_t launch_adam(const FitDev& F, const float* eps, int step, int t, hipStream_t s) {
-  hipLaunchKernelGGL(k_elbo, dim3(1), dim3(1024), 0, s, F, step);
-  hipLaunchKernelGGL(k_adam, dim3((F.dim + 255) / 256), dim3(256), 0, s, F, eps, step, t);
   return hipGetLastError();
 }
 

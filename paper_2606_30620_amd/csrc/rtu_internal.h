@@ -86,6 +86,7 @@ struct FitDev {
   float *mu, *rho, *m_mu, *v_mu, *m_rho, *v_rho;   // [dim]
   float *z_lens, *z_ps, *z_lat;                    // [S][...] samples (evaluation inputs)
   float *g_lens, *g_ps, *g_lat;                    // [S][...] gradients (evaluation outputs)
+  float* eps_s;                                    // [S][dim] this step's standard-normal draws
   double* loss;               // [S]
   double* chi2m;              // [S]
   uint32_t* status;           // [S]
@@ -106,8 +107,6 @@ hipError_t launch_psf(const SysDev& h, int batch, bool adjoint, hipStream_t s);
 hipError_t launch_rays_adj(const SysDev& h, int batch, hipStream_t s);
 hipError_t launch_post(const SysDev& h, int batch, hipStream_t s);
 // fit kernels (rtu_fit.hip)
-hipError_t launch_sample(const FitDev& F, const float* eps, int step, hipStream_t s);
-hipError_t launch_adam(const FitDev& F, const float* eps, int step, int t, hipStream_t s);
 
 // host helpers shared by plans, fits and the serving fleet (rtu_runtime.hip)
 struct ObsHost {

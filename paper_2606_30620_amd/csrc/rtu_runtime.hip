@@ -202,6 +202,7 @@ size_t carve_fit(FitDev& F, int S, int max_steps, char* base) {
   F.z_lat = cv.take<float>((size_t)S * F.n_src2);
   F.g_lens = cv.take<float>((size_t)S * F.n_lens); F.g_ps = cv.take<float>((size_t)S * 4);
   F.g_lat = cv.take<float>((size_t)S * F.n_src2);
+  F.eps_s = cv.take<float>((size_t)S * F.dim);
   F.loss = cv.take<double>(S); F.chi2m = cv.take<double>(S);
   F.status = cv.take<uint32_t>(S); F.n_sub = cv.take<int>(S);
   F.trace = cv.take<double>(max_steps);
