@@ -20,12 +20,32 @@ extern __constant__ double c_D[K * K];
 extern __constant__ float2 c_tw[128];
 
 // ------------------------------------------------------------------ softplus
+// log(1 + u) for u >= 0 without cancellation: log(w) u / (w - 1) with
+// w = 1 + u rounded (Goldberg 1991, Theorem 4)
+__device__ __forceinline__ float log1p_pos(float u) {
+  const float w = 1.f + u;
+  return w == 1.f ? u : __logf(w) * (u / (w - 1.f));
+}
 __device__ __forceinline__ float softplus_f(float x) {
-  return fmaxf(x, 0.f) + log1pf(__expf(-fabsf(x)));
+  return fmaxf(x, 0.f) + log1p_pos(__expf(-fabsf(x)));
 }
 // log(softplus(x)), finite for all x
 __device__ __forceinline__ float log_softplus_f(float x) {
   return x < -15.f ? x : __logf(softplus_f(x));
+}
+// softplus(x), log softplus(x) and sigmoid(x) / softplus(x) from one exponential
+struct SoftplusTerms {
+  float lsp, ratio;
+};
+__device__ __forceinline__ SoftplusTerms softplus_terms(float x) {
+  const float e = __expf(-fabsf(x));                 // (0, 1]
+  const float sp = fmaxf(x, 0.f) + log1p_pos(e);     // softplus(x)
+  const float sig = (x >= 0.f ? 1.f : e) / (1.f + e);
+  SoftplusTerms o;
+  // below -15 both tend to e^x (which may underflow): the ratio is 1 - e^x/2
+  o.lsp = x < -15.f ? x : __logf(sp);
+  o.ratio = x < -15.f ? 1.f - 0.5f * e : sig / sp;
+  return o;
 }
 
 // ------------------------------------------------------------------ SIE + shear
@@ -425,51 +445,151 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place radix-2 transforms of nl lines of length n = 2^logn held in LDS with
-// line stride ls, input already in bit-reversed order.  sign = -1 forward
-// (e^{-2 pi i k x / n}), +1 inverse; no normalisation.  tw: LDS copy of the
-// 128 twiddles e^{-2 pi i k / 256}.  Each thread takes its butterflies of a
-// stage FFT_U at a time, all loads first, so LDS latency overlaps.
-constexpr int FFT_U = 8;
-__device__ __forceinline__ void fft_lines(float2* buf, const float2* tw, int nl, int n, int logn, int ls,
-                                          float sign) {
-  const int half_n = n >> 1;
-  const int nb = nl * half_n;
-  const int nt = blockDim.x;
-  for (int s = 1; s <= logn; ++s) {
+// ---- FFT of lines held in LDS: n = N1 * N2 with N1 = min(n, 16), N2 = n / N1,
+// each factor a small DFT in registers, so that a line makes two passes
+// through LDS.  The natural-order element i = i1 + N1 i2 of a line (i1 < N1)
+// is in "split" order stored at N2 i1 + i2.  fft_to_split transforms natural
+// input into split-order output; fft_to_natural transforms split-order input
+// into natural output (both with W = exp(sign 2 pi i / n)).
+
+// exp(-2 pi i p / 16), p < 8
+__device__ __forceinline__ float2 w16(int p) {
+  constexpr float C[8] = {1.f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                          0.f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f};
+  constexpr float Sn[8] = {0.f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+                           -1.f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f};
+  return make_float2(C[p], Sn[p]);
+}
+
+__host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+__host__ __device__ constexpr int bitrevc(int i, int l) {
+  int r = 0;
+  for (int k = 0; k < l; ++k) r |= ((i >> k) & 1) << (l - 1 - k);
+  return r;
+}
+
+// In-register DFT of N <= 16 points, natural order in and out.
+template <int N>
+__device__ __forceinline__ void dft_reg(float2* v, float sign) {
+  constexpr int L = ilog2c(N);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int j = bitrevc(i, L);
+    if (j > i) { const float2 t = v[i]; v[i] = v[j]; v[j] = t; }
+  }
+#pragma unroll
+  for (int s = 1; s <= L; ++s) {
     const int half = 1 << (s - 1);
-    for (int base = threadIdx.x; base < nb; base += FFT_U * nt) {
-      float2 a[FFT_U], b[FFT_U], w[FFT_U];
-      int o[FFT_U];
 #pragma unroll
-      for (int j = 0; j < FFT_U; ++j) {
-        const int idx = base + j * nt;
-        if (idx < nb) {
-          const int l = idx >> (logn - 1);
-          const int k = idx & (half_n - 1);
-          const int pos = k & (half - 1);
-          o[j] = l * ls + ((k >> (s - 1)) << s) + pos;
-          w[j] = tw[pos << (8 - s)];
-          a[j] = buf[o[j]];
-          b[j] = buf[o[j] + half];
-        }
-      }
+    for (int g = 0; g < N; g += 2 * half) {
 #pragma unroll
-      for (int j = 0; j < FFT_U; ++j) {
-        if (base + j * nt < nb) {
-          const float2 ww = make_float2(w[j].x, -sign * w[j].y);  // table holds e^{-i}: inverse conjugates
-          const float2 t = cmul(b[j], ww);
-          buf[o[j]] = make_float2(a[j].x + t.x, a[j].y + t.y);
-          buf[o[j] + half] = make_float2(a[j].x - t.x, a[j].y - t.y);
-        }
+      for (int q = 0; q < half; ++q) {
+        float2 w = w16(q << (4 - s));
+        w.y *= -sign;                      // the table holds exp(-i ...): sign +1 conjugates
+        const float2 a = v[g + q], b = cmul(v[g + q + half], w);
+        v[g + q] = make_float2(a.x + b.x, a.y + b.y);
+        v[g + q + half] = make_float2(a.x - b.x, a.y - b.y);
       }
+    }
+  }
+}
+
+// exp(sign 2 pi i e / n) for n <= 256 from the LDS table tw[k] = exp(-2 pi i k / 256)
+__device__ __forceinline__ float2 twiddle(const float2* tw, int e, int n, float sign) {
+  const int k = (e * (256 / n)) & 255;
+  float2 w = tw[k & 127];
+  if (k & 128) { w.x = -w.x; w.y = -w.y; }
+  w.y *= -sign;
+  return w;
+}
+
+template <int N1, int N2>
+__device__ __forceinline__ void fft_to_split(float2* buf, const float2* tw, int nl, int ls, float sign) {
+  constexpr int n = N1 * N2;
+  float2 v[N1 > N2 ? N1 : N2];
+  // DFT over i2... step 1: for each t < N2, the N1 points t + N2 m
+  for (int it = threadIdx.x; it < nl * N2; it += blockDim.x) {
+    const int l = it / N2, t = it - l * N2;
+    float2* p = buf + l * ls + t;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) v[m] = p[N2 * m];
+    dft_reg<N1>(v, sign);
+#pragma unroll
+    for (int k = 1; k < N1; ++k) v[k] = cmul(v[k], twiddle(tw, t * k, n, sign));
+#pragma unroll
+    for (int k = 0; k < N1; ++k) p[N2 * k] = v[k];
+  }
+  __syncthreads();
+  if (N2 > 1) {
+    // step 2: for each k1 < N1, the N2 contiguous points N2 k1 + t
+    for (int it = threadIdx.x; it < nl * N1; it += blockDim.x) {
+      const int l = it / N1, k1 = it - l * N1;
+      float2* p = buf + l * ls + N2 * k1;
+#pragma unroll
+      for (int t = 0; t < N2; ++t) v[t] = p[t];
+      dft_reg<N2>(v, sign);
+#pragma unroll
+      for (int t = 0; t < N2; ++t) p[t] = v[t];
     }
     __syncthreads();
   }
 }
 
-__device__ __forceinline__ int bitrev(int i, int logn) {
-  return (int)(__brev((unsigned)i) >> (32 - logn));
+template <int N1, int N2>
+__device__ __forceinline__ void fft_to_natural(float2* buf, const float2* tw, int nl, int ls, float sign) {
+  constexpr int n = N1 * N2;
+  float2 v[N1 > N2 ? N1 : N2];
+  if (N2 > 1) {
+    // step A: for each i1 < N1, the N2 contiguous points N2 i1 + i2, then W^(i1 k2)
+    for (int it = threadIdx.x; it < nl * N1; it += blockDim.x) {
+      const int l = it / N1, i1 = it - l * N1;
+      float2* p = buf + l * ls + N2 * i1;
+#pragma unroll
+      for (int t = 0; t < N2; ++t) v[t] = p[t];
+      dft_reg<N2>(v, sign);
+#pragma unroll
+      for (int k = 1; k < N2; ++k) v[k] = cmul(v[k], twiddle(tw, i1 * k, n, sign));
+#pragma unroll
+      for (int t = 0; t < N2; ++t) p[t] = v[t];
+    }
+    __syncthreads();
+  }
+  // step B: for each k2 < N2, the N1 points N2 i1 + k2 (stride N2)
+  for (int it = threadIdx.x; it < nl * N2; it += blockDim.x) {
+    const int l = it / N2, k2 = it - l * N2;
+    float2* p = buf + l * ls + k2;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) v[m] = p[N2 * m];
+    dft_reg<N1>(v, sign);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) p[N2 * k] = v[k];
+  }
+  __syncthreads();
+}
+
+// position of natural element i of a line in split order
+__device__ __forceinline__ int split_pos(int i, int logn) {
+  const int l1 = logn < 4 ? logn : 4, n2 = 1 << (logn - l1);
+  return n2 * (i & ((1 << l1) - 1)) + (i >> l1);
+}
+
+__device__ __forceinline__ void fft_lines_dir(float2* buf, const float2* tw, int nl, int logn, int ls, float sign,
+                                              bool to_split) {
+  switch (logn) {
+#define RTU_FFT_CASE(LG, A, B)                                   \
+    case LG:                                                     \
+      if (to_split) fft_to_split<A, B>(buf, tw, nl, ls, sign);   \
+      else fft_to_natural<A, B>(buf, tw, nl, ls, sign);          \
+      break;
+    RTU_FFT_CASE(3, 8, 1)
+    RTU_FFT_CASE(4, 16, 1)
+    RTU_FFT_CASE(5, 16, 2)
+    RTU_FFT_CASE(6, 16, 4)
+    RTU_FFT_CASE(7, 16, 8)
+    RTU_FFT_CASE(8, 16, 16)
+#undef RTU_FFT_CASE
+    default: break;
+  }
 }
 
 // One pass of a 2-D FFT over an n x n complex array: every row (cols = false)
@@ -479,8 +599,8 @@ __device__ __forceinline__ int bitrev(int i, int logn) {
 // Lines are processed in chunks that fit the cap float2 slots of the LDS
 // buffer, which holds 128 more slots after them for the twiddle table.  The
 // global loads and stores go U per thread at a time.
-template <int U = FFT_U, class LD, class MID, class ST>
-__device__ void fft_pass(float2* lds, int cap, int n, int logn, bool cols, float sign1, bool twice, float sign2,
+template <int U = 8, class LD, class MID, class ST>
+__device__ __forceinline__ void fft_pass(float2* lds, int cap, int n, int logn, bool cols, float sign1, bool twice, float sign2,
                          LD ld, MID mid, ST st) {
   float2* tw = lds + cap;
   for (int k = threadIdx.x; k < 128; k += blockDim.x) tw[k] = c_tw[k];
@@ -513,33 +633,20 @@ __device__ void fft_pass(float2* lds, int cap, int n, int logn, bool cols, float
         int l, i, row, col;
         if (base + j * nt < tot) {
           place(base + j * nt, l, i, row, col);
-          lds[l * ls + bitrev(i, logn)] = v[j];
+          lds[l * ls + i] = v[j];
         }
       }
     }
     __syncthreads();
-    fft_lines(lds, tw, nl, n, logn, ls, sign1);
+    fft_lines_dir(lds, tw, nl, logn, ls, sign1, true);
     for (int idx = threadIdx.x; idx < tot; idx += nt) {
       int l, i, row, col;
       place(idx, l, i, row, col);
-      lds[l * ls + i] = mid(row, col, lds[l * ls + i]);
+      const int q = l * ls + split_pos(i, logn);
+      lds[q] = mid(row, col, lds[q]);
     }
     __syncthreads();
-    if (twice) {
-      // bit-reverse in place, then transform again
-      for (int idx = threadIdx.x; idx < tot; idx += nt) {
-        const int l = idx >> logn, i = idx & (n - 1);
-        const int j = bitrev(i, logn);
-        if (j > i) {
-          float2* p = lds + l * ls;
-          const float2 t = p[i];
-          p[i] = p[j];
-          p[j] = t;
-        }
-      }
-      __syncthreads();
-      fft_lines(lds, tw, nl, n, logn, ls, sign2);
-    }
+    if (twice) fft_lines_dir(lds, tw, nl, logn, ls, sign2, false);
     for (int base = threadIdx.x; base < tot; base += U * nt) {
       float2 v[U];
 #pragma unroll
@@ -547,7 +654,7 @@ __device__ void fft_pass(float2* lds, int cap, int n, int logn, bool cols, float
         int l, i, row, col;
         if (base + j * nt < tot) {
           place(base + j * nt, l, i, row, col);
-          v[j] = lds[l * ls + i];
+          v[j] = lds[l * ls + (twice ? i : split_pos(i, logn))];
         }
       }
 #pragma unroll

@@ -15,7 +15,7 @@ constexpr int RAY_THREADS = RAY_TILE * RAY_TILE;
 constexpr int PSF_TW = 64;              // PSF kernels: 64 x 16 output tile,
 constexpr int PSF_TH = 16;              // 256 threads x 4 columns each
 constexpr int PSF_THREADS = 256;
-constexpr int PREP_THREADS = 1024;      // quantile selection and FFT workgroups
+constexpr int PREP_THREADS = 512;       // quantile selection and FFT workgroups
 constexpr int GRID_LDS_MAX = 64;        // n_src <= this: source grid staged in LDS
 constexpr int FFT_LDS_MAX = 128 * 129;  // FFT line buffer (float2): 128 lines of 128 + 1 pad = 129 KB
 constexpr int KBAR = 4 * K;             // per axis pair: dX[K], dS[K]  (x: 0..2K, y: 2K..4K)

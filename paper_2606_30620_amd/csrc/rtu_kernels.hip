@@ -465,7 +465,7 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
 }
 
 // GP source (eqs. 1-4): F = DFT(w); f = Re IDFT(sqrt(P) F)/n^2; s = (s0 softplus(f/s0))^alpha
-__device__ void prep_gp(const SysDev& S, int b, unsigned char* smem, int cap) {
+__device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* smem, int cap) {
   float2* lds = reinterpret_cast<float2*>(smem);
   const int n = S.n_src, logn = S.log2_src, n2 = n * n;
   const float* w = S.latent + (size_t)b * n2;
@@ -997,7 +997,7 @@ struct PostLds {
   uint32_t stat;
 };
 
-__device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, int cap, PostLds& P) {
+__device__ __forceinline__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, int cap, PostLds& P) {
   const int tid = threadIdx.x;
   const int n = S.n_src, n2 = n * n, logn = S.log2_src;
   const int nl = S.n_lens;
@@ -1103,17 +1103,17 @@ __device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, int c
     float2* lds = reinterpret_cast<float2*>(fft_smem);
     double pacc[4] = {0.0, 0.0, 0.0, 0.0};   // sigma, n, zeta, alpha
     const float inv_n2 = 1.f / (float)n2;
+    const float inv_sig = 1.f / ps[0], inv_zeta = 1.f / mt.zeta, dn_c = (mt.n + 1.f) / (2.f * mt.n);
     // rows: fbar = sbar ds/df, ds/df = alpha s sigmoid(x)/(s0 softplus(x)), x = f/s0
     fft_pass<2>(lds, cap, n, logn, false, -1.f, false, 0.f,
              [&](int r, int c) {
                const int q = r * n + c;
                const float x = fo[q] * 100.f;
                const float s = so[q];
-               const float lsp = log_softplus_f(x);
-               const float ratio = __expf(-softplus_f(-x) - lsp);   // sigmoid/softplus
+               const SoftplusTerms sp = softplus_terms(x);
                const float sbq = (float)sb[q];
-               pacc[3] += (double)sbq * s * (-4.605170186f + lsp);
-               return make_float2(sbq * alpha * s * ratio * 100.f, 0.f);
+               pacc[3] += (double)(sbq * s * (-4.605170186f + sp.lsp));
+               return make_float2(sbq * alpha * s * sp.ratio * 100.f, 0.f);
              },
              [&](int, int, float2 v) { return v; },
              [&](int r, int c, float2 v) { T[r * n + c] = v; });
@@ -1125,13 +1125,13 @@ __device__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, int c
                const float k2 = kx * kx + ky * ky;
                const float sp = matern_sqrtP(mt, k2);
                const float2 f0 = F[r * n + c];
-               // Re(F conj(Fbar)) / n^2
-               const double re = ((double)f0.x * v.x + (double)f0.y * v.y) * (double)inv_n2 * sp;
-               const float apk = mt.a + k2;
-               pacc[0] += re / ps[0];
-               pacc[1] += re * (0.5 / mt.n + 0.5 * log((double)mt.a / apk) + 0.5 -
-                                (mt.n + 1.0) * mt.a / (2.0 * mt.n * apk));
-               pacc[2] += re * (-mt.n / mt.zeta + (mt.n + 1.0) * mt.a / (mt.zeta * apk));
+               // Re(F conj(Fbar)) sqrt(P) / n^2 times d log sqrt(P) / d (sigma, n, zeta):
+               //   1/sigma,  ((n+1)/(2n)) k^2/(a+k^2) + log(a/(a+k^2))/2,  (a - n k^2)/(zeta (a+k^2))
+               const float re = (f0.x * v.x + f0.y * v.y) * inv_n2 * sp;
+               const float iapk = 1.f / (mt.a + k2);
+               pacc[0] += (double)(re * inv_sig);
+               pacc[1] += (double)(re * (dn_c * k2 * iapk + 0.5f * __logf(mt.a * iapk)));
+               pacc[2] += (double)(re * ((mt.a - mt.n * k2) * iapk * inv_zeta));
                return make_float2(v.x * sp, v.y * sp);
              },
              [&](int r, int c, float2 v) { T[r * n + c] = v; });
