@@ -168,10 +168,12 @@ int rtu_debug_fetch(rtu_plan p, int32_t what, int32_t sample, void* host_dst, si
 #define RTU_STAGE_ADAM      7   /* fit: ELBO value and Adam update                */
 #define RTU_N_STAGES        8
 
-/* Start recording HIP events around every stage of the next max_calls
- * evaluations (rtu_loss_grad or fit steps) of this plan, on the stream each
- * evaluation runs on.  Recording adds no synchronisation. */
-int rtu_profile_begin(rtu_plan p, int32_t max_calls);
+/* Start recording HIP events around the stages selected by stage_mask (bit
+ * k = stage k; 0 = every stage) of the next max_calls evaluations
+ * (rtu_loss_grad or fit steps) of this plan, on the stream each evaluation
+ * runs on.  Recording adds no synchronisation, but every event is a marker
+ * in the stream: select only the stages to be timed. */
+int rtu_profile_begin(rtu_plan p, int32_t max_calls, uint32_t stage_mask);
 /* Stop recording; wait for the recorded events and return, per stage, the
  * summed GPU time in milliseconds (stage_ms[RTU_N_STAGES], host) and the
  * number of recorded launches of each stage (launches[RTU_N_STAGES], host,

@@ -64,7 +64,7 @@ def _load():
     lib.rtu_masked_count.restype = I32
     lib.rtu_loss_grad.argtypes = [P, I32] + [VP] * 11 + [VP]
     lib.rtu_debug_fetch.argtypes = [P, I32, I32, VP, SZ, VP]
-    lib.rtu_profile_begin.argtypes = [P, I32]
+    lib.rtu_profile_begin.argtypes = [P, I32, C.c_uint32]
     lib.rtu_profile_end.argtypes = [P, VP, VP]
     lib.rtu_fit_create.argtypes = [P, I32, VP, VP, C.c_float, C.c_uint64, I32, I32, C.POINTER(P)]
     lib.rtu_fit_destroy.argtypes = [P]
@@ -202,8 +202,11 @@ class Plan:
         return out
 
 
-    def profile_begin(self, max_calls: int) -> None:
-        check(LIB.rtu_profile_begin(self._h, int(max_calls)), "rtu_profile_begin")
+    def profile_begin(self, max_calls: int, stages=None) -> None:
+        """Time the given stages (names of STAGES; None = all) of the next
+        max_calls evaluations or fit steps."""
+        mask = 0 if stages is None else sum(1 << STAGES.index(s) for s in stages)
+        check(LIB.rtu_profile_begin(self._h, int(max_calls), mask), "rtu_profile_begin")
 
     def profile_end(self):
         """{stage: (total_ms, launches)} of the recorded evaluations."""

@@ -15,6 +15,7 @@ using namespace rtu;
 // HIP events around the stages of up to max_calls evaluations
 struct Prof {
   bool on = false;
+  uint32_t mask = 0;
   int max_calls = 0, calls = 0, cur = -1;
   std::vector<hipEvent_t> ev;      // [max_calls][RTU_N_STAGES][2]
   std::vector<uint8_t> used;       // [max_calls][RTU_N_STAGES]
@@ -240,7 +241,7 @@ void prof_call_begin(rtu_plan p) {
 }
 void prof_stage(rtu_plan p, int stage, bool end, hipStream_t s) {
   Prof& P = p->prof;
-  if (P.cur < 0) return;
+  if (P.cur < 0 || !(P.mask & (1u << stage))) return;
   const size_t q = (size_t)P.cur * RTU_N_STAGES + stage;
   (void)hipEventRecord(P.ev[q * 2 + (end ? 1 : 0)], s);
   if (end) P.used[q] = 1;
@@ -401,7 +402,7 @@ int rtu_debug_fetch(rtu_plan p, int32_t what, int32_t sample, void* host_dst, si
   return RTU_OK;
 }
 
-int rtu_profile_begin(rtu_plan p, int32_t max_calls) {
+int rtu_profile_begin(rtu_plan p, int32_t max_calls, uint32_t stage_mask) {
   if (!p || max_calls < 1) return RTU_EINVAL;
   if (hipSetDevice(p->device) != hipSuccess) return RTU_EHIP;
   Prof& P = p->prof;
@@ -411,6 +412,7 @@ int rtu_profile_begin(rtu_plan p, int32_t max_calls) {
   for (auto& e : P.ev)
     if (hipEventCreate(&e) != hipSuccess) return RTU_EHIP;
   P.on = true;
+  P.mask = stage_mask ? stage_mask : (1u << RTU_N_STAGES) - 1u;
   P.max_calls = max_calls;
   P.calls = 0;
   P.cur = -1;
