@@ -426,18 +426,38 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
   __syncthreads();
 }
 
-// Column sums of a row-major [rows][cols] array with row stride ld: wave w
-// reduces columns w, w + nw, ... in a fixed order (deterministic); emit(c, sum)
-// runs on lane 0 of the owning wave.
+// FP64 column sums of a rows x cols matrix of row stride ld, each in a fixed
+// order.  The workgroup reads the matrix row-major (coalesced): thread t takes
+// column t % cols and every G-th row from t / cols (G = min(blockDim / cols,
+// 16) groups); the G partials of a column are then added in group order.
+// `part` is LDS for blockDim doubles.  Called by the whole workgroup.
 template <class T, class EMIT>
-__device__ __forceinline__ void reduce_columns(const T* a, int rows, int cols, int ld, EMIT emit) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int c = wv; c < cols; c += nw) {
-    double s = 0.0;
-    for (int r = lane; r < rows; r += 64) s += (double)a[(size_t)r * ld + c];
-    s = wave_sum(s);
-    if (lane == 0) emit(c, s);
+__device__ __forceinline__ void reduce_columns(const T* a, int rows, int cols, int ld, double* part, EMIT emit) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (cols > nt) {
+    for (int c = tid; c < cols; c += nt) {
+      double s = 0.0;
+      for (int r = 0; r < rows; ++r) s += (double)a[(size_t)r * ld + c];
+      emit(c, s);
+    }
+    __syncthreads();
+    return;
   }
+  const int G = min(nt / cols, 16);
+  const int g = tid / cols, c = tid - g * cols;
+  if (g < G) {
+    double s = 0.0;
+#pragma unroll 8
+    for (int r = g; r < rows; r += G) s += (double)a[(size_t)r * ld + c];
+    part[tid] = s;
+  }
+  __syncthreads();
+  if (tid < cols) {
+    double s = 0.0;
+    for (int k = 0; k < G; ++k) s += part[k * cols + tid];
+    emit(tid, s);
+  }
+  __syncthreads();
 }
 
 // ------------------------------------------------------------------ FFT
@@ -503,66 +523,74 @@ __device__ __forceinline__ float2 twiddle(const float2* tw, int e, int n, float 
   return w;
 }
 
-template <int N1, int N2>
-__device__ __forceinline__ void fft_to_split(float2* buf, const float2* tw, int nl, int ls, float sign) {
+// A set of nl lines: element j of line l sits at buf[l * ls + j * es].  With
+// LFAST the work items run along the lines first (consecutive threads take
+// consecutive lines: the right order for columns of a row-major grid),
+// otherwise along the elements of one line first.
+template <int N1, int N2, bool LFAST>
+__device__ __forceinline__ void fft_to_split(float2* buf, const float2* tw, int nl, int ls, int es, float sign) {
   constexpr int n = N1 * N2;
   float2 v[N1 > N2 ? N1 : N2];
-  // DFT over i2... step 1: for each t < N2, the N1 points t + N2 m
+  // step 1: for each t < N2, the N1 points t + N2 m
   for (int it = threadIdx.x; it < nl * N2; it += blockDim.x) {
-    const int l = it / N2, t = it - l * N2;
-    float2* p = buf + l * ls + t;
+    int l, t;
+    if (LFAST) { t = it / nl; l = it - t * nl; } else { l = it / N2; t = it - l * N2; }
+    float2* p = buf + l * ls + t * es;
 #pragma unroll
-    for (int m = 0; m < N1; ++m) v[m] = p[N2 * m];
+    for (int m = 0; m < N1; ++m) v[m] = p[N2 * m * es];
     dft_reg<N1>(v, sign);
 #pragma unroll
     for (int k = 1; k < N1; ++k) v[k] = cmul(v[k], twiddle(tw, t * k, n, sign));
 #pragma unroll
-    for (int k = 0; k < N1; ++k) p[N2 * k] = v[k];
+    for (int k = 0; k < N1; ++k) p[N2 * k * es] = v[k];
   }
   __syncthreads();
   if (N2 > 1) {
-    // step 2: for each k1 < N1, the N2 contiguous points N2 k1 + t
+    // step 2: for each k1 < N1, the N2 consecutive points N2 k1 + t
     for (int it = threadIdx.x; it < nl * N1; it += blockDim.x) {
-      const int l = it / N1, k1 = it - l * N1;
-      float2* p = buf + l * ls + N2 * k1;
+      int l, k1;
+      if (LFAST) { k1 = it / nl; l = it - k1 * nl; } else { l = it / N1; k1 = it - l * N1; }
+      float2* p = buf + l * ls + N2 * k1 * es;
 #pragma unroll
-      for (int t = 0; t < N2; ++t) v[t] = p[t];
+      for (int t = 0; t < N2; ++t) v[t] = p[t * es];
       dft_reg<N2>(v, sign);
 #pragma unroll
-      for (int t = 0; t < N2; ++t) p[t] = v[t];
+      for (int t = 0; t < N2; ++t) p[t * es] = v[t];
     }
     __syncthreads();
   }
 }
 
-template <int N1, int N2>
-__device__ __forceinline__ void fft_to_natural(float2* buf, const float2* tw, int nl, int ls, float sign) {
+template <int N1, int N2, bool LFAST>
+__device__ __forceinline__ void fft_to_natural(float2* buf, const float2* tw, int nl, int ls, int es, float sign) {
   constexpr int n = N1 * N2;
   float2 v[N1 > N2 ? N1 : N2];
   if (N2 > 1) {
-    // step A: for each i1 < N1, the N2 contiguous points N2 i1 + i2, then W^(i1 k2)
+    // step A: for each i1 < N1, the N2 consecutive points N2 i1 + i2, then W^(i1 k2)
     for (int it = threadIdx.x; it < nl * N1; it += blockDim.x) {
-      const int l = it / N1, i1 = it - l * N1;
-      float2* p = buf + l * ls + N2 * i1;
+      int l, i1;
+      if (LFAST) { i1 = it / nl; l = it - i1 * nl; } else { l = it / N1; i1 = it - l * N1; }
+      float2* p = buf + l * ls + N2 * i1 * es;
 #pragma unroll
-      for (int t = 0; t < N2; ++t) v[t] = p[t];
+      for (int t = 0; t < N2; ++t) v[t] = p[t * es];
       dft_reg<N2>(v, sign);
 #pragma unroll
       for (int k = 1; k < N2; ++k) v[k] = cmul(v[k], twiddle(tw, i1 * k, n, sign));
 #pragma unroll
-      for (int t = 0; t < N2; ++t) p[t] = v[t];
+      for (int t = 0; t < N2; ++t) p[t * es] = v[t];
     }
     __syncthreads();
   }
   // step B: for each k2 < N2, the N1 points N2 i1 + k2 (stride N2)
   for (int it = threadIdx.x; it < nl * N2; it += blockDim.x) {
-    const int l = it / N2, k2 = it - l * N2;
-    float2* p = buf + l * ls + k2;
+    int l, k2;
+    if (LFAST) { k2 = it / nl; l = it - k2 * nl; } else { l = it / N2; k2 = it - l * N2; }
+    float2* p = buf + l * ls + k2 * es;
 #pragma unroll
-    for (int m = 0; m < N1; ++m) v[m] = p[N2 * m];
+    for (int m = 0; m < N1; ++m) v[m] = p[N2 * m * es];
     dft_reg<N1>(v, sign);
 #pragma unroll
-    for (int k = 0; k < N1; ++k) p[N2 * k] = v[k];
+    for (int k = 0; k < N1; ++k) p[N2 * k * es] = v[k];
   }
   __syncthreads();
 }
@@ -573,13 +601,22 @@ __device__ __forceinline__ int split_pos(int i, int logn) {
   return n2 * (i & ((1 << l1) - 1)) + (i >> l1);
 }
 
-__device__ __forceinline__ void fft_lines_dir(float2* buf, const float2* tw, int nl, int logn, int ls, float sign,
-                                              bool to_split) {
+// natural index of the element at split position p of a line
+__device__ __forceinline__ int split_nat(int p, int logn) {
+  const int l1 = logn < 4 ? logn : 4, l2 = logn - l1;
+  return (p >> l2) + ((p & ((1 << l2) - 1)) << l1);
+}
+
+// Transform nl lines (element j of line l at buf[l * ls + j * es]) from
+// natural to split order (to_split) or from split to natural order.
+template <bool LFAST>
+__device__ __forceinline__ void fft_lines_dir(float2* buf, const float2* tw, int nl, int logn, int ls, int es,
+                                              float sign, bool to_split) {
   switch (logn) {
-#define RTU_FFT_CASE(LG, A, B)                                   \
-    case LG:                                                     \
-      if (to_split) fft_to_split<A, B>(buf, tw, nl, ls, sign);   \
-      else fft_to_natural<A, B>(buf, tw, nl, ls, sign);          \
+#define RTU_FFT_CASE(LG, A, B)                                                \
+    case LG:                                                                  \
+      if (to_split) fft_to_split<A, B, LFAST>(buf, tw, nl, ls, es, sign);     \
+      else fft_to_natural<A, B, LFAST>(buf, tw, nl, ls, es, sign);            \
       break;
     RTU_FFT_CASE(3, 8, 1)
     RTU_FFT_CASE(4, 16, 1)
@@ -589,6 +626,30 @@ __device__ __forceinline__ void fft_lines_dir(float2* buf, const float2* tw, int
     RTU_FFT_CASE(8, 16, 16)
 #undef RTU_FFT_CASE
     default: break;
+  }
+}
+
+// Rows (cols = false) or columns of an n x n grid held whole in LDS at row
+// stride n + 1.
+__device__ __forceinline__ void fft_grid_dir(float2* A, const float2* tw, int n, int logn, bool cols, float sign,
+                                             bool to_split) {
+  if (cols) fft_lines_dir<true>(A, tw, n, logn, 1, n + 1, sign, to_split);
+  else fft_lines_dir<false>(A, tw, n, logn, n + 1, 1, sign, to_split);
+}
+
+// U-wide batches of independent global loads over [0, tot): v = ld(q), then
+// st(q, v) for every q of the thread, so that U loads are in flight at once.
+template <int U, class LD, class ST>
+__device__ __forceinline__ void batched_copy(int tot, LD ld, ST st) {
+  const int nt = blockDim.x;
+  for (int base = threadIdx.x; base < tot; base += U * nt) {
+    decltype(ld(0)) v[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+      if (base + j * nt < tot) v[j] = ld(base + j * nt);
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+      if (base + j * nt < tot) st(base + j * nt, v[j]);
   }
 }
 
@@ -638,7 +699,7 @@ __device__ __forceinline__ void fft_pass(float2* lds, int cap, int n, int logn, 
       }
     }
     __syncthreads();
-    fft_lines_dir(lds, tw, nl, logn, ls, sign1, true);
+    fft_lines_dir<false>(lds, tw, nl, logn, ls, 1, sign1, true);
     for (int idx = threadIdx.x; idx < tot; idx += nt) {
       int l, i, row, col;
       place(idx, l, i, row, col);
@@ -646,7 +707,7 @@ __device__ __forceinline__ void fft_pass(float2* lds, int cap, int n, int logn, 
       lds[q] = mid(row, col, lds[q]);
     }
     __syncthreads();
-    if (twice) fft_lines_dir(lds, tw, nl, logn, ls, sign2, false);
+    if (twice) fft_lines_dir<false>(lds, tw, nl, logn, ls, 1, sign2, false);
     for (int base = threadIdx.x; base < tot; base += U * nt) {
       float2 v[U];
 #pragma unroll

@@ -127,7 +127,7 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
         adj[h.lds_adj ? 0 : 1].push_back(make_int4(si, b, t, 0));
       }
       for (int t = 0; t < h.psf_tiles; ++t) psf.push_back(make_int4(si, b, t, 0));
-      post.push_back(make_int4(si, b, 0, 0));
+      for (int r = 0; r < (h.want_grad ? 2 : 1); ++r) post.push_back(make_int4(si, b, r, 0));
     }
     const int nblk = (F.dim + 255) / 256;
     for (int j = 0; j < nblk; ++j) {

@@ -15,6 +15,7 @@ constexpr int RAY_THREADS = RAY_TILE * RAY_TILE;
 constexpr int PSF_TW = 64;              // PSF kernels: 64 x 16 output tile,
 constexpr int PSF_TH = 16;              // 256 threads x 4 columns each
 constexpr int PSF_THREADS = 256;
+constexpr int ST_WORDS = 8;
 constexpr int PREP_THREADS = 512;       // quantile selection and FFT workgroups
 constexpr int GRID_LDS_MAX = 64;        // n_src <= this: source grid staged in LDS
 constexpr int FFT_LDS_MAX = 128 * 129;  // FFT line buffer (float2): 128 lines of 128 + 1 pad = 129 KB
@@ -73,7 +74,8 @@ struct SysDev {
   double* kbar;               // [B][ray_tiles][4K] per-tile dX, dS partials
   double* lpart;              // [B][ray_tiles][n_lens] per-tile lens-gradient partials
   double* c2part;             // [B][psf_tiles][2] per-tile chi^2 partials (all, mask)
-  uint32_t* st;               // [B][4] status words of the stages
+  uint32_t* st;               // [B][ST_WORDS] status words: selection x, y; parameter domain;
+                              // post roles 0, 1; post completion count
 };
 
 // One stochastic variational fit: guide, Adam state and per-sample buffers.

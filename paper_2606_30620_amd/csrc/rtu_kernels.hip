@@ -13,8 +13,10 @@
 //   k_rays_adj  per tile: the same rays again, scattering d loss/d s into an
 //               LDS copy of the grid and accumulating d loss/d knots and
 //               d loss/d lens parameters.
-//   k_post      per sample: knot adjoint back to the selected masked rays,
-//               final reductions, GP adjoint through the FFT, status.
+//   k_post      per sample, two workgroup roles: (0) the loss, the knot
+//               adjoint back to the selected masked rays and the lens
+//               gradient; (1) the GP adjoint through the FFT.  The role
+//               that finishes last writes the sample's status.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -460,7 +462,7 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
       double* sd = S.stdv + (size_t)b * 4;
       sd[0] = mux; sd[1] = muy; sd[2] = sc; sd[3] = (double)M;
     }
-    S.st[b * 4 + axis] = st | L.stat;
+    S.st[b * ST_WORDS + axis] = st | L.stat;
   }
 }
 
@@ -496,11 +498,46 @@ __device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* s
     for (int j = 0; j < ns; ++j)
       if (!(L[RTU_N_LENS_BASE + RTU_N_PER_SUB * j + 1] > 0.f)) st |= RTU_ST_DOMAIN;
     if (!(ps[0] > 0.f) || !(ps[1] > 0.f) || !(ps[2] > 0.f)) st |= RTU_ST_DOMAIN;
-    S.st[b * 4 + 2] = st;
+    S.st[b * ST_WORDS + 2] = st;
+    S.st[b * ST_WORDS + 5] = 0;   // completion count of the two post roles
   }
   const Matern mt = make_matern(ps);
   const float alpha = ps[3];
   const float inv_n2 = 1.f / (float)n2;
+  auto positivity = [&](int q, float f) {
+    fo[q] = f;
+    const float x = f * 100.f;   // f / s0, s0 = 0.01
+    const float s = __expf(alpha * (-4.605170186f + log_softplus_f(x)));
+    so[q] = s;
+    sp[((q >> logn) + 1) * (n + 2) + (q & (n - 1)) + 1] = s;
+  };
+  if (n <= 128) {
+    // the whole grid in LDS at row stride n + 1: rows, then columns, to split
+    // order; F kept in that layout; times sqrt(P); columns, then rows, back
+    float2* tw = lds + cap;
+    for (int k = threadIdx.x; k < 128; k += blockDim.x) tw[k] = c_tw[k];
+    const int ls = n + 1;
+    batched_copy<8>(n2, [&](int q) { return w[q]; },
+                    [&](int q, float v) { lds[(q >> logn) * ls + (q & (n - 1))] = make_float2(v, 0.f); });
+    __syncthreads();
+    fft_grid_dir(lds, tw, n, logn, false, -1.f, true);
+    fft_grid_dir(lds, tw, n, logn, true, -1.f, true);
+    for (int q = threadIdx.x; q < n2; q += blockDim.x) {
+      const int rs = q >> logn, cs = q & (n - 1);
+      const float2 v = lds[rs * ls + cs];
+      F[q] = v;
+      const float kx = fft_freq(split_nat(cs, logn), n), ky = fft_freq(split_nat(rs, logn), n);
+      const float sq = matern_sqrtP(mt, kx * kx + ky * ky);
+      lds[rs * ls + cs] = make_float2(v.x * sq, v.y * sq);
+    }
+    __syncthreads();
+    fft_grid_dir(lds, tw, n, logn, true, 1.f, false);
+    fft_grid_dir(lds, tw, n, logn, false, 1.f, false);
+    for (int q = threadIdx.x; q < n2; q += blockDim.x)
+      positivity(q, lds[(q >> logn) * ls + (q & (n - 1))].x * inv_n2);
+    return;
+  }
+  // larger grids: lines in chunks through the workspace T
   // rows: forward transform of the real latent
   fft_pass(lds, cap, n, logn, false, -1.f, false, 0.f,
            [&](int r, int c) { return make_float2(w[r * n + c], 0.f); },
@@ -520,14 +557,7 @@ __device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* s
   fft_pass(lds, cap, n, logn, false, 1.f, false, 0.f,
            [&](int r, int c) { return T[r * n + c]; },
            [&](int, int, float2 v) { return v; },
-           [&](int r, int c, float2 v) {
-             const float f = v.x * inv_n2;
-             fo[r * n + c] = f;
-             const float x = f * 100.f;   // f / s0, s0 = 0.01
-             const float s = __expf(alpha * (-4.605170186f + log_softplus_f(x)));
-             so[r * n + c] = s;
-             sp[(r + 1) * (n + 2) + c + 1] = s;
-           });
+           [&](int r, int c, float2 v) { positivity(r * n + c, v.x * inv_n2); });
 }
 
 // Dynamic LDS of the prep kernels: the larger of the selection layout and the
@@ -992,19 +1022,20 @@ __global__ void __launch_bounds__(PSF_THREADS) k_psf(SysDev S, int adjoint) {
 // ====================================================================== k_post
 struct PostLds {
   double red[16 * 16];
+  double part[PREP_THREADS];
   double xbar[2][K];      // d loss / d X (beta units), after the slope chain
   double lsum[RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB];
   uint32_t stat;
 };
 
-__device__ __forceinline__ void post_body(const SysDev& S, int b, unsigned char* fft_smem, int cap, PostLds& P) {
+__device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsigned char* fft_smem, int cap, PostLds& P) {
   const int tid = threadIdx.x;
   const int n = S.n_src, n2 = n * n, logn = S.log2_src;
   const int nl = S.n_lens;
   if (tid == 0) P.stat = 0;
   __syncthreads();
-  // ---- loss and chi^2 in the mask
-  {
+  // ---- role 0: loss and chi^2 in the mask, then the lens gradient
+  if (role == 0) {
     double v[3] = {0.0, 0.0, 0.0};
     for (int t = tid; t < S.psf_tiles; t += blockDim.x) {
       const double* o = S.c2part + ((size_t)b * S.psf_tiles + t) * 2;
@@ -1021,14 +1052,14 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, unsigned char*
       if (!isfinite(loss)) P.stat |= RTU_ST_NONFINITE;
     }
   }
-  if (S.want_grad) {
+  if (role == 0 && S.want_grad) {
     const float* lensp = S.lens + (size_t)b * nl;
     const int nsub = n_sub_of(S, b);
     const Sie L = make_sie(lensp);
     // ---- knot adjoint: sum the tile partials, then S_k = 1/p'_k with
     //      p'_k = sum_l D_kl X_l  ->  dX_l += sum_k (-S_k^2 dS_k) D_kl
     reduce_columns(S.kbar + (size_t)b * S.ray_tiles * 4 * K, S.ray_tiles, 4 * K, 4 * K,
-                   [&](int c, double v) { P.red[c] = v; });
+                   P.part, [&](int c, double v) { P.red[c] = v; });
     __syncthreads();
     if (tid < 2 * K) {
       const int ax = tid / K, l = tid - ax * K;
@@ -1079,18 +1110,19 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, unsigned char*
     }
     __syncthreads();
     // tile partials, then the masked-ray rows, each summed in a fixed order
-    reduce_columns(S.lpart + (size_t)b * S.ray_tiles * nl, S.ray_tiles, nl, nl,
+    reduce_columns(S.lpart + (size_t)b * S.ray_tiles * nl, S.ray_tiles, nl, nl, P.part,
                    [&](int c, double v) { P.lsum[c] = v; });
     __syncthreads();
-    reduce_columns(mp, 4 * K, nl, nl, [&](int c, double v) { P.lsum[c] += v; });
+    reduce_columns(mp, 4 * K, nl, nl, P.part, [&](int c, double v) { P.lsum[c] += v; });
     __syncthreads();
     if (tid < nl) {
       const double v = P.lsum[tid];
       if (S.g_lens) S.g_lens[(size_t)b * nl + tid] = (float)v;
       if (!isfinite(v)) atomicOr(&P.stat, RTU_ST_NONFINITE);
     }
-    __syncthreads();
-    // ---- GP adjoint
+  }
+  // ---- role 1: the GP adjoint
+  if (role == 1) {
     const float* ps = S.ps + (size_t)b * 4;
     const Matern mt = make_matern(ps);
     const float alpha = ps[3];
@@ -1104,46 +1136,74 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, unsigned char*
     double pacc[4] = {0.0, 0.0, 0.0, 0.0};   // sigma, n, zeta, alpha
     const float inv_n2 = 1.f / (float)n2;
     const float inv_sig = 1.f / ps[0], inv_zeta = 1.f / mt.zeta, dn_c = (mt.n + 1.f) / (2.f * mt.n);
-    // rows: fbar = sbar ds/df, ds/df = alpha s sigmoid(x)/(s0 softplus(x)), x = f/s0
-    fft_pass<2>(lds, cap, n, logn, false, -1.f, false, 0.f,
-             [&](int r, int c) {
-               const int q = r * n + c;
-               const float x = fo[q] * 100.f;
-               const float s = so[q];
-               const SoftplusTerms sp = softplus_terms(x);
-               const float sbq = (float)sb[q];
-               pacc[3] += (double)(sbq * s * (-4.605170186f + sp.lsp));
-               return make_float2(sbq * alpha * s * sp.ratio * 100.f, 0.f);
-             },
-             [&](int, int, float2 v) { return v; },
-             [&](int r, int c, float2 v) { T[r * n + c] = v; });
-    // columns: forward -> Fbar; spectrum gradient; multiply by sqrt(P); inverse
-    fft_pass<2>(lds, cap, n, logn, true, -1.f, true, 1.f,
-             [&](int r, int c) { return T[r * n + c]; },
-             [&](int r, int c, float2 v) {
-               const float kx = fft_freq(c, n), ky = fft_freq(r, n);
-               const float k2 = kx * kx + ky * ky;
-               const float sp = matern_sqrtP(mt, k2);
-               const float2 f0 = F[r * n + c];
-               // Re(F conj(Fbar)) sqrt(P) / n^2 times d log sqrt(P) / d (sigma, n, zeta):
-               //   1/sigma,  ((n+1)/(2n)) k^2/(a+k^2) + log(a/(a+k^2))/2,  (a - n k^2)/(zeta (a+k^2))
-               const float re = (f0.x * v.x + f0.y * v.y) * inv_n2 * sp;
-               const float iapk = 1.f / (mt.a + k2);
-               pacc[0] += (double)(re * inv_sig);
-               pacc[1] += (double)(re * (dn_c * k2 * iapk + 0.5f * __logf(mt.a * iapk)));
-               pacc[2] += (double)(re * ((mt.a - mt.n * k2) * iapk * inv_zeta));
-               return make_float2(v.x * sp, v.y * sp);
-             },
-             [&](int r, int c, float2 v) { T[r * n + c] = v; });
+    // fbar = sbar ds/df, ds/df = alpha s sigmoid(x)/(s0 softplus(x)), x = f/s0
+    auto fbar_of = [&](float sbq, float f, float s) {
+      const SoftplusTerms sp = softplus_terms(f * 100.f);
+      pacc[3] += (double)(sbq * s * (-4.605170186f + sp.lsp));
+      return sbq * alpha * s * sp.ratio * 100.f;
+    };
+    // the spectrum: Re(F conj(Fbar)) sqrt(P) / n^2 times d log sqrt(P) / d (sigma, n, zeta):
+    //   1/sigma,  ((n+1)/(2n)) k^2/(a+k^2) + log(a/(a+k^2))/2,  (a - n k^2)/(zeta (a+k^2));
+    // returns Fbar sqrt(P)
+    auto spectrum = [&](int r, int c, float2 v, float2 f0) {
+      const float kx = fft_freq(c, n), ky = fft_freq(r, n);
+      const float k2 = kx * kx + ky * ky;
+      const float sq = matern_sqrtP(mt, k2);
+      const float re = (f0.x * v.x + f0.y * v.y) * inv_n2 * sq;
+      const float iapk = 1.f / (mt.a + k2);
+      pacc[0] += (double)(re * inv_sig);
+      pacc[1] += (double)(re * (dn_c * k2 * iapk + 0.5f * __logf(mt.a * iapk)));
+      pacc[2] += (double)(re * ((mt.a - mt.n * k2) * iapk * inv_zeta));
+      return make_float2(v.x * sq, v.y * sq);
+    };
     uint32_t bad = 0;
-    fft_pass<2>(lds, cap, n, logn, false, 1.f, false, 0.f,
-             [&](int r, int c) { return T[r * n + c]; },
-             [&](int, int, float2 v) { return v; },
-             [&](int r, int c, float2 v) {
-               const float g = v.x * inv_n2 + w[r * n + c];
-               if (S.g_lat) S.g_lat[(size_t)b * n2 + r * n + c] = g;
-               if (!isfinite(g)) bad = 1;
-             });
+    auto latent_grad = [&](int q, float v, float wq) {
+      const float g = v * inv_n2 + wq;
+      if (S.g_lat) S.g_lat[(size_t)b * n2 + q] = g;
+      if (!isfinite(g)) bad = 1;
+    };
+    if (n <= 128) {
+      // the whole grid in LDS (as in the prep transform; F in split layout)
+      float2* tw = lds + cap;
+      for (int k = tid; k < 128; k += blockDim.x) tw[k] = c_tw[k];
+      const int ls = n + 1;
+      batched_copy<4>(n2, [&](int q) { return make_float4((float)sb[q], fo[q], so[q], 0.f); },
+                      [&](int q, float4 v) {
+                        lds[(q >> logn) * ls + (q & (n - 1))] = make_float2(fbar_of(v.x, v.y, v.z), 0.f);
+                      });
+      __syncthreads();
+      fft_grid_dir(lds, tw, n, logn, false, -1.f, true);
+      fft_grid_dir(lds, tw, n, logn, true, -1.f, true);
+      batched_copy<8>(n2, [&](int q) { return F[q]; },
+                      [&](int q, float2 f0) {
+                        const int rs = q >> logn, cs = q & (n - 1);
+                        float2* a = lds + rs * ls + cs;
+                        *a = spectrum(split_nat(rs, logn), split_nat(cs, logn), *a, f0);
+                      });
+      __syncthreads();
+      fft_grid_dir(lds, tw, n, logn, true, 1.f, false);
+      fft_grid_dir(lds, tw, n, logn, false, 1.f, false);
+      batched_copy<8>(n2, [&](int q) { return w[q]; },
+                      [&](int q, float wq) { latent_grad(q, lds[(q >> logn) * ls + (q & (n - 1))].x, wq); });
+    } else {
+      // larger grids: lines in chunks through the workspace T
+      fft_pass<2>(lds, cap, n, logn, false, -1.f, false, 0.f,
+               [&](int r, int c) {
+                 const int q = r * n + c;
+                 return make_float2(fbar_of((float)sb[q], fo[q], so[q]), 0.f);
+               },
+               [&](int, int, float2 v) { return v; },
+               [&](int r, int c, float2 v) { T[r * n + c] = v; });
+      // columns: forward -> Fbar; spectrum gradient; times sqrt(P); inverse
+      fft_pass<2>(lds, cap, n, logn, true, -1.f, true, 1.f,
+               [&](int r, int c) { return T[r * n + c]; },
+               [&](int r, int c, float2 v) { return spectrum(r, c, v, F[r * n + c]); },
+               [&](int r, int c, float2 v) { T[r * n + c] = v; });
+      fft_pass<2>(lds, cap, n, logn, false, 1.f, false, 0.f,
+               [&](int r, int c) { return T[r * n + c]; },
+               [&](int, int, float2 v) { return v; },
+               [&](int r, int c, float2 v) { latent_grad(r * n + c, v.x, w[r * n + c]); });
+    }
     if (bad) atomicOr(&P.stat, RTU_ST_NONFINITE);
     block_sum<4>(pacc, P.red);
     if (tid < 4 && S.g_ps) {
@@ -1152,13 +1212,29 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, unsigned char*
     }
   }
   __syncthreads();
-  if (tid == 0) S.status[b] = P.stat | S.st[b * 4 + 0] | S.st[b * 4 + 1] | S.st[b * 4 + 2];
+  // status: the OR of the stages' words, written by the role that finishes last
+  if (tid == 0) {
+    uint32_t* st = S.st + (size_t)b * ST_WORDS;
+    if (!S.want_grad) {
+      S.status[b] = P.stat | st[0] | st[1] | st[2];
+    } else {
+      st[3 + role] = P.stat;
+      __threadfence();
+      if (atomicAdd(&st[5], 1u) == 1u) {
+        __threadfence();
+        S.status[b] = st[0] | st[1] | st[2] | __atomic_load_n(&st[3], __ATOMIC_RELAXED) |
+                      __atomic_load_n(&st[4], __ATOMIC_RELAXED);
+      }
+    }
+  }
 }
 
 __global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S, int fft_cap) {
   extern __shared__ __align__(16) unsigned char fft_smem[];
   __shared__ PostLds P;
-  post_body(S, blockIdx.x, fft_smem, fft_cap, P);
+  // one inlined copy per role, so that each holds only its own code
+  if (blockIdx.y == 0) post_body(S, blockIdx.x, 0, fft_smem, fft_cap, P);
+  else post_body(S, blockIdx.x, 1, fft_smem, fft_cap, P);
 }
 
 // ====================================================================== launchers
@@ -1270,7 +1346,7 @@ hipError_t launch_psf(const SysDev& h, int batch, bool adjoint, hipStream_t s) {
 }
 
 hipError_t launch_post(const SysDev& h, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_post, dim3(batch), dim3(PREP_THREADS), post_lds_bytes(h.n_src, h.n_lens), s, h,
+  hipLaunchKernelGGL(k_post, dim3(batch, h.want_grad ? 2 : 1), dim3(PREP_THREADS), post_lds_bytes(h.n_src, h.n_lens), s, h,
                      fft_lds_cap(h.n_src));
   return hipGetLastError();
 }
@@ -1331,7 +1407,8 @@ __global__ void __launch_bounds__(PREP_THREADS) kf_post(const SysDev* __restrict
   const Task t = tasks[blockIdx.x];
   const SysDev S = sys[t.x];
   if (!sys_active(S, round)) return;
-  post_body(S, t.y, fft_smem, fft_cap, P);
+  if (t.z == 0) post_body(S, t.y, 0, fft_smem, fft_cap, P);
+  else post_body(S, t.y, 1, fft_smem, fft_cap, P);
 }
 
 hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, const float* eps, hipStream_t s);

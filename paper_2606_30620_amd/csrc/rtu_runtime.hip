@@ -131,7 +131,7 @@ size_t carve_workspace(SysDev& h, int B, char* base) {
   h.kbar = c.take<double>((size_t)B * h.ray_tiles * 4 * K);
   h.lpart = c.take<double>((size_t)B * h.ray_tiles * h.n_lens);
   h.c2part = c.take<double>((size_t)B * h.psf_tiles * 2);
-  h.st = c.take<uint32_t>((size_t)B * 4);
+  h.st = c.take<uint32_t>((size_t)B * ST_WORDS);
   return c.off + 256;
 }
 
