@@ -166,7 +166,7 @@ __device__ bool select_by_counting(SelLds& L, const float* zb, int M, float vmin
     if (!(t > 0.f)) return isinf(v) && v > 0.f ? HIST_BINS - 1 : 0;
     return t < (float)HIST_BINS ? (int)t : HIST_BINS - 1;
   };
-  for (int m = tid; m < M; m += nt) atomicAdd(&hist[bin_of(zb[m])], 1);
+  batched_copy<8>(M, [&](int m) { return zb[m]; }, [&](int, float v) { atomicAdd(&hist[bin_of(v)], 1); });
   __syncthreads();
   block_exclusive_scan(hist, HIST_BINS, reinterpret_cast<int*>(L.red));
   if (tid < 2 * K) {
@@ -179,24 +179,36 @@ __device__ bool select_by_counting(SelLds& L, const float* zb, int M, float vmin
     L.tbin[tid] = lo;
   }
   __syncthreads();
-  if (tid == 0) {
-    int ns = 0, tot = 0, mx = 0;
-    for (int t = 0; t < 2 * K; ++t) {
-      const int bb = L.tbin[t];
-      if (ns == 0 || L.seg_bin[ns - 1] != bb) {
-        L.seg_bin[ns] = bb;
-        L.seg_t0[ns] = t;
-        L.seg_start[ns] = tot;
-        L.seg_count[ns] = hist[bb + 1] - hist[bb];
-        L.seg_fill[ns] = 0;
-        tot += L.seg_count[ns];
-        mx = max(mx, L.seg_count[ns]);
-        ++ns;
-      }
+  // segments = runs of targets in one bin (the target bins ascend): one wave,
+  // lane t for target t; a run starts where the bin changes
+  if (tid < 64) {
+    const int t = tid;
+    const bool valid = t < 2 * K;
+    const int bb = valid ? L.tbin[t] : -1;
+    const int prev = __shfl_up(bb, 1, 64);
+    const bool head = valid && (t == 0 || prev != bb);
+    const unsigned long long hm = __ballot(head);
+    const int cnt = head ? hist[bb + 1] - hist[bb] : 0;
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(incl, o, 64);
+      if (t >= o) incl += u;
     }
-    L.nseg = ns;
-    L.total = tot;
-    L.maxcnt = mx;
+    int mx = cnt;
+    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    if (head) {
+      const int sg = __popcll(hm & ((2ull << t) - 1ull)) - 1;   // heads at lanes <= t, minus one
+      L.seg_bin[sg] = bb;
+      L.seg_t0[sg] = t;
+      L.seg_start[sg] = incl - cnt;
+      L.seg_count[sg] = cnt;
+      L.seg_fill[sg] = 0;
+    }
+    if (t == 63) {
+      L.nseg = __popcll(hm);
+      L.total = incl;
+      L.maxcnt = mx;
+    }
   }
   __syncthreads();
   const int nseg = L.nseg, total = L.total;
@@ -208,14 +220,13 @@ __device__ bool select_by_counting(SelLds& L, const float* zb, int M, float vmin
   __syncthreads();
   if (tid < nseg) hist[L.seg_bin[tid]] = tid;
   __syncthreads();
-  for (int m = tid; m < M; m += nt) {
-    const float v = zb[m];
+  batched_copy<8>(M, [&](int m) { return zb[m]; }, [&](int m, float v) {
     const int sg = hist[bin_of(v)];
     if (sg >= 0) {
       const int pos = atomicAdd(&L.seg_fill[sg], 1);
       L.c.cand[L.seg_start[sg] + pos] = sel_key(v, m);
     }
-  }
+  });
   __syncthreads();
   // rank inside each segment by counting, all candidates in parallel; the
   // targets of a segment are a contiguous range of t (ranks are sorted)
@@ -363,8 +374,13 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
   double sx = 0, sy = 0, sxx = 0, syy = 0;
   float vmin = INFINITY, vmax = -INFINITY;      // over the finite values
   unsigned umin = 0xffffffffu, umax = 0u;       // key range over all values
+  // the mask index of the iteration after next is loaded ahead
+  int p1 = tid < M ? S.mask_idx[tid] : 0;
+  int p2 = tid + nt < M ? S.mask_idx[tid + nt] : 0;
   for (int m = tid; m < M; m += nt) {
-    const int p = S.mask_idx[m];
+    const int p = p1;
+    p1 = p2;
+    if (m + 2 * nt < M) p2 = S.mask_idx[m + 2 * nt];
     const int i = p / S.n_img, j = p - i * S.n_img;
     const float x = ((float)j - 0.5f * (float)(S.n_img - 1)) * S.pix;
     const float y = ((float)i - 0.5f * (float)(S.n_img - 1)) * S.pix;
