@@ -21,6 +21,23 @@ constexpr int GRID_LDS_MAX = 64;        // n_src <= this: source grid staged in 
 constexpr int FFT_LDS_MAX = 128 * 129;  // FFT line buffer (float2): 128 lines of 128 + 1 pad = 129 KB
 constexpr int KBAR = 4 * K;             // per axis pair: dX[K], dS[K]  (x: 0..2K, y: 2K..4K)
 
+// Per-sample tables of the two smoothed-CDF splines, in the layout the ray
+// kernels keep in LDS; built once per sample by the selection workgroups (each
+// writes its axis).  For axis ax and interval k (0: below the first knot, K:
+// above the last; else [X_{k-1}, X_k)): the local coordinate
+// t = (z - ct.x) ct.y and the grid coordinate T = n g - 1/2 =
+// ((cq.w t + cq.z) t + cq.y) t + cq.x.
+struct KnotTab {
+  float4 cq[2][K + 1];
+  float2 ct[2][K + 1];
+  float2 kr[2][K + 1];  // interval k as [kr.x, kr.y), with -inf / +inf at the ends
+  float xs[2][32];      // knots, then +inf (branch-free search)
+  float X[2][K], Sl[2][K], ih[2][K], dp[2][K];
+  float du[K];          // u_{l+1} - u_l (0 for l = K-1)
+  float pad[2];
+};
+static_assert(sizeof(KnotTab) % 16 == 0, "KnotTab is copied as float4");
+
 // Everything a kernel needs about one lens system and the samples of a call.
 // Sample b of a per-sample array starts at base + b * (its per-sample size).
 struct SysDev {
@@ -58,6 +75,7 @@ struct SysDev {
   // workspace (owned by the plan)
   float* src;                 // [B][n^2] source brightness s
   float* srcp;                // [B][(n+2)^2] s with a one-cell zero border (corner reads need no bounds checks)
+  KnotTab* ktab;              // [B] spline tables for the ray kernels
   float* fld;                 // [B][n^2] GP field f
   float2* F;                  // [B][n^2] DFT of the latent
   float2* tmp;                // [B][n^2] FFT scratch

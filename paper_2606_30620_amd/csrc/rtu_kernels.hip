@@ -125,6 +125,7 @@ struct SelLds {
   float tval[2 * K];
   int tidx[2 * K];
   double q[K];
+  float kx[K], ks[K], kd[K];   // the knots, slopes and d p / d u as stored (FP32)
   uint32_t stat;
 };
 
@@ -356,6 +357,42 @@ __device__ void select_by_radix(SelLds& L, const float* zb, int M, unsigned umin
   __syncthreads();
 }
 
+// The spline tables of one axis for the ray kernels (App. C iv): the Hermite
+// pieces g = u_l + du (3t^2 - 2t^3) + h S_l (t^3 - 2t^2 + t) + h S_r (t^3 - t^2)
+// as cubics in t, scaled to grid coordinates, with linear continuation by the
+// end slopes outside the knots.
+__device__ __forceinline__ void knot_table(const SysDev& S, int b, int ax, const float* X, const float* Sl,
+                                           const float* dp) {
+  KnotTab& T = S.ktab[b];
+  const int tid = threadIdx.x;
+  const float n = (float)S.n_src;
+  if (tid < K) {
+    T.X[ax][tid] = X[tid];
+    T.Sl[ax][tid] = Sl[tid];
+    T.dp[ax][tid] = dp[tid];
+    T.ih[ax][tid] = tid < K - 1 ? 1.f / (X[tid + 1] - X[tid]) : 0.f;
+    if (ax == 0) T.du[tid] = tid < K - 1 ? c_u[tid + 1] - c_u[tid] : 0.f;
+  }
+  if (tid < 32) T.xs[ax][tid] = tid < K ? X[tid] : INFINITY;
+  if (tid <= K) {
+    const int k = tid;
+    T.kr[ax][k] = make_float2(k == 0 ? -INFINITY : X[k - 1], k == K ? INFINITY : X[k]);
+    if (k == 0 || k == K) {
+      const int e = k == 0 ? 0 : K - 1;
+      T.ct[ax][k] = make_float2(X[e], 1.f);
+      T.cq[ax][k] = make_float4(n * c_u[e] - 0.5f, n * Sl[e], 0.f, 0.f);
+    } else {
+      const int l = k - 1;
+      const float h = X[l + 1] - X[l];
+      const float du = c_u[l + 1] - c_u[l], hs0 = h * Sl[l], hs1 = h * Sl[l + 1];
+      T.ct[ax][k] = make_float2(X[l], 1.f / h);
+      T.cq[ax][k] = make_float4(n * c_u[l] - 0.5f, n * hs0, n * (3.f * du - 2.f * hs0 - hs1),
+                                n * (hs0 + hs1 - 2.f * du));
+    }
+  }
+  if (ax == 0 && tid < 2) T.pad[tid] = 0.f;
+}
+
 __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* smem) {
   SelLds& L = *reinterpret_cast<SelLds*>(smem);
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -468,11 +505,12 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
     const double mud = degenerate ? 0.0 : mu;
     kd[tid] = (float)q[tid];
     kd[K + tid] = (float)(1.0 / dpc);
-    kn[tid] = (float)(mud + scd * q[tid]);
-    kn[K + tid] = (float)(1.0 / (scd * dpc));
-    dpo[tid] = clamp ? -1.f : (float)(scd * dpc);
+    L.kx[tid] = kn[tid] = (float)(mud + scd * q[tid]);
+    L.ks[tid] = kn[K + tid] = (float)(1.0 / (scd * dpc));
+    L.kd[tid] = dpo[tid] = clamp ? -1.f : (float)(scd * dpc);
   }
   __syncthreads();
+  knot_table(S, b, axis, L.kx, L.ks, L.kd);
   if (tid == 0) {
     if (axis == 0) {
       double* sd = S.stdv + (size_t)b * 4;
@@ -588,67 +626,23 @@ __global__ void __launch_bounds__(PREP_THREADS) k_prep(SysDev S, int fft_cap) {
 // ====================================================================== ray tiles
 // Source grid staged in LDS with a one-cell zero border:
 // padded index (i + 1) * (n + 2) + (j + 1) for i, j in [-1, n].
-struct RayLdsHead {
+struct RayLdsHead : KnotTab {
   double kb[4 * K];  // knot adjoint: dX (x), dS (x), dX (y), dS (y)
-  // per axis and interval k (0: below the first knot, K: above the last; else
-  // [X_{k-1}, X_k)): the local coordinate t = (z - ct.x) * ct.y and the grid
-  // coordinate T = n g - 1/2 = ((cq.w t + cq.z) t + cq.y) t + cq.x
-  float4 cq[2][K + 1];
-  float2 ct[2][K + 1];
-  float2 kr[2][K + 1];  // interval k as [kr.x, kr.y), with -inf / +inf at the ends
-  float xs[2][32];      // knots, then +inf (branch-free search)
-  float du[K];          // u_{l+1} - u_l (0 for l = K-1)
-  float X[2][K], Sl[2][K], ih[2][K], dp[2][K];
   Nfw nfw[RTU_MAX_SUB];
-  float pad[2];
 };
 
+// The sample's spline tables into LDS (one 16-byte load per thread), the
+// knot-adjoint accumulators zeroed, the subhalo constants.
 __device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H) {
   {
     const int ns = n_sub_of(S, b);
     const float* lensp = S.lens + (size_t)b * S.n_lens;
     if ((int)threadIdx.x < ns) H.nfw[threadIdx.x] = make_nfw(lensp + RTU_N_LENS_BASE + RTU_N_PER_SUB * threadIdx.x, S.tau);
   }
-  const float* kn = S.knots + (size_t)b * 4 * K;
-  const float* dp = S.dp + (size_t)b * 2 * K;
-  for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
-    const int ax = i / K, k = i - ax * K;
-    H.X[ax][k] = kn[ax * 2 * K + k];
-    H.Sl[ax][k] = kn[ax * 2 * K + K + k];
-    H.dp[ax][k] = dp[i];
-  }
+  const float4* src = reinterpret_cast<const float4*>(S.ktab + b);
+  float4* dst = reinterpret_cast<float4*>(static_cast<KnotTab*>(&H));
+  for (int i = threadIdx.x; i < (int)(sizeof(KnotTab) / 16); i += blockDim.x) dst[i] = src[i];
   for (int i = threadIdx.x; i < 4 * K; i += blockDim.x) H.kb[i] = 0.0;
-  for (int i = threadIdx.x; i < 2 * K; i += blockDim.x) {
-    const int ax = i / K, k = i - ax * K;
-    H.ih[ax][k] = k < K - 1 ? 1.f / (kn[ax * 2 * K + k + 1] - kn[ax * 2 * K + k]) : 0.f;
-  }
-  for (int i = threadIdx.x; i < 2 * 32; i += blockDim.x) {
-    const int ax = i >> 5, k = i & 31;
-    H.xs[ax][k] = k < K ? kn[ax * 2 * K + k] : INFINITY;
-    if (k <= K)
-      H.kr[ax][k] = make_float2(k == 0 ? -INFINITY : kn[ax * 2 * K + k - 1], k == K ? INFINITY : kn[ax * 2 * K + k]);
-  }
-  for (int i = threadIdx.x; i < K; i += blockDim.x) H.du[i] = i < K - 1 ? c_u[i + 1] - c_u[i] : 0.f;
-  // the Hermite pieces (App. C iv) as cubics in t, scaled to grid coordinates:
-  // g = u_l + du (3t^2 - 2t^3) + h S_l (t^3 - 2t^2 + t) + h S_r (t^3 - t^2)
-  const float n = (float)S.n_src;
-  for (int i = threadIdx.x; i < 2 * (K + 1); i += blockDim.x) {
-    const int ax = i / (K + 1), k = i - ax * (K + 1);
-    const float* X = kn + ax * 2 * K;
-    const float* Sl = X + K;
-    if (k == 0 || k == K) {          // linear continuation with the end slope
-      const int e = k == 0 ? 0 : K - 1;
-      H.ct[ax][k] = make_float2(X[e], 1.f);
-      H.cq[ax][k] = make_float4(n * c_u[e] - 0.5f, n * Sl[e], 0.f, 0.f);
-    } else {
-      const int l = k - 1;
-      const float h = X[l + 1] - X[l];
-      const float du = c_u[l + 1] - c_u[l], hs0 = h * Sl[l], hs1 = h * Sl[l + 1];
-      H.ct[ax][k] = make_float2(X[l], 1.f / h);
-      H.cq[ax][k] = make_float4(n * c_u[l] - 0.5f, n * hs0, n * (3.f * du - 2.f * hs0 - hs1),
-                                n * (hs0 + hs1 - 2.f * du));
-    }
-  }
 }
 
 // Interval of z on axis ax (the number of knots <= z), trying the previous
@@ -682,7 +676,7 @@ __device__ __forceinline__ void load_grid(const SysDev& S, int b, float* g) {
   if (!LDSGRID) return;
   const int np = S.n_src + 2;
   const float* sp = S.srcp + (size_t)b * np * np;
-  for (int i = threadIdx.x; i < np * np; i += blockDim.x) g[i] = sp[i];
+  batched_copy<8>(np * np, [&](int i) { return sp[i]; }, [&](int i, float v) { g[i] = v; });
 }
 
 // bilinear weights at grid coordinates (tx, ty) = n y - 1/2 (nodes at
@@ -916,7 +910,21 @@ __global__ void __launch_bounds__(RAY_THREADS) k_rays_adj(SysDev S) {
 // out[i, j] = sum_{a,b} W[a, b] in[i + a - h, j + b - h] (zero outside), h = (KP-1)/2.
 // Forward: in = u, W = flipped PSF (a convolution), also r = (m - d)/sigma^2 and
 // chi^2 partials.  Adjoint: in = r, W = PSF (the transpose of the convolution).
-__device__ __forceinline__ int psf_row_stride(int KP) { return (PSF_TW + KP - 1 + 3) & ~3; }
+// The correlation runs on the matrix cores.  For a block of 16 x 16 outputs
+// (x: column, y: row) and PSF row a it is a product with a banded Toeplitz
+// matrix of the weights:
+//   out[y][x] += sum_k T_a[x][k] in[y + a][x0 + k],  T_a[x][k] = W[a][k - x] (0 outside [0, KP)),
+// k < 4 psf_nk(KP) (at least 15 + KP), as psf_nk(KP) steps of
+// v_mfma_f32_16x16x4_f32 per PSF row (FP32 products and sums).
+__host__ __device__ constexpr int psf_nk(int KP) { return (15 + KP + 3) / 4; }
+// weight rows zero-padded on both sides: T_a[x][k] = Wp[a][k - x + 15]
+__host__ __device__ constexpr int psf_ws(int KP) { return 4 * psf_nk(KP) + 16; }
+// LDS row stride of the input tile: it covers the halo and the reads of the
+// last wave's last step, and is 4 mod 8, so that the 16 rows x 4 columns read
+// by one MFMA operand fall in distinct banks.
+__host__ __device__ constexpr int psf_row_stride(int KP) {
+  return (PSF_TW - 16 + 4 * psf_nk(KP)) % 8 == 4 ? PSF_TW - 16 + 4 * psf_nk(KP) : PSF_TW - 12 + 4 * psf_nk(KP);
+}
 
 // residual, model and chi^2 partials of 4 output pixels (forward), or the
 // adjoint image (adjoint), then the tile's FP64 chi^2 sums
@@ -960,62 +968,61 @@ __device__ __forceinline__ void psf_load_tile(const SysDev& S, int b, int adjoin
   const int N = S.n_img, h = KP / 2;
   const int HW = PSF_TW + KP - 1, LS = psf_row_stride(KP), HH = PSF_TH + KP - 1;
   const float* in = (adjoint ? S.r : S.u) + (size_t)b * N * N;
-  for (int q = threadIdx.x; q < HH * LS; q += blockDim.x) {
-    const int rr = q / LS, cc = q - rr * LS;
-    const int gi = ty0 + rr - h, gj = tx0 + cc - h;
-    tilein[q] = (cc < HW && gi >= 0 && gi < N && gj >= 0 && gj < N) ? in[gi * N + gj] : 0.f;
-  }
+  batched_copy<8>(HH * LS,
+                  [&](int q) {
+                    const int rr = q / LS, cc = q - rr * LS;
+                    const int gi = ty0 + rr - h, gj = tx0 + cc - h;
+                    return (cc < HW && gi >= 0 && gi < N && gj >= 0 && gj < N) ? in[gi * N + gj] : 0.f;
+                  },
+                  [&](int q, float v) { tilein[q] = v; });
   __syncthreads();
 }
 
 // out[i, j] = sum_{a,b} W[a, b] in[i + a - h, j + b - h] (zero outside), h = (KP-1)/2.
 // Forward: in = u, W = flipped PSF (a convolution), also r = (m - d)/sigma^2 and
 // chi^2 partials.  Adjoint: in = r, W = PSF (the transpose of the convolution).
-template <int KP>
+// Wave w of the workgroup computes the 16 x 16 outputs of tile columns
+// [16 w, 16 w + 16); a wave wholly right of the image skips its products.
+// Lane l: A = Wp[a][4 q + l / 16 - l % 16 + 15], B = in[l % 16 + a][16 w + 4 q + l / 16];
+// the accumulator holds row l % 16, columns 16 w + 4 (l / 16) + r, r < 4.
+// KPT = 0: the PSF size is a run-time value.
+template <int KPT>
 __device__ void psf_body(const SysDev& S, int b, int tile, int adjoint, float* tilein, double* red) {
-  constexpr int LS = (PSF_TW + KP - 1 + 3) & ~3;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const int KP = KPT ? KPT : S.psf_k;
+  const int NK = psf_nk(KP), WS = psf_ws(KP), LS = psf_row_stride(KP);
   const int ty0 = (tile / S.psf_tx) * PSF_TH, tx0 = (tile % S.psf_tx) * PSF_TW;
-  const float* W = adjoint ? S.psf : S.psf_flip;
-  psf_load_tile(S, b, adjoint, KP, ty0, tx0, tilein);
-  const int ly = threadIdx.x >> 4, lx = (threadIdx.x & 15) * 4;
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-  for (int a = 0; a < KP; ++a) {
-    const float* row = tilein + (ly + a) * LS + lx;
-    float win[KP + 3];
-#pragma unroll
-    for (int q = 0; q < KP + 3; ++q) win[q] = row[q];
-#pragma unroll
-    for (int c = 0; c < KP; ++c) {
-      const float wv = W[a * KP + c];
-      acc[0] = fmaf(wv, win[c], acc[0]);
-      acc[1] = fmaf(wv, win[c + 1], acc[1]);
-      acc[2] = fmaf(wv, win[c + 2], acc[2]);
-      acc[3] = fmaf(wv, win[c + 3], acc[3]);
+  float* wp = tilein + (PSF_TH + KP - 1) * LS;
+  {
+    const float* W = adjoint ? S.psf : S.psf_flip;
+    for (int q = threadIdx.x; q < KP * WS; q += blockDim.x) {
+      const int a = q / WS, c = q - a * WS - 15;
+      wp[q] = (c >= 0 && c < KP) ? W[a * KP + c] : 0.f;
     }
   }
-  psf_epilogue(S, b, tile, adjoint, ty0, tx0, ly, lx, acc, red);
-}
-
-// any PSF size: direct LDS reads
-__device__ void psf_any_body(const SysDev& S, int b, int tile, int adjoint, float* tilein, double* red) {
-  const int KP = S.psf_k, LS = psf_row_stride(KP);
-  const int ty0 = (tile / S.psf_tx) * PSF_TH, tx0 = (tile % S.psf_tx) * PSF_TW;
-  const float* W = adjoint ? S.psf : S.psf_flip;
   psf_load_tile(S, b, adjoint, KP, ty0, tx0, tilein);
-  const int ly = threadIdx.x >> 4, lx = (threadIdx.x & 15) * 4;
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int a = 0; a < KP; ++a) {
-    const float* row = tilein + (ly + a) * LS + lx;
-    for (int c = 0; c < KP; ++c) {
-      const float wv = W[a * KP + c];
-      acc[0] = fmaf(wv, row[c], acc[0]);
-      acc[1] = fmaf(wv, row[c + 1], acc[1]);
-      acc[2] = fmaf(wv, row[c + 2], acc[2]);
-      acc[3] = fmaf(wv, row[c + 3], acc[3]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+  if (tx0 + wave * 16 < S.n_img) {
+    const float* ap = wp + 15 + lq - lr;
+    const float* bp = tilein + lr * LS + wave * 16 + lq;
+    const int nk = KPT ? psf_nk(KPT) : NK;   // a constant for the templated sizes
+    int a = 0;
+    for (; a + 1 < KP; a += 2) {
+#pragma unroll
+      for (int q = 0; q < nk; ++q) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[a * WS + 4 * q], bp[a * LS + 4 * q], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[(a + 1) * WS + 4 * q], bp[(a + 1) * LS + 4 * q], acc1, 0,
+                                                    0, 0);
+      }
     }
+    if (a < KP)
+      for (int q = 0; q < nk; ++q)
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[a * WS + 4 * q], bp[a * LS + 4 * q], acc0, 0, 0, 0);
   }
-  psf_epilogue(S, b, tile, adjoint, ty0, tx0, ly, lx, acc, red);
+  const float out[4] = {acc0[0] + acc1[0], acc0[1] + acc1[1], acc0[2] + acc1[2], acc0[3] + acc1[3]};
+  psf_epilogue(S, b, tile, adjoint, ty0, tx0, lr, wave * 16 + lq * 4, out, red);
 }
 
 __device__ __forceinline__ void psf_dispatch(const SysDev& S, int b, int tile, int adjoint, float* tilein,
@@ -1024,7 +1031,7 @@ __device__ __forceinline__ void psf_dispatch(const SysDev& S, int b, int tile, i
     case 15: psf_body<15>(S, b, tile, adjoint, tilein, red); break;
     case 21: psf_body<21>(S, b, tile, adjoint, tilein, red); break;
     case 31: psf_body<31>(S, b, tile, adjoint, tilein, red); break;
-    default: psf_any_body(S, b, tile, adjoint, tilein, red);
+    default: psf_body<0>(S, b, tile, adjoint, tilein, red);
   }
 }
 
@@ -1350,9 +1357,9 @@ hipError_t launch_rays_adj(const SysDev& h, int batch, hipStream_t s) {
   return hipGetLastError();
 }
 
+// input tile, then the zero-padded weight rows
 size_t psf_lds_bytes(int KP) {
-  const int HW = PSF_TW + KP - 1, LS = (HW + 3) & ~3, HH = PSF_TH + KP - 1;
-  return (size_t)HH * LS * 4;
+  return ((size_t)(PSF_TH + KP - 1) * psf_row_stride(KP) + (size_t)KP * psf_ws(KP)) * 4;
 }
 
 hipError_t launch_psf(const SysDev& h, int batch, bool adjoint, hipStream_t s) {

@@ -70,6 +70,13 @@ def test_ragged_generic_psf_parity():
     _check(p, range(3))
 
 
+def test_smallest_source_grid_parity():
+    say("[gpu] n_src=8 (one 8-point FFT factor per line): 48x48 ss=2 psf=15, batch 2")
+    g = synth.Geometry(48, 0.08, 2, 8, 15, 1.2)
+    p = synth.make_problem("X", batch=2, seed=11, geom=g)
+    _check(p, range(2))
+
+
 def test_subhalo_parity():
     say("[gpu] subhaloes: 96x96 ss=2 n_src=64 psf=15, 3 truncated NFW, batch 2")
     g = synth.Geometry(96, 0.05, 2, 64, 15, 1.0, n_sub_max=3, tnfw_tau=10.0)
