@@ -19,7 +19,18 @@ constexpr int ST_WORDS = 8;
 constexpr int PREP_THREADS = 512;       // quantile selection and FFT workgroups
 constexpr int GRID_LDS_MAX = 64;        // n_src <= this: source grid staged in LDS
 constexpr int FFT_LDS_MAX = 128 * 129;  // FFT line buffer (float2): 128 lines of 128 + 1 pad = 129 KB
-constexpr int KBAR = 4 * K;             // per axis pair: dX[K], dS[K]  (x: 0..2K, y: 2K..4K)
+constexpr int KBAR = 4 * K;
+
+// PSF on the matrix cores: K-steps of 4 per PSF row for 16 output columns
+// (at least 15 + KP window columns), the padded weight-row length, and the
+// LDS row stride of the input tile (covers the halo and the last wave's last
+// step; 4 mod 8, so that one MFMA operand's 16 rows x 4 columns fall in
+// distinct banks).
+__host__ __device__ constexpr int psf_nk(int KP) { return (15 + KP + 3) / 4; }
+__host__ __device__ constexpr int psf_ws(int KP) { return 4 * psf_nk(KP) + 16; }
+__host__ __device__ constexpr int psf_row_stride(int KP) {
+  return (PSF_TW - 16 + 4 * psf_nk(KP)) % 8 == 4 ? PSF_TW - 16 + 4 * psf_nk(KP) : PSF_TW - 12 + 4 * psf_nk(KP);
+}             // per axis pair: dX[K], dS[K]  (x: 0..2K, y: 2K..4K)
 
 // Per-sample tables of the two smoothed-CDF splines, in the layout the ray
 // kernels keep in LDS; built once per sample by the selection workgroups (each
@@ -53,8 +64,9 @@ struct SysDev {
   // observation (owned by the plan)
   const float* image;         // [N*N]
   const float* inv_var;       // [N*N] 1/sigma^2
-  const float* psf_flip;      // [K*K] PSF rotated by 180 degrees (forward correlation)
-  const float* psf;           // [K*K] PSF as given (adjoint correlation)
+  const float* psf_flip;      // [KP][psf_ws(KP)] PSF rotated by 180 degrees (forward correlation),
+                              // each row zero-padded: W[a][c] at [a][c + 15]
+  const float* psf;           // [KP][psf_ws(KP)] PSF as given (adjoint correlation), padded the same way
   const uint8_t* mask;        // [N*N]
   const int* mask_idx;        // [M] row-major pixel index of each masked pixel
   const int* rank_j;          // [K] floor((M-1) u_k)
@@ -133,7 +145,7 @@ struct ObsHost {
   std::vector<int> idx;       // masked pixels, row-major
   int rank_j[K];
   double rank_t[K];
-  std::vector<float> inv_var, flip;
+  std::vector<float> inv_var, wfwd, wadj;   // 1/sigma^2; padded PSF weight rows (forward, adjoint)
 };
 int ensure_constants(int device);
 bool valid_geometry(const rtu_geometry* g);

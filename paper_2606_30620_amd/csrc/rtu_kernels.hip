@@ -646,16 +646,24 @@ __device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H
 }
 
 // Interval of z on axis ax (the number of knots <= z), trying the previous
-// sub-ray's interval k first; the wave searches only if one of its lanes
-// missed, and then without branches.
+// sub-ray's interval k first, then its neighbour on the side z left by; the
+// wave runs the (branch-free) binary search only if one of its lanes is still
+// outside.
 __device__ __forceinline__ int knot_find(const RayLdsHead& H, int ax, float z, int k) {
   const float2 r = H.kr[ax][k];
   const bool ok = r.x <= z && z < r.y;
   if (__any(!ok)) {
-    int s = 0;
+    const int k1 = z < r.x ? max(k - 1, 0) : (z >= r.y ? min(k + 1, K) : k);
+    const float2 r1 = H.kr[ax][k1];
+    const bool ok1 = r1.x <= z && z < r1.y;
+    if (__any(!ok1)) {
+      int s = 0;
 #pragma unroll
-    for (int step = 16; step >= 1; step >>= 1) s = H.xs[ax][s + step - 1] <= z ? s + step : s;
-    k = ok ? k : min(s, K);
+      for (int step = 16; step >= 1; step >>= 1) s = H.xs[ax][s + step - 1] <= z ? s + step : s;
+      k = ok1 ? k1 : min(s, K);
+    } else {
+      k = k1;
+    }
   }
   return k;
 }
@@ -916,15 +924,6 @@ __global__ void __launch_bounds__(RAY_THREADS) k_rays_adj(SysDev S) {
 //   out[y][x] += sum_k T_a[x][k] in[y + a][x0 + k],  T_a[x][k] = W[a][k - x] (0 outside [0, KP)),
 // k < 4 psf_nk(KP) (at least 15 + KP), as psf_nk(KP) steps of
 // v_mfma_f32_16x16x4_f32 per PSF row (FP32 products and sums).
-__host__ __device__ constexpr int psf_nk(int KP) { return (15 + KP + 3) / 4; }
-// weight rows zero-padded on both sides: T_a[x][k] = Wp[a][k - x + 15]
-__host__ __device__ constexpr int psf_ws(int KP) { return 4 * psf_nk(KP) + 16; }
-// LDS row stride of the input tile: it covers the halo and the reads of the
-// last wave's last step, and is 4 mod 8, so that the 16 rows x 4 columns read
-// by one MFMA operand fall in distinct banks.
-__host__ __device__ constexpr int psf_row_stride(int KP) {
-  return (PSF_TW - 16 + 4 * psf_nk(KP)) % 8 == 4 ? PSF_TW - 16 + 4 * psf_nk(KP) : PSF_TW - 12 + 4 * psf_nk(KP);
-}
 
 // residual, model and chi^2 partials of 4 output pixels (forward), or the
 // adjoint image (adjoint), then the tile's FP64 chi^2 sums
@@ -963,13 +962,18 @@ __device__ __forceinline__ void psf_epilogue(const SysDev& S, int b, int tile, i
   }
 }
 
+// The input tile with its halo (zero outside the image), then the padded
+// weight rows right after it, in one pass of batched loads.
 __device__ __forceinline__ void psf_load_tile(const SysDev& S, int b, int adjoint, int KP, int ty0, int tx0,
                                               float* tilein) {
   const int N = S.n_img, h = KP / 2;
   const int HW = PSF_TW + KP - 1, LS = psf_row_stride(KP), HH = PSF_TH + KP - 1;
+  const int nt = HH * LS, nw = KP * psf_ws(KP);
   const float* in = (adjoint ? S.r : S.u) + (size_t)b * N * N;
-  batched_copy<8>(HH * LS,
+  const float* W = adjoint ? S.psf : S.psf_flip;
+  batched_copy<8>(nt + nw,
                   [&](int q) {
+                    if (q >= nt) return W[q - nt];
                     const int rr = q / LS, cc = q - rr * LS;
                     const int gi = ty0 + rr - h, gj = tx0 + cc - h;
                     return (cc < HW && gi >= 0 && gi < N && gj >= 0 && gj < N) ? in[gi * N + gj] : 0.f;
@@ -992,14 +996,7 @@ __device__ void psf_body(const SysDev& S, int b, int tile, int adjoint, float* t
   const int KP = KPT ? KPT : S.psf_k;
   const int NK = psf_nk(KP), WS = psf_ws(KP), LS = psf_row_stride(KP);
   const int ty0 = (tile / S.psf_tx) * PSF_TH, tx0 = (tile % S.psf_tx) * PSF_TW;
-  float* wp = tilein + (PSF_TH + KP - 1) * LS;
-  {
-    const float* W = adjoint ? S.psf : S.psf_flip;
-    for (int q = threadIdx.x; q < KP * WS; q += blockDim.x) {
-      const int a = q / WS, c = q - a * WS - 15;
-      wp[q] = (c >= 0 && c < KP) ? W[a * KP + c] : 0.f;
-    }
-  }
+  const float* wp = tilein + (PSF_TH + KP - 1) * LS;   // the padded weight rows
   psf_load_tile(S, b, adjoint, KP, ty0, tx0, tilein);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lq = lane >> 4;

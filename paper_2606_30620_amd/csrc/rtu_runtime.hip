@@ -139,11 +139,11 @@ size_t carve_workspace(SysDev& h, int B, char* base) {
 // observation and mask-dependent buffers
 size_t carve_observation(SysDev& h, int B, int M, char* base) {
   Carve c{base};
-  const size_t N2 = (size_t)h.n_img * h.n_img, k2 = (size_t)h.psf_k * h.psf_k;
+  const size_t N2 = (size_t)h.n_img * h.n_img, kw = (size_t)h.psf_k * psf_ws(h.psf_k);
   h.image = c.take<float>(N2);
   h.inv_var = c.take<float>(N2);
-  h.psf_flip = c.take<float>(k2);
-  h.psf = c.take<float>(k2);
+  h.psf_flip = c.take<float>(kw);
+  h.psf = c.take<float>(kw);
   h.mask = c.take<uint8_t>(N2);
   h.mask_idx = c.take<int>(M > 0 ? M : 1);
   h.rank_j = c.take<int>(K);
@@ -153,7 +153,9 @@ size_t carve_observation(SysDev& h, int B, int M, char* base) {
 }
 
 // Host side of an observation: masked pixel list, quantile ranks
-// h_k = (M-1) u_k in FP64, inverse variances and the flipped PSF.
+// h_k = (M-1) u_k in FP64, inverse variances and the PSF weight rows of both
+// correlations (the flipped PSF forward, the PSF as given for the adjoint),
+// zero-padded as the matrix-core PSF kernel reads them.
 void prepare_observation(const rtu_geometry* g, const float* noise_sigma, const float* psf,
                          const uint8_t* arc_mask, ObsHost& o) {
   const int N = g->n_img, KP = g->psf_size;
@@ -171,22 +173,27 @@ void prepare_observation(const rtu_geometry* g, const float* noise_sigma, const 
   }
   o.inv_var.resize(N2);
   for (size_t q = 0; q < N2; ++q) o.inv_var[q] = 1.f / (noise_sigma[q] * noise_sigma[q]);
-  o.flip.resize((size_t)KP * KP);
+  const int WS = psf_ws(KP);
+  o.wfwd.assign((size_t)KP * WS, 0.f);
+  o.wadj.assign((size_t)KP * WS, 0.f);
   for (int a = 0; a < KP; ++a)
-    for (int b = 0; b < KP; ++b) o.flip[(size_t)a * KP + b] = psf[(size_t)(KP - 1 - a) * KP + (KP - 1 - b)];
+    for (int b = 0; b < KP; ++b) {
+      o.wfwd[(size_t)a * WS + b + 15] = psf[(size_t)(KP - 1 - a) * KP + (KP - 1 - b)];
+      o.wadj[(size_t)a * WS + b + 15] = psf[(size_t)a * KP + b];
+    }
 }
 
 hipError_t upload_observation(const SysDev& h, const float* image, const float* psf, const uint8_t* arc_mask,
                               const ObsHost& o, hipStream_t s) {
-  const size_t N2 = (size_t)h.n_img * h.n_img, k2 = (size_t)h.psf_k * h.psf_k;
+  const size_t N2 = (size_t)h.n_img * h.n_img, kw = (size_t)h.psf_k * psf_ws(h.psf_k);
   hipError_t e = hipSuccess;
   auto cp = [&](const void* dst, const void* src, size_t n) {
     if (e == hipSuccess && n) e = hipMemcpyAsync(const_cast<void*>(dst), src, n, hipMemcpyHostToDevice, s);
   };
   cp(h.image, image, N2 * 4);
   cp(h.inv_var, o.inv_var.data(), N2 * 4);
-  cp(h.psf_flip, o.flip.data(), k2 * 4);
-  cp(h.psf, psf, k2 * 4);
+  cp(h.psf_flip, o.wfwd.data(), kw * 4);
+  cp(h.psf, o.wadj.data(), kw * 4);
   cp(h.mask, arc_mask, N2);
   cp(h.mask_idx, o.idx.data(), o.idx.size() * 4);
   cp(h.rank_j, o.rank_j, sizeof(o.rank_j));
