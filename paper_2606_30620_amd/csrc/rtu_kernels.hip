@@ -868,9 +868,19 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
     km_flush(cx, H.X[0], H.Sl[0], H.ih[0], H.du, H.kb);
     km_flush(cy, H.X[1], H.Sl[1], H.ih[1], H.du, H.kb + 2 * K);
   }
+  // the touched window: reduced within each wave first, so that the LDS
+  // atomics see one lane per wave (same-address atomics serialise)
   if (LDSGRID) {
-    atomicMin(&bbox[0], bi0); atomicMin(&bbox[1], bj0);
-    atomicMax(&bbox[2], bi1); atomicMax(&bbox[3], bj1);
+    for (int o = 32; o >= 1; o >>= 1) {
+      bi0 = min(bi0, __shfl_xor(bi0, o, 64));
+      bj0 = min(bj0, __shfl_xor(bj0, o, 64));
+      bi1 = max(bi1, __shfl_xor(bi1, o, 64));
+      bj1 = max(bj1, __shfl_xor(bj1, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicMin(&bbox[0], bi0); atomicMin(&bbox[1], bj0);
+      atomicMax(&bbox[2], bi1); atomicMax(&bbox[3], bj1);
+    }
   }
   // ---- lens-gradient partials of this tile (FP64 block sums)
   double* lp = S.lpart + ((size_t)b * S.ray_tiles + tile) * S.n_lens;
