@@ -225,6 +225,20 @@ __device__ __forceinline__ void sie_shear_vjp(const Sie& L, const SieRay& E, flo
 }
 
 // Convert summed accumulators (double) to d loss / d (theta_E, e1, e2, x0, y0, g1, g2).
+// Component q < 7 of the lens gradient from the SIE and shear sums a (the
+// same chain as sie_grad, one output).
+__device__ __forceinline__ double sie_grad_one(const Sie& L, const double* a, int q) {
+  if (q == 0) return a[0] * sqrt((double)L.q);
+  if (q >= 3) return a[q + 1];
+  const double sq = sqrt((double)L.q);
+  const double e = (double)L.e;
+  const double qb = a[1] + a[0] * (double)L.the / (2.0 * sq);
+  const double dqde = -2.0 / ((1.0 + e) * (1.0 + e));
+  const double dfde = (1.0 - e) / (sqrt(e) * (1.0 + e) * (1.0 + e));
+  const double eb = qb * dqde + a[2] * dfde;
+  const double e1 = L.e1, e2 = L.e2;
+  return q == 1 ? eb * e1 / e - a[3] * e2 / (2.0 * e * e) : eb * e2 / e + a[3] * e1 / (2.0 * e * e);
+}
 __device__ __forceinline__ void sie_grad(const Sie& L, const double* a, double* g) {
   // a: P, q, f, phi, x0, y0, g1, g2
   const double sq = sqrt((double)L.q);
@@ -393,6 +407,27 @@ __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// Sum over the 64 lanes of a fully active wave with DPP lane moves inside
+// each row of 16 (swap within pairs, within quads, half-row mirror, row
+// mirror: every lane of a row then holds the row's sum) and the four row sums
+// read from lanes 0, 16, 32, 48.  No LDS traffic; a fixed order, so the result
+// is the same on every lane and in every run.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141>(v);   // row_half_mirror
+  v += dpp_move<0x140>(v);   // row_mirror
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
 }
 __device__ __forceinline__ float wave_min(float v) {
 #pragma unroll

@@ -102,7 +102,7 @@ struct SysDev {
   float* ubar;                // [B][N^2] d loss / d u
   double* sbar;               // [B][n^2] d loss / d s (FP64 accumulation: order-independent to FP32 rounding)
   double* kbar;               // [B][ray_tiles][4K] per-tile dX, dS partials
-  double* lpart;              // [B][ray_tiles][n_lens] per-tile lens-gradient partials
+  double* lpart;              // [B][ray_tiles][4 waves][n_lens + 1] per-wave raw lens-gradient partials
   double* c2part;             // [B][psf_tiles][2] per-tile chi^2 partials (all, mask)
   uint32_t* st;               // [B][ST_WORDS] status words: selection x, y; parameter domain;
                               // post roles 0, 1; post completion count

@@ -882,24 +882,26 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
       atomicMax(&bbox[2], bi1); atomicMax(&bbox[3], bj1);
     }
   }
-  // ---- lens-gradient partials of this tile (FP64 block sums)
-  double* lp = S.lpart + ((size_t)b * S.ray_tiles + tile) * S.n_lens;
+  // ---- lens-gradient partials of this tile, one row per wave: the raw SIE
+  //      and shear accumulators (P, q, f, phi, x0, y0, g1, g2), then the
+  //      subhalo sums; the chain to the lens parameters is linear in them and
+  //      is applied once per sample, after the sums
   {
-    double v[8] = {acc.P, acc.q, acc.f, acc.phi, acc.x0, acc.y0, acc.g1, acc.g2};
-    block_sum<8>(v, red);
-    if (threadIdx.x == 0) {
-      double gl[7];
-      sie_grad(L, v, gl);
-      for (int k = 0; k < 7; ++k) lp[k] = gl[k];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double* lp = S.lpart + (((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64) + wave) * (S.n_lens + 1);
+    const float v[8] = {acc.P, acc.q, acc.f, acc.phi, acc.x0, acc.y0, acc.g1, acc.g2};
+    float r[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r[k] = wave_sum_dpp(v[k]);
+    if (lane == 0)
+      for (int k = 0; k < 8; ++k) lp[k] = (double)r[k];
+    for (int q = 0; q < 4 * S.n_sub_max; ++q) {
+      const float sq = wave_sum_dpp(subacc[q * RAY_THREADS + threadIdx.x]);
+      if (lane == 0) lp[8 + q] = (double)sq;
     }
   }
-  // subhaloes: 4 n_sub_max columns of per-thread sums
-  for (int q = threadIdx.x >> 6; q < 4 * S.n_sub_max; q += RAY_THREADS / 64) {
-    float s = 0.f;
-    for (int t = threadIdx.x & 63; t < RAY_THREADS; t += 64) s += subacc[q * RAY_THREADS + t];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) lp[RTU_N_LENS_BASE + q] = (double)s;
-  }
+  // every wave's knot-moment and window atomics are done before they are read
+  __syncthreads();
   // knot partials of this tile
   double* kbo = S.kbar + ((size_t)b * S.ray_tiles + tile) * 4 * K;
   for (int q = threadIdx.x; q < 4 * K; q += blockDim.x) kbo[q] = H.kb[q];
@@ -1054,7 +1056,7 @@ struct PostLds {
   double red[16 * 16];
   double part[PREP_THREADS];
   double xbar[2][K];      // d loss / d X (beta units), after the slope chain
-  double lsum[RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB];
+  double lsum[RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB + 1];   // raw sums
   uint32_t stat;
 };
 
@@ -1104,10 +1106,11 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
     __syncthreads();
     // ---- selected masked rays: X_k = (1-t_k) beta_(j) + t_k beta_(j+1); each of
     //      the 4K (axis, rank) items writes its lens-gradient row into LDS
-    double* mp = reinterpret_cast<double*>(fft_smem);   // [4K][nl]
+    const int nc = nl + 1;   // raw SIE + shear accumulators (8), subhalo terms
+    double* mp = reinterpret_cast<double*>(fft_smem);   // [4K][nc]
     if (tid < 4 * K) {
-      double* row = mp + tid * nl;
-      for (int q = 0; q < nl; ++q) row[q] = 0.0;
+      double* row = mp + tid * nc;
+      for (int q = 0; q < nc; ++q) row[q] = 0.0;
       const int ax = tid / (2 * K), r = tid - ax * 2 * K, k = r >> 1;
       const double t = S.rank_t[k];
       const double wgt = (r & 1) ? t : 1.0 - t;
@@ -1126,27 +1129,28 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
         float ax_, ay_;
         sie_shear_alpha<true>(L, x, y, ax_, ay_, E);
         sie_shear_vjp(L, E, x, y, abx, aby, a);
-        double av[8] = {a.P, a.q, a.f, a.phi, a.x0, a.y0, a.g1, a.g2};
-        double gl[7];
-        sie_grad(L, av, gl);
-        for (int q = 0; q < 7; ++q) row[q] = gl[q];
+        row[0] = a.P; row[1] = a.q; row[2] = a.f; row[3] = a.phi;
+        row[4] = a.x0; row[5] = a.y0; row[6] = a.g1; row[7] = a.g2;
         for (int q = 0; q < nsub; ++q) {
           const Nfw N = make_nfw(lensp + RTU_N_LENS_BASE + RTU_N_PER_SUB * q, S.tau);
           float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
           nfw_vjp(N, S.tau, x, y, abx, aby, g0, g1, g2, g3);
-          row[7 + 4 * q] = g0; row[8 + 4 * q] = g1; row[9 + 4 * q] = g2; row[10 + 4 * q] = g3;
+          row[8 + 4 * q] = g0; row[9 + 4 * q] = g1; row[10 + 4 * q] = g2; row[11 + 4 * q] = g3;
         }
       }
     }
     __syncthreads();
-    // tile partials, then the masked-ray rows, each summed in a fixed order
-    reduce_columns(S.lpart + (size_t)b * S.ray_tiles * nl, S.ray_tiles, nl, nl, P.part,
+    // the per-wave tile rows, then the masked-ray rows, each summed in a
+    // fixed order; then the chain from the SIE quantities to the lens
+    // parameters, once
+    const int rows = S.ray_tiles * (RAY_THREADS / 64);
+    reduce_columns(S.lpart + (size_t)b * rows * nc, rows, nc, nc, P.part,
                    [&](int c, double v) { P.lsum[c] = v; });
     __syncthreads();
-    reduce_columns(mp, 4 * K, nl, nl, P.part, [&](int c, double v) { P.lsum[c] += v; });
+    reduce_columns(mp, 4 * K, nc, nc, P.part, [&](int c, double v) { P.lsum[c] += v; });
     __syncthreads();
     if (tid < nl) {
-      const double v = P.lsum[tid];
+      const double v = tid < 7 ? sie_grad_one(L, P.lsum, tid) : P.lsum[tid + 1];
       if (S.g_lens) S.g_lens[(size_t)b * nl + tid] = (float)v;
       if (!isfinite(v)) atomicOr(&P.stat, RTU_ST_NONFINITE);
     }
@@ -1314,10 +1318,10 @@ size_t prep_lds_bytes(int n_src) {
   return f > sizeof(SelLds) ? f : sizeof(SelLds);
 }
 // k_post shares its dynamic LDS between the FFT lines and the per-node
-// lens-parameter rows of the knot adjoint ([4K][n_lens] doubles).
+// lens-gradient rows of the masked rays ([4K][n_lens + 1] doubles).
 size_t post_lds_bytes(int n_src, int n_lens) {
   const size_t f = (size_t)(fft_lds_cap(n_src) + 128) * sizeof(float2);
-  const size_t m = (size_t)4 * K * n_lens * sizeof(double);
+  const size_t m = (size_t)4 * K * (n_lens + 1) * sizeof(double);
   return f > m ? f : m;
 }
 

@@ -130,7 +130,7 @@ size_t carve_workspace(SysDev& h, int B, char* base) {
   h.ubar = c.take<float>(B * N2);
   h.sbar = c.take<double>(B * n2);
   h.kbar = c.take<double>((size_t)B * h.ray_tiles * 4 * K);
-  h.lpart = c.take<double>((size_t)B * h.ray_tiles * h.n_lens);
+  h.lpart = c.take<double>((size_t)B * h.ray_tiles * (RAY_THREADS / 64) * (h.n_lens + 1));
   h.c2part = c.take<double>((size_t)B * h.psf_tiles * 2);
   h.st = c.take<uint32_t>((size_t)B * ST_WORDS);
   return c.off + 256;
