@@ -17,7 +17,7 @@ constexpr int PSF_TH = 16;              // 256 threads x 4 columns each
 constexpr int PSF_THREADS = 256;
 constexpr int ST_WORDS = 8;
 constexpr int PREP_THREADS = 512;       // quantile selection and FFT workgroups
-constexpr int GRID_LDS_MAX = 64;        // n_src <= this: source grid staged in LDS
+constexpr int GRID_LDS_MAX = 64;        // n_src <= this: the ray adjoint keeps d loss / d s in LDS
 constexpr int FFT_LDS_MAX = 128 * 129;  // FFT line buffer (float2): 128 lines of 128 + 1 pad = 129 KB
 constexpr int KBAR = 4 * K;
 
@@ -59,7 +59,7 @@ struct SysDev {
   int psf_tx, psf_tiles;      // 64x16 PSF tiles along x / per sample
   int want_grad, batch;
   int round0, nsteps;         // serving: rounds [round0, round0 + nsteps) are this system's steps
-  int lds_fwd, lds_adj;       // ray kernels stage the grid / its adjoint in LDS (1) or not (0)
+  int lds_adj;                // the ray adjoint keeps d loss / d s in LDS (1) or adds to global memory (0)
   int sel_radix;              // quantile selection: always the radix select (1)
   // observation (owned by the plan)
   const float* image;         // [N*N]
@@ -162,7 +162,7 @@ hipError_t init_fit_state(const FitDev& F, const float* mu0, const float* rho0, 
 
 // LDS sizing shared by both launch paths
 size_t ray_lds_bytes(const SysDev& h, bool adjoint, bool lds_grid);
-bool ray_lds_grid(const SysDev& h, bool adjoint);
+bool adj_lds_grid(const SysDev& h);
 size_t psf_lds_bytes(int KP);
 int fft_lds_cap(int n_src);          // float2 slots of the FFT line buffer for this grid
 size_t prep_lds_bytes(int n_src);
@@ -174,9 +174,11 @@ struct FleetLaunch {
   const FitDev* fit;          // device [n_slots]
   const Task *t_prep, *t_psf, *t_post, *t_param, *t_sample, *t_fit;
   int n_prep, n_psf, n_post, n_param, n_sample, n_fit;
-  // ray tiles split by LDS mode: [0] grid in LDS, [1] grid through L1/L2
-  const Task *t_fwd[2], *t_adj[2];
-  int n_fwd[2], n_adj[2];
+  const Task* t_fwd;
+  int n_fwd;
+  // adjoint ray tiles split by LDS mode: [0] d loss / d s in LDS, [1] in global memory
+  const Task* t_adj[2];
+  int n_adj[2];
   size_t lds_rays_fwd, lds_rays_adj, lds_psf, lds_prep, lds_post;
 };
 // One stage (RTU_STAGE_*) of a shared launch; eps (device [S][dim] per fit,

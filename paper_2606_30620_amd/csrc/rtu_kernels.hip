@@ -679,14 +679,6 @@ __device__ __forceinline__ float cdf_grid(const RayLdsHead& H, int ax, int k, fl
   return fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
 }
 
-template <bool LDSGRID>
-__device__ __forceinline__ void load_grid(const SysDev& S, int b, float* g) {
-  if (!LDSGRID) return;
-  const int np = S.n_src + 2;
-  const float* sp = S.srcp + (size_t)b * np * np;
-  batched_copy<8>(np * np, [&](int i) { return sp[i]; }, [&](int i, float v) { g[i] = v; });
-}
-
 // bilinear weights at grid coordinates (tx, ty) = n y - 1/2 (nodes at
 // (j + 1/2)/n); returns false if all four corners lie outside the zero-padded
 // grid.
@@ -711,21 +703,20 @@ __device__ __forceinline__ void bil_corners(const float* g, int n, const Bil& B,
   s00 = g[p]; s01 = g[p + 1]; s10 = g[p + np]; s11 = g[p + np + 1];
 }
 
-template <bool LDSGRID>
+// The corner values are read from the zero-bordered grid in global memory
+// (through L1/L2): staging the grid in LDS per tile cost more than it saved.
 __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* smem) {
   RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
-  float* g = reinterpret_cast<float*>(smem + sizeof(RayLdsHead));
   const int ti = tile / S.ray_tx, tj = tile - ti * S.ray_tx;
   const int i = ti * RAY_TILE + (threadIdx.x >> 4), j = tj * RAY_TILE + (threadIdx.x & 15);
   load_knots(S, b, H);
-  load_grid<LDSGRID>(S, b, g);
   __syncthreads();
   if (i >= S.n_img || j >= S.n_img) return;
   const float* lensp = S.lens + (size_t)b * S.n_lens;
   const int nsub = n_sub_of(S, b);
   const Sie L = make_sie(lensp);
   const int n = S.n_src;
-  const float* gsrc = LDSGRID ? g : S.srcp + (size_t)b * (n + 2) * (n + 2);
+  const float* gsrc = S.srcp + (size_t)b * (n + 2) * (n + 2);
   float acc = 0.f;
   int kx = 0, ky = 0;
   float x0, y0, dxs;
@@ -753,11 +744,10 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
   S.u[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] = acc * S.inv_ss2;
 }
 
-template <bool LDSGRID>
 __global__ void __launch_bounds__(RAY_THREADS) k_rays_fwd(SysDev S) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x / S.ray_tiles;
-  rays_fwd_body<LDSGRID>(S, b, blockIdx.x - b * S.ray_tiles, smem);
+  rays_fwd_body(S, b, blockIdx.x - b * S.ray_tiles, smem);
 }
 
 template <bool LDSGRID>
@@ -1333,33 +1323,27 @@ hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
 
 // The source grid (and its adjoint) are staged in LDS when the grid is at most
 // GRID_LDS_MAX per side and the workgroup's LDS stays within 64 KB.
+// The forward keeps only the spline tables in LDS; the adjoint also keeps
+// d loss / d s (FP64) of the whole grid when it is small enough.
 size_t ray_lds_bytes(const SysDev& h, bool adjoint, bool lds_grid) {
+  if (!adjoint) return sizeof(RayLdsHead);
   const size_t np = (size_t)(h.n_src + 2);
-  size_t bytes = sizeof(RayLdsHead) + (lds_grid ? np * np * 4 : 0);
-  if (adjoint) {
-    // the adjoint keeps d loss / d s (FP64, not the source grid) in LDS
-    bytes = sizeof(RayLdsHead) + (lds_grid ? np * np * 8 : 0) + (size_t)4 * h.n_sub_max * RAY_THREADS * 4;
-    bytes = (bytes + 15) & ~(size_t)15;
-    bytes += 8 * 4 * 8 + 16;
-  }
-  return bytes;
+  size_t bytes = sizeof(RayLdsHead) + (lds_grid ? np * np * 8 : 0) + (size_t)4 * h.n_sub_max * RAY_THREADS * 4;
+  bytes = (bytes + 15) & ~(size_t)15;
+  return bytes + 8 * 4 * 8 + 16;
 }
-bool ray_lds_grid(const SysDev& h, bool adjoint) {
-  return h.n_src <= GRID_LDS_MAX && ray_lds_bytes(h, adjoint, true) <= 65536;
+bool adj_lds_grid(const SysDev& h) {
+  return h.n_src <= GRID_LDS_MAX && ray_lds_bytes(h, true, true) <= 65536;
 }
 
 hipError_t launch_rays_fwd(const SysDev& h, int batch, hipStream_t s) {
-  const bool lg = ray_lds_grid(h, false);
-  const size_t lds = ray_lds_bytes(h, false, lg);
-  if (lg)
-    hipLaunchKernelGGL(k_rays_fwd<true>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), lds, s, h);
-  else
-    hipLaunchKernelGGL(k_rays_fwd<false>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), lds, s, h);
+  hipLaunchKernelGGL(k_rays_fwd, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), ray_lds_bytes(h, false, false), s,
+                     h);
   return hipGetLastError();
 }
 
 hipError_t launch_rays_adj(const SysDev& h, int batch, hipStream_t s) {
-  const bool lg = ray_lds_grid(h, true);
+  const bool lg = adj_lds_grid(h);
   const size_t lds = ray_lds_bytes(h, true, lg);
   if (lg)
     hipLaunchKernelGGL(k_rays_adj<true>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), lds, s, h);
@@ -1404,14 +1388,13 @@ __global__ void __launch_bounds__(PREP_THREADS) kf_prep(const SysDev* __restrict
   else prep_gp(S, t.y, smem, fft_cap);
 }
 
-template <bool LDSGRID>
 __global__ void __launch_bounds__(RAY_THREADS) kf_rays_fwd(const SysDev* __restrict__ sys,
                                                            const Task* __restrict__ tasks, int round) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Task t = tasks[blockIdx.x];
   const SysDev S = sys[t.x];
   if (!sys_active(S, round)) return;
-  rays_fwd_body<LDSGRID>(S, t.y, t.z, smem);
+  rays_fwd_body(S, t.y, t.z, smem);
 }
 
 template <bool LDSGRID>
@@ -1455,12 +1438,9 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
                            (int)(L.lds_prep / sizeof(float2)) - 128);
       break;
     case RTU_STAGE_RAYS_FWD:
-      if (L.n_fwd[0])
-        hipLaunchKernelGGL(kf_rays_fwd<true>, dim3(L.n_fwd[0]), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys,
-                           L.t_fwd[0], round);
-      if (L.n_fwd[1])
-        hipLaunchKernelGGL(kf_rays_fwd<false>, dim3(L.n_fwd[1]), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys,
-                           L.t_fwd[1], round);
+      if (L.n_fwd)
+        hipLaunchKernelGGL(kf_rays_fwd, dim3(L.n_fwd), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys, L.t_fwd,
+                           round);
       break;
     case RTU_STAGE_PSF_FWD:
     case RTU_STAGE_PSF_ADJ:

@@ -495,8 +495,7 @@ int rtu_fit_create(rtu_plan p, int32_t samples, const float* mu0, const float* r
   h.lens = F.z_lens; h.n_sub = F.n_sub; h.ps = F.z_ps; h.latent = F.z_lat;
   h.loss = F.loss; h.chi2m = F.chi2m; h.g_lens = F.g_lens; h.g_ps = F.g_ps; h.g_lat = F.g_lat;
   h.model = nullptr; h.status = F.status;
-  h.lds_fwd = ray_lds_grid(h, false) ? 1 : 0;
-  h.lds_adj = ray_lds_grid(h, true) ? 1 : 0;
+  h.lds_adj = adj_lds_grid(h) ? 1 : 0;
   h.round0 = 0;
   h.nsteps = max_steps;
   const int rc = f->tables.upload({h}, {F}, f->L);
