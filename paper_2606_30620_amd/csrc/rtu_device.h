@@ -398,46 +398,62 @@ __device__ __forceinline__ void km_flush(KnotMom& c, const float* X, const float
 }
 
 // ------------------------------------------------------------------ reductions
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Reductions over the 64 lanes of a fully active wave with DPP lane moves
+// inside each row of 16 (swap within pairs, within quads, half-row mirror,
+// row mirror: every lane of a row then holds the row's result) and the four
+// row results read from lanes 0, 16, 32, 48.  No LDS traffic, and a fixed
+// order, so the result is the same on every lane and in every run.
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Sum over the 64 lanes of a fully active wave with DPP lane moves inside
-// each row of 16 (swap within pairs, within quads, half-row mirror, row
-// mirror: every lane of a row then holds the row's sum) and the four row sums
-// read from lanes 0, 16, 32, 48.  No LDS traffic; a fixed order, so the result
-// is the same on every lane and in every run.
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+  return __int_as_float(dpp_move<CTRL>(__float_as_int(v)));
 }
-__device__ __forceinline__ float wave_sum_dpp(float v) {
-  v += dpp_move<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-  v += dpp_move<0x4E>(v);    // quad_perm [2, 3, 0, 1]
-  v += dpp_move<0x141>(v);   // row_half_mirror
-  v += dpp_move<0x140>(v);   // row_mirror
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-  return (r0 + r1) + (r2 + r3);
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  return __hiloint2double(dpp_move<CTRL>(__double2hiint(v)), dpp_move<CTRL>(__double2loint(v)));
+}
+__device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+template <class T, class OP>
+__device__ __forceinline__ T wave_reduce(T v, OP op) {
+  v = op(v, dpp_move<0xB1>(v));    // quad_perm [1, 0, 3, 2]
+  v = op(v, dpp_move<0x4E>(v));    // quad_perm [2, 3, 0, 1]
+  v = op(v, dpp_move<0x141>(v));   // row_half_mirror
+  v = op(v, dpp_move<0x140>(v));   // row_mirror
+  return op(op(lane_value(v, 0), lane_value(v, 16)), op(lane_value(v, 32), lane_value(v, 48)));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  return wave_reduce(v, [](double a, double b) { return a + b; });
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  return wave_reduce(v, [](float a, float b) { return a + b; });
 }
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return v;
+  return wave_reduce(v, [](float a, float b) { return fminf(a, b); });
 }
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
+  return wave_reduce(v, [](float a, float b) { return fmaxf(a, b); });
+}
+__device__ __forceinline__ int wave_min(int v) {
+  return wave_reduce(v, [](int a, int b) { return min(a, b); });
+}
+__device__ __forceinline__ int wave_max(int v) {
+  return wave_reduce(v, [](int a, int b) { return max(a, b); });
+}
+__device__ __forceinline__ unsigned wave_min(unsigned v) {
+  return (unsigned)wave_reduce((int)v, [](int a, int b) { return (int)min((unsigned)a, (unsigned)b); });
+}
+__device__ __forceinline__ unsigned wave_max(unsigned v) {
+  return (unsigned)wave_reduce((int)v, [](int a, int b) { return (int)max((unsigned)a, (unsigned)b); });
 }
 
 // Sum of n doubles per thread across the block; result valid in every thread.

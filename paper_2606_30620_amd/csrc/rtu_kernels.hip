@@ -195,8 +195,7 @@ __device__ bool select_by_counting(SelLds& L, const float* zb, int M, float vmin
       const int u = __shfl_up(incl, o, 64);
       if (t >= o) incl += u;
     }
-    int mx = cnt;
-    for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    const int mx = wave_max(cnt);
     if (head) {
       const int sg = __popcll(hm & ((2ull << t) - 1ull)) - 1;   // heads at lanes <= t, minus one
       L.seg_bin[sg] = bb;
@@ -439,10 +438,8 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
     block_sum<4>(v4, L.red);
     sx = v4[0]; sy = v4[1]; sxx = v4[2]; syy = v4[3];
     float a = wave_min(vmin), c = wave_max(vmax);
-    for (int o = 32; o >= 1; o >>= 1) {
-      umin = min(umin, (unsigned)__shfl_xor((int)umin, o, 64));
-      umax = max(umax, (unsigned)__shfl_xor((int)umax, o, 64));
-    }
+    umin = wave_min(umin);
+    umax = wave_max(umax);
     if (lane == 0) { L.fred[wv] = a; L.fred[16 + wv] = c; L.ured[wv] = umin; L.ured[16 + wv] = umax; }
     __syncthreads();
     vmin = INFINITY; vmax = -INFINITY;
@@ -861,12 +858,10 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   // the touched window: reduced within each wave first, so that the LDS
   // atomics see one lane per wave (same-address atomics serialise)
   if (LDSGRID) {
-    for (int o = 32; o >= 1; o >>= 1) {
-      bi0 = min(bi0, __shfl_xor(bi0, o, 64));
-      bj0 = min(bj0, __shfl_xor(bj0, o, 64));
-      bi1 = max(bi1, __shfl_xor(bi1, o, 64));
-      bj1 = max(bj1, __shfl_xor(bj1, o, 64));
-    }
+    bi0 = wave_min(bi0);
+    bj0 = wave_min(bj0);
+    bi1 = wave_max(bi1);
+    bj1 = wave_max(bj1);
     if ((threadIdx.x & 63) == 0) {
       atomicMin(&bbox[0], bi0); atomicMin(&bbox[1], bj0);
       atomicMax(&bbox[2], bi1); atomicMax(&bbox[3], bj1);
@@ -882,11 +877,11 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
     const float v[8] = {acc.P, acc.q, acc.f, acc.phi, acc.x0, acc.y0, acc.g1, acc.g2};
     float r[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) r[k] = wave_sum_dpp(v[k]);
+    for (int k = 0; k < 8; ++k) r[k] = wave_sum(v[k]);
     if (lane == 0)
       for (int k = 0; k < 8; ++k) lp[k] = (double)r[k];
     for (int q = 0; q < 4 * S.n_sub_max; ++q) {
-      const float sq = wave_sum_dpp(subacc[q * RAY_THREADS + threadIdx.x]);
+      const float sq = wave_sum(subacc[q * RAY_THREADS + threadIdx.x]);
       if (lane == 0) lp[8 + q] = (double)sq;
     }
   }
@@ -1321,7 +1316,7 @@ hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
   return hipGetLastError();
 }
 
-// The source grid (and its adjoint) are staged in LDS when the grid is at most
+// The ray adjoint keeps d loss / d s in LDS when the grid is at most
 // GRID_LDS_MAX per side and the workgroup's LDS stays within 64 KB.
 // The forward keeps only the spline tables in LDS; the adjoint also keeps
 // d loss / d s (FP64) of the whole grid when it is small enough.
