@@ -251,6 +251,7 @@ int admit_one(rtu_fleet f, hipStream_t s) {
   h.loss = F.loss; h.chi2m = F.chi2m; h.g_lens = F.g_lens; h.g_ps = F.g_ps; h.g_lat = F.g_lat;
   h.model = nullptr; h.status = F.status;
   h.lds_adj = adj_lds_grid(h) ? 1 : 0;
+  h.psf_rank1 = e.obs.rank1 ? 1 : 0;
   e.round0 = f->round;
   h.round0 = f->round;
   h.nsteps = e.steps;

@@ -67,6 +67,9 @@ struct SysDev {
   const float* psf_flip;      // [KP][psf_ws(KP)] PSF rotated by 180 degrees (forward correlation),
                               // each row zero-padded: W[a][c] at [a][c + 15]
   const float* psf;           // [KP][psf_ws(KP)] PSF as given (adjoint correlation), padded the same way
+  const float* psf_sep;       // [4][KP] for a rank-one PSF W[a][c] = u[a] v[c]: u, v of the forward
+                              // (flipped) correlation, then u, v of the adjoint one
+  int psf_rank1;              // the PSF is rank one (to FP32 rounding): the separable PSF kernel
   const uint8_t* mask;        // [N*N]
   const int* mask_idx;        // [M] row-major pixel index of each masked pixel
   const int* rank_j;          // [K] floor((M-1) u_k)
@@ -146,6 +149,8 @@ struct ObsHost {
   int rank_j[K];
   double rank_t[K];
   std::vector<float> inv_var, wfwd, wadj;   // 1/sigma^2; padded PSF weight rows (forward, adjoint)
+  std::vector<float> wsep;                  // rank-one factors [4][KP] (see SysDev::psf_sep)
+  bool rank1 = false;
 };
 int ensure_constants(int device);
 bool valid_geometry(const rtu_geometry* g);

@@ -959,15 +959,14 @@ __device__ __forceinline__ void psf_epilogue(const SysDev& S, int b, int tile, i
   }
 }
 
-// The input tile with its halo (zero outside the image), then the padded
-// weight rows right after it, in one pass of batched loads.
+// The input tile with its halo (zero outside the image), then nw weights
+// from W right after it, in one pass of batched loads.
 __device__ __forceinline__ void psf_load_tile(const SysDev& S, int b, int adjoint, int KP, int ty0, int tx0,
-                                              float* tilein) {
+                                              float* tilein, const float* W, int nw) {
   const int N = S.n_img, h = KP / 2;
   const int HW = PSF_TW + KP - 1, LS = psf_row_stride(KP), HH = PSF_TH + KP - 1;
-  const int nt = HH * LS, nw = KP * psf_ws(KP);
+  const int nt = HH * LS;
   const float* in = (adjoint ? S.r : S.u) + (size_t)b * N * N;
-  const float* W = adjoint ? S.psf : S.psf_flip;
   batched_copy<8>(nt + nw,
                   [&](int q) {
                     if (q >= nt) return W[q - nt];
@@ -994,7 +993,7 @@ __device__ void psf_body(const SysDev& S, int b, int tile, int adjoint, float* t
   const int NK = psf_nk(KP), WS = psf_ws(KP), LS = psf_row_stride(KP);
   const int ty0 = (tile / S.psf_tx) * PSF_TH, tx0 = (tile % S.psf_tx) * PSF_TW;
   const float* wp = tilein + (PSF_TH + KP - 1) * LS;   // the padded weight rows
-  psf_load_tile(S, b, adjoint, KP, ty0, tx0, tilein);
+  psf_load_tile(S, b, adjoint, KP, ty0, tx0, tilein, adjoint ? S.psf : S.psf_flip, KP * WS);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lq = lane >> 4;
   f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
@@ -1019,8 +1018,63 @@ __device__ void psf_body(const SysDev& S, int b, int tile, int adjoint, float* t
   psf_epilogue(S, b, tile, adjoint, ty0, tx0, lr, wave * 16 + lq * 4, out, red);
 }
 
+// A rank-one PSF, W[a][c] = u[a] v[c] (a Gaussian is one): a pass along the
+// rows of the input tile with v into LDS (the tile's rows and its halo rows),
+// then a pass along the columns with u; 2 K_psf instead of K_psf^2
+// multiply-adds per pixel, FP32.  Each thread sums 4 consecutive columns.
+template <int KPT>
+__device__ void psf_sep_body(const SysDev& S, int b, int tile, int adjoint, float* tilein, double* red) {
+  const int KP = KPT ? KPT : S.psf_k;
+  const int LS = psf_row_stride(KP), HH = PSF_TH + KP - 1;
+  const int ty0 = (tile / S.psf_tx) * PSF_TH, tx0 = (tile % S.psf_tx) * PSF_TW;
+  psf_load_tile(S, b, adjoint, KP, ty0, tx0, tilein, S.psf_sep + (adjoint ? 2 * KP : 0), 2 * KP);
+  const float* uf = tilein + HH * LS;
+  const float* vf = uf + KP;
+  float* tr = tilein + HH * LS + ((2 * KP + 3) & ~3);    // [HH][PSF_TW] row-pass sums
+  for (int it = threadIdx.x; it < HH * (PSF_TW / 4); it += blockDim.x) {
+    const int rr = it / (PSF_TW / 4), x = (it - rr * (PSF_TW / 4)) * 4;
+    if (tx0 + x >= S.n_img) continue;
+    const float* row = tilein + rr * LS + x;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+    for (int c = 0; c < (KPT ? KPT : 1); ++c) {
+      if (!KPT) break;
+      const float w = vf[c];
+      a0 = fmaf(w, row[c], a0); a1 = fmaf(w, row[c + 1], a1); a2 = fmaf(w, row[c + 2], a2); a3 = fmaf(w, row[c + 3], a3);
+    }
+    if (!KPT)
+      for (int c = 0; c < KP; ++c) {
+        const float w = vf[c];
+        a0 = fmaf(w, row[c], a0); a1 = fmaf(w, row[c + 1], a1); a2 = fmaf(w, row[c + 2], a2); a3 = fmaf(w, row[c + 3], a3);
+      }
+    *reinterpret_cast<float4*>(tr + rr * PSF_TW + x) = make_float4(a0, a1, a2, a3);
+  }
+  __syncthreads();
+  const int ly = threadIdx.x >> 4, lx = (threadIdx.x & 15) * 4;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  if (tx0 + lx < S.n_img) {
+    const float* col = tr + ly * PSF_TW + lx;
+    for (int a = 0; a < KP; ++a) {
+      const float w = uf[a];
+      const float4 t = *reinterpret_cast<const float4*>(col + a * PSF_TW);
+      acc[0] = fmaf(w, t.x, acc[0]); acc[1] = fmaf(w, t.y, acc[1]);
+      acc[2] = fmaf(w, t.z, acc[2]); acc[3] = fmaf(w, t.w, acc[3]);
+    }
+  }
+  psf_epilogue(S, b, tile, adjoint, ty0, tx0, ly, lx, acc, red);
+}
+
 __device__ __forceinline__ void psf_dispatch(const SysDev& S, int b, int tile, int adjoint, float* tilein,
                                              double* red) {
+  if (S.psf_rank1) {
+    switch (S.psf_k) {
+      case 15: psf_sep_body<15>(S, b, tile, adjoint, tilein, red); break;
+      case 21: psf_sep_body<21>(S, b, tile, adjoint, tilein, red); break;
+      case 31: psf_sep_body<31>(S, b, tile, adjoint, tilein, red); break;
+      default: psf_sep_body<0>(S, b, tile, adjoint, tilein, red);
+    }
+    return;
+  }
   switch (S.psf_k) {
     case 15: psf_body<15>(S, b, tile, adjoint, tilein, red); break;
     case 21: psf_body<21>(S, b, tile, adjoint, tilein, red); break;
@@ -1347,9 +1401,13 @@ hipError_t launch_rays_adj(const SysDev& h, int batch, hipStream_t s) {
   return hipGetLastError();
 }
 
-// input tile, then the zero-padded weight rows
+// input tile, then the zero-padded weight rows (matrix-core kernel) or the
+// rank-one factors and the row-pass sums (separable kernel)
 size_t psf_lds_bytes(int KP) {
-  return ((size_t)(PSF_TH + KP - 1) * psf_row_stride(KP) + (size_t)KP * psf_ws(KP)) * 4;
+  const size_t tile = (size_t)(PSF_TH + KP - 1) * psf_row_stride(KP);
+  const size_t mfma = tile + (size_t)KP * psf_ws(KP);
+  const size_t sep = tile + (size_t)((2 * KP + 3) & ~3) + (size_t)(PSF_TH + KP - 1) * PSF_TW;
+  return (mfma > sep ? mfma : sep) * 4;
 }
 
 hipError_t launch_psf(const SysDev& h, int batch, bool adjoint, hipStream_t s) {

@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <vector>
 
@@ -144,6 +146,7 @@ size_t carve_observation(SysDev& h, int B, int M, char* base) {
   h.inv_var = c.take<float>(N2);
   h.psf_flip = c.take<float>(kw);
   h.psf = c.take<float>(kw);
+  h.psf_sep = c.take<float>((size_t)4 * h.psf_k);
   h.mask = c.take<uint8_t>(N2);
   h.mask_idx = c.take<int>(M > 0 ? M : 1);
   h.rank_j = c.take<int>(K);
@@ -181,6 +184,37 @@ void prepare_observation(const rtu_geometry* g, const float* noise_sigma, const 
       o.wfwd[(size_t)a * WS + b + 15] = psf[(size_t)(KP - 1 - a) * KP + (KP - 1 - b)];
       o.wadj[(size_t)a * WS + b + 15] = psf[(size_t)a * KP + b];
     }
+  // Rank one (a Gaussian PSF is): W[a][c] = u[a] v[c] with u the column and v
+  // the row through the largest weight, accepted when every weight is
+  // reproduced to a few FP32 ulps of the largest one.
+  o.wsep.assign((size_t)4 * KP, 0.f);
+  o.rank1 = false;
+  int ar = 0, ac = 0;
+  double wmax = 0.0;
+  for (int a = 0; a < KP; ++a)
+    for (int b = 0; b < KP; ++b)
+      if (std::fabs((double)psf[(size_t)a * KP + b]) > wmax) {
+        wmax = std::fabs((double)psf[(size_t)a * KP + b]);
+        ar = a;
+        ac = b;
+      }
+  if (wmax > 0.0) {
+    std::vector<float> u(KP), v(KP);
+    const double piv = psf[(size_t)ar * KP + ac];
+    for (int a = 0; a < KP; ++a) u[a] = psf[(size_t)a * KP + ac];
+    for (int b = 0; b < KP; ++b) v[b] = (float)((double)psf[(size_t)ar * KP + b] / piv);
+    double err = 0.0;
+    for (int a = 0; a < KP; ++a)
+      for (int b = 0; b < KP; ++b)
+        err = std::max(err, std::fabs((double)psf[(size_t)a * KP + b] - (double)u[a] * (double)v[b]));
+    o.rank1 = err <= 4e-7 * wmax;
+    for (int a = 0; a < KP; ++a) {
+      o.wsep[a] = u[KP - 1 - a];                 // forward: the flipped PSF
+      o.wsep[KP + a] = v[KP - 1 - a];
+      o.wsep[2 * KP + a] = u[a];                 // adjoint: the PSF as given
+      o.wsep[3 * KP + a] = v[a];
+    }
+  }
 }
 
 hipError_t upload_observation(const SysDev& h, const float* image, const float* psf, const uint8_t* arc_mask,
@@ -194,6 +228,7 @@ hipError_t upload_observation(const SysDev& h, const float* image, const float* 
   cp(h.inv_var, o.inv_var.data(), N2 * 4);
   cp(h.psf_flip, o.wfwd.data(), kw * 4);
   cp(h.psf, o.wadj.data(), kw * 4);
+  cp(h.psf_sep, o.wsep.data(), o.wsep.size() * 4);
   cp(h.mask, arc_mask, N2);
   cp(h.mask_idx, o.idx.data(), o.idx.size() * 4);
   cp(h.rank_j, o.rank_j, sizeof(o.rank_j));
@@ -351,6 +386,7 @@ int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma
   if (upload_observation(h, image, psf, arc_mask, o, nullptr) != hipSuccess) return RTU_EHIP;
   if (hipDeviceSynchronize() != hipSuccess) return RTU_EHIP;
   h.M = M;
+  h.psf_rank1 = o.rank1 ? 1 : 0;
   p->h = h;
   p->M = M;
   p->inv_var = o.inv_var;

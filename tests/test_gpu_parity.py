@@ -70,6 +70,26 @@ def test_ragged_generic_psf_parity():
     _check(p, range(3))
 
 
+def _rank_two_psf(psf):
+    """The problem's (Gaussian, rank-one) PSF plus a shifted, elongated lobe:
+    rank two, so the matrix-core PSF kernel runs instead of the separable one."""
+    K = psf.shape[0]
+    a = np.arange(K) - K // 2
+    lobe = np.exp(-0.5 * ((a[:, None] - 2.0) ** 2 / 2.0 + (a[None, :] + 1.0) ** 2 / 0.7))
+    w = psf.astype(np.float64) + 0.2 * psf.max() * lobe / lobe.max()
+    return (w / w.sum()).astype(np.float32)
+
+
+@pytest.mark.parametrize("psf_size", [21, 9])
+def test_rank_two_psf_parity(psf_size):
+    say(f"[gpu] PSF of rank two ({psf_size}x{psf_size}, matrix-core PSF kernel): 96x96 ss=2 n_src=32, batch 2")
+    g = synth.Geometry(96, 0.05, 2, 32, psf_size, 1.4)
+    p = synth.make_problem("X", batch=2, seed=13, geom=g)
+    p.psf = _rank_two_psf(p.psf)
+    assert np.linalg.matrix_rank(p.psf.astype(np.float64), tol=1e-4 * np.abs(p.psf).max()) == 2
+    _check(p, range(2))
+
+
 def test_smallest_source_grid_parity():
     say("[gpu] n_src=8 (one 8-point FFT factor per line): 48x48 ss=2 psf=15, batch 2")
     g = synth.Geometry(48, 0.08, 2, 8, 15, 1.2)
