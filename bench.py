@@ -58,7 +58,7 @@ PEAK_HBM_GBS = 8000.0
 
 KERNEL_OF_STAGE = {"rays_adj": "kf_rays_adj<true>", "rays_fwd": "kf_rays_fwd", "psf_fwd": "kf_psf",
                    "psf_adj": "kf_psf", "prep": "kf_prep", "post": "kf_post", "sample": "kf_sample",
-                   "adam": "kf_elbo+kf_adam"}
+                   "adam": "kf_adam"}
 
 
 def kernel_source_hash() -> str:

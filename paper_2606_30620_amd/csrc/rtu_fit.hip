@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "rtu_device.h"
 #include "rtu_internal.h"
 
 namespace rtu {
@@ -55,40 +56,6 @@ __device__ __forceinline__ float grad_at(const FitDev& F, int s, int i) {
   return F.g_lat[(size_t)s * F.n_src2 + (i - F.n_lens - 4)];
 }
 
-// ELBO of this step (before the update), and the OR of the samples' status
-// words: one workgroup of 1024 threads
-__device__ void elbo_body(const FitDev& F, int step, double* red) {
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < F.dim; i += blockDim.x) acc += (double)F.rho[i];
-  double ls = 0.0;
-  for (int s = threadIdx.x; s < F.S; s += blockDim.x) ls += F.loss[s];
-  for (int o = 32; o >= 1; o >>= 1) {
-    acc += __shfl_xor(acc, o, 64);
-    ls += __shfl_xor(ls, o, 64);
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) { red[wv] = acc; red[16 + wv] = ls; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0.0, l = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += red[w]; l += red[16 + w]; }
-    F.trace[step] = -l / (double)F.S + F.elbo_const + a;
-  }
-  // OR of the samples' status words
-  uint32_t st = 0;
-  for (int s = threadIdx.x; s < F.S; s += blockDim.x) st |= F.status[s];
-  for (int o = 32; o >= 1; o >>= 1) st |= (uint32_t)__shfl_xor((int)st, o, 64);
-  __syncthreads();
-  uint32_t* sred = reinterpret_cast<uint32_t*>(red);
-  if (lane == 0) sred[wv] = st;
-  __syncthreads();
-  if (threadIdx.x == 0 && F.status_acc) {
-    uint32_t all = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) all |= sred[w];
-    F.status_acc[0] |= all;
-  }
-}
-
 // Adam on (mu, rho) with the gradient of -ELBO:
 //   d/dmu_i  = mean_s g_si,   d/drho_i = mean_s g_si exp(rho_i) eps_si - 1
 __device__ __forceinline__ void adam_body(const FitDev& F, int t, int i) {
@@ -133,29 +100,58 @@ __global__ void kf_sample(const FitDev* __restrict__ fits, const Task* __restric
   sample_body(F, eps, step, t.z, t.y * blockDim.x + threadIdx.x);
 }
 
-__global__ void __launch_bounds__(1024) kf_elbo(const FitDev* __restrict__ fits, const Task* __restrict__ tasks,
-                                               int round) {
-  __shared__ double red[32];
-  const FitDev& F = fits[tasks[blockIdx.x].x];
-  int step;
-  if (!fit_step(F, round, step)) return;
-  elbo_body(F, step, red);
-}
-
-__global__ void kf_adam(const FitDev* __restrict__ fits, const Task* __restrict__ tasks, int round) {
+// Adam, and the ELBO of this step from the values before the update: each
+// block sums its rho into rho_part; the last block of the fit to finish adds
+// the parts in block order, the sample losses and the status words.
+constexpr int ADAM_THREADS = 256;
+__global__ void __launch_bounds__(ADAM_THREADS) kf_adam(const FitDev* __restrict__ fits,
+                                                        const Task* __restrict__ tasks, int round) {
+  __shared__ double red[ADAM_THREADS / 64];
+  __shared__ int last;
   const Task t = tasks[blockIdx.x];      // x fit, y parameter block
   const FitDev& F = fits[t.x];
   int step;
   if (!fit_step(F, round, step)) return;
-  adam_body(F, step + 1, t.y * blockDim.x + threadIdx.x);
+  const int i = t.y * ADAM_THREADS + threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double r = wave_sum(i < F.dim ? (double)F.rho[i] : 0.0);
+  if (lane == 0) red[wv] = r;
+  __syncthreads();
+  adam_body(F, step + 1, i);
+  if (threadIdx.x == 0) {
+    double part = 0.0;
+    for (int w = 0; w < ADAM_THREADS / 64; ++w) part += red[w];
+    F.rho_part[t.y] = part;
+    __threadfence();
+    const uint32_t nblk = (uint32_t)((F.dim + ADAM_THREADS - 1) / ADAM_THREADS);
+    last = atomicAdd(F.adam_done, 1u) == nblk - 1u ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last || wv != 0) return;
+  __threadfence();
+  const int nblk = (F.dim + ADAM_THREADS - 1) / ADAM_THREADS;
+  double a = 0.0, ls = 0.0;
+  uint32_t st = 0;
+  for (int j0 = 0; j0 < nblk; j0 += 64)
+    a += wave_sum(j0 + lane < nblk ? *reinterpret_cast<volatile const double*>(&F.rho_part[j0 + lane]) : 0.0);
+  for (int s0 = 0; s0 < F.S; s0 += 64) {
+    ls += wave_sum(s0 + lane < F.S ? F.loss[s0 + lane] : 0.0);
+    const int v = s0 + lane < F.S ? (int)F.status[s0 + lane] : 0;
+    st |= (uint32_t)wave_reduce(v, [](int x, int y) { return x | y; });
+  }
+  if (lane == 0) {
+    F.trace[step] = -ls / (double)F.S + F.elbo_const + a;
+    if (F.status_acc) F.status_acc[0] |= st;
+    *F.adam_done = 0u;
+  }
 }
 
 hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, const float* eps, hipStream_t s) {
   if (stage == RTU_STAGE_SAMPLE) {
     if (L.n_sample) hipLaunchKernelGGL(kf_sample, dim3(L.n_sample), dim3(256), 0, s, L.fit, L.t_sample, round, eps);
   } else if (stage == RTU_STAGE_ADAM) {
-    if (L.n_fit) hipLaunchKernelGGL(kf_elbo, dim3(L.n_fit), dim3(1024), 0, s, L.fit, L.t_fit, round);
-    if (L.n_param) hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(256), 0, s, L.fit, L.t_param, round);
+    if (L.n_param)
+      hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(ADAM_THREADS), 0, s, L.fit, L.t_param, round);
   }
   return hipGetLastError();
 }

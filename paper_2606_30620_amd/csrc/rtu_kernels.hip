@@ -1095,6 +1095,7 @@ struct PostLds {
   double red[16 * 16];
   double part[PREP_THREADS];
   double xbar[2][K];      // d loss / d X (beta units), after the slope chain
+  double wk[2][K];        // -S_k^2 d loss / d S_k
   double lsum[RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB + 1];   // raw sums
   uint32_t stat;
 };
@@ -1114,7 +1115,7 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
       v[1] += o[1];
     }
     const float* w = S.latent + (size_t)b * n2;
-    for (int q = tid; q < n2; q += blockDim.x) v[2] += (double)w[q] * w[q];
+    batched_copy<8>(n2, [&](int q) { return w[q]; }, [&](int, float x) { v[2] += (double)x * x; });
     block_sum<3>(v, P.red);
     if (tid == 0) {
       const double loss = 0.5 * v[0] + 0.5 * v[2];
@@ -1132,14 +1133,18 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
     reduce_columns(S.kbar + (size_t)b * S.ray_tiles * 4 * K, S.ray_tiles, 4 * K, 4 * K,
                    P.part, [&](int c, double v) { P.red[c] = v; });
     __syncthreads();
+    // the factors -S_k^2 dS_k, one thread per (axis, k); then the sums over k
+    if (tid < 2 * K) {
+      const int ax = tid / K, k = tid - ax * K;
+      const double d = S.dp[((size_t)b * 2 + ax) * K + k];
+      P.wk[ax][k] = d > 0.0 ? -P.red[ax * 2 * K + K + k] / (d * d) : 0.0;
+    }
+    __syncthreads();
     if (tid < 2 * K) {
       const int ax = tid / K, l = tid - ax * K;
-      const float* dp = S.dp + ((size_t)b * 2 + ax) * K;
       double xb = P.red[ax * 2 * K + l];
-      for (int k = 0; k < K; ++k) {
-        const double d = dp[k];
-        if (d > 0.0) xb += -P.red[ax * 2 * K + K + k] / (d * d) * c_D[k * K + l];
-      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) xb += P.wk[ax][k] * c_D[k * K + l];
       P.xbar[ax][l] = xb;
     }
     __syncthreads();
