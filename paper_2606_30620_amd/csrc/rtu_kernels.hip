@@ -568,7 +568,7 @@ __device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* s
     float2* tw = lds + cap;
     for (int k = threadIdx.x; k < 128; k += blockDim.x) tw[k] = c_tw[k];
     const int ls = n + 1;
-    batched_copy<8>(n2, [&](int q) { return w[q]; },
+    batched_copy<16>(n2, [&](int q) { return w[q]; },
                     [&](int q, float v) { lds[(q >> logn) * ls + (q & (n - 1))] = make_float2(v, 0.f); });
     __syncthreads();
     fft_grid_dir(lds, tw, n, logn, false, -1.f, true);
@@ -1245,7 +1245,7 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
       float2* tw = lds + cap;
       for (int k = tid; k < 128; k += blockDim.x) tw[k] = c_tw[k];
       const int ls = n + 1;
-      batched_copy<4>(n2, [&](int q) { return make_float4((float)sb[q], fo[q], so[q], 0.f); },
+      batched_copy<8>(n2, [&](int q) { return make_float4((float)sb[q], fo[q], so[q], 0.f); },
                       [&](int q, float4 v) {
                         lds[(q >> logn) * ls + (q & (n - 1))] = make_float2(fbar_of(v.x, v.y, v.z), 0.f);
                       });
