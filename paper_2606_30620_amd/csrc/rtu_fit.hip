@@ -91,49 +91,47 @@ __device__ __forceinline__ bool fit_step(const FitDev& F, int round, int& step) 
   return step >= 0 && step < F.nsteps;
 }
 
-__global__ void kf_sample(const FitDev* __restrict__ fits, const Task* __restrict__ tasks, int round,
-                          const float* eps) {
+// The blocks of sample 0 also sum the guide's rho over their 256 parameters
+// (the ELBO's entropy term, before this step's update) into rho_part.
+constexpr int FIT_THREADS = 256;
+__global__ void __launch_bounds__(FIT_THREADS) kf_sample(const FitDev* __restrict__ fits,
+                                                         const Task* __restrict__ tasks, int round,
+                                                         const float* eps) {
+  __shared__ double red[FIT_THREADS / 64];
   const Task t = tasks[blockIdx.x];      // x fit, y parameter block, z sample
   const FitDev& F = fits[t.x];
   int step;
   if (!fit_step(F, round, step)) return;
-  sample_body(F, eps, step, t.z, t.y * blockDim.x + threadIdx.x);
+  const int i = t.y * FIT_THREADS + threadIdx.x;
+  sample_body(F, eps, step, t.z, i);
+  if (t.z == 0) {
+    const double r = wave_sum(i < F.dim ? (double)F.rho[i] : 0.0);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double part = 0.0;
+      for (int w = 0; w < FIT_THREADS / 64; ++w) part += red[w];
+      F.rho_part[t.y] = part;
+    }
+  }
 }
 
-// Adam, and the ELBO of this step from the values before the update: each
-// block sums its rho into rho_part; the last block of the fit to finish adds
-// the parts in block order, the sample losses and the status words.
-constexpr int ADAM_THREADS = 256;
-__global__ void __launch_bounds__(ADAM_THREADS) kf_adam(const FitDev* __restrict__ fits,
-                                                        const Task* __restrict__ tasks, int round) {
-  __shared__ double red[ADAM_THREADS / 64];
-  __shared__ int last;
+// Adam; block 0 of each fit also writes the ELBO of this step from the
+// sampling kernel's rho sums (taken before the update), the losses and the
+// status words, each summed in a fixed order.
+__global__ void __launch_bounds__(FIT_THREADS) kf_adam(const FitDev* __restrict__ fits,
+                                                       const Task* __restrict__ tasks, int round) {
   const Task t = tasks[blockIdx.x];      // x fit, y parameter block
   const FitDev& F = fits[t.x];
   int step;
   if (!fit_step(F, round, step)) return;
-  const int i = t.y * ADAM_THREADS + threadIdx.x;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double r = wave_sum(i < F.dim ? (double)F.rho[i] : 0.0);
-  if (lane == 0) red[wv] = r;
-  __syncthreads();
-  adam_body(F, step + 1, i);
-  if (threadIdx.x == 0) {
-    double part = 0.0;
-    for (int w = 0; w < ADAM_THREADS / 64; ++w) part += red[w];
-    F.rho_part[t.y] = part;
-    __threadfence();
-    const uint32_t nblk = (uint32_t)((F.dim + ADAM_THREADS - 1) / ADAM_THREADS);
-    last = atomicAdd(F.adam_done, 1u) == nblk - 1u ? 1 : 0;
-  }
-  __syncthreads();
-  if (!last || wv != 0) return;
-  __threadfence();
-  const int nblk = (F.dim + ADAM_THREADS - 1) / ADAM_THREADS;
+  adam_body(F, step + 1, t.y * FIT_THREADS + threadIdx.x);
+  if (t.y != 0 || threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  const int nblk = (F.dim + FIT_THREADS - 1) / FIT_THREADS;
   double a = 0.0, ls = 0.0;
   uint32_t st = 0;
-  for (int j0 = 0; j0 < nblk; j0 += 64)
-    a += wave_sum(j0 + lane < nblk ? *reinterpret_cast<volatile const double*>(&F.rho_part[j0 + lane]) : 0.0);
+  for (int j0 = 0; j0 < nblk; j0 += 64) a += wave_sum(j0 + lane < nblk ? F.rho_part[j0 + lane] : 0.0);
   for (int s0 = 0; s0 < F.S; s0 += 64) {
     ls += wave_sum(s0 + lane < F.S ? F.loss[s0 + lane] : 0.0);
     const int v = s0 + lane < F.S ? (int)F.status[s0 + lane] : 0;
@@ -142,16 +140,16 @@ __global__ void __launch_bounds__(ADAM_THREADS) kf_adam(const FitDev* __restrict
   if (lane == 0) {
     F.trace[step] = -ls / (double)F.S + F.elbo_const + a;
     if (F.status_acc) F.status_acc[0] |= st;
-    *F.adam_done = 0u;
   }
 }
 
 hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, const float* eps, hipStream_t s) {
   if (stage == RTU_STAGE_SAMPLE) {
-    if (L.n_sample) hipLaunchKernelGGL(kf_sample, dim3(L.n_sample), dim3(256), 0, s, L.fit, L.t_sample, round, eps);
+    if (L.n_sample) hipLaunchKernelGGL(kf_sample, dim3(L.n_sample), dim3(FIT_THREADS), 0, s, L.fit, L.t_sample,
+                                      round, eps);
   } else if (stage == RTU_STAGE_ADAM) {
     if (L.n_param)
-      hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(ADAM_THREADS), 0, s, L.fit, L.t_param, round);
+      hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(FIT_THREADS), 0, s, L.fit, L.t_param, round);
   }
   return hipGetLastError();
 }

@@ -128,8 +128,7 @@ struct FitDev {
   int* n_sub;                 // [S]
   double* trace;              // [max_steps] ELBO per step
   uint32_t* status_acc;       // [1] OR of every sample status over all steps
-  double* rho_part;           // [ceil(dim / 256)] per Adam block: the sum of rho before the update
-  uint32_t* adam_done;        // [1] Adam blocks finished this step (the last one writes the ELBO)
+  double* rho_part;           // [ceil(dim / 256)] per parameter block: the sum of rho at sampling time
 };
 
 // One work item of a shared (serving) launch: x = system/fit slot,

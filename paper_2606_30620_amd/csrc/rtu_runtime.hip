@@ -252,7 +252,6 @@ size_t carve_fit(FitDev& F, int S, int max_steps, char* base) {
   F.trace = cv.take<double>(max_steps);
   F.status_acc = cv.take<uint32_t>(1);
   F.rho_part = cv.take<double>(((size_t)F.dim + 255) / 256);
-  F.adam_done = cv.take<uint32_t>(1);
   return cv.off + 256;
 }
 
@@ -271,7 +270,6 @@ hipError_t init_fit_state(const FitDev& F, const float* mu0, const float* rho0, 
   float* z[4] = {F.m_mu, F.v_mu, F.m_rho, F.v_rho};
   for (int k = 0; k < 4 && e == hipSuccess; ++k) e = hipMemsetAsync(z[k], 0, (size_t)F.dim * 4, s);
   if (e == hipSuccess && F.status_acc) e = hipMemsetAsync(F.status_acc, 0, 4, s);
-  if (e == hipSuccess) e = hipMemsetAsync(F.adam_done, 0, 4, s);
   if (e == hipSuccess) e = hipMemcpyAsync(F.n_sub, ns.data(), (size_t)F.S * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host vector above must outlive the copy
   return e;
