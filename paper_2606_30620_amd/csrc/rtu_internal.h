@@ -107,8 +107,7 @@ struct SysDev {
   double* kbar;               // [B][ray_tiles][4K] per-tile dX, dS partials
   double* lpart;              // [B][ray_tiles][4 waves][n_lens + 1] per-wave raw lens-gradient partials
   double* c2part;             // [B][psf_tiles][2] per-tile chi^2 partials (all, mask)
-  uint32_t* st;               // [B][ST_WORDS] status words: selection x, y; parameter domain;
-                              // post roles 0, 1; post completion count
+  uint32_t* st;               // [B][ST_WORDS] status words: selection x, y; parameter domain
 };
 
 // One stochastic variational fit: guide, Adam state and per-sample buffers.

@@ -15,8 +15,8 @@
 //               d loss/d lens parameters.
 //   k_post      per sample, two workgroup roles: (0) the loss, the knot
 //               adjoint back to the selected masked rays and the lens
-//               gradient; (1) the GP adjoint through the FFT.  The role
-//               that finishes last writes the sample's status.
+//               gradient; (1) the GP adjoint through the FFT.  Each role
+//               ORs its status bits into the sample's status word.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -550,7 +550,7 @@ __device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* s
       if (!(L[RTU_N_LENS_BASE + RTU_N_PER_SUB * j + 1] > 0.f)) st |= RTU_ST_DOMAIN;
     if (!(ps[0] > 0.f) || !(ps[1] > 0.f) || !(ps[2] > 0.f)) st |= RTU_ST_DOMAIN;
     S.st[b * ST_WORDS + 2] = st;
-    S.st[b * ST_WORDS + 5] = 0;   // completion count of the two post roles
+    S.status[b] = 0u;             // the post roles OR their words into it
   }
   const Matern mt = make_matern(ps);
   const float alpha = ps[3];
@@ -1290,20 +1290,11 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
     }
   }
   __syncthreads();
-  // status: the OR of the stages' words, written by the role that finishes last
+  // status: each role ORs its word (role 0 also the selection and domain
+  // words) into the sample's status, which prep cleared
   if (tid == 0) {
-    uint32_t* st = S.st + (size_t)b * ST_WORDS;
-    if (!S.want_grad) {
-      S.status[b] = P.stat | st[0] | st[1] | st[2];
-    } else {
-      st[3 + role] = P.stat;
-      __threadfence();
-      if (atomicAdd(&st[5], 1u) == 1u) {
-        __threadfence();
-        S.status[b] = st[0] | st[1] | st[2] | __atomic_load_n(&st[3], __ATOMIC_RELAXED) |
-                      __atomic_load_n(&st[4], __ATOMIC_RELAXED);
-      }
-    }
+    const uint32_t* st = S.st + (size_t)b * ST_WORDS;
+    atomicOr(&S.status[b], role == 0 ? (P.stat | st[0] | st[1] | st[2]) : P.stat);
   }
 }
 
