@@ -27,6 +27,7 @@ S0 = 0.01            # softplus scale s_0 (Sec. 2.1, eq. 3)
 K_NODES = 22         # Chebyshev nodes = degree 21 + 1 (App. C, step iii; Fig. C1)
 N_LENS_BASE = 7
 N_PER_SUB = 4
+N_PER_GAUSS = 6      # lens-light Gaussian: A, sigma, e1, e2, x_c, y_c
 
 ST_NONFINITE = 1
 ST_NONMONOTONE = 2
@@ -154,6 +155,30 @@ def ray_shoot(x, y, lens, n_sub=0, tau=0.0):
     """Lens equation beta = theta - alpha(theta)."""
     ax, ay = deflection(x, y, lens, n_sub, tau)
     return x - ax, y - ay
+
+
+# ------------------------------------------------------------------ lens light
+def mge_light(x, y, light):
+    """Lens light as a multi-Gaussian expansion (App. A, Multi Gaussian
+    Expansion): component n, with parameters (A_n, sigma_n, e1_n, e2_n, x_n, y_n),
+    adds A_n/(2 pi) exp(-rho_n^2/(2 sigma_n^2)), where rho_n^2 = q_n x'^2 + y'^2/q_n
+    in the frame centred on (x_n, y_n) and rotated by the component's position
+    angle.  The paper frees q_n and the angle per component and parametrises
+    ellipticities as for the mass; q_n and the angle come from (e1_n, e2_n) with
+    q_phi_from_e (reading: the mass's convention).  The light is not lensed: it
+    is evaluated at the image-plane positions.  Through the angle this form is
+    not differentiable at e_n = 0 exactly."""
+    total = torch.zeros_like(x)
+    for n in range(light.shape[0] // N_PER_GAUSS):
+        A, sig, e1, e2, xc, yc = (light[N_PER_GAUSS * n + k] for k in range(N_PER_GAUSS))
+        q, phi, _ = q_phi_from_e(e1, e2)
+        c, s = torch.cos(phi), torch.sin(phi)
+        dx, dy = x - xc, y - yc
+        xp = c * dx + s * dy
+        yp = -s * dx + c * dy
+        rho2 = q * xp * xp + yp * yp / q
+        total = total + A / (2.0 * math.pi) * torch.exp(-0.5 * rho2 / (sig * sig))
+    return total
 
 
 # ------------------------------------------------------------------ RTU transform
@@ -352,7 +377,10 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
             round32=False):
     """One evaluation of the lens model.
 
-    obs: dict with n_img, pix, ss, image[N,N], sigma[N,N], psf[K,K], mask[N,N].
+    obs: dict with n_img, pix, ss, image[N,N], sigma[N,N], psf[K,K], mask[N,N],
+    and optionally n_gauss: the last N_PER_GAUSS n_gauss entries of lens are
+    lens-light Gaussians (mge_light), added to every sub-ray's value before the
+    sub-ray mean and the PSF.
     uniform_box: if given as (x_lo, y_lo, side), the RTU transform is replaced by
     the plain affine map of that box onto the unit square (the paper's uniform
     grid, Sec. 2.1).
@@ -363,10 +391,16 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
     r32 = (lambda t: t.float().to(DT)) if round32 else (lambda t: t)
     status = 0
     lv, pv = lens.detach(), ps.detach()
+    n_gauss = int(obs.get("n_gauss", 0))
+    light = lens[lens.shape[0] - N_PER_GAUSS * n_gauss:] if n_gauss else None
     if float(lv[0]) <= 0 or float(torch.hypot(lv[1], lv[2])) >= 1 or \
             any(float(lv[N_LENS_BASE + N_PER_SUB * j + 1]) <= 0 for j in range(n_sub)) or \
             bool((pv[:3] <= 0).any()) or bool((obs["sigma"] <= 0).any()):
         status |= ST_DOMAIN
+    if n_gauss:
+        lt = light.detach().reshape(n_gauss, N_PER_GAUSS)
+        if bool((lt[:, 1] <= 0).any()) or bool((torch.hypot(lt[:, 2], lt[:, 3]) >= 1).any()):
+            status |= ST_DOMAIN
     xr, yr = subray_positions(N, pix, ss)
     bx, by = ray_shoot(xr, yr, lens, n_sub, tau)
     bx, by = r32(bx), r32(by)
@@ -390,6 +424,8 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
         gx, gy = (bx - x_lo) / side, (by - y_lo) / side
     s_grid, f = gp_source(w, ps)
     v = bilinear(s_grid, gx, gy, cell_shift)
+    if n_gauss:
+        v = v + mge_light(xr, yr, light)
     u_img = v.mean(dim=1).reshape(N, N)
     m = psf_convolve(u_img, obs["psf"])
     res = (m - obs["image"]) / obs["sigma"]
@@ -410,7 +446,8 @@ def obs_from_problem(p) -> dict:
     g = p.geom
     return {"n_img": g.n_img, "pix": float(np.float32(g.pixel_scale)), "ss": g.supersample,
             "image": _t(p.image), "sigma": _t(p.noise_sigma), "psf": _t(p.psf),
-            "mask": torch.as_tensor(p.mask.astype(np.int64)), "tau": g.tnfw_tau}
+            "mask": torch.as_tensor(p.mask.astype(np.int64)), "tau": g.tnfw_tau,
+            "n_gauss": getattr(g, "n_gauss", 0)}
 
 
 def loss_grad(lens, ps, w, obs, n_sub=0, tau=0.0, want_grad=True, return_all=False, cell_shift=0.0):

@@ -41,6 +41,9 @@ N_LENS_BASE = 7
 N_PER_SUB = 4
 #: power-spectrum parameters: sigma_src, n_src, zeta_src, alpha_src
 N_PS = 4
+#: parameters per lens-light Gaussian: A, sigma, e1, e2, x_c, y_c (after the
+#: subhalo slots in the lens vector)
+N_PER_GAUSS = 6
 
 
 @dataclasses.dataclass(frozen=True)
@@ -53,10 +56,11 @@ class Geometry:
     psf_sigma_px: float     # Gaussian PSF sigma in image pixels
     n_sub_max: int = 0
     tnfw_tau: float = 0.0   # truncation radius in units of r_s; 0 = none
+    n_gauss: int = 0        # lens-light Gaussians; 0 = no lens light
 
     @property
     def n_lens(self) -> int:
-        return N_LENS_BASE + N_PER_SUB * self.n_sub_max
+        return N_LENS_BASE + N_PER_SUB * self.n_sub_max + N_PER_GAUSS * self.n_gauss
 
 
 def e_from_q_phi(q: float, phi: float):
@@ -197,6 +201,36 @@ def _subhaloes(rng, n_sub, n_sub_max):
     return np.array(out, dtype=np.float64)
 
 
+def _light_truth(rng, n_gauss, centre):
+    """Lens-light Gaussians: widths log-uniform in [0.1, 1.0] arcsec and sorted
+    (the paper's prior range), amplitudes, mildly elliptical, centred near the
+    lens."""
+    sig = np.sort(10 ** rng.uniform(-1.0, 0.0, n_gauss))
+    out = []
+    for n in range(n_gauss):
+        e1, e2 = e_from_q_phi(rng.uniform(0.7, 0.95), rng.uniform(0.0, math.pi))
+        cx, cy = np.asarray(centre) + rng.uniform(-0.02, 0.02, 2)
+        out += [rng.uniform(0.5, 2.0), sig[n], e1, e2, cx, cy]
+    return np.array(out, dtype=np.float64)
+
+
+def _light_image(n_img, pix, light):
+    """Noiseless image of the lens-light Gaussians at the pixel centres (data
+    only: an elliptical Gaussian blob per component)."""
+    x, y = pixel_centres(n_img, pix)
+    img = np.zeros_like(x)
+    for n in range(light.size // N_PER_GAUSS):
+        A, sig, e1, e2, cx, cy = light[N_PER_GAUSS * n:N_PER_GAUSS * (n + 1)]
+        e = math.hypot(e1, e2)
+        q = (1 - e) / (1 + e)
+        phi = 0.5 * math.atan2(e2, e1)
+        dx, dy = x - cx, y - cy
+        xp = math.cos(phi) * dx + math.sin(phi) * dy
+        yp = -math.sin(phi) * dx + math.cos(phi) * dy
+        img += A / (2 * math.pi) * np.exp(-0.5 * (q * xp * xp + yp * yp / q) / sig ** 2)
+    return img
+
+
 CONFIGS = {
     "C1": Geometry(64, 0.05, 1, 32, 15, 1.6),
     "C2": Geometry(200, 0.031, 4, 64, 21, 2.0 / (2.0 * math.sqrt(2.0 * math.log(2.0)))),
@@ -246,6 +280,14 @@ def make_problem(name: str, batch: Optional[int] = None, seed: Optional[int] = N
     latent = rng.standard_normal((B, geom.n_src, geom.n_src))
     mask = annulus_mask(N, pix, truth[3:5], truth[0])
     clean = arc_image(N, pix, truth, rng)
+    if geom.n_gauss:
+        light = _light_truth(rng, geom.n_gauss, truth[3:5])
+        truth = np.concatenate([truth, light])
+        spread = np.tile([0.02, 0.02, 0.01, 0.01, 0.005, 0.005], geom.n_gauss)
+        lens = np.concatenate([lens, light[None, :] * np.ones((B, 1))
+                               + rng.standard_normal((B, light.size)) * spread[None, :]
+                               * np.tile([light[0], light[1], 1, 1, 1, 1], geom.n_gauss)[None, :]], axis=1)
+        clean = clean + _light_image(N, pix, light)
     sig = float(clean[mask.astype(bool)].mean()) / 13.5
     image = clean + sig * rng.standard_normal((N, N))
     sigma = np.full((N, N), sig)
