@@ -130,6 +130,42 @@ def serving_bench(n: int, steps: int) -> dict:
             "fits_leaving_parameter_domain": out_of_domain}
 
 
+def light_bench(steps: int, warmup: int, n_gauss: int = 5) -> dict:
+    """The C2 ELBO step with the paper's multi-Gaussian lens light (5 Gaussians,
+    App. A) added to the model: throughput and stage times."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2606_30620_amd import _lib, api, synth
+    S = 32
+    geom = dataclasses.replace(synth.CONFIGS["C2"], n_gauss=n_gauss)
+    problem = synth.make_problem("C2", batch=S, geom=geom)
+    plan = api.plan_for_problem(problem, max_batch=S)
+    nl = geom.n_lens
+    mu = np.concatenate([problem.lens[0], problem.ps[0], problem.latent[0].reshape(-1)]).astype(np.float32)
+    rho = np.full(mu.size, math.log(0.1), np.float32)
+    rho[:nl] = math.log(0.01)
+    rho[nl:nl + 4] = math.log(0.02)
+    fit = _lib.Fit(plan, S, mu, rho, lr=1e-2, seed=203, max_steps=warmup + steps + 6)
+    fit.step(warmup)
+    plan.profile_begin(5)
+    fit.step(5)
+    stages = plan.profile_end()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    fit.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    note(f"lens light ({n_gauss} Gaussians): {ms:.4f} ms/step")
+    return {"workload": f"C2 + {n_gauss} lens-light Gaussians", "evals_per_s": round(S * 1e3 / ms, 1),
+            "ms_per_step": round(ms, 4), "steps": steps,
+            "stage_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +174,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-light", action="store_true", help="skip the lens-light section")
     ap.add_argument("--serve-only", action="store_true", help="only the serving section (for profiling)")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=200)
@@ -227,6 +264,8 @@ def main():
     }
     if not args.no_serve:
         line["serving"] = serving_bench(args.serve_requests, args.serve_steps)
+    if not args.no_light:
+        line["lens_light"] = light_bench(20, 5)
     if args.calib_copy:
         src = torch.ones(args.calib_copy // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -59,12 +59,19 @@ extern "C" {
  * (App. C step iii and Fig. C1). */
 #define RTU_K_NODES 22
 /* Lens parameters: theta_E, e1, e2, x0, y0, gamma1, gamma2, then per
- * subhalo kappa_s, r_s, x_s, y_s (App. A).  Power-spectrum parameters:
- * sigma_src, n_src, zeta_src, alpha_src (eqs. 3-4). */
+ * subhalo kappa_s, r_s, x_s, y_s (App. A), then per lens-light Gaussian
+ * A, sigma, e1, e2, x_c, y_c (App. A, Multi Gaussian Expansion: the
+ * component adds A/(2 pi) exp(-rho^2/(2 sigma^2)) to every sub-ray, with
+ * rho^2 = q x'^2 + y'^2/q about (x_c, y_c) and q, angle from (e1, e2) as for
+ * the mass).  Power-spectrum parameters: sigma_src, n_src, zeta_src,
+ * alpha_src (eqs. 3-4). */
 #define RTU_N_LENS_BASE 7
 #define RTU_N_PER_SUB   4
+#define RTU_N_PER_GAUSS 6
 #define RTU_N_PS        4
 #define RTU_MAX_SUB    10
+#define RTU_MAX_GAUSS   8
+#define RTU_MAX_LENS   (RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB + RTU_N_PER_GAUSS * RTU_MAX_GAUSS)
 
 typedef struct rtu_plan_s* rtu_plan;
 
@@ -79,6 +86,8 @@ typedef struct {
   float    tnfw_tau;     /* subhalo projected-mass truncation in units of r_s;
                             0 = untruncated NFW                                     */
   uint32_t flags;        /* 0 or RTU_GEOM_RADIX_SELECT                              */
+  int32_t  n_gauss;      /* lens-light Gaussians per sample, 0..RTU_MAX_GAUSS
+                            (0 = no lens light)                                     */
 } rtu_geometry;
 
 /* Geometry flag: select the quantile order statistics with the bounded-pass
@@ -87,7 +96,7 @@ typedef struct {
  * same rays (ties by index); the flag exists to exercise the fallback. */
 #define RTU_GEOM_RADIX_SELECT 1u
 
-/* Number of lens parameters per sample: 7 + 4 n_sub_max. */
+/* Number of lens parameters per sample: 7 + 4 n_sub_max + 6 n_gauss. */
 int32_t rtu_n_lens(const rtu_geometry* g);
 
 /* Device memory (bytes) a plan of this geometry and batch allocates; a
@@ -116,7 +125,7 @@ int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma
 int32_t rtu_masked_count(rtu_plan p);
 
 /* One loss evaluation per sample, and its gradient, for `batch` samples.
- *   lens_params [B][7 + 4 n_sub_max]  device, see RTU_N_LENS_BASE
+ *   lens_params [B][rtu_n_lens(g)]    device, see RTU_N_LENS_BASE
  *   n_sub       [B] device int32, number of active subhaloes (<= n_sub_max),
  *               or NULL for none
  *   ps_params   [B][4]                device
@@ -124,7 +133,7 @@ int32_t rtu_masked_count(rtu_plan p);
  * Outputs (device; any may be NULL except loss and status):
  *   loss        [B] double: chi^2/2 + |w|^2/2, chi^2 over all pixels
  *   chi2_mask   [B] double: mean of ((m - d)/sigma)^2 over the masked pixels
- *   grad_lens   [B][7 + 4 n_sub_max], grad_ps [B][4], grad_latent [B][n_src^2]
+ *   grad_lens   [B][rtu_n_lens(g)], grad_ps [B][4], grad_latent [B][n_src^2]
  *               d loss / d parameters; if all three are NULL only the forward
  *               pass runs.  Gradient slots of inactive subhaloes are zero.
  *   model_image [B][n_img][n_img]: PSF-convolved model

@@ -22,6 +22,7 @@ RTU_EINVAL, RTU_ENOMEM, RTU_EBATCH, RTU_EHIP, RTU_ESTATE, RTU_ENOTFOUND = -1, -2
 ST_NONFINITE, ST_NONMONOTONE, ST_MASK_SMALL, ST_DOMAIN = 1, 2, 4, 8
 K_NODES = 22
 N_LENS_BASE, N_PER_SUB, N_PS, MAX_SUB = 7, 4, 4, 10
+N_PER_GAUSS, MAX_GAUSS = 6, 8
 DBG_KNOTS, DBG_SELECT, DBG_STD, DBG_SOURCE, DBG_PREPSF = 1, 2, 3, 4, 5
 STAGES = ("prep", "rays_fwd", "psf_fwd", "psf_adj", "rays_adj", "post", "sample", "adam")
 
@@ -29,7 +30,8 @@ STAGES = ("prep", "rays_fwd", "psf_fwd", "psf_adj", "rays_adj", "post", "sample"
 class Geometry(C.Structure):
     _fields_ = [("n_img", C.c_int32), ("supersample", C.c_int32), ("n_src", C.c_int32),
                 ("psf_size", C.c_int32), ("n_sub_max", C.c_int32), ("k_nodes", C.c_int32),
-                ("pixel_scale", C.c_float), ("tnfw_tau", C.c_float), ("flags", C.c_uint32)]
+                ("pixel_scale", C.c_float), ("tnfw_tau", C.c_float), ("flags", C.c_uint32),
+                ("n_gauss", C.c_int32)]
 
 
 class FitRequest(C.Structure):
@@ -110,9 +112,9 @@ GEOM_RADIX_SELECT = 1
 
 
 def make_geometry(n_img, supersample, n_src, psf_size, pixel_scale, n_sub_max=0, tnfw_tau=0.0,
-                  flags=0) -> Geometry:
+                  flags=0, n_gauss=0) -> Geometry:
     return Geometry(int(n_img), int(supersample), int(n_src), int(psf_size), int(n_sub_max), K_NODES,
-                    float(pixel_scale), float(tnfw_tau), int(flags))
+                    float(pixel_scale), float(tnfw_tau), int(flags), int(n_gauss))
 
 
 def _ptr(t) -> Optional[int]:

@@ -31,7 +31,7 @@ def plan_for_problem(problem, max_batch: Optional[int] = None, device: int = 0, 
     """Plan + observation for a problem from the seeded input generator."""
     g = problem.geom
     geom = make_geometry(g.n_img, g.supersample, g.n_src, g.psf_size, g.pixel_scale,
-                         g.n_sub_max, g.tnfw_tau, flags)
+                         g.n_sub_max, g.tnfw_tau, flags, g.n_gauss)
     plan = Plan(geom, max_batch or problem.batch, device)
     plan.set_observation(problem.image, problem.noise_sigma, problem.psf, problem.mask)
     return plan

@@ -397,6 +397,70 @@ __device__ __forceinline__ void km_flush(KnotMom& c, const float* X, const float
   c.m0 = c.m1 = c.m2 = c.m3 = 0.f;
 }
 
+// ------------------------------------------------------------------ lens light
+// A lens-light Gaussian (App. A, Multi Gaussian Expansion) from its parameters
+// (A, sigma, e1, e2, x_c, y_c): value A/(2 pi) exp(-rho^2/(2 sigma^2)).  With
+// q = (1-e)/(1+e) and the angle atan2(e2, e1)/2, the elliptical radius
+// rho^2 = q x'^2 + y'^2/q of the rotated frame is, in the unrotated offsets,
+//   rho^2 = [(1+e^2)(dx^2+dy^2) - 2 e1 (dx^2-dy^2) - 4 e2 dx dy] / (1-e^2)
+//         = c1 dx^2 + c2 dy^2 + c3 dx dy,
+// which needs no angle and is smooth at e = 0.
+struct LightG {
+  float A, sig, e1, e2, xc, yc;
+  float a2pi;          // A / (2 pi)
+  float c1, c2, c3, D; // D = 1/(1-e^2)
+  float q1, q2, q3;    // c1..c3 times -log2(e)/(2 sigma^2): the exponent in base 2
+};
+__device__ __forceinline__ LightG make_light(const float* p) {
+  LightG g;
+  g.A = p[0]; g.sig = p[1]; g.e1 = p[2]; g.e2 = p[3]; g.xc = p[4]; g.yc = p[5];
+  const float ee = g.e1 * g.e1 + g.e2 * g.e2;
+  g.D = 1.f / (1.f - ee);
+  g.c1 = g.D * (1.f + ee - 2.f * g.e1);
+  g.c2 = g.D * (1.f + ee + 2.f * g.e1);
+  g.c3 = -4.f * g.D * g.e2;
+  g.a2pi = g.A * 0.15915494309189535f;
+  const float k2 = -0.72134752044448170f / (g.sig * g.sig);
+  g.q1 = k2 * g.c1; g.q2 = k2 * g.c2; g.q3 = k2 * g.c3;
+  return g;
+}
+__device__ __forceinline__ float light_value(const LightG& g, float x, float y) {
+  const float dx = x - g.xc, dy = y - g.yc;
+  return g.a2pi * __builtin_amdgcn_exp2f(fmaf(g.q1 * dx, dx, fmaf(g.q2 * dy, dy, g.q3 * dx * dy)));
+}
+// Moments of X = exp(-rho^2/(2 sigma^2)) over a pixel's sub-rays:
+// m = (sum X, sum X dx^2, sum X dy^2, sum X dx dy, sum X dx, sum X dy).
+__device__ __forceinline__ void light_moments_add(const LightG& g, float x, float y, float (&m)[6]) {
+  const float dx = x - g.xc, dy = y - g.yc;
+  const float dd = dx * dx, ee = dy * dy, pq = dx * dy;
+  const float X = __builtin_amdgcn_exp2f(fmaf(g.q1, dd, fmaf(g.q2, ee, g.q3 * pq)));
+  m[0] += X;
+  m[1] = fmaf(X, dd, m[1]);
+  m[2] = fmaf(X, ee, m[2]);
+  m[3] = fmaf(X, pq, m[3]);
+  m[4] = fmaf(X, dx, m[4]);
+  m[5] = fmaf(X, dy, m[5]);
+}
+// d loss / d (A, sigma, e1, e2, x_c, y_c) of one pixel, weight vb = d loss / d
+// (sub-ray value), from the moments.  With G = A/(2 pi) X:
+//   dG/dA = X/(2 pi), dG/dsigma = G rho^2/sigma^3, and through
+//   dG/drho^2 = -G/(2 sigma^2):
+//   drho^2/de1 = 2 e1 D rho^2 + D (2 e1 r^2 - 2 (dx^2 - dy^2)),
+//   drho^2/de2 = 2 e2 D rho^2 + D (2 e2 r^2 - 4 dx dy),
+//   drho^2/dx_c = -(2 c1 dx + c3 dy), drho^2/dy_c = -(2 c2 dy + c3 dx),
+// each summed over the sub-rays as a combination of the moments.
+__device__ __forceinline__ void light_vjp(const LightG& g, float vb, const float (&m)[6], float (&a)[6]) {
+  const float xr2 = g.c1 * m[1] + g.c2 * m[2] + g.c3 * m[3];   // sum X rho^2
+  const float xr = m[1] + m[2], xd = m[1] - m[2];                // sum X r^2, sum X (dx^2 - dy^2)
+  const float w = vb * g.a2pi, h = -0.5f / (g.sig * g.sig);
+  a[0] = vb * 0.15915494309189535f * m[0];
+  a[1] = w * xr2 / (g.sig * g.sig * g.sig);
+  a[2] = w * h * (2.f * g.e1 * g.D * xr2 + g.D * (2.f * g.e1 * xr - 2.f * xd));
+  a[3] = w * h * (2.f * g.e2 * g.D * xr2 + g.D * (2.f * g.e2 * xr - 4.f * m[3]));
+  a[4] = -w * h * (2.f * g.c1 * m[4] + g.c3 * m[5]);
+  a[5] = -w * h * (2.f * g.c2 * m[5] + g.c3 * m[4]);
+}
+
 // ------------------------------------------------------------------ reductions
 // Reductions over the 64 lanes of a fully active wave with DPP lane moves
 // inside each row of 16 (swap within pairs, within quads, half-row mirror,

@@ -54,6 +54,7 @@ static_assert(sizeof(KnotTab) % 16 == 0, "KnotTab is copied as float4");
 struct SysDev {
   // geometry
   int n_img, ss, n_src, log2_src, psf_k, n_sub_max, n_lens, M;
+  int n_gauss, light_off;     // lens-light Gaussians and their offset in the lens vector
   float pix, tau, inv_ss2;
   int ray_tx, ray_tiles;      // 16x16 ray tiles per side / per sample
   int psf_tx, psf_tiles;      // 64x16 PSF tiles along x / per sample

@@ -548,6 +548,10 @@ __device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* s
     const int ns = n_sub_of(S, b);
     for (int j = 0; j < ns; ++j)
       if (!(L[RTU_N_LENS_BASE + RTU_N_PER_SUB * j + 1] > 0.f)) st |= RTU_ST_DOMAIN;
+    for (int g = 0; g < S.n_gauss; ++g) {
+      const float* lg = L + S.light_off + RTU_N_PER_GAUSS * g;
+      if (!(lg[1] > 0.f) || !(lg[2] * lg[2] + lg[3] * lg[3] < 1.f)) st |= RTU_ST_DOMAIN;
+    }
     if (!(ps[0] > 0.f) || !(ps[1] > 0.f) || !(ps[2] > 0.f)) st |= RTU_ST_DOMAIN;
     S.st[b * ST_WORDS + 2] = st;
     S.status[b] = 0u;             // the post roles OR their words into it
@@ -738,6 +742,14 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
       }
     }
   }
+  // lens light at the same sub-ray positions (not lensed)
+  for (int g = 0; g < S.n_gauss; ++g) {
+    const LightG G = make_light(lensp + S.light_off + RTU_N_PER_GAUSS * g);
+    for (int a = 0; a < S.ss; ++a) {
+      const float y = fmaf((float)a, dxs, y0);
+      for (int c = 0; c < S.ss; ++c) acc += light_value(G, fmaf((float)c, dxs, x0), y);
+    }
+  }
   S.u[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] = acc * S.inv_ss2;
 }
 
@@ -883,6 +895,28 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
     for (int q = 0; q < 4 * S.n_sub_max; ++q) {
       const float sq = wave_sum(subacc[q * RAY_THREADS + threadIdx.x]);
       if (lane == 0) lp[8 + q] = (double)sq;
+    }
+    // lens-light gradients: every lane of the wave takes part in the sums,
+    // a pixel outside the image with weight zero
+    if (S.n_gauss) {
+      const bool in = i < S.n_img && j < S.n_img;
+      const float vbl = in ? S.ubar[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] * S.inv_ss2 : 0.f;
+      float x0, y0, dxs;
+      subray_origin(S, i, j, x0, y0, dxs);
+      for (int g = 0; g < S.n_gauss; ++g) {
+        const LightG G = make_light(lensp + S.light_off + RTU_N_PER_GAUSS * g);
+        float m[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, a[6];
+        for (int ai = 0; ai < S.ss; ++ai) {
+          const float y = fmaf((float)ai, dxs, y0);
+          for (int c = 0; c < S.ss; ++c) light_moments_add(G, fmaf((float)c, dxs, x0), y, m);
+        }
+        light_vjp(G, vbl, m, a);
+#pragma unroll
+        for (int k = 0; k < RTU_N_PER_GAUSS; ++k) {
+          const float r = wave_sum(a[k]);
+          if (lane == 0) lp[S.light_off + 1 + RTU_N_PER_GAUSS * g + k] = (double)r;
+        }
+      }
     }
   }
   // every wave's knot-moment and window atomics are done before they are read
@@ -1096,7 +1130,7 @@ struct PostLds {
   double part[PREP_THREADS];
   double xbar[2][K];      // d loss / d X (beta units), after the slope chain
   double wk[2][K];        // -S_k^2 d loss / d S_k
-  double lsum[RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB + 1];   // raw sums
+  double lsum[RTU_MAX_LENS + 1];   // raw sums
   uint32_t stat;
 };
 
@@ -1519,9 +1553,8 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
 // The FFT kernels may take up to 129 KB of dynamic LDS (plus their static
 // part) of the 160 KB per CU.
 hipError_t configure_fft_kernels() {
-  const int big = (int)(prep_lds_bytes(128) > post_lds_bytes(128, RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB)
-                            ? prep_lds_bytes(128)
-                            : post_lds_bytes(128, RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB));
+  const int big = (int)(prep_lds_bytes(128) > post_lds_bytes(128, RTU_MAX_LENS) ? prep_lds_bytes(128)
+                                                                               : post_lds_bytes(128, RTU_MAX_LENS));
   const void* fns[4] = {(const void*)k_prep, (const void*)k_post, (const void*)kf_prep, (const void*)kf_post};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);

@@ -72,6 +72,7 @@ bool valid_geometry(const rtu_geometry* g) {
   if (n < 8 || n > 256 || (n & (n - 1))) return false;
   if (g->psf_size < 1 || g->psf_size > 63 || !(g->psf_size & 1)) return false;
   if (g->n_sub_max < 0 || g->n_sub_max > RTU_MAX_SUB) return false;
+  if (g->n_gauss < 0 || g->n_gauss > RTU_MAX_GAUSS) return false;
   if (g->k_nodes != RTU_K_NODES) return false;
   if (!(g->pixel_scale > 0.f) || !(g->tnfw_tau >= 0.f) || (g->flags & ~RTU_GEOM_RADIX_SELECT) != 0) return false;
   return true;
@@ -101,7 +102,9 @@ void fill_geometry(const rtu_geometry* g, SysDev& h) {
   h.log2_src = l;
   h.psf_k = g->psf_size;
   h.n_sub_max = g->n_sub_max;
-  h.n_lens = RTU_N_LENS_BASE + RTU_N_PER_SUB * g->n_sub_max;
+  h.n_gauss = g->n_gauss;
+  h.light_off = RTU_N_LENS_BASE + RTU_N_PER_SUB * g->n_sub_max;
+  h.n_lens = h.light_off + RTU_N_PER_GAUSS * g->n_gauss;
   h.pix = g->pixel_scale;
   h.tau = g->tnfw_tau;
   h.inv_ss2 = 1.f / (float)(g->supersample * g->supersample);
@@ -323,7 +326,7 @@ int run_eval(rtu_plan p, const SysDev& h, int batch, hipStream_t s) {
 extern "C" {
 
 int32_t rtu_n_lens(const rtu_geometry* g) {
-  return g ? RTU_N_LENS_BASE + RTU_N_PER_SUB * g->n_sub_max : 0;
+  return g ? RTU_N_LENS_BASE + RTU_N_PER_SUB * g->n_sub_max + RTU_N_PER_GAUSS * g->n_gauss : 0;
 }
 
 size_t rtu_workspace_bytes(const rtu_geometry* g, int32_t max_batch) {

@@ -60,7 +60,7 @@ def make_requests(n: int, rate: float, steps: int = 200, samples: int = 1, seed:
 
 def _geometry(lib, g: synth.Geometry):
     return lib.make_geometry(g.n_img, g.supersample, g.n_src, g.psf_size, g.pixel_scale, g.n_sub_max,
-                             g.tnfw_tau)
+                             g.tnfw_tau, n_gauss=g.n_gauss)
 
 
 @dataclasses.dataclass

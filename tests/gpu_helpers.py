@@ -101,24 +101,36 @@ def compare(plan, problem, b, res, ref, check_stages=True):
         out["prepsf"] = relinf(u, ref["u"].detach().numpy())
         assert out["prepsf"] <= TOL_IMG, ("pre-PSF image", out["prepsf"])
     if res.grad_lens is not None:
+        # lens vector: mass (7), subhalo slots (4 n_sub_max, of which the
+        # first n_sub are active), lens-light Gaussians (6 n_gauss)
         ns = int(problem.n_sub[b])
-        nl = 7 + 4 * ns
+        g = problem.geom
+        lo = 7 + 4 * g.n_sub_max
+        act = np.r_[0:7 + 4 * ns]
+        light = np.r_[lo:lo + 6 * getattr(g, "n_gauss", 0)]
+        inact = np.r_[7 + 4 * ns:lo]
         out["g_ps"] = relinf(res.grad_ps[b].cpu().numpy(), ref["grad_ps"].numpy())
         out["g_latent"] = relinf(res.grad_latent[b].cpu().numpy(), ref["grad_latent"].numpy())
         assert out["g_ps"] <= TOL_GRAD, ("grad_ps", res.grad_ps[b].cpu().numpy(), ref["grad_ps"].numpy())
         assert out["g_latent"] <= TOL_GRAD, ("grad_latent", out["g_latent"])
-        gl = res.grad_lens[b].cpu().numpy()
-        assert np.all(gl[nl:] == 0.0), "inactive subhalo gradient slots must be zero"
+        gl_all = res.grad_lens[b].cpu().numpy()
+        assert np.all(gl_all[inact] == 0.0), "inactive subhalo gradient slots must be zero"
+        if light.size:
+            # the lens light does not move rays: its gradient is one group of
+            # its own, independent of the order statistics
+            out["g_light"] = relinf(gl_all[light], ref["grad_lens"].numpy()[light])
+            assert out["g_light"] <= TOL_GRAD, ("grad light", gl_all[light], ref["grad_lens"].numpy()[light])
+        gl = gl_all[act]
         if same_sel:
-            gr = ref["grad_lens"].numpy()[:nl]
-            out["g_lens"] = relinf(gl[:nl], gr)
+            gr = ref["grad_lens"].numpy()[act]
+            out["g_lens"] = relinf(gl, gr)
             if out["g_lens"] > TOL_GRAD:
                 # sub-rays near a cell edge of the bilinear interpolation may
                 # take the other side's derivative: allow the oracle's bound
                 slack, npk, delta = lens_slack(problem, b)
-                excess = np.abs(gl[:nl] - gr) - TOL_GRAD * np.abs(gr).max() - slack[:nl]
+                excess = np.abs(gl - gr) - TOL_GRAD * np.abs(gr).max() - slack[act]
                 out["g_lens_edge"] = f"{npk} sub-ray axes within {delta:.1e} cells of an edge"
-                assert np.all(excess <= 0), ("grad_lens beyond cell-edge slack", gl[:nl], gr, slack[:nl])
+                assert np.all(excess <= 0), ("grad_lens beyond cell-edge slack", gl, gr, slack[act])
         else:
             out["g_lens"] = "skipped: near-tie order statistic"
     return out

@@ -36,5 +36,9 @@ def test_host_validation_without_gpu():
     assert L.rtu_workspace_bytes(ok, 1) == L.rtu_workspace_bytes(g, 1)
     bad = _lib.make_geometry(64, 1, 32, 15, 0.05, flags=2)     # unknown flag
     assert L.rtu_workspace_bytes(bad, 1) == 0
+    lit = _lib.make_geometry(64, 1, 32, 15, 0.05, n_sub_max=2, n_gauss=5)
+    assert L.rtu_n_lens(lit) == 7 + 4 * 2 + 6 * 5
+    bad = _lib.make_geometry(64, 1, 32, 15, 0.05, n_gauss=_lib.MAX_GAUSS + 1)
+    assert L.rtu_workspace_bytes(bad, 1) == 0
     assert L.rtu_strerror(_lib.RTU_EBATCH).decode().startswith("batch")
     assert L.rtu_loss_grad(None, 1, *([None] * 12)) == _lib.RTU_EINVAL

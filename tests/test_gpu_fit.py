@@ -22,8 +22,19 @@ def _guide(p, rho_val=math.log(1e-3)):
 
 def test_elbo_step_matches_oracle():
     say("[gpu] fit: one ELBO+Adam step, C1, S=2, eps given")
+    _elbo_step_check(c1_mock(), {"lens": slice(0, 7), "ps": slice(7, 11), "latent": slice(11, None)})
+
+
+def test_elbo_step_with_lens_light_matches_oracle():
+    say("[gpu] fit: one ELBO+Adam step with 3 lens-light Gaussians, 48x48 ss=2 n_src=16, S=2, eps given")
+    g = synth.Geometry(48, 0.08, 2, 16, 15, 1.0, n_gauss=3)
+    p = synth.make_problem("X", batch=1, seed=31, geom=g)
+    _elbo_step_check(p, {"lens": slice(0, 7), "light": slice(7, 25), "ps": slice(25, 29),
+                         "latent": slice(29, None)})
+
+
+def _elbo_step_check(p, groups):
     from paper_2606_30620_amd import _lib, api
-    p = c1_mock()
     plan = api.plan_for_problem(p, max_batch=2)
     mu, rho = _guide(p)
     mu32, rho32 = mu.astype(np.float32), rho.astype(np.float32)
@@ -36,11 +47,10 @@ def test_elbo_step_matches_oracle():
     assert steps == 1 and trace.size == 1
     obs = O.obs_from_problem(p)
     elbo, gmu, grho = O.elbo_and_grad(mu32.astype(np.float64), rho32.astype(np.float64),
-                                      eps.astype(np.float64), obs, 7)
+                                      eps.astype(np.float64), obs, p.geom.n_lens)
     # after one step from zero moments, m = (1 - 0.9) * d(-ELBO)/d(param)
     m_mu, m_rho = state[2] / 0.1, state[4] / 0.1
     ref_mu, ref_rho = -gmu.numpy(), -grho.numpy()
-    groups = {"lens": slice(0, 7), "ps": slice(7, 11), "latent": slice(11, None)}
     for name, sl in groups.items():
         e1 = relinf(m_mu[sl], ref_mu[sl])
         e2 = relinf(m_rho[sl] + 1.0, ref_rho[sl] + 1.0)     # remove the entropy term's -1

@@ -104,6 +104,15 @@ def test_subhalo_parity():
     _check(p, range(2))
 
 
+@pytest.mark.parametrize("n_sub_max, n_gauss", [(0, 5), (2, 3)])
+def test_lens_light_parity(n_sub_max, n_gauss):
+    say(f"[gpu] lens light: 80x80 ss=3 n_src=32 psf=15, {n_gauss} Gaussians, {n_sub_max} subhalo slots, batch 2")
+    g = synth.Geometry(80, 0.06, 3, 32, 15, 1.0, n_sub_max=n_sub_max, tnfw_tau=10.0 if n_sub_max else 0.0,
+                       n_gauss=n_gauss)
+    p = synth.make_problem("X", batch=2, seed=23, geom=g)
+    _check(p, range(2))
+
+
 def test_large_source_grid_parity():
     say("[gpu] n_src=128 (grid read from global memory, chunked FFT): 80x80 ss=2 psf=21, batch 2")
     g = synth.Geometry(80, 0.06, 2, 128, 21, 0.85)
