@@ -61,6 +61,7 @@ struct SysDev {
   int want_grad, batch;
   int round0, nsteps;         // serving: rounds [round0, round0 + nsteps) are this system's steps
   int lds_adj;                // the ray adjoint keeps d loss / d s in LDS (1) or adds to global memory (0)
+  int adj_wcap;               // global mode: cells of the per-tile LDS window of d loss / d s
   int sel_radix;              // quantile selection: always the radix select (1)
   // observation (owned by the plan)
   const float* image;         // [N*N]
@@ -106,6 +107,8 @@ struct SysDev {
   float* ubar;                // [B][N^2] d loss / d u
   double* sbar;               // [B][n^2] d loss / d s (FP64 accumulation: order-independent to FP32 rounding)
   double* kbar;               // [B][ray_tiles][4K] per-tile dX, dS partials
+  int4* tbox;                 // [B][ray_tiles][4 waves] source cells the forward's sub-rays fell in:
+                              // (min row, min column, max row, max column) of the cell's lower corner
   double* lpart;              // [B][ray_tiles][4 waves][n_lens + 1] per-wave raw lens-gradient partials
   double* c2part;             // [B][psf_tiles][2] per-tile chi^2 partials (all, mask)
   uint32_t* st;               // [B][ST_WORDS] status words: selection x, y; parameter domain
@@ -168,6 +171,7 @@ hipError_t init_fit_state(const FitDev& F, const float* mu0, const float* rho0, 
 
 // LDS sizing shared by both launch paths
 size_t ray_lds_bytes(const SysDev& h, bool adjoint, bool lds_grid);
+int adj_window_cap(const SysDev& h);
 bool adj_lds_grid(const SysDev& h);
 size_t psf_lds_bytes(int KP);
 int fft_lds_cap(int n_src);          // float2 slots of the FFT line buffer for this grid

@@ -18,6 +18,8 @@
 //               gradient; (1) the GP adjoint through the FFT.  Each role
 //               ORs its status bits into the sample's status word.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -706,57 +708,78 @@ __device__ __forceinline__ void bil_corners(const float* g, int n, const Bil& B,
 
 // The corner values are read from the zero-bordered grid in global memory
 // (through L1/L2): staging the grid in LDS per tile cost more than it saved.
+// With BOX each wave also records the range of source cells its sub-rays
+// fell in (tbox), which sizes the adjoint's LDS window when the source grid
+// does not fit in LDS.
+template <bool BOX>
 __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* smem) {
   RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
   const int ti = tile / S.ray_tx, tj = tile - ti * S.ray_tx;
   const int i = ti * RAY_TILE + (threadIdx.x >> 4), j = tj * RAY_TILE + (threadIdx.x & 15);
   load_knots(S, b, H);
   __syncthreads();
-  if (i >= S.n_img || j >= S.n_img) return;
-  const float* lensp = S.lens + (size_t)b * S.n_lens;
-  const int nsub = n_sub_of(S, b);
-  const Sie L = make_sie(lensp);
-  const int n = S.n_src;
-  const float* gsrc = S.srcp + (size_t)b * (n + 2) * (n + 2);
-  float acc = 0.f;
-  int kx = 0, ky = 0;
-  float x0, y0, dxs;
-  subray_origin(S, i, j, x0, y0, dxs);
-  for (int a = 0; a < S.ss; ++a) {
-    const float y = fmaf((float)a, dxs, y0);
-    for (int cc = 0; cc < S.ss; ++cc) {
-      const int c = (a & 1) ? S.ss - 1 - cc : cc;   // serpentine: neighbouring sub-rays in turn
-      const float x = fmaf((float)c, dxs, x0);
-      float bx, by;
-      shoot(S, L, H.nfw, nsub, x, y, bx, by);
-      kx = knot_find(H, 0, bx, kx);
-      ky = knot_find(H, 1, by, ky);
-      float tx, ty, dTx, dTy;
-      const float Tx = cdf_grid<false>(H, 0, kx, bx, tx, dTx);
-      const float Ty = cdf_grid<false>(H, 1, ky, by, ty, dTy);
-      Bil B;
-      if (bil_setup(Tx, Ty, n, B)) {
-        float s00, s01, s10, s11;
-        bil_corners(gsrc, n, B, s00, s01, s10, s11);
-        acc += (1.f - B.fy) * ((1.f - B.fx) * s00 + B.fx * s01) + B.fy * ((1.f - B.fx) * s10 + B.fx * s11);
-      }
-    }
-  }
-  // lens light at the same sub-ray positions (not lensed)
-  for (int g = 0; g < S.n_gauss; ++g) {
-    const LightG G = make_light(lensp + S.light_off + RTU_N_PER_GAUSS * g);
+  const bool in = i < S.n_img && j < S.n_img;
+  if (!BOX && !in) return;
+  int bi0 = 1 << 30, bj0 = 1 << 30, bi1 = -(1 << 30), bj1 = -(1 << 30);
+  if (in) {
+    const float* lensp = S.lens + (size_t)b * S.n_lens;
+    const int nsub = n_sub_of(S, b);
+    const Sie L = make_sie(lensp);
+    const int n = S.n_src;
+    const float* gsrc = S.srcp + (size_t)b * (n + 2) * (n + 2);
+    float acc = 0.f;
+    int kx = 0, ky = 0;
+    float x0, y0, dxs;
+    subray_origin(S, i, j, x0, y0, dxs);
     for (int a = 0; a < S.ss; ++a) {
       const float y = fmaf((float)a, dxs, y0);
-      for (int c = 0; c < S.ss; ++c) acc += light_value(G, fmaf((float)c, dxs, x0), y);
+      for (int cc = 0; cc < S.ss; ++cc) {
+        const int c = (a & 1) ? S.ss - 1 - cc : cc;   // serpentine: neighbouring sub-rays in turn
+        const float x = fmaf((float)c, dxs, x0);
+        float bx, by;
+        shoot(S, L, H.nfw, nsub, x, y, bx, by);
+        kx = knot_find(H, 0, bx, kx);
+        ky = knot_find(H, 1, by, ky);
+        float tx, ty, dTx, dTy;
+        const float Tx = cdf_grid<false>(H, 0, kx, bx, tx, dTx);
+        const float Ty = cdf_grid<false>(H, 1, ky, by, ty, dTy);
+        Bil B;
+        if (bil_setup(Tx, Ty, n, B)) {
+          float s00, s01, s10, s11;
+          bil_corners(gsrc, n, B, s00, s01, s10, s11);
+          acc += (1.f - B.fy) * ((1.f - B.fx) * s00 + B.fx * s01) + B.fy * ((1.f - B.fx) * s10 + B.fx * s11);
+          if (BOX) {
+            bi0 = min(bi0, B.i0); bj0 = min(bj0, B.j0);
+            bi1 = max(bi1, B.i0); bj1 = max(bj1, B.j0);
+          }
+        }
+      }
     }
+    // lens light at the same sub-ray positions (not lensed)
+    for (int g = 0; g < S.n_gauss; ++g) {
+      const LightG G = make_light(lensp + S.light_off + RTU_N_PER_GAUSS * g);
+      for (int a = 0; a < S.ss; ++a) {
+        const float y = fmaf((float)a, dxs, y0);
+        for (int c = 0; c < S.ss; ++c) acc += light_value(G, fmaf((float)c, dxs, x0), y);
+      }
+    }
+    S.u[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] = acc * S.inv_ss2;
   }
-  S.u[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] = acc * S.inv_ss2;
+  if (BOX) {   // every lane of the wave is here
+    bi0 = wave_min(bi0);
+    bj0 = wave_min(bj0);
+    bi1 = wave_max(bi1);
+    bj1 = wave_max(bj1);
+    if ((threadIdx.x & 63) == 0)
+      S.tbox[((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64) + (threadIdx.x >> 6)] = make_int4(bi0, bj0, bi1, bj1);
+  }
 }
 
+template <bool BOX>
 __global__ void __launch_bounds__(RAY_THREADS) k_rays_fwd(SysDev S) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x / S.ray_tiles;
-  rays_fwd_body(S, b, blockIdx.x - b * S.ray_tiles, smem);
+  rays_fwd_body<BOX>(S, b, blockIdx.x - b * S.ray_tiles, smem);
 }
 
 template <bool LDSGRID>
@@ -766,9 +789,10 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   // the source grid is read from its zero-bordered copy through L1/L2 here;
   // only d loss / d s lives in LDS, accumulated in FP64 so that its value does
   // not depend on the order of the atomic additions (to FP32 rounding)
-  double* gb = reinterpret_cast<double*>(smem + sizeof(RayLdsHead));          // padded grid
-  float* subacc = reinterpret_cast<float*>(gb + (LDSGRID ? np * np : 0));    // [4 n_sub_max][256]
-  size_t off = sizeof(RayLdsHead) + (size_t)(LDSGRID ? np * np : 0) * 8 +
+  // padded grid (LDSGRID), else the tile's window of the grid
+  double* gb = reinterpret_cast<double*>(smem + sizeof(RayLdsHead));
+  float* subacc = reinterpret_cast<float*>(gb + (LDSGRID ? np * np : S.adj_wcap));   // [4 n_sub_max][256]
+  size_t off = sizeof(RayLdsHead) + (size_t)(LDSGRID ? np * np : S.adj_wcap) * 8 +
                (size_t)4 * S.n_sub_max * RAY_THREADS * 4;
   off = (off + 15) & ~(size_t)15;
   double* red = reinterpret_cast<double*>(smem + off);     // [8 * 4]
@@ -778,6 +802,25 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   load_knots(S, b, H);
   if (LDSGRID)
     for (int q = threadIdx.x; q < np * np; q += blockDim.x) gb[q] = 0.0;
+  // grid in global memory: d loss / d s of the grid points (rows wr0 .. wr0 +
+  // wrs, columns wc0 .. wc0 + wcs) around the cells the forward's sub-rays of
+  // this tile fell in is summed in LDS, and added to the sample's grid once;
+  // a point outside that window, or every point of a tile whose window
+  // exceeds the capacity, is added to global memory at once
+  int wr0 = 0, wc0 = 0, wrs = 0, wcs = 0;
+  if (!LDSGRID) {
+    const int4* tb = S.tbox + ((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64);
+    int r0 = 1 << 30, c0 = 1 << 30, r1 = -(1 << 30), c1 = -(1 << 30);
+    for (int w = 0; w < RAY_THREADS / 64; ++w) {
+      const int4 v = tb[w];
+      r0 = min(r0, v.x); c0 = min(c0, v.y); r1 = max(r1, v.z); c1 = max(c1, v.w);
+    }
+    r0 = max(r0, 0); c0 = max(c0, 0); r1 = min(r1 + 1, n - 1); c1 = min(c1 + 1, n - 1);   // cell corners
+    if (r1 >= r0 && c1 >= c0 && (long)(r1 - r0 + 1) * (long)(c1 - c0 + 1) <= (long)S.adj_wcap) {
+      wr0 = r0; wc0 = c0; wrs = r1 - r0 + 1; wcs = c1 - c0 + 1;
+    }
+    for (int q = threadIdx.x; q < wrs * wcs; q += blockDim.x) gb[q] = 0.0;
+  }
   for (int q = threadIdx.x; q < 4 * S.n_sub_max * RAY_THREADS; q += blockDim.x) subacc[q] = 0.f;
   if (threadIdx.x == 0) { bbox[0] = bbox[1] = 1 << 30; bbox[2] = bbox[3] = -(1 << 30); }
   __syncthreads();
@@ -809,7 +852,13 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         bi0 = min(bi0, ci); bj0 = min(bj0, cj); bi1 = max(bi1, ci + 1); bj1 = max(bj1, cj + 1);
       } else {
         auto add = [&](int ii, int jj, float v) {
-          if (ii >= 0 && ii < n && jj >= 0 && jj < n) atomicAdd(&gsb[ii * n + jj], (double)v);
+          if (ii >= 0 && ii < n && jj >= 0 && jj < n) {
+            const int wi = ii - wr0, wj = jj - wc0;
+            if ((unsigned)wi < (unsigned)wrs && (unsigned)wj < (unsigned)wcs)
+              atomicAdd(&gb[wi * wcs + wj], (double)v);
+            else
+              atomicAdd(&gsb[ii * n + jj], (double)v);
+          }
         };
         add(ci, cj, c00); add(ci, cj + 1, c01); add(ci + 1, cj, c10); add(ci + 1, cj + 1, c11);
       }
@@ -933,6 +982,14 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         const int ii = i0 + q / wj, jj = j0 + q % wj;
         const double v = gb[(ii + 1) * np + jj + 1];
         if (v != 0.0) atomicAdd(&gsb[ii * n + jj], v);
+      }
+    }
+  } else {
+    for (int q = threadIdx.x; q < wrs * wcs; q += blockDim.x) {
+      const double v = gb[q];
+      if (v != 0.0) {
+        const int r = q / wcs;
+        atomicAdd(&gsb[(wr0 + r) * n + wc0 + (q - r * wcs)], v);
       }
     }
   }
@@ -1404,10 +1461,21 @@ hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
 // GRID_LDS_MAX per side and the workgroup's LDS stays within 64 KB.
 // The forward keeps only the spline tables in LDS; the adjoint also keeps
 // d loss / d s (FP64) of the whole grid when it is small enough.
+// The global-mode window: as many grid points as keep the adjoint within 64 KB
+// of LDS, at most ADJ_WCAP_MAX (the tiles of the n = 128 workloads mostly touch
+// 1-2k points).
+constexpr int ADJ_WCAP_MAX = 3072;
+int adj_window_cap(const SysDev& h) {
+  const long fixed = (long)sizeof(RayLdsHead) + 4L * h.n_sub_max * RAY_THREADS * 4 + 8 * 4 * 8 + 16 + 16;
+  const long room = (65536 - fixed) / 8;
+  return (int)(std::max(0L, std::min((long)ADJ_WCAP_MAX, room)) & ~1L);
+}
+
 size_t ray_lds_bytes(const SysDev& h, bool adjoint, bool lds_grid) {
   if (!adjoint) return sizeof(RayLdsHead);
   const size_t np = (size_t)(h.n_src + 2);
-  size_t bytes = sizeof(RayLdsHead) + (lds_grid ? np * np * 8 : 0) + (size_t)4 * h.n_sub_max * RAY_THREADS * 4;
+  size_t bytes = sizeof(RayLdsHead) + (lds_grid ? np * np * 8 : (size_t)h.adj_wcap * 8) +
+                 (size_t)4 * h.n_sub_max * RAY_THREADS * 4;
   bytes = (bytes + 15) & ~(size_t)15;
   return bytes + 8 * 4 * 8 + 16;
 }
@@ -1416,8 +1484,13 @@ bool adj_lds_grid(const SysDev& h) {
 }
 
 hipError_t launch_rays_fwd(const SysDev& h, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_rays_fwd, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), ray_lds_bytes(h, false, false), s,
-                     h);
+  // the tile boxes size the adjoint's LDS window when the grid is in global memory
+  if (adj_lds_grid(h))
+    hipLaunchKernelGGL(k_rays_fwd<false>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS),
+                       ray_lds_bytes(h, false, false), s, h);
+  else
+    hipLaunchKernelGGL(k_rays_fwd<true>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS),
+                       ray_lds_bytes(h, false, false), s, h);
   return hipGetLastError();
 }
 
@@ -1477,7 +1550,8 @@ __global__ void __launch_bounds__(RAY_THREADS) kf_rays_fwd(const SysDev* __restr
   const Task t = tasks[blockIdx.x];
   const SysDev S = sys[t.x];
   if (!sys_active(S, round)) return;
-  rays_fwd_body(S, t.y, t.z, smem);
+  if (S.lds_adj) rays_fwd_body<false>(S, t.y, t.z, smem);
+  else rays_fwd_body<true>(S, t.y, t.z, smem);
 }
 
 template <bool LDSGRID>

@@ -111,6 +111,7 @@ void fill_geometry(const rtu_geometry* g, SysDev& h) {
   h.sel_radix = (g->flags & RTU_GEOM_RADIX_SELECT) ? 1 : 0;
   h.ray_tx = (g->n_img + RAY_TILE - 1) / RAY_TILE;
   h.ray_tiles = h.ray_tx * h.ray_tx;
+  h.adj_wcap = adj_window_cap(h);
   h.psf_tx = (g->n_img + PSF_TW - 1) / PSF_TW;
   h.psf_tiles = h.psf_tx * ((g->n_img + PSF_TH - 1) / PSF_TH);
 }
@@ -135,6 +136,7 @@ size_t carve_workspace(SysDev& h, int B, char* base) {
   h.ubar = c.take<float>(B * N2);
   h.sbar = c.take<double>(B * n2);
   h.kbar = c.take<double>((size_t)B * h.ray_tiles * 4 * K);
+  h.tbox = c.take<int4>((size_t)B * h.ray_tiles * (RAY_THREADS / 64));
   h.lpart = c.take<double>((size_t)B * h.ray_tiles * (RAY_THREADS / 64) * (h.n_lens + 1));
   h.c2part = c.take<double>((size_t)B * h.psf_tiles * 2);
   h.st = c.take<uint32_t>((size_t)B * ST_WORDS);
