@@ -1544,8 +1544,20 @@ __global__ void __launch_bounds__(PREP_THREADS) kf_prep(const SysDev* __restrict
   else prep_gp(S, t.y, smem, fft_cap);
 }
 
+template <bool BOX>
 __global__ void __launch_bounds__(RAY_THREADS) kf_rays_fwd(const SysDev* __restrict__ sys,
                                                            const Task* __restrict__ tasks, int round) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Task t = tasks[blockIdx.x];
+  const SysDev S = sys[t.x];
+  if (!sys_active(S, round)) return;
+  rays_fwd_body<BOX>(S, t.y, t.z, smem);
+}
+
+// both kinds of system in one launch (a mixed fleet): one launch instead of
+// two, in a larger kernel than either of the above
+__global__ void __launch_bounds__(RAY_THREADS) kf_rays_fwd_mixed(const SysDev* __restrict__ sys,
+                                                                 const Task* __restrict__ tasks, int round) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Task t = tasks[blockIdx.x];
   const SysDev S = sys[t.x];
@@ -1595,9 +1607,17 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
                            (int)(L.lds_prep / sizeof(float2)) - 128);
       break;
     case RTU_STAGE_RAYS_FWD:
-      if (L.n_fwd)
-        hipLaunchKernelGGL(kf_rays_fwd, dim3(L.n_fwd), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys, L.t_fwd,
-                           round);
+      // [1]: grids in global memory, whose tiles record their cell ranges;
+      // the two lists are adjacent in the task table
+      if (L.n_fwd[0] && L.n_fwd[1])
+        hipLaunchKernelGGL(kf_rays_fwd_mixed, dim3(L.n_fwd[0] + L.n_fwd[1]), dim3(RAY_THREADS), L.lds_rays_fwd, s,
+                           L.sys, L.t_fwd[0], round);
+      else if (L.n_fwd[0])
+        hipLaunchKernelGGL(kf_rays_fwd<false>, dim3(L.n_fwd[0]), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys,
+                           L.t_fwd[0], round);
+      else if (L.n_fwd[1])
+        hipLaunchKernelGGL(kf_rays_fwd<true>, dim3(L.n_fwd[1]), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys,
+                           L.t_fwd[1], round);
       break;
     case RTU_STAGE_PSF_FWD:
     case RTU_STAGE_PSF_ADJ:
