@@ -129,7 +129,8 @@ int32_t rtu_masked_count(rtu_plan p);
  *   n_sub       [B] device int32, number of active subhaloes (<= n_sub_max),
  *               or NULL for none
  *   ps_params   [B][4]                device
- *   latent      [B][n_src][n_src]     device, the white-noise field w of eq. 1
+ *   latent      [B][n_src][n_src]     device, 16-byte aligned, the white-noise
+ *               field w of eq. 1
  * Outputs (device; any may be NULL except loss and status):
  *   loss        [B] double: chi^2/2 + |w|^2/2, chi^2 over all pixels
  *   chi2_mask   [B] double: mean of ((m - d)/sigma)^2 over the masked pixels
@@ -139,7 +140,8 @@ int32_t rtu_masked_count(rtu_plan p);
  *   model_image [B][n_img][n_img]: PSF-convolved model
  *   status      [B] uint32 RTU_ST_* bits of each sample
  * Asynchronous on `stream`.  RTU_ESTATE without an observation, RTU_EBATCH
- * if batch > max_batch, RTU_EINVAL for NULL required pointers. */
+ * if batch > max_batch, RTU_EINVAL for NULL required pointers or a latent
+ * pointer that is not 16-byte aligned. */
 int rtu_loss_grad(rtu_plan p, int32_t batch,
                   const float* lens_params, const int32_t* n_sub,
                   const float* ps_params, const float* latent,

@@ -574,8 +574,14 @@ __device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* s
     float2* tw = lds + cap;
     for (int k = threadIdx.x; k < 128; k += blockDim.x) tw[k] = c_tw[k];
     const int ls = n + 1;
-    batched_copy<16>(n2, [&](int q) { return w[q]; },
-                    [&](int q, float v) { lds[(q >> logn) * ls + (q & (n - 1))] = make_float2(v, 0.f); });
+    // four consecutive points of a row per item (n >= 8), all of a thread's
+    // loads in flight at once for n <= 128
+    batched_copy<8>(n2 >> 2, [&](int q4) { return reinterpret_cast<const float4*>(w)[q4]; },
+                    [&](int q4, float4 v) {
+                      float2* row = lds + ((4 * q4) >> logn) * ls + ((4 * q4) & (n - 1));
+                      row[0] = make_float2(v.x, 0.f); row[1] = make_float2(v.y, 0.f);
+                      row[2] = make_float2(v.z, 0.f); row[3] = make_float2(v.w, 0.f);
+                    });
     __syncthreads();
     fft_grid_dir(lds, tw, n, logn, false, -1.f, true);
     fft_grid_dir(lds, tw, n, logn, true, -1.f, true);
@@ -1336,24 +1342,61 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
       float2* tw = lds + cap;
       for (int k = tid; k < 128; k += blockDim.x) tw[k] = c_tw[k];
       const int ls = n + 1;
-      batched_copy<8>(n2, [&](int q) { return make_float4((float)sb[q], fo[q], so[q], 0.f); },
-                      [&](int q, float4 v) {
-                        lds[(q >> logn) * ls + (q & (n - 1))] = make_float2(fbar_of(v.x, v.y, v.z), 0.f);
+      // four consecutive points of a row per item (n >= 8): two double2
+      // loads of d loss / d s, float4 loads of the field and the source
+      struct G4 {
+        double2 a, c;
+        float4 f, s;
+      };
+      batched_copy<4>(n2 >> 2,
+                      [&](int q4) {
+                        G4 g;
+                        g.a = reinterpret_cast<const double2*>(sb)[2 * q4];
+                        g.c = reinterpret_cast<const double2*>(sb)[2 * q4 + 1];
+                        g.f = reinterpret_cast<const float4*>(fo)[q4];
+                        g.s = reinterpret_cast<const float4*>(so)[q4];
+                        return g;
+                      },
+                      [&](int q4, const G4& g) {
+                        float2* row = lds + ((4 * q4) >> logn) * ls + ((4 * q4) & (n - 1));
+                        row[0] = make_float2(fbar_of((float)g.a.x, g.f.x, g.s.x), 0.f);
+                        row[1] = make_float2(fbar_of((float)g.a.y, g.f.y, g.s.y), 0.f);
+                        row[2] = make_float2(fbar_of((float)g.c.x, g.f.z, g.s.z), 0.f);
+                        row[3] = make_float2(fbar_of((float)g.c.y, g.f.w, g.s.w), 0.f);
                       });
       __syncthreads();
       fft_grid_dir(lds, tw, n, logn, false, -1.f, true);
       fft_grid_dir(lds, tw, n, logn, true, -1.f, true);
-      batched_copy<8>(n2, [&](int q) { return F[q]; },
-                      [&](int q, float2 f0) {
-                        const int rs = q >> logn, cs = q & (n - 1);
+      // F: four consecutive entries of a row per item (two float4 loads)
+      struct F4 {
+        float4 lo, hi;
+      };
+      batched_copy<4>(n2 >> 2,
+                      [&](int q4) {
+                        const float4* f4 = reinterpret_cast<const float4*>(F);
+                        return F4{f4[2 * q4], f4[2 * q4 + 1]};
+                      },
+                      [&](int q4, const F4& g) {
+                        const int rs = (4 * q4) >> logn, cs = (4 * q4) & (n - 1);
+                        const int r = split_nat(rs, logn);
                         float2* a = lds + rs * ls + cs;
-                        *a = spectrum(split_nat(rs, logn), split_nat(cs, logn), *a, f0);
+                        a[0] = spectrum(r, split_nat(cs, logn), a[0], make_float2(g.lo.x, g.lo.y));
+                        a[1] = spectrum(r, split_nat(cs + 1, logn), a[1], make_float2(g.lo.z, g.lo.w));
+                        a[2] = spectrum(r, split_nat(cs + 2, logn), a[2], make_float2(g.hi.x, g.hi.y));
+                        a[3] = spectrum(r, split_nat(cs + 3, logn), a[3], make_float2(g.hi.z, g.hi.w));
                       });
       __syncthreads();
       fft_grid_dir(lds, tw, n, logn, true, 1.f, false);
       fft_grid_dir(lds, tw, n, logn, false, 1.f, false);
-      batched_copy<8>(n2, [&](int q) { return w[q]; },
-                      [&](int q, float wq) { latent_grad(q, lds[(q >> logn) * ls + (q & (n - 1))].x, wq); });
+      batched_copy<8>(n2 >> 2, [&](int q4) { return reinterpret_cast<const float4*>(w)[q4]; },
+                      [&](int q4, float4 v) {
+                        const int q = 4 * q4;
+                        const float2* a = lds + (q >> logn) * ls + (q & (n - 1));
+                        latent_grad(q, a[0].x, v.x);
+                        latent_grad(q + 1, a[1].x, v.y);
+                        latent_grad(q + 2, a[2].x, v.z);
+                        latent_grad(q + 3, a[3].x, v.w);
+                      });
     } else {
       // larger grids: lines in chunks through the workspace T
       fft_pass<2>(lds, cap, n, logn, false, -1.f, false, 0.f,

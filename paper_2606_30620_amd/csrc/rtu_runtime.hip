@@ -410,6 +410,7 @@ int rtu_loss_grad(rtu_plan p, int32_t batch, const float* lens_params, const int
   if (batch < 1) return RTU_EINVAL;
   if (batch > p->max_batch) return RTU_EBATCH;
   if (!lens_params || !ps_params || !latent || !loss || !status) return RTU_EINVAL;
+  if (reinterpret_cast<uintptr_t>(latent) % 16) return RTU_EINVAL;   // read four floats at a time
   if (hipSetDevice(p->device) != hipSuccess) return RTU_EHIP;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   SysDev h = p->h;
