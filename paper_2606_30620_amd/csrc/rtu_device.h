@@ -424,22 +424,59 @@ __device__ __forceinline__ LightG make_light(const float* p) {
   g.q1 = k2 * g.c1; g.q2 = k2 * g.c2; g.q3 = k2 * g.c3;
   return g;
 }
-__device__ __forceinline__ float light_value(const LightG& g, float x, float y) {
-  const float dx = x - g.xc, dy = y - g.yc;
-  return g.a2pi * __builtin_amdgcn_exp2f(fmaf(g.q1 * dx, dx, fmaf(g.q2 * dy, dy, g.q3 * dx * dy)));
+// Along a row of sub-rays (x = x0 + c h, c < cnt, at fixed y) the base-2
+// exponent E(c) = q1 dx^2 + q2 dy^2 + q3 dx dy is quadratic in c, so
+// X(c) = 2^E(c) follows from X(c+1) = X(c) R(c), R(c+1) = R(c) Q2 with
+// R(0) = 2^(E(1) - E(0)) and Q2 = 2^(2 q1 h^2): two exponentials per row
+// instead of one per sub-ray (the relative rounding grows by about one unit
+// in the last place per step).  Q2 is per Gaussian and spacing.
+__device__ __forceinline__ float light_q2(const LightG& g, float h) {
+  return __builtin_amdgcn_exp2f(2.f * g.q1 * h * h);
 }
-// Moments of X = exp(-rho^2/(2 sigma^2)) over a pixel's sub-rays:
-// m = (sum X, sum X dx^2, sum X dy^2, sum X dx dy, sum X dx, sum X dy).
-__device__ __forceinline__ void light_moments_add(const LightG& g, float x, float y, float (&m)[6]) {
-  const float dx = x - g.xc, dy = y - g.yc;
-  const float dd = dx * dx, ee = dy * dy, pq = dx * dy;
-  const float X = __builtin_amdgcn_exp2f(fmaf(g.q1, dd, fmaf(g.q2, ee, g.q3 * pq)));
-  m[0] += X;
-  m[1] = fmaf(X, dd, m[1]);
-  m[2] = fmaf(X, ee, m[2]);
-  m[3] = fmaf(X, pq, m[3]);
-  m[4] = fmaf(X, dx, m[4]);
-  m[5] = fmaf(X, dy, m[5]);
+__device__ __forceinline__ void light_row_start(const LightG& g, float x0, float y, float h, float& X, float& R,
+                                                float& dx0, float& dy) {
+  dx0 = x0 - g.xc;
+  dy = y - g.yc;
+  const float e0 = fmaf(g.q1 * dx0, dx0, fmaf(g.q2 * dy, dy, g.q3 * dx0 * dy));
+  const float de = fmaf(g.q1, fmaf(2.f * dx0, h, h * h), g.q3 * dy * h);   // E(1) - E(0)
+  X = __builtin_amdgcn_exp2f(e0);
+  R = __builtin_amdgcn_exp2f(de);
+}
+// sum over the row of the Gaussian's value
+__device__ __forceinline__ float light_row_sum(const LightG& g, float x0, float y, float h, float q2, int cnt) {
+  float X, R, dx0, dy;
+  light_row_start(g, x0, y, h, X, R, dx0, dy);
+  float s = 0.f;
+  for (int c = 0; c < cnt; ++c) {
+    s += X;
+    X *= R;
+    R *= q2;
+  }
+  return g.a2pi * s;
+}
+// Moments of X = exp(-rho^2/(2 sigma^2)) over a row, added to
+// m = (sum X, sum X dx^2, sum X dy^2, sum X dx dy, sum X dx, sum X dy)
+// (dy is constant along the row).
+__device__ __forceinline__ void light_row_moments(const LightG& g, float x0, float y, float h, float q2, int cnt,
+                                                  float (&m)[6]) {
+  float X, R, dx, dy;
+  light_row_start(g, x0, y, h, X, R, dx, dy);
+  float sx = 0.f, sxd = 0.f, sxdd = 0.f;
+  for (int c = 0; c < cnt; ++c) {
+    const float t = X * dx;
+    sx += X;
+    sxd += t;
+    sxdd = fmaf(t, dx, sxdd);
+    X *= R;
+    R *= q2;
+    dx += h;
+  }
+  m[0] += sx;
+  m[1] += sxdd;
+  m[2] = fmaf(dy * dy, sx, m[2]);
+  m[3] = fmaf(dy, sxd, m[3]);
+  m[4] += sxd;
+  m[5] = fmaf(dy, sx, m[5]);
 }
 // d loss / d (A, sigma, e1, e2, x_c, y_c) of one pixel, weight vb = d loss / d
 // (sub-ray value), from the moments.  With G = A/(2 pi) X:

@@ -764,10 +764,8 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
     // lens light at the same sub-ray positions (not lensed)
     for (int g = 0; g < S.n_gauss; ++g) {
       const LightG G = make_light(lensp + S.light_off + RTU_N_PER_GAUSS * g);
-      for (int a = 0; a < S.ss; ++a) {
-        const float y = fmaf((float)a, dxs, y0);
-        for (int c = 0; c < S.ss; ++c) acc += light_value(G, fmaf((float)c, dxs, x0), y);
-      }
+      const float q2 = light_q2(G, dxs);
+      for (int a = 0; a < S.ss; ++a) acc += light_row_sum(G, x0, fmaf((float)a, dxs, y0), dxs, q2, S.ss);
     }
     S.u[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] = acc * S.inv_ss2;
   }
@@ -961,10 +959,8 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
       for (int g = 0; g < S.n_gauss; ++g) {
         const LightG G = make_light(lensp + S.light_off + RTU_N_PER_GAUSS * g);
         float m[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, a[6];
-        for (int ai = 0; ai < S.ss; ++ai) {
-          const float y = fmaf((float)ai, dxs, y0);
-          for (int c = 0; c < S.ss; ++c) light_moments_add(G, fmaf((float)c, dxs, x0), y, m);
-        }
+        const float q2 = light_q2(G, dxs);
+        for (int ai = 0; ai < S.ss; ++ai) light_row_moments(G, x0, fmaf((float)ai, dxs, y0), dxs, q2, S.ss, m);
         light_vjp(G, vbl, m, a);
 #pragma unroll
         for (int k = 0; k < RTU_N_PER_GAUSS; ++k) {
