@@ -58,16 +58,32 @@ __device__ __forceinline__ float grad_at(const FitDev& F, int s, int i) {
 
 // Adam on (mu, rho) with the gradient of -ELBO:
 //   d/dmu_i  = mean_s g_si,   d/drho_i = mean_s g_si exp(rho_i) eps_si - 1
-__device__ __forceinline__ void adam_body(const FitDev& F, int t, int i) {
-  if (i >= F.dim) return;
-  const float sig = __expf(F.rho[i]);
+// A workgroup takes ADAM_P parameters; its ADAM_G groups of threads each sum
+// every ADAM_G-th sample of a parameter, and group 0 adds the group sums in
+// group order (so that more workgroups share the memory latency of the
+// S gradient and draw loads).  Called by every thread of the workgroup.
+__device__ __forceinline__ void adam_body(const FitDev& F, int t, int i, int g, float* red) {
+  const int p = threadIdx.x % ADAM_P;
   float gm = 0.f, gr = 0.f;
-#pragma unroll 8
-  for (int s = 0; s < F.S; ++s) {
-    const float g = grad_at(F, s, i);
-    gm += g;
-    gr += g * F.eps_s[(size_t)s * F.dim + i];
+  if (i < F.dim) {
+#pragma unroll 4
+    for (int s = g; s < F.S; s += ADAM_G) {
+      const float gs = grad_at(F, s, i);
+      gm += gs;
+      gr += gs * F.eps_s[(size_t)s * F.dim + i];
+    }
   }
+  red[g * ADAM_P + p] = gm;
+  red[(ADAM_G + g) * ADAM_P + p] = gr;
+  __syncthreads();
+  if (g != 0 || i >= F.dim) return;
+  gm = red[p];
+  gr = red[ADAM_G * ADAM_P + p];
+  for (int k = 1; k < ADAM_G; ++k) {
+    gm += red[k * ADAM_P + p];
+    gr += red[(ADAM_G + k) * ADAM_P + p];
+  }
+  const float sig = __expf(F.rho[i]);
   const float invS = 1.f / (float)F.S;
   gm *= invS;
   gr = gr * invS * sig - 1.f;
@@ -93,7 +109,6 @@ __device__ __forceinline__ bool fit_step(const FitDev& F, int round, int& step) 
 
 // The blocks of sample 0 also sum the guide's rho over their 256 parameters
 // (the ELBO's entropy term, before this step's update) into rho_part.
-constexpr int FIT_THREADS = 256;
 __global__ void __launch_bounds__(FIT_THREADS) kf_sample(const FitDev* __restrict__ fits,
                                                          const Task* __restrict__ tasks, int round,
                                                          const float* eps) {
@@ -121,11 +136,12 @@ __global__ void __launch_bounds__(FIT_THREADS) kf_sample(const FitDev* __restric
 // status words, each summed in a fixed order.
 __global__ void __launch_bounds__(FIT_THREADS) kf_adam(const FitDev* __restrict__ fits,
                                                        const Task* __restrict__ tasks, int round) {
-  const Task t = tasks[blockIdx.x];      // x fit, y parameter block
+  __shared__ float red[2 * FIT_THREADS];
+  const Task t = tasks[blockIdx.x];      // x fit, y block of ADAM_P parameters
   const FitDev& F = fits[t.x];
   int step;
   if (!fit_step(F, round, step)) return;
-  adam_body(F, step + 1, t.y * FIT_THREADS + threadIdx.x);
+  adam_body(F, step + 1, t.y * ADAM_P + threadIdx.x % ADAM_P, threadIdx.x / ADAM_P, red);
   if (t.y != 0 || threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
   const int nblk = (F.dim + FIT_THREADS - 1) / FIT_THREADS;

@@ -130,8 +130,8 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
       for (int r = 0; r < (h.want_grad ? 2 : 1); ++r) post.push_back(make_int4(si, b, r, 0));
     }
     const int nblk = (F.dim + 255) / 256;
+    for (int j = 0; j < (F.dim + ADAM_P - 1) / ADAM_P; ++j) param.push_back(make_int4(si, j, 0, 0));
     for (int j = 0; j < nblk; ++j) {
-      param.push_back(make_int4(si, j, 0, 0));
       for (int s = 0; s < S; ++s) samp.push_back(make_int4(si, j, s, 0));
     }
     fits.push_back(make_int4(si, 0, 0, 0));

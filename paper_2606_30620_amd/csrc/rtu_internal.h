@@ -20,6 +20,9 @@ constexpr int PREP_THREADS = 512;       // quantile selection and FFT workgroups
 constexpr int GRID_LDS_MAX = 64;        // n_src <= this: the ray adjoint keeps d loss / d s in LDS
 constexpr int FFT_LDS_MAX = 128 * 129;  // FFT line buffer (float2): 128 lines of 128 + 1 pad = 129 KB
 constexpr int KBAR = 4 * K;
+constexpr int FIT_THREADS = 256;        // fit kernels: sampling blocks of 256 parameters,
+constexpr int ADAM_P = 64;              // Adam blocks of 64 parameters x 4 sample groups
+constexpr int ADAM_G = FIT_THREADS / ADAM_P;
 
 // PSF on the matrix cores: K-steps of 4 per PSF row for 16 output columns
 // (at least 15 + KP window columns), the padded weight-row length, and the
