@@ -113,6 +113,28 @@ def test_lens_light_parity(n_sub_max, n_gauss):
     _check(p, range(2))
 
 
+def test_misaligned_latent_is_rejected():
+    """The latent is read four floats at a time: a pointer that is not 16-byte
+    aligned is refused on the host (RTU_EINVAL) before anything is launched."""
+    say("[gpu] misaligned latent pointer -> RTU_EINVAL")
+    from paper_2606_30620_amd import _lib, api
+    p = synth.make_problem("C1")
+    plan = api.plan_for_problem(p)
+    lens, ps, lat, nsub = api.device_inputs(p)
+    buf = torch.zeros(lat.numel() + 4, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    status = torch.empty(1, dtype=torch.int32, device="cuda")
+    L = _lib.LIB
+    vp = lambda t: t.data_ptr()
+    rc = L.rtu_loss_grad(plan._h, 1, vp(lens), None, vp(ps), buf.data_ptr() + 4, vp(loss), None, None, None,
+                         None, None, vp(status), None)
+    assert rc == _lib.RTU_EINVAL
+    rc = L.rtu_loss_grad(plan._h, 1, vp(lens), None, vp(ps), buf.data_ptr(), vp(loss), None, None, None,
+                         None, None, vp(status), None)
+    torch.cuda.synchronize()
+    assert rc == 0
+
+
 def test_large_source_grid_parity():
     say("[gpu] n_src=128 (grid read from global memory, chunked FFT): 80x80 ss=2 psf=21, batch 2")
     g = synth.Geometry(80, 0.06, 2, 128, 21, 0.85)
