@@ -429,28 +429,40 @@ __device__ __forceinline__ LightG make_light(const float* p) {
 // X(c) = 2^E(c) follows from X(c+1) = X(c) R(c), R(c+1) = R(c) Q2 with
 // R(0) = 2^(E(1) - E(0)) and Q2 = 2^(2 q1 h^2): two exponentials per row
 // instead of one per sub-ray (the relative rounding grows by about one unit
-// in the last place per step).  Q2 is per Gaussian and spacing.
+// in the last place per step).  Q2 is per Gaussian and spacing.  Where the
+// exponent's change along the row could leave 2^(+-60) (a component far
+// narrower than the sub-ray spacing), X would underflow while R overflows;
+// such a row takes one exponential per sub-ray instead.
 __device__ __forceinline__ float light_q2(const LightG& g, float h) {
   return __builtin_amdgcn_exp2f(2.f * g.q1 * h * h);
 }
-__device__ __forceinline__ void light_row_start(const LightG& g, float x0, float y, float h, float& X, float& R,
-                                                float& dx0, float& dy) {
+// Returns false when the row must take the direct exponentials.
+__device__ __forceinline__ bool light_row_start(const LightG& g, float x0, float y, float h, int cnt, float& X,
+                                                float& R, float& dx0, float& dy) {
   dx0 = x0 - g.xc;
   dy = y - g.yc;
   const float e0 = fmaf(g.q1 * dx0, dx0, fmaf(g.q2 * dy, dy, g.q3 * dx0 * dy));
   const float de = fmaf(g.q1, fmaf(2.f * dx0, h, h * h), g.q3 * dy * h);   // E(1) - E(0)
   X = __builtin_amdgcn_exp2f(e0);
   R = __builtin_amdgcn_exp2f(de);
+  return fabsf(de) + 2.f * fabsf(g.q1) * h * h * (float)cnt < 60.f;
+}
+__device__ __forceinline__ float light_exp_at(const LightG& g, float dx, float dy) {
+  return __builtin_amdgcn_exp2f(fmaf(g.q1 * dx, dx, fmaf(g.q2 * dy, dy, g.q3 * dx * dy)));
 }
 // sum over the row of the Gaussian's value
 __device__ __forceinline__ float light_row_sum(const LightG& g, float x0, float y, float h, float q2, int cnt) {
   float X, R, dx0, dy;
-  light_row_start(g, x0, y, h, X, R, dx0, dy);
+  const bool rec = light_row_start(g, x0, y, h, cnt, X, R, dx0, dy);
   float s = 0.f;
-  for (int c = 0; c < cnt; ++c) {
-    s += X;
-    X *= R;
-    R *= q2;
+  if (rec) {
+    for (int c = 0; c < cnt; ++c) {
+      s += X;
+      X *= R;
+      R *= q2;
+    }
+  } else {
+    for (int c = 0; c < cnt; ++c) s += light_exp_at(g, fmaf((float)c, h, dx0), dy);
   }
   return g.a2pi * s;
 }
@@ -460,9 +472,14 @@ __device__ __forceinline__ float light_row_sum(const LightG& g, float x0, float 
 __device__ __forceinline__ void light_row_moments(const LightG& g, float x0, float y, float h, float q2, int cnt,
                                                   float (&m)[6]) {
   float X, R, dx, dy;
-  light_row_start(g, x0, y, h, X, R, dx, dy);
+  const bool rec = light_row_start(g, x0, y, h, cnt, X, R, dx, dy);
   float sx = 0.f, sxd = 0.f, sxdd = 0.f;
+  const float dx0 = dx;
   for (int c = 0; c < cnt; ++c) {
+    if (!rec) {
+      dx = fmaf((float)c, h, dx0);
+      X = light_exp_at(g, dx, dy);
+    }
     const float t = X * dx;
     sx += X;
     sxd += t;

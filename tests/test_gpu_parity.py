@@ -113,6 +113,21 @@ def test_lens_light_parity(n_sub_max, n_gauss):
     _check(p, range(2))
 
 
+def test_lens_light_narrow_component_parity():
+    """A lens-light component much narrower than the sub-ray spacing (sigma =
+    0.004 arcsec against 0.02) makes the row recurrence's factors leave the
+    FP32 range; those rows take one exponential per sub-ray and the result
+    stays finite and equal to the oracle's."""
+    say("[gpu] lens light with a 0.004 arcsec component: 64x64 ss=3 n_src=32 psf=15, batch 2")
+    g = synth.Geometry(64, 0.06, 3, 32, 15, 1.0, n_gauss=2)
+    p = synth.make_problem("X", batch=2, seed=41, geom=g)
+    lens = p.lens.astype(np.float64)
+    lens[:, 7 + 6 + 1] = 0.004              # second component's sigma
+    lens[:, 7 + 6 + 4] = 0.3                # its centre, so that pixels lie on both sides
+    p.lens = lens.astype(np.float32)
+    _check(p, range(2))
+
+
 def test_misaligned_latent_is_rejected():
     """The latent is read four floats at a time: a pointer that is not 16-byte
     aligned is refused on the host (RTU_EINVAL) before anything is launched."""
