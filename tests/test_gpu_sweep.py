@@ -33,13 +33,14 @@ def _case(k):
 # Case 4 (24 x 24, 3 x 3 sub-rays, n_src = 128, rank-two 9-tap PSF, 3 lens-light
 # Gaussians, 52 masked pixels) ended its first GPU run with a memory fault;
 # cases 5-7 did not run after it.  Reading the kernels has not found the
-# cause yet, so the sweep stays off the GPU until it is found.
+# cause yet, so cases 4-7 stay off the GPU until it is found; cases 0-3
+# passed in that run.
 SKIP_REASON = ("case 4 ended its first GPU run with a memory fault whose cause is not found yet; "
                "cases 5-7 have not run")
 
 
-@pytest.mark.skip(reason=SKIP_REASON)
-@pytest.mark.parametrize("k", range(8))
+@pytest.mark.parametrize("k", [0, 1, 2, 3] + [pytest.param(k, marks=pytest.mark.skip(reason=SKIP_REASON))
+                                              for k in range(4, 8)])
 def test_sweep_parity(k):
     g, rank_two, seed = _case(k)
     say(f"[gpu] sweep {k}: {g.n_img}x{g.n_img} ss={g.supersample} n_src={g.n_src} psf={g.psf_size}"
