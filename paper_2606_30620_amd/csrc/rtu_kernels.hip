@@ -1176,11 +1176,21 @@ __device__ __forceinline__ void psf_dispatch(const SysDev& S, int b, int tile, i
   }
 }
 
+// Workgroup i of a launch of G is dispatched to XCD i mod 8.  This maps the
+// workgroups of XCD x to one contiguous range of the G work items (XCDs
+// below G mod 8 take one item more), so that neighbouring PSF tiles, whose
+// input halos overlap, read them through the same L2.  A bijection on [0, G).
+__device__ __forceinline__ int xcd_contiguous(int i, int G) {
+  const int x = i & 7, k = i >> 3, q = G >> 3, r = G & 7;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 __global__ void __launch_bounds__(PSF_THREADS) k_psf(SysDev S, int adjoint) {
   extern __shared__ __align__(16) float tilein[];
   __shared__ double red[2 * 4];
-  const int b = blockIdx.x / S.psf_tiles;
-  psf_dispatch(S, b, blockIdx.x - b * S.psf_tiles, adjoint, tilein, red);
+  const int w = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int b = w / S.psf_tiles;
+  psf_dispatch(S, b, w - b * S.psf_tiles, adjoint, tilein, red);
 }
 
 // ====================================================================== k_post
@@ -1619,7 +1629,7 @@ __global__ void __launch_bounds__(PSF_THREADS) kf_psf(const SysDev* __restrict__
                                                     int round, int adjoint) {
   extern __shared__ __align__(16) float tilein[];
   __shared__ double red[2 * 4];
-  const Task t = tasks[blockIdx.x];
+  const Task t = tasks[xcd_contiguous(blockIdx.x, gridDim.x)];
   const SysDev S = sys[t.x];
   if (!sys_active(S, round)) return;
   psf_dispatch(S, t.y, t.z, adjoint, tilein, red);
