@@ -111,15 +111,20 @@ int rtu_plan_create(const rtu_geometry* g, int32_t max_batch, int32_t device, rt
 /* Frees the plan and its device memory (synchronises the plan's device). */
 int rtu_plan_destroy(rtu_plan p);
 
-/* Observation of one lens system (host arrays, copied into the plan):
+/* Observation of one lens system (host arrays, read during the call only):
  * image[N*N] and noise_sigma[N*N] (sigma > 0) in data units, psf[K*K]
  * (applied as given, not renormalised), arc_mask[N*N] (nonzero = pixel
  * used to build the RTU grid; Sec. 2.2, the rays are traced from the
  * observed pixel centres, not supersampled).  Builds the masked pixel list
- * and the quantile ranks (h = (M-1) u_k, in FP64).  Synchronous.
- * RTU_EINVAL if a pointer is NULL. */
+ * and the quantile ranks (h = (M-1) u_k, in FP64) on the host, stages them
+ * with the observation in the plan's pinned buffer and queues one copy to the
+ * device on `stream`: evaluations queued after it on the same stream see the
+ * new observation.  No device-wide synchronisation; the call waits only, if
+ * the previous call's copy out of the staging buffer has not finished yet,
+ * for that copy.  The device region was sized for any mask when the plan was
+ * created, so nothing is reallocated.  RTU_EINVAL if a pointer is NULL. */
 int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma,
-                        const float* psf, const uint8_t* arc_mask);
+                        const float* psf, const uint8_t* arc_mask, void* stream);
 
 /* Number of masked pixels M of the current observation (-1 if none). */
 int32_t rtu_masked_count(rtu_plan p);

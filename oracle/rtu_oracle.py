@@ -67,24 +67,59 @@ def q_phi_from_e(e1, e2):
     return (1.0 - e) / (1.0 + e), 0.5 * torch.atan2(e2, e1), e
 
 
+E_SERIES = 1e-3     # below this |(e1, e2)| the SIE is summed as its series about the SIS
+
+
 def sie_deflection(x, y, theta_e, e1, e2, x0, y0):
     """Deflection of the EPL of App. A.1, eq. (A1), at slope gamma = 2 (singular
     isothermal ellipsoid): kappa = (theta_E / 2) / rho, rho^2 = q x'^2 + y'^2 / q in
     the frame rotated by phi about (x0, y0).  Closed form with f = sqrt(1 - q^2),
     psi = sqrt(q^2 x'^2 + y'^2):
         a'_x = theta_E sqrt(q)/f atan(f x'/psi),  a'_y = theta_E sqrt(q)/f atanh(f y'/psi),
-    rotated back by phi."""
-    q, phi, e = q_phi_from_e(e1, e2)
-    c, s = torch.cos(phi), torch.sin(phi)
+    rotated back by phi.
+
+    For a nearly round lens (|e| < E_SERIES) the position angle is ill defined
+    and the closed form divides by f -> 0; there the same deflection is written
+    without any angle.  With complex positions z = (x - x0) + i (y - y0) and
+    ellipticity eps = e1 + i e2, the frame change and the elliptical angle
+    combine into u = m/|m|, m = z - eps conj(z), and the deflection is
+        alpha = theta_E sqrt(1 - |eps|^2) u G(conj(eps) u^2),
+        G(w) = atan(sqrt w)/sqrt w = sum_k (-w)^k / (2k + 1)
+    (the hypergeometric form of the elliptical power law of Tessore & Metcalf
+    2015 at slope 2, with e^{2 i phi} absorbed into eps), summed as its series
+    (|w| = |eps| < E_SERIES: eight terms reach 1e-24).  At eps = 0 it is the
+    singular isothermal sphere theta_E z/|z|, and it is smooth in (e1, e2).
+
+    A ray exactly on the lens centre (psi = 0), where the direction of the
+    deflection is undefined, is not deflected (alpha = 0, the value the
+    symmetric limit averages to)."""
     dx, dy = x - x0, y - y0
-    xp = c * dx + s * dy
-    yp = -s * dx + c * dy
-    f = 2.0 * torch.sqrt(e) / (1.0 + e)          # = sqrt(1 - q^2) without cancellation
-    psi = torch.sqrt(q * q * xp * xp + yp * yp)
-    pref = theta_e * torch.sqrt(q) / f
-    axp = pref * torch.atan(f * xp / psi)
-    ayp = pref * torch.atanh(f * yp / psi)
-    return c * axp - s * ayp, s * axp + c * ayp
+    centre = (dx == 0) & (dy == 0)
+    # stand-in position for rays on the centre: keeps every branch finite
+    dx = torch.where(centre, torch.ones_like(dx), dx)
+    dy = torch.where(centre, torch.zeros_like(dy), dy)
+    if float(torch.hypot(e1.detach(), e2.detach())) >= E_SERIES:
+        q, phi, e = q_phi_from_e(e1, e2)
+        c, s = torch.cos(phi), torch.sin(phi)
+        xp = c * dx + s * dy
+        yp = -s * dx + c * dy
+        f = 2.0 * torch.sqrt(e) / (1.0 + e)          # = sqrt(1 - q^2) without cancellation
+        psi = torch.sqrt(q * q * xp * xp + yp * yp)
+        pref = theta_e * torch.sqrt(q) / f
+        axp = pref * torch.atan(f * xp / psi)
+        ayp = pref * torch.atanh(f * yp / psi)
+        ax, ay = c * axp - s * ayp, s * axp + c * ayp
+    else:
+        z = torch.complex(dx, dy)
+        eps = torch.complex(e1 * torch.ones_like(dx), e2 * torch.ones_like(dx))
+        m = z - eps * z.conj()
+        u = m / m.abs()
+        w = eps.conj() * u * u
+        G = sum((-w) ** k / (2 * k + 1) for k in range(8))
+        a = theta_e * torch.sqrt(1.0 - (e1 * e1 + e2 * e2)) * u * G
+        ax, ay = a.real, a.imag
+    zero = torch.zeros_like(ax)
+    return torch.where(centre, zero, ax), torch.where(centre, zero, ay)
 
 
 def shear_deflection(x, y, g1, g2):
@@ -130,12 +165,14 @@ def nfw_deflection(x, y, ks, rs, xs, ys, tau: float = 0.0):
     With tau > 0 the projected mass is frozen beyond X = tau (hard truncation:
     h(min(X, tau)))."""
     dx, dy = x - xs, y - ys
+    centre = (dx == 0) & (dy == 0)       # a ray on the subhalo centre is not deflected
+    dx = torch.where(centre, torch.ones_like(dx), dx)
     r = torch.sqrt(dx * dx + dy * dy)
     X = r / rs
     Xh = torch.clamp(X, max=tau) if tau > 0 else X
-    Xs = torch.clamp(X, min=1e-300)
     # alpha_vec = 4 ks rs h(X)/X * d/|d| = 4 ks rs^2 h(X) d / r^2
-    fac = 4.0 * ks * rs * nfw_h(torch.clamp(Xh, min=1e-300)) / (Xs * torch.clamp(r, min=1e-300))
+    fac = 4.0 * ks * rs * nfw_h(Xh) / (X * r)
+    fac = torch.where(centre, torch.zeros_like(fac), fac)
     return fac * dx, fac * dy
 
 
@@ -198,17 +235,25 @@ def standardise(bx, by):
     return mx, my, s
 
 
-def quantiles_type7(z, u):
+def quantiles_type7(z, u, picks=None):
     """App. C step (ii): the eCDF by sorting, and its inverse between the sorted
     positions by linear interpolation (Sec. 2.2, App. C first paragraph):
     h = (M-1) u, j = floor h, Q(u) = (1 - (h-j)) z_(j) + (h-j) z_(j+1).
     Ties are ordered by ray index (stable sort).  Returns Q and the sorted
-    positions' original indices at j and j+1."""
+    positions' original indices at j and j+1.
+
+    picks = (i0, i1), ray indices standing in for the order statistics at j and
+    j + 1: where two rays are closer than the rounding of an evaluation,
+    another evaluation may order them the other way; with its picks the same
+    formula gives the quantiles and their derivatives for that order."""
     M = z.shape[0]
-    zs, order = torch.sort(z, stable=True)
     h = (M - 1) * u
     j = torch.floor(h).long()
     t = h - j.to(DT)
+    if picks is not None:
+        i0, i1 = (torch.as_tensor(np.asarray(p), dtype=torch.long) for p in picks)
+        return (1.0 - t) * z[i0] + t * z[i1], i0, i1
+    zs, order = torch.sort(z, stable=True)
     j1 = torch.clamp(j + 1, max=M - 1)
     q = (1.0 - t) * zs[j] + t * zs[j1]
     return q, order[j], order[j1]
@@ -265,16 +310,18 @@ def cdf_spline(z, X, S, u):
     return torch.where(k == 0, g_lo, torch.where(k >= K, g_hi, g_in))
 
 
-def build_transform(bxm, bym, K: int = K_NODES):
+def build_transform(bxm, bym, K: int = K_NODES, picks=None):
     """RTU transform from the masked rays (Sec. 2.2; App. C steps i-iv).
     Returns a dict with mu, s, knots X[2][K], slopes S[2][K], nodes u, the
-    selected ray indices and the status bits."""
+    selected ray indices and the status bits.  picks (optional, per axis the
+    pair (i0, i1) of quantiles_type7) fixes which rays stand for the order
+    statistics."""
     u = chebyshev_nodes(K)
     mx, my, s = standardise(bxm, bym)
     out = {"u": u, "mu": (mx, my), "s": s, "status": 0}
     X, S, idx = [], [], []
-    for zc in ((bxm - mx) / s, (bym - my) / s):
-        q, i0, i1 = quantiles_type7(zc, u)
+    for ax, zc in enumerate(((bxm - mx) / s, (bym - my) / s)):
+        q, i0, i1 = quantiles_type7(zc, u, None if picks is None else picks[ax])
         dp = qf_polynomial(q, u)
         # X_k = p(u_k) equals q_k exactly (interpolation); q_k is used directly.
         eps = 1e-6 * (q[-1] - q[0]).detach()
@@ -374,7 +421,7 @@ def psf_convolve(u, psf):
 
 
 def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=False, cell_shift=0.0,
-            round32=False):
+            round32=False, picks=None):
     """One evaluation of the lens model.
 
     obs: dict with n_img, pix, ss, image[N,N], sigma[N,N], psf[K,K], mask[N,N],
@@ -386,7 +433,8 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
     grid, Sec. 2.1).
     round32: round the ray positions, the knots and slopes and the grid
     positions to binary32 (a model of an evaluation that shoots rays and
-    evaluates the spline in binary32 with the quantile fit in binary64)."""
+    evaluates the spline in binary32 with the quantile fit in binary64).
+    picks: the masked rays standing for the order statistics (build_transform)."""
     N, pix, ss = obs["n_img"], obs["pix"], obs["ss"]
     r32 = (lambda t: t.float().to(DT)) if round32 else (lambda t: t)
     status = 0
@@ -412,7 +460,7 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
     tr = None
     if uniform_box is None:
         bxm, bym = ray_shoot(xc[mflat], yc[mflat], lens, n_sub, tau)
-        tr = build_transform(r32(bxm), r32(bym))
+        tr = build_transform(r32(bxm), r32(bym), picks=picks)
         status |= tr["status"]
         if round32:
             tr["X"] = [r32(x) for x in tr["X"]]
@@ -450,14 +498,15 @@ def obs_from_problem(p) -> dict:
             "n_gauss": getattr(g, "n_gauss", 0)}
 
 
-def loss_grad(lens, ps, w, obs, n_sub=0, tau=0.0, want_grad=True, return_all=False, cell_shift=0.0):
+def loss_grad(lens, ps, w, obs, n_sub=0, tau=0.0, want_grad=True, return_all=False, cell_shift=0.0,
+              picks=None):
     """Loss = chi^2/2 + |w|^2/2 (Gaussian likelihood over all pixels, N(0,1)
     prior on the latent) and its exact gradient with respect to the lens
     parameters, the power-spectrum parameters and the latent field."""
     lens = _t(lens).clone().requires_grad_(want_grad)
     ps = _t(ps).clone().requires_grad_(want_grad)
     w = _t(w).clone().requires_grad_(want_grad)
-    out = forward(lens, ps, w, obs, n_sub, tau, return_all=return_all, cell_shift=cell_shift)
+    out = forward(lens, ps, w, obs, n_sub, tau, return_all=return_all, cell_shift=cell_shift, picks=picks)
     res = {k: v for k, v in out.items()}
     if want_grad:
         gl, gp, gw = torch.autograd.grad(out["loss"], (lens, ps, w), allow_unused=True)
@@ -470,13 +519,13 @@ def loss_grad(lens, ps, w, obs, n_sub=0, tau=0.0, want_grad=True, return_all=Fal
     return res
 
 
-def loss_grad_problem(p, b: int, want_grad=True, return_all=False):
+def loss_grad_problem(p, b: int, want_grad=True, return_all=False, picks=None):
     """loss_grad for sample b of a problem from the seeded input generator."""
     obs = obs_from_problem(p)
     ns = int(p.n_sub[b])
     return loss_grad(p.lens[b].astype(np.float64), p.ps[b].astype(np.float64),
                      p.latent[b].astype(np.float64), obs, ns, p.geom.tnfw_tau,
-                     want_grad=want_grad, return_all=return_all)
+                     want_grad=want_grad, return_all=return_all, picks=picks)
 
 
 def position_rounding_bound(lens, ps, w, obs, n_sub=0, tau=0.0):

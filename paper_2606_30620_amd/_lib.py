@@ -14,8 +14,7 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# RTU_LIB may point at another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("RTU_LIB") or os.path.join(HERE, "librtu.so")
+LIB_PATH = os.path.join(HERE, "librtu.so")
 
 RTU_OK = 0
 RTU_EINVAL, RTU_ENOMEM, RTU_EBATCH, RTU_EHIP, RTU_ESTATE, RTU_ENOTFOUND = -1, -2, -3, -4, -5, -6
@@ -61,7 +60,7 @@ def _load():
     lib.rtu_workspace_bytes.restype = SZ
     lib.rtu_plan_create.argtypes = [C.POINTER(Geometry), I32, I32, C.POINTER(P)]
     lib.rtu_plan_destroy.argtypes = [P]
-    lib.rtu_set_observation.argtypes = [P, VP, VP, VP, VP]
+    lib.rtu_set_observation.argtypes = [P, VP, VP, VP, VP, VP]
     lib.rtu_masked_count.argtypes = [P]
     lib.rtu_masked_count.restype = I32
     lib.rtu_loss_grad.argtypes = [P, I32] + [VP] * 11 + [VP]
@@ -171,7 +170,8 @@ class Plan:
     def masked_count(self) -> int:
         return LIB.rtu_masked_count(self._h)
 
-    def set_observation(self, image, noise_sigma, psf, mask) -> None:
+    def set_observation(self, image, noise_sigma, psf, mask, stream=None) -> None:
+        """Queue the observation's upload on `stream` (default: torch's current)."""
         a = np.ascontiguousarray(image, dtype=np.float32)
         s = np.ascontiguousarray(noise_sigma, dtype=np.float32)
         k = np.ascontiguousarray(psf, dtype=np.float32)
@@ -179,7 +179,8 @@ class Plan:
         n = self.geom.n_img
         assert a.size == n * n and s.size == n * n and m.size == n * n
         assert k.size == self.geom.psf_size ** 2
-        check(LIB.rtu_set_observation(self._h, _ptr(a), _ptr(s), _ptr(k), _ptr(m)), "rtu_set_observation")
+        check(LIB.rtu_set_observation(self._h, _ptr(a), _ptr(s), _ptr(k), _ptr(m), _stream_ptr(stream)),
+              "rtu_set_observation")
 
     def loss_grad(self, lens, ps, latent, n_sub=None, *, loss, status, chi2_mask=None, grad_lens=None,
                   grad_ps=None, grad_latent=None, model=None, stream=None) -> None:

@@ -51,12 +51,21 @@ __device__ __forceinline__ SoftplusTerms softplus_terms(float x) {
 // ------------------------------------------------------------------ SIE + shear
 // Per-sample constants of the singular isothermal ellipsoid (eq. A1 at slope 2)
 // kappa = (theta_E/2) / sqrt(q x'^2 + y'^2/q) and of the external shear.
+// Below this |(e1, e2)| the gradient with respect to the lens parameters is
+// formed without the position angle (sie_vjp_round): the angle is undefined at
+// e = 0, and its derivative terms cancel to O(e) in FP32 near it.
+constexpr float E_ROUND = 0.02f;
+
 struct Sie {
   float the, x0, y0, g1, g2;
   float c, s;        // cos, sin of the position angle phi = atan2(e2, e1)/2
   float q, f, P;     // axis ratio, f = sqrt(1-q^2), P = theta_E sqrt(q)
   float invf;        // 1/f
   float e1, e2, e;
+  bool round;        // e < E_ROUND: the angle-free gradient
+  float cpe, spe;    // c/(1+e), s/(1+e)
+  float cq, sq;      // c q, s q
+  float im2f;        // 1/(1+e)^2
 };
 
 __device__ __forceinline__ Sie make_sie(const float* L) {
@@ -69,6 +78,11 @@ __device__ __forceinline__ Sie make_sie(const float* L) {
   o.f = 2.f * sqrtf(o.e) / (1.f + o.e);   // sqrt(1 - q^2) without cancellation
   o.P = o.the * sqrtf(o.q);
   o.invf = o.f > 0.f ? 1.f / o.f : 0.f;
+  o.round = o.e < E_ROUND;
+  const float ie = 1.f / (1.f + o.e);
+  o.cpe = o.c * ie; o.spe = o.s * ie;
+  o.cq = o.c * o.q; o.sq = o.s * o.q;
+  o.im2f = ie * ie;
   return o;
 }
 
@@ -194,6 +208,57 @@ struct SieAcc {
   __device__ __forceinline__ void zero() { P = q = f = phi = x0 = y0 = g1 = g2 = 0.f; }
 };
 
+// The SIE part of the vector-Jacobian product for a nearly round lens, with
+// no position angle.  In complex notation (z = (x - x0) + i (y - y0), eps =
+// e1 + i e2, abar = d loss/d alpha_x + i d loss/d alpha_y) the deflection is
+//   alpha = K u G(w),  K = theta_E sqrt(1 - e^2),  m = z - eps conj(z),
+//   u = m/|m|,  w = conj(eps) u^2,  G(w) = atan(sqrt w)/sqrt w
+// (the elliptical power law in the hypergeometric form of Tessore & Metcalf
+// 2015 at slope 2).  Since |u| = 1, du = i u Im(dm/m), and
+//   d(u G) = tau_r Im(dm/m) + u^3 G'(w) d conj(eps),  tau_r = i u (G + 2 w G'),
+// with dm = -conj(z) d eps - d z0 + eps d conj(z0).  Per ray this adds, without
+// the factor K (applied once per sample by sie_grad_one):
+//   P <- Re(conj(abar) H), H = u G (so d loss/d theta_E = sqrt(1-e^2) P),
+//   q <- d/d e1, f <- d/d e2, x0, y0 <- d/d x0, y0 (phi stays 0).
+// u G is the closed-form deflection already computed (E.A, E.B rotated back,
+// divided by K), u = R(phi) (q a, b); |m| = psi (1 + e); G' is the series
+// sum_{k>=1} (-1)^k k w^(k-1)/(2k+1), |w| = e < E_ROUND (five terms: 2e-9).
+__device__ __forceinline__ void sie_vjp_round(const Sie& L, const SieRay& E, float x, float y, float abx,
+                                              float aby, SieAcc& acc) {
+  const float Hx = L.cpe * E.A - L.spe * E.B, Hy = L.spe * E.A + L.cpe * E.B;
+  const float ux = L.cq * E.a - L.s * E.b, uy = L.sq * E.a + L.c * E.b;
+  const float u2x = ux * ux - uy * uy, u2y = 2.f * ux * uy;
+  const float wx = L.e1 * u2x + L.e2 * u2y, wy = L.e1 * u2y - L.e2 * u2x;
+  const float Gx = Hx * ux + Hy * uy, Gy = Hy * ux - Hx * uy;        // H conj(u)
+  float px = -5.f / 11.f, py = 0.f;                                  // G'(w), Horner
+  {
+    constexpr float cf[4] = {4.f / 9.f, -3.f / 7.f, 2.f / 5.f, -1.f / 3.f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float tx = px * wx - py * wy + cf[k], ty = px * wy + py * wx;
+      px = tx; py = ty;
+    }
+  }
+  const float g2x = Gx + 2.f * (wx * px - wy * py), g2y = Gy + 2.f * (wx * py + wy * px);
+  const float ugx = ux * g2x - uy * g2y, ugy = ux * g2y + uy * g2x;
+  const float tau = -abx * ugy + aby * ugx;                          // Re(conj(abar) i u g2)
+  const float u3x = u2x * ux - u2y * uy, u3y = u2x * uy + u2y * ux;
+  const float sx = u3x * px - u3y * py, sy = u3x * py + u3y * px;    // u^3 G'
+  const float sgx = abx * sx + aby * sy, sgy = abx * sy - aby * sx;  // conj(abar) u^3 G'
+  const float dx = x - L.x0, dy = y - L.y0;
+  const float mx = (1.f - L.e1) * dx - L.e2 * dy, my = (1.f + L.e1) * dy - L.e2 * dx;
+  const float im2 = E.ip * E.ip * L.im2f;                            // 1/|m|^2
+  const float zmx = dx * mx - dy * my, zmy = dx * my + dy * mx;       // z m
+  const float zbmx = zmx * im2, zbmy = -zmy * im2;                    // conj(z)/m
+  const float imx = mx * im2, imy = -my * im2;                        // 1/m
+  const float emx = (L.e1 * mx + L.e2 * my) * im2, emy = (L.e2 * mx - L.e1 * my) * im2;   // eps/m
+  acc.P += abx * Hx + aby * Hy;
+  acc.q += sgx - tau * zbmy;
+  acc.f += sgy - tau * zbmx;
+  acc.x0 += tau * (emy - imy);
+  acc.y0 -= tau * (imx + emx);
+}
+
 // Given d loss / d alpha at (x, y) and the ray's SIE intermediates, accumulate
 // d loss / d (internal SIE quantities) and the shear gradient.
 __device__ __forceinline__ void sie_shear_vjp(const Sie& L, const SieRay& E, float x, float y, float abx,
@@ -204,6 +269,10 @@ __device__ __forceinline__ void sie_shear_vjp(const Sie& L, const SieRay& E, flo
   const float m = E.ok ? 1.f : 0.f;
   abx *= m;
   aby *= m;
+  if (L.round) {   // one lens per workgroup: uniform
+    sie_vjp_round(L, E, x, y, abx, aby, acc);
+    return;
+  }
   const float axp = L.P * E.A, ayp = L.P * E.B;
   // rotation alpha = R(phi) alpha': d/dphi R(phi) alpha' = (-alpha_y, alpha_x) of the SIE part
   const float rx = L.c * axp - L.s * ayp, ry = L.s * axp + L.c * ayp;
@@ -226,8 +295,22 @@ __device__ __forceinline__ void sie_shear_vjp(const Sie& L, const SieRay& E, flo
 
 // Convert summed accumulators (double) to d loss / d (theta_E, e1, e2, x0, y0, g1, g2).
 // Component q < 7 of the lens gradient from the SIE and shear sums a (the
-// same chain as sie_grad, one output).
+// same chain as sie_grad, one output).  A nearly round lens summed the
+// angle-free terms of sie_vjp_round: theta_E enters through K = theta_E
+// sqrt(1 - e^2) alone.
 __device__ __forceinline__ double sie_grad_one(const Sie& L, const double* a, int q) {
+  if (L.round) {
+    const double ee = (double)L.e1 * L.e1 + (double)L.e2 * L.e2, r = sqrt(1.0 - ee);
+    const double K = (double)L.the * r;
+    switch (q) {
+      case 0: return a[0] * r;
+      case 1: return K * a[1] - a[0] * (double)L.the * (double)L.e1 / r;
+      case 2: return K * a[2] - a[0] * (double)L.the * (double)L.e2 / r;
+      case 3: return K * a[4];
+      case 4: return K * a[5];
+      default: return a[q + 1];
+    }
+  }
   if (q == 0) return a[0] * sqrt((double)L.q);
   if (q >= 3) return a[q + 1];
   const double sq = sqrt((double)L.q);
@@ -240,6 +323,10 @@ __device__ __forceinline__ double sie_grad_one(const Sie& L, const double* a, in
   return q == 1 ? eb * e1 / e - a[3] * e2 / (2.0 * e * e) : eb * e2 / e + a[3] * e1 / (2.0 * e * e);
 }
 __device__ __forceinline__ void sie_grad(const Sie& L, const double* a, double* g) {
+  if (L.round) {
+    for (int q = 0; q < 7; ++q) g[q] = sie_grad_one(L, a, q);
+    return;
+  }
   // a: P, q, f, phi, x0, y0, g1, g2
   const double sq = sqrt((double)L.q);
   const double e = (double)L.e;

@@ -29,8 +29,11 @@ struct rtu_plan_s {
   int device = 0;
   SysDev h;                       // geometry, observation and workspace pointers
   char* pool = nullptr;           // workspace allocation (independent of M)
-  char* obs_pool = nullptr;       // observation + M-dependent buffers
+  char* obs_pool = nullptr;       // observation + M-dependent buffers, sized for M = N^2
+  char* stage = nullptr;          // pinned host image of the observation region (one copy per call)
   size_t obs_bytes = 0;
+  hipEvent_t stage_done = nullptr;   // the last copy out of `stage` has finished
+  bool stage_pending = false;
   int M = -1;
   SysDev last;                    // descriptor of the last evaluation (debug fetch)
   bool have_last = false;
@@ -351,7 +354,17 @@ int rtu_plan_create(const rtu_geometry* g, int32_t max_batch, int32_t device, rt
   p->device = device;
   fill_geometry(g, p->h);
   const size_t bytes = carve_workspace(p->h, max_batch, nullptr);
-  if (hipMalloc(&p->pool, bytes) != hipSuccess) {
+  // the observation region for any mask (M <= N^2), so that a new observation
+  // never reallocates
+  SysDev tmp = p->h;
+  p->obs_bytes = carve_observation(tmp, max_batch, g->n_img * g->n_img, nullptr);
+  if (hipMalloc(&p->pool, bytes) != hipSuccess || hipMalloc(&p->obs_pool, p->obs_bytes) != hipSuccess ||
+      hipHostMalloc(&p->stage, p->obs_bytes, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&p->stage_done, hipEventDisableTiming) != hipSuccess) {
+    if (p->pool) (void)hipFree(p->pool);
+    if (p->obs_pool) (void)hipFree(p->obs_pool);
+    if (p->stage) (void)hipHostFree(p->stage);
+    if (p->stage_done) (void)hipEventDestroy(p->stage_done);
     delete p;
     return RTU_ENOMEM;
   }
@@ -366,31 +379,44 @@ int rtu_plan_destroy(rtu_plan p) {
   (void)hipDeviceSynchronize();
   if (p->pool) (void)hipFree(p->pool);
   if (p->obs_pool) (void)hipFree(p->obs_pool);
+  if (p->stage) (void)hipHostFree(p->stage);
+  if (p->stage_done) (void)hipEventDestroy(p->stage_done);
   for (hipEvent_t e : p->prof.ev) (void)hipEventDestroy(e);
   delete p;
   return RTU_OK;
 }
 
 int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma, const float* psf,
-                        const uint8_t* arc_mask) {
+                        const uint8_t* arc_mask, void* stream) {
   if (!p || !image || !noise_sigma || !psf || !arc_mask) return RTU_EINVAL;
   if (hipSetDevice(p->device) != hipSuccess) return RTU_EHIP;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   ObsHost o;
   prepare_observation(&p->g, noise_sigma, psf, arc_mask, o);
   const int M = (int)o.idx.size();
-  SysDev h = p->h;
-  const size_t bytes = carve_observation(h, p->max_batch, M, nullptr);
-  if (bytes > p->obs_bytes) {
-    (void)hipDeviceSynchronize();
-    if (p->obs_pool) (void)hipFree(p->obs_pool);
-    p->obs_pool = nullptr;
-    p->obs_bytes = 0;
-    if (hipMalloc(&p->obs_pool, bytes) != hipSuccess) return RTU_ENOMEM;
-    p->obs_bytes = bytes;
-  }
+  // the pinned staging buffer still feeds the previous call's copy until its
+  // event has passed (that copy only: no other work is waited for)
+  if (p->stage_pending && hipEventSynchronize(p->stage_done) != hipSuccess) return RTU_EHIP;
+  p->stage_pending = false;
+  // the observation region laid out in the staging buffer exactly as on the
+  // device (same offsets), filled, then sent in one asynchronous copy
+  SysDev hs = p->h, h = p->h;
+  carve_observation(hs, p->max_batch, M, p->stage);
   carve_observation(h, p->max_batch, M, p->obs_pool);
-  if (upload_observation(h, image, psf, arc_mask, o, nullptr) != hipSuccess) return RTU_EHIP;
-  if (hipDeviceSynchronize() != hipSuccess) return RTU_EHIP;
+  const size_t N2 = (size_t)h.n_img * h.n_img, kw = (size_t)h.psf_k * psf_ws(h.psf_k);
+  memcpy(const_cast<float*>(hs.image), image, N2 * 4);
+  memcpy(const_cast<float*>(hs.inv_var), o.inv_var.data(), N2 * 4);
+  memcpy(const_cast<float*>(hs.psf_flip), o.wfwd.data(), kw * 4);
+  memcpy(const_cast<float*>(hs.psf), o.wadj.data(), kw * 4);
+  memcpy(const_cast<float*>(hs.psf_sep), o.wsep.data(), o.wsep.size() * 4);
+  memcpy(const_cast<uint8_t*>(hs.mask), arc_mask, N2);
+  if (M) memcpy(const_cast<int*>(hs.mask_idx), o.idx.data(), (size_t)M * 4);
+  memcpy(const_cast<int*>(hs.rank_j), o.rank_j, sizeof(o.rank_j));
+  memcpy(const_cast<double*>(hs.rank_t), o.rank_t, sizeof(o.rank_t));
+  const size_t bytes = (size_t)(reinterpret_cast<const char*>(h.zbuf) - p->obs_pool);
+  if (hipMemcpyAsync(p->obs_pool, p->stage, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return RTU_EHIP;
+  if (hipEventRecord(p->stage_done, s) != hipSuccess) return RTU_EHIP;
+  p->stage_pending = true;
   h.M = M;
   h.psf_rank1 = o.rank1 ? 1 : 0;
   p->h = h;

@@ -187,3 +187,107 @@ def test_nfw_series_switch_continuity():
     for x0 in [0.5, (1 - 1e-3) / (1 + 1e-3), (1 + 1e-3) / (1 - 1e-3)]:
         lo, hi = O.nfw_h(T([x0 * (1 - 1e-13), x0 * (1 + 1e-13)]))
         assert abs(float(hi) - float(lo)) < 1e-12 * abs(float(lo))
+
+
+# ---------------------------------------------------------------- round lens, lens centre
+def _first_order_sie(x, y, the, e1, e2):
+    """First order in the ellipticity about the singular isothermal sphere,
+    derived by hand from the closed form (q = 1 - 2e, f^2 = 4e, psi = r (1 - 2e
+    cos^2 t') to first order, rotated back): with zeta = z/|z| and eps = e1 + i e2,
+        alpha/theta_E = zeta - eps conj(zeta)/2 + conj(eps) zeta^3/6 + O(e^2)."""
+    z = np.asarray(x) + 1j * np.asarray(y)
+    zeta = z / np.abs(z)
+    eps = e1 + 1j * e2
+    a = the * (zeta - 0.5 * eps * np.conj(zeta) + np.conj(eps) * zeta ** 3 / 6.0)
+    return a.real, a.imag
+
+
+@pytest.mark.parametrize("e", [2e-4, 4e-3])
+def test_sie_near_round_lens_matches_first_order_expansion(e):
+    """Both evaluations (the series below E_SERIES, the closed form above it)
+    leave a residual against the hand-derived first-order expansion that
+    shrinks as e^2: a dropped or wrong first-order term would leave O(e)."""
+    x = np.array([0.3, -1.2, 0.7, 1.5, -0.4])
+    y = np.array([1.1, 0.4, -0.9, -0.2, -1.3])
+    res = []
+    for scale in (1.0, 0.5):
+        ang = 0.7
+        e1, e2 = scale * e * math.cos(ang), scale * e * math.sin(ang)
+        ax, ay = O.sie_deflection(T(x), T(y), T(1.3), T(e1), T(e2), T(0.0), T(0.0))
+        rx, ry = _first_order_sie(x, y, 1.3, e1, e2)
+        res.append(max(np.abs(ax.numpy() - rx).max(), np.abs(ay.numpy() - ry).max()))
+    assert res[0] < 3.0 * e * e
+    assert 3.0 < res[0] / res[1] < 5.0       # O(e^2): halving e quarters the residual
+
+
+def test_sie_series_and_closed_form_agree_at_the_switch():
+    x, y = T([0.3, -1.2, 0.7, 1e-3]), T([1.1, 0.4, -0.9, 2e-3])
+    for ang in (0.3, 2.0, -1.1):
+        lo = O.sie_deflection(x, y, T(1.2), T(O.E_SERIES * (1 - 1e-9) * math.cos(ang)),
+                              T(O.E_SERIES * (1 - 1e-9) * math.sin(ang)), T(0.01), T(-0.02))
+        hi = O.sie_deflection(x, y, T(1.2), T(O.E_SERIES * (1 + 1e-9) * math.cos(ang)),
+                              T(O.E_SERIES * (1 + 1e-9) * math.sin(ang)), T(0.01), T(-0.02))
+        for a, b in zip(lo, hi):
+            assert float((a - b).abs().max()) < 1e-11
+
+
+def test_sie_series_matches_schramm_integral_for_a_nearly_round_lens():
+    e = 2e-4
+    q = (1 - e) / (1 + e)
+    for x, y in [(0.4, 1.1), (-1.3, 0.2), (0.05, -0.7)]:
+        ax, ay = O.sie_deflection(T(x), T(y), T(1.1), T(e), T(0.0), T(0.0), T(0.0))
+        rx, ry = schramm_alpha(x, y, 1.1, q)
+        assert abs(float(ax) - rx) < 1e-10 and abs(float(ay) - ry) < 1e-10
+
+
+def test_round_lens_gradient_is_finite_and_matches_central_differences():
+    """At e1 = e2 = 0 the position angle is undefined, but the deflection is
+    smooth in (e1, e2): the gradient exists and equals central differences
+    (which straddle e = 0)."""
+    x, y = T([0.3, -1.2, 0.7, 1e-3]), T([1.1, 0.4, -0.9, 2e-3])
+    wx, wy = T([1.0, 2.0, 3.0, 4.0]), T([-1.0, 0.5, 2.0, 1.0])
+
+    def f(p):
+        ax, ay = O.sie_deflection(x, y, p[0], p[1], p[2], p[3], p[4])
+        return (ax * wx + ay * wy).sum()
+
+    p = T([1.2, 0.0, 0.0, 0.01, -0.02]).requires_grad_(True)
+    (g,) = torch.autograd.grad(f(p), p)
+    assert bool(torch.isfinite(g).all())
+    h = 1e-6
+    for i in range(5):
+        pp, pm = p.detach().clone(), p.detach().clone()
+        pp[i] += h
+        pm[i] -= h
+        fd = (float(f(pp)) - float(f(pm))) / (2 * h)
+        assert abs(float(g[i]) - fd) < 1e-7 * max(1.0, abs(fd)), (i, float(g[i]), fd)
+
+
+def test_lens_equation_sign_on_the_einstein_ring():
+    """beta = theta - alpha: for a singular isothermal sphere a ray on the
+    Einstein ring maps to the source-plane origin, and a ray at 2 theta_E to
+    theta_E along the same direction."""
+    the = 1.3
+    lens = T([the, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    ang = torch.linspace(0, 2 * math.pi, 9, dtype=torch.float64)[:-1]
+    for rad, expect in ((the, 0.0), (2 * the, the)):
+        bx, by = O.ray_shoot(rad * torch.cos(ang), rad * torch.sin(ang), lens)
+        assert torch.allclose(bx, expect * torch.cos(ang), atol=1e-13)
+        assert torch.allclose(by, expect * torch.sin(ang), atol=1e-13)
+    # off-centre lens: the same about its centre
+    lens = T([the, 0.1, -0.05, 0.2, -0.3, 0.0, 0.0])
+    bx, by = O.ray_shoot(T([0.2]), T([-0.3]), lens)
+    assert float(bx) == 0.2 and float(by) == -0.3     # the centre ray is not deflected
+
+
+def test_rays_on_the_lens_or_subhalo_centre_are_not_deflected():
+    lens = T([1.1, 0.12, -0.07, 0.05, -0.04, 0.0, 0.0, 0.4, 0.2, 0.3, 0.25]).requires_grad_(True)
+    x, y = T([0.05, 0.3, 0.9]), T([-0.04, 0.25, 0.1])
+    ax, ay = O.deflection(x, y, lens, n_sub=1)
+    # ray 0 sits on the SIE centre, ray 1 on the subhalo centre
+    ax_sie, ay_sie = O.sie_deflection(x, y, lens[0], lens[1], lens[2], lens[3], lens[4])
+    nx, ny = O.nfw_deflection(x, y, lens[7], lens[8], lens[9], lens[10])
+    assert float(ax_sie[0].detach()) == 0.0 and float(ay_sie[0].detach()) == 0.0
+    assert float(nx[1].detach()) == 0.0 and float(ny[1].detach()) == 0.0
+    (g,) = torch.autograd.grad((ax + ay).sum(), lens)
+    assert bool(torch.isfinite(g).all())

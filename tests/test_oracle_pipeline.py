@@ -37,6 +37,31 @@ def test_type7_quantiles_match_numpy_and_hand_example():
 
 
 # ------------------------------------------------------------ QF polynomial (iii)
+def test_quantiles_with_given_picks():
+    """Given order-statistic rays reproduce the sorted selection exactly when
+    they are the sorted ones, and give the other order's quantiles when two
+    tied rays are swapped (the loss is the same, the selection differs)."""
+    rng = np.random.default_rng(4)
+    z = T(rng.normal(size=200))
+    u = O.chebyshev_nodes()
+    q, i0, i1 = O.quantiles_type7(z, u)
+    q2, j0, j1 = O.quantiles_type7(z, u, picks=(i0.numpy(), i1.numpy()))
+    assert torch.equal(q, q2) and torch.equal(i0, j0) and torch.equal(i1, j1)
+    zt = z.clone()
+    zt[i1[5]] = zt[i0[5]]                      # a tie at node 5
+    q, i0, i1 = O.quantiles_type7(zt, u)
+    sw0, sw1 = i0.clone(), i1.clone()
+    sw0[5], sw1[5] = i1[5], i0[5]
+    q3, _, _ = O.quantiles_type7(zt, u, picks=(sw0.numpy(), sw1.numpy()))
+    assert torch.equal(q, q3)
+    p = synth.make_problem("C1")
+    obs = O.obs_from_problem(p)
+    a = O.loss_grad(p.lens[0], p.ps[0], p.latent[0], obs, return_all=True)
+    picks = [(a["transform"]["idx"][ax][0].numpy(), a["transform"]["idx"][ax][1].numpy()) for ax in range(2)]
+    b = O.loss_grad(p.lens[0], p.ps[0], p.latent[0], obs, picks=picks)
+    assert float(a["loss"]) == float(b["loss"]) and torch.equal(a["grad_lens"], b["grad_lens"])
+
+
 def test_chebyshev_slopes_reproduce_polynomials():
     rng = np.random.default_rng(1)
     u = O.chebyshev_nodes()
@@ -305,6 +330,53 @@ def test_status_bits():
     small["mask"] = m
     st = O.loss_grad(p.lens[0], p.ps[0], p.latent[0], small, want_grad=False)["status"]
     assert st & O.ST_MASK_SMALL
+
+
+def test_nonmonotone_quantile_function_sets_status_bit_2():
+    """Masked rays in two tight clusters make the quantile function a near
+    step: the degree-21 interpolant through it overshoots and its slope turns
+    negative at some nodes, so the transform clamps those slopes and sets bit 2.
+    Unimodal rays give a monotone fit and no bit."""
+    rng = np.random.default_rng(5)
+    two = np.concatenate([rng.normal(0.0, 0.01, 60), rng.normal(5.0, 0.01, 60)])
+    tr = O.build_transform(T(two), T(rng.normal(0.0, 1.0, 120)))
+    assert tr["status"] & O.ST_NONMONOTONE
+    S = tr["S"][0]
+    assert bool((S > 0).all()) and bool(torch.isfinite(S).all())   # clamped, not negative
+    dp = O.qf_polynomial(tr["X"][0], tr["u"])
+    assert bool((dp <= 1e-6 * (tr["X"][0][-1] - tr["X"][0][0])).any())
+    one = O.build_transform(T(rng.normal(0.0, 1.0, 120)), T(rng.normal(0.0, 1.0, 120)))
+    assert one["status"] == 0
+
+
+def test_chebyshev_nodes_match_numpy_first_kind_points():
+    """u_k = (1 + x_k)/2 for the Chebyshev points of the first kind x_k
+    (numpy's chebpts1), in ascending order."""
+    for K in (5, 22):
+        ref = 0.5 * (1.0 + np.sort(np.polynomial.chebyshev.chebpts1(K)))
+        assert np.allclose(O.chebyshev_nodes(K).numpy(), ref, atol=1e-15, rtol=0)
+
+
+def test_subray_lattice():
+    """Sub-rays: one per pixel at the pixel centre for ss = 1; for ss > 1 a
+    regular lattice of spacing pix/ss, centred on the pixel centre (zero mean
+    offset), every point inside its pixel."""
+    N, pix = 6, 0.07
+    xc, yc = O.pixel_centres(N, pix)
+    x1, y1 = O.subray_positions(N, pix, 1)
+    assert torch.equal(x1[:, 0], xc) and torch.equal(y1[:, 0], yc)
+    # pixel (i, j) centre at ((j - (N-1)/2) pix, (i - (N-1)/2) pix), row-major
+    assert abs(float(xc[1 * N + 4]) - (4 - 2.5) * pix) < 1e-15
+    assert abs(float(yc[1 * N + 4]) - (1 - 2.5) * pix) < 1e-15
+    for ss in (2, 3, 4):
+        xs, ys = O.subray_positions(N, pix, ss)
+        ox, oy = xs - xc[:, None], ys - yc[:, None]
+        assert float(ox.mean(1).abs().max()) < 1e-15 and float(oy.mean(1).abs().max()) < 1e-15
+        assert float(ox.abs().max()) < 0.5 * pix and float(oy.abs().max()) < 0.5 * pix
+        g = ox[0].reshape(ss, ss)                 # sub-ray (a, b) at index a ss + b
+        assert torch.allclose(g[:, 1:] - g[:, :-1], torch.full((ss, ss - 1), pix / ss, dtype=torch.float64))
+        h = oy[0].reshape(ss, ss)
+        assert torch.allclose(h[1:, :] - h[:-1, :], torch.full((ss - 1, ss), pix / ss, dtype=torch.float64))
 
 
 # ------------------------------------------------------------ gradients
