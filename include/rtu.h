@@ -48,6 +48,7 @@ extern "C" {
 #define RTU_EHIP     -4   /* a HIP runtime call or kernel launch failed        */
 #define RTU_ESTATE   -5   /* call out of order (e.g. no observation set)      */
 #define RTU_ENOTFOUND -6  /* unknown fit id                                   */
+#define RTU_ETOOBIG  -7   /* more than the static scratch array holds          */
 
 /* ---- per-sample status bits (device uint32 words) -------------------- */
 #define RTU_ST_NONFINITE    1u  /* loss or a gradient is not finite                    */
@@ -128,6 +129,32 @@ int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma
 
 /* Number of masked pixels M of the current observation (-1 if none). */
 int32_t rtu_masked_count(rtu_plan p);
+
+/* ---- allocation-free evaluation ----------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as rtu_loss_grad with no plan.  The geometry comes by value
+ * (host), the observation as device arrays in rtu_set_observation's layout
+ * (image[N*N], noise_sigma[N*N], psf[K*K], arc_mask[N*N] uint8), and the
+ * per-sample inputs and outputs as for rtu_loss_grad.  Every intermediate
+ * (the observation's tables, prepared on the device by this call, and the
+ * evaluation's workspace) lives in a static device array of
+ * RTU_NOALLOC_MAX_BYTES that each GPU the library runs on holds until the
+ * process ends; nothing is allocated or freed and nothing is synchronised.
+ * Queued on `stream` on the current device.  The first call on a device does
+ * the library's set-up there (constant tables, the array's address) and must
+ * not be captured into a graph.  Every call on a device shares that device's
+ * array: calls that overlap on one device (other streams, other threads)
+ * race and must be ordered by the caller.  RTU_ETOOBIG if the geometry and
+ * batch need more than the array (C2 at 32 samples fits); RTU_EINVAL as for
+ * rtu_loss_grad. */
+#define RTU_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int rtu_loss_grad_noalloc(const rtu_geometry* g, int32_t batch, const float* image,
+                          const float* noise_sigma, const float* psf, const uint8_t* arc_mask,
+                          const float* lens_params, const int32_t* n_sub, const float* ps_params,
+                          const float* latent, double* loss, double* chi2_mask, float* grad_lens,
+                          float* grad_ps, float* grad_latent, float* model_image, uint32_t* status,
+                          void* stream);
 
 /* One loss evaluation per sample, and its gradient, for `batch` samples.
  *   lens_params [B][rtu_n_lens(g)]    device, see RTU_N_LENS_BASE

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librtu.so")
 
 RTU_OK = 0
-RTU_EINVAL, RTU_ENOMEM, RTU_EBATCH, RTU_EHIP, RTU_ESTATE, RTU_ENOTFOUND = -1, -2, -3, -4, -5, -6
+RTU_EINVAL, RTU_ENOMEM, RTU_EBATCH, RTU_EHIP, RTU_ESTATE, RTU_ENOTFOUND, RTU_ETOOBIG = -1, -2, -3, -4, -5, -6, -7
+NOALLOC_MAX_BYTES = 64 << 20
 ST_NONFINITE, ST_NONMONOTONE, ST_MASK_SMALL, ST_DOMAIN = 1, 2, 4, 8
 K_NODES = 22
 N_LENS_BASE, N_PER_SUB, N_PS, MAX_SUB = 7, 4, 4, 10
@@ -64,6 +65,8 @@ def _load():
     lib.rtu_masked_count.argtypes = [P]
     lib.rtu_masked_count.restype = I32
     lib.rtu_loss_grad.argtypes = [P, I32] + [VP] * 11 + [VP]
+    lib.rtu_loss_grad_noalloc.argtypes = [C.POINTER(Geometry), I32] + [VP] * 15 + [VP]
+    lib.rtu_loss_grad_noalloc.restype = C.c_int
     lib.rtu_debug_fetch.argtypes = [P, I32, I32, VP, SZ, VP]
     lib.rtu_profile_begin.argtypes = [P, I32, C.c_uint32]
     lib.rtu_profile_end.argtypes = [P, VP, VP]
@@ -356,7 +359,8 @@ class Fleet:
 def exported_symbols():
     """Names declared in include/rtu.h that the loaded library exports."""
     return [n for n in ("rtu_n_lens", "rtu_workspace_bytes", "rtu_plan_create", "rtu_plan_destroy",
-                        "rtu_set_observation", "rtu_masked_count", "rtu_loss_grad", "rtu_debug_fetch",
+                        "rtu_set_observation", "rtu_masked_count", "rtu_loss_grad", "rtu_loss_grad_noalloc",
+                        "rtu_debug_fetch",
                         "rtu_profile_begin", "rtu_profile_end", "rtu_fit_create", "rtu_fit_destroy",
                         "rtu_fit_dim", "rtu_fit_step", "rtu_fit_read", "rtu_fit_last_outputs",
                         "rtu_fit_get_state", "rtu_fit_set_state", "rtu_fit_samples", "rtu_fleet_create",

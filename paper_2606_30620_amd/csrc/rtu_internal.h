@@ -75,6 +75,8 @@ struct SysDev {
   const float* psf_sep;       // [4][KP] for a rank-one PSF W[a][c] = u[a] v[c]: u, v of the forward
                               // (flipped) correlation, then u, v of the adjoint one
   int psf_rank1;              // the PSF is rank one (to FP32 rounding): the separable PSF kernel
+  const int* obs_dyn;         // null, or an observation prepared on the device: [0] M, [1] psf_rank1
+                              // (these then replace the two fields above)
   const uint8_t* mask;        // [N*N]
   const int* mask_idx;        // [M] row-major pixel index of each masked pixel
   const int* rank_j;          // [K] floor((M-1) u_k)
@@ -148,6 +150,10 @@ hipError_t launch_rays_fwd(const SysDev& h, int batch, hipStream_t s);
 hipError_t launch_psf(const SysDev& h, int batch, bool adjoint, hipStream_t s);
 hipError_t launch_rays_adj(const SysDev& h, int batch, hipStream_t s);
 hipError_t launch_post(const SysDev& h, int batch, hipStream_t s);
+// the observation tables of h (inv_var, PSF rows, rank-one factors, masked
+// pixels, ranks) prepared on the device from the raw observation, M and the
+// rank-one flag written to dyn[0], dyn[1]
+hipError_t launch_observe(const SysDev& h, const float* noise_sigma, const float* psf, int* dyn, hipStream_t s);
 // fit kernels (rtu_fit.hip)
 
 // host helpers shared by plans, fits and the serving fleet (rtu_runtime.hip)

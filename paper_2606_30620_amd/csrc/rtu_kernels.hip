@@ -29,8 +29,14 @@
 namespace rtu {
 
 __constant__ float c_u[K];
+__constant__ double c_ud[K];
 __constant__ double c_D[K * K];
 __constant__ float2 c_tw[128];
+
+// Masked-pixel count and rank-one PSF flag of the observation: from the
+// descriptor, or from the table of an observation prepared on the device.
+__device__ __forceinline__ int obs_M(const SysDev& S) { return S.obs_dyn ? S.obs_dyn[0] : S.M; }
+__device__ __forceinline__ int obs_rank1(const SysDev& S) { return S.obs_dyn ? S.obs_dyn[1] : S.psf_rank1; }
 
 // ====================================================================== helpers
 // Sub-ray (a, b) of pixel (i, j) sits at the pixel centre
@@ -398,7 +404,7 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
   SelLds& L = *reinterpret_cast<SelLds*>(smem);
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-  const int M = S.M;
+  const int M = obs_M(S);
   const float* lensp = S.lens + (size_t)b * S.n_lens;
   const int nsub = n_sub_of(S, b);
   const Sie sie = make_sie(lensp);
@@ -1159,7 +1165,7 @@ __device__ void psf_sep_body(const SysDev& S, int b, int tile, int adjoint, floa
 
 __device__ __forceinline__ void psf_dispatch(const SysDev& S, int b, int tile, int adjoint, float* tilein,
                                              double* red) {
-  if (S.psf_rank1) {
+  if (obs_rank1(S)) {
     switch (S.psf_k) {
       case 15: psf_sep_body<15>(S, b, tile, adjoint, tilein, red); break;
       case 21: psf_sep_body<21>(S, b, tile, adjoint, tilein, red); break;
@@ -1223,7 +1229,8 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
     if (tid == 0) {
       const double loss = 0.5 * v[0] + 0.5 * v[2];
       S.loss[b] = loss;
-      if (S.chi2m) S.chi2m[b] = S.M > 0 ? v[1] / (double)S.M : 0.0;
+      const int M = obs_M(S);
+      if (S.chi2m) S.chi2m[b] = M > 0 ? v[1] / (double)M : 0.0;
       if (!isfinite(loss)) P.stat |= RTU_ST_NONFINITE;
     }
   }
@@ -1262,9 +1269,10 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
       const double t = S.rank_t[k];
       const double wgt = (r & 1) ? t : 1.0 - t;
       int m = S.sel[((size_t)b * 2 + ax) * 2 * K + r];
-      m = m < 0 ? 0 : (m >= S.M ? S.M - 1 : m);
+      const int M = obs_M(S);
+      m = m < 0 ? 0 : (m >= M ? M - 1 : m);
       const double bb = wgt * P.xbar[ax][k];
-      if (bb != 0.0 && S.M > 0) {
+      if (bb != 0.0 && M > 0) {
         const int p = S.mask_idx[m];
         const int i = p / S.n_img, j = p - i * S.n_img;
         const float x = ((float)j - 0.5f * (float)(S.n_img - 1)) * S.pix;
@@ -1446,6 +1454,126 @@ __global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S, int fft_cap) {
   else post_body(S, blockIdx.x, 1, fft_smem, fft_cap, P);
 }
 
+// ====================================================================== k_observe
+// An observation prepared on the device, for the allocation-free entry point:
+// the same tables the host prepares for a plan, bit for bit.
+//  - inv_var = 1/sigma^2;
+//  - the PSF weight rows of the forward (flipped) and adjoint correlations,
+//    zero-padded: W[a][c] at [a][c + 15] of rows of psf_ws(KP);
+//  - rank-one factors: u the column and v the row (divided by the pivot, in
+//    FP64) through the largest |weight| (the first in row-major order), the
+//    PSF taken as rank one if every weight is reproduced to 4e-7 of the
+//    largest;
+//  - the masked pixels in row-major order, their count M, and the quantile
+//    ranks h_k = (M - 1) u_k (FP64, floor and fraction).
+// One workgroup.
+constexpr int OBS_THREADS = 1024;
+__global__ void __launch_bounds__(OBS_THREADS) k_observe(SysDev S, const float* __restrict__ sigma,
+                                                         const float* __restrict__ psf, int* dyn) {
+  __shared__ float rv[OBS_THREADS];
+  __shared__ int ri[OBS_THREADS];
+  __shared__ double re[OBS_THREADS];
+  __shared__ int wcnt[OBS_THREADS / 64];
+  __shared__ int s_off;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int N2 = S.n_img * S.n_img, KP = S.psf_k, WS = psf_ws(KP);
+  float* fwd = const_cast<float*>(S.psf_flip);
+  float* adj = const_cast<float*>(S.psf);
+  float* sep = const_cast<float*>(S.psf_sep);
+  for (int q = tid; q < KP * WS; q += OBS_THREADS) {
+    const int a = q / WS, c = q - a * WS - 15;
+    const bool in = c >= 0 && c < KP;
+    fwd[q] = in ? psf[(KP - 1 - a) * KP + (KP - 1 - c)] : 0.f;
+    adj[q] = in ? psf[a * KP + c] : 0.f;
+  }
+  // the largest |weight|, the first in row-major order among equal ones
+  float bv = 0.f;
+  int bi = 0x7fffffff;
+  for (int q = tid; q < KP * KP; q += OBS_THREADS) {
+    const float v = fabsf(psf[q]);
+    if (v > bv) { bv = v; bi = q; }
+  }
+  rv[tid] = bv;
+  ri[tid] = bi;
+  __syncthreads();
+  for (int w = OBS_THREADS / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      const float v2 = rv[tid + w];
+      const int i2 = ri[tid + w];
+      if (v2 > rv[tid] || (v2 == rv[tid] && i2 < ri[tid])) { rv[tid] = v2; ri[tid] = i2; }
+    }
+    __syncthreads();
+  }
+  const double wmax = (double)rv[0];
+  const int ar = wmax > 0.0 ? ri[0] / KP : 0, ac = wmax > 0.0 ? ri[0] - ar * KP : 0;
+  const double piv = psf[ar * KP + ac];
+  auto uf = [&](int a) { return psf[a * KP + ac]; };
+  auto vf = [&](int c) { return (float)((double)psf[ar * KP + c] / piv); };
+  double err = 0.0;
+  if (wmax > 0.0)
+    for (int q = tid; q < KP * KP; q += OBS_THREADS) {
+      const int a = q / KP, c = q - a * KP;
+      err = fmax(err, fabs((double)psf[q] - (double)uf(a) * (double)vf(c)));
+    }
+  re[tid] = err;
+  __syncthreads();
+  for (int w = OBS_THREADS / 2; w > 0; w >>= 1) {
+    if (tid < w) re[tid] = fmax(re[tid], re[tid + w]);
+    __syncthreads();
+  }
+  const int rank1 = wmax > 0.0 && re[0] <= 4e-7 * wmax;
+  for (int a = tid; a < KP; a += OBS_THREADS) {
+    sep[a] = wmax > 0.0 ? uf(KP - 1 - a) : 0.f;
+    sep[KP + a] = wmax > 0.0 ? vf(KP - 1 - a) : 0.f;
+    sep[2 * KP + a] = wmax > 0.0 ? uf(a) : 0.f;
+    sep[3 * KP + a] = wmax > 0.0 ? vf(a) : 0.f;
+  }
+  // inverse variances and the masked pixels in row-major order (a running
+  // offset over chunks of OBS_THREADS pixels, ballot ranks inside each wave)
+  float* iv = const_cast<float*>(S.inv_var);
+  int* idx = const_cast<int*>(S.mask_idx);
+  if (tid == 0) s_off = 0;
+  __syncthreads();
+  for (int base = 0; base < N2; base += OBS_THREADS) {
+    const int p = base + tid;
+    const bool m = p < N2 && S.mask[p] != 0;
+    if (p < N2) {
+      const float sg = sigma[p];
+      iv[p] = 1.f / (sg * sg);
+    }
+    const unsigned long long bal = __ballot(m);
+    const int below = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[wv] = __popcll(bal);
+    __syncthreads();
+    int off = s_off;
+    for (int w = 0; w < wv; ++w) off += wcnt[w];
+    if (m) idx[off + below] = p;
+    __syncthreads();
+    if (tid == 0) {
+      int t = 0;
+      for (int w = 0; w < OBS_THREADS / 64; ++w) t += wcnt[w];
+      s_off += t;
+    }
+    __syncthreads();
+  }
+  const int M = s_off;
+  if (tid < K) {
+    const double hh = (double)(M > 0 ? M - 1 : 0) * c_ud[tid];
+    const double fl = floor(hh);
+    const_cast<int*>(S.rank_j)[tid] = (int)fl;
+    const_cast<double*>(S.rank_t)[tid] = hh - fl;
+  }
+  if (tid == 0) {
+    dyn[0] = M;
+    dyn[1] = rank1;
+  }
+}
+
+hipError_t launch_observe(const SysDev& h, const float* noise_sigma, const float* psf, int* dyn, hipStream_t s) {
+  hipLaunchKernelGGL(k_observe, dim3(1), dim3(OBS_THREADS), 0, s, h, noise_sigma, psf, dyn);
+  return hipGetLastError();
+}
+
 // ====================================================================== launchers
 hipError_t configure_fft_kernels();
 
@@ -1479,6 +1607,7 @@ hipError_t upload_constants() {
   for (int k = 0; k < 128; ++k) tw[k] = make_float2((float)cos(2.0 * M_PI * k / 256.0), (float)-sin(2.0 * M_PI * k / 256.0));
   hipError_t e;
   if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_u), uf, sizeof(uf))) != hipSuccess) return e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_ud), u, sizeof(u))) != hipSuccess) return e;
   if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_D), D, sizeof(D))) != hipSuccess) return e;
   if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_tw), tw, sizeof(tw))) != hipSuccess) return e;
   return configure_fft_kernels();

@@ -285,7 +285,34 @@ hipError_t init_fit_state(const FitDev& F, const float* mu0, const float* rho0, 
 
 }  // namespace rtu
 
+// The allocation-free entry point keeps every intermediate in this array.
+// Each device holds its own copy at its own address, found once per device
+// with hipGetSymbolAddress; host code uses only that address, never the
+// array's name.
+static __device__ __align__(256) char scratch[RTU_NOALLOC_MAX_BYTES];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::vector<std::pair<int, char*>> g_scratch;   // (device, address of its copy)
+
+// Set-up on the current device, once: the constant tables and the address of
+// its copy of the array.
+int scratch_base(int device, char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  for (const auto& d : g_scratch)
+    if (d.first == device) {
+      *out = d.second;
+      return RTU_OK;
+    }
+  const int rc = ensure_constants(device);
+  if (rc) return rc;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RTU_EHIP;
+  g_scratch.emplace_back(device, static_cast<char*>(ptr));
+  *out = static_cast<char*>(ptr);
+  return RTU_OK;
+}
 
 void prof_call_begin(rtu_plan p) {
   Prof& P = p->prof;
@@ -426,6 +453,63 @@ int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma
 }
 
 int32_t rtu_masked_count(rtu_plan p) { return p ? p->M : -1; }
+
+int rtu_loss_grad_noalloc(const rtu_geometry* g, int32_t batch, const float* image, const float* noise_sigma,
+                          const float* psf, const uint8_t* arc_mask, const float* lens_params,
+                          const int32_t* n_sub, const float* ps_params, const float* latent, double* loss,
+                          double* chi2_mask, float* grad_lens, float* grad_ps, float* grad_latent,
+                          float* model_image, uint32_t* status, void* stream) {
+  if (!valid_geometry(g) || batch < 1) return RTU_EINVAL;
+  if (!image || !noise_sigma || !psf || !arc_mask || !lens_params || !ps_params || !latent || !loss || !status)
+    return RTU_EINVAL;
+  if (reinterpret_cast<uintptr_t>(latent) % 16) return RTU_EINVAL;   // read four floats at a time
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return RTU_EHIP;
+  SysDev h;
+  fill_geometry(g, h);
+  // layout in the static array: workspace, observation tables (room for any
+  // mask), the observation's M and rank-one flag
+  const size_t ws = carve_workspace(h, batch, nullptr);
+  const size_t ob = carve_observation(h, batch, g->n_img * g->n_img, nullptr);
+  if (ws + ob + 256 > RTU_NOALLOC_MAX_BYTES) return RTU_ETOOBIG;
+  char* base = nullptr;
+  const int rc = scratch_base(device, &base);
+  if (rc) return rc;
+  carve_workspace(h, batch, base);
+  carve_observation(h, batch, g->n_img * g->n_img, base + ws);
+  int* dyn = reinterpret_cast<int*>(base + ws + ob);
+  // the kernels read the image and the mask where the caller keeps them
+  h.image = image;
+  h.mask = arc_mask;
+  h.obs_dyn = dyn;
+  h.batch = batch;
+  h.lens = lens_params;
+  h.n_sub = n_sub;
+  h.ps = ps_params;
+  h.latent = latent;
+  h.loss = loss;
+  h.chi2m = chi2_mask;
+  h.g_lens = grad_lens;
+  h.g_ps = grad_ps;
+  h.g_lat = grad_latent;
+  h.model = model_image;
+  h.status = status;
+  h.want_grad = (grad_lens || grad_ps || grad_latent) ? 1 : 0;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // every scratch value the evaluation reads is written earlier in this call:
+  // the observation tables here, the rest by the stages (prep zeroes the
+  // source adjoint and the status words), so nothing is cleared
+  if (launch_observe(h, noise_sigma, psf, dyn, s) != hipSuccess) return RTU_EHIP;
+  if (launch_prep(h, batch, s) != hipSuccess) return RTU_EHIP;
+  if (launch_rays_fwd(h, batch, s) != hipSuccess) return RTU_EHIP;
+  if (launch_psf(h, batch, false, s) != hipSuccess) return RTU_EHIP;
+  if (h.want_grad) {
+    if (launch_psf(h, batch, true, s) != hipSuccess) return RTU_EHIP;
+    if (launch_rays_adj(h, batch, s) != hipSuccess) return RTU_EHIP;
+  }
+  if (launch_post(h, batch, s) != hipSuccess) return RTU_EHIP;
+  return RTU_OK;
+}
 
 int rtu_loss_grad(rtu_plan p, int32_t batch, const float* lens_params, const int32_t* n_sub,
                   const float* ps_params, const float* latent, double* loss, double* chi2_mask,
@@ -689,6 +773,7 @@ const char* rtu_strerror(int code) {
     case RTU_EHIP: return "HIP runtime call or kernel launch failed";
     case RTU_ESTATE: return "call out of order (no observation set)";
     case RTU_ENOTFOUND: return "unknown fit id";
+    case RTU_ETOOBIG: return "geometry and batch need more than the static scratch array (RTU_NOALLOC_MAX_BYTES)";
     default: return "unknown error";
   }
 }
