@@ -89,7 +89,9 @@ __device__ __forceinline__ unsigned long long sel_key(float v, int m) {
 
 // ====================================================================== k_prep
 // The type-7 quantiles need the masked rays at 2K ranks of their sorted order
-// (ties by ray index).  First a value-linear histogram over the finite range
+// (ties by ray index): floor(h_k) and floor(h_k) + 1 for every node.  Both
+// selections below take the distinct ranks in ascending order (L.trank[0,
+// ntgt)); prep_select builds that list and the map from the nodes to it.  First a value-linear histogram over the finite range
 // [vmin, vmax] names the bin of every target rank.  When the target bins are
 // small, their rays are gathered into LDS and ranked by counting.  Otherwise
 // (rays clustered far below the histogram's resolution, many ties,
@@ -117,7 +119,9 @@ struct SelLds {
   double red[8 * 16];
   float fred[2 * 16];
   unsigned ured[2 * 16];
-  int trank[2 * K];
+  int trank[2 * K];                      // distinct target ranks, ascending: [0, ntgt)
+  int tmap[2 * K];                       // rank floor(h_k) + (t & 1) of node t/2 is target tmap[t]
+  int ntgt;
   // counting path
   int tbin[2 * K];
   int seg_bin[2 * K], seg_start[2 * K], seg_count[2 * K], seg_fill[2 * K], seg_t0[2 * K];
@@ -178,7 +182,8 @@ __device__ bool select_by_counting(SelLds& L, const float* zb, int M, float vmin
   batched_copy<8>(M, [&](int m) { return zb[m]; }, [&](int, float v) { atomicAdd(&hist[bin_of(v)], 1); });
   __syncthreads();
   block_exclusive_scan(hist, HIST_BINS, reinterpret_cast<int*>(L.red));
-  if (tid < 2 * K) {
+  const int ntgt = L.ntgt;
+  if (tid < ntgt) {
     const int r = L.trank[tid];
     int lo = 0, hi = HIST_BINS - 1;   // largest bin with cum <= r
     while (lo < hi) {
@@ -192,7 +197,7 @@ __device__ bool select_by_counting(SelLds& L, const float* zb, int M, float vmin
   // lane t for target t; a run starts where the bin changes
   if (tid < 64) {
     const int t = tid;
-    const bool valid = t < 2 * K;
+    const bool valid = t < ntgt;
     const int bb = valid ? L.tbin[t] : -1;
     const int prev = __shfl_up(bb, 1, 64);
     const bool head = valid && (t == 0 || prev != bb);
@@ -221,7 +226,7 @@ __device__ bool select_by_counting(SelLds& L, const float* zb, int M, float vmin
   __syncthreads();
   const int nseg = L.nseg, total = L.total;
   if (total > SEL_LDS_CAP || L.maxcnt > SEL_SEG_MAX) return false;
-  if (tid < 2 * K) L.trank[tid] -= hist[L.tbin[tid]];     // rank inside the bin
+  if (tid < ntgt) L.trank[tid] -= hist[L.tbin[tid]];     // rank inside the bin
   __syncthreads();
   // map bin -> segment (reuse the histogram)
   for (int i = tid; i < HIST_BINS; i += nt) hist[i] = -1;
@@ -248,7 +253,7 @@ __device__ bool select_by_counting(SelLds& L, const float* zb, int M, float vmin
     const unsigned long long kc = L.c.cand[idx];
     int rk = 0;
     for (int c2 = 0; c2 < cnt; ++c2) rk += L.c.cand[st0 + c2] < kc;
-    for (int t = L.seg_t0[lo]; t < 2 * K && L.tbin[t] == bb; ++t) {
+    for (int t = L.seg_t0[lo]; t < ntgt && L.tbin[t] == bb; ++t) {
       if (L.trank[t] == rk) {
         const int m = (int)(kc & 0xffffffffu);
         L.tval[t] = zb[m];
@@ -271,7 +276,8 @@ __device__ void select_by_radix(SelLds& L, const float* zb, int M, unsigned umin
   auto key = [&](int m) {
     return ((unsigned long long)(ord_key(zb[m]) - umin) << ib) | (unsigned)m;
   };
-  if (tid < 2 * K) {
+  const int ntgt = L.ntgt;
+  if (tid < ntgt) {
     L.tpre[tid] = 0ull;
     L.tlen[tid] = 0;
     L.tres[tid] = tb == 0;                      // a single ray
@@ -280,7 +286,7 @@ __device__ void select_by_radix(SelLds& L, const float* zb, int M, unsigned umin
   for (;;) {
     if (tid == 0) {
       int ng = 0, consumed = tb;
-      for (int t = 0; t < 2 * K; ++t) {
+      for (int t = 0; t < ntgt; ++t) {
         if (L.tres[t]) continue;
         if (ng == 0 || L.gpre[ng - 1] != L.tpre[t]) L.gpre[ng++] = L.tpre[t];
         L.tgrp[t] = ng - 1;
@@ -315,7 +321,7 @@ __device__ void select_by_radix(SelLds& L, const float* zb, int M, unsigned umin
     }
     __syncthreads();
     block_exclusive_scan(hist, nb, reinterpret_cast<int*>(L.red));
-    if (tid < 2 * K && !L.tres[tid]) {
+    if (tid < ntgt && !L.tres[tid]) {
       const int base = L.tgrp[tid] << w;
       const int target = hist[base] + L.trank[tid];
       int lo = 0, hi = (1 << w) - 1;            // largest digit whose start <= target
@@ -334,7 +340,7 @@ __device__ void select_by_radix(SelLds& L, const float* zb, int M, unsigned umin
   // every target's prefix now holds exactly one ray: fetch it
   if (tid == 0) {
     int nu = 0;
-    for (int t = 0; t < 2 * K; ++t) {
+    for (int t = 0; t < ntgt; ++t) {
       const int free_bits = tb - L.tlen[t];
       const unsigned long long lo = L.tpre[t] << free_bits;
       if (nu == 0 || L.ulo[nu - 1] != lo) {
@@ -467,10 +473,25 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
   const double mu = axis == 0 ? mux : muy;
 
   if (M > 0) {
-    // target ranks floor(h_k) and floor(h_k) + 1, h_k = (M-1) u_k (ascending)
-    if (tid < 2 * K) {
-      const int r = S.rank_j[tid >> 1] + (tid & 1);
-      L.trank[tid] = r < 0 ? 0 : (r > M - 1 ? M - 1 : r);
+    // target ranks floor(h_k) and floor(h_k) + 1, h_k = (M-1) u_k.  Each of
+    // the two sequences is non-decreasing in k, but with few masked rays
+    // neighbouring nodes share floor(h_k), so floor(h_k) + 1 can exceed
+    // floor(h_{k+1}): merge them into one ascending list of distinct ranks
+    // (the selections need ascending targets) and record where each node's
+    // pair went.
+    if (tid == 0) {
+      auto clampM = [&](int r) { return r < 0 ? 0 : (r > M - 1 ? M - 1 : r); };
+      int ia = 0, ib = 0, nu = 0, last = -1;
+      while (ia < K || ib < K) {
+        const int a = ia < K ? clampM(S.rank_j[ia]) : 0x7fffffff;
+        const int c = ib < K ? clampM(S.rank_j[ib] + 1) : 0x7fffffff;
+        const bool fa = a <= c;
+        const int v = fa ? a : c;
+        const int t = fa ? 2 * ia++ : 2 * ib++ + 1;
+        if (v != last) { L.trank[nu++] = v; last = v; }
+        L.tmap[t] = nu - 1;
+      }
+      L.ntgt = nu;
     }
     __syncthreads();
     if (S.sel_radix || !select_by_counting(L, zb, M, vmin, vmax)) select_by_radix(L, zb, M, umin, umax);
@@ -485,15 +506,16 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
   const bool degenerate = !(sc > 0.0) || M < 2;
   if (tid < K) {
     double qb;
+    const int t0 = M > 0 ? L.tmap[2 * tid] : 0, t1 = M > 0 ? L.tmap[2 * tid + 1] : 0;
     if (M > 0) {
       const double t = (double)S.rank_t[tid];
-      qb = (1.0 - t) * (double)L.tval[2 * tid] + t * (double)L.tval[2 * tid + 1];
+      qb = (1.0 - t) * (double)L.tval[t0] + t * (double)L.tval[t1];
     } else {
       qb = 0.0;
     }
     L.q[tid] = degenerate ? (double)c_u[tid] : (qb - mu) / sc;  // standardised quantile
-    sel[2 * tid] = M > 0 ? L.tidx[2 * tid] : 0;
-    sel[2 * tid + 1] = M > 0 ? L.tidx[2 * tid + 1] : 0;
+    sel[2 * tid] = M > 0 ? L.tidx[t0] : 0;
+    sel[2 * tid + 1] = M > 0 ? L.tidx[t1] : 0;
   }
   __syncthreads();
   if (tid < K) {

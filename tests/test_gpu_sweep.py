@@ -30,17 +30,15 @@ def _case(k):
     return g, rank_two, int(rng.integers(1 << 30))
 
 
-# Case 4 (24 x 24, 3 x 3 sub-rays, n_src = 128, rank-two 9-tap PSF, 3 lens-light
-# Gaussians, 52 masked pixels) ended its first GPU run with a memory fault;
-# cases 5-7 did not run after it.  Reading the kernels has not found the
-# cause yet, so cases 4-7 stay off the GPU until it is found; cases 0-3
-# passed in that run.
-SKIP_REASON = ("case 4 ended its first GPU run with a memory fault whose cause is not found yet; "
-               "cases 5-7 have not run")
-
-
-@pytest.mark.parametrize("k", [0, 1, 2, 3] + [pytest.param(k, marks=pytest.mark.skip(reason=SKIP_REASON))
-                                              for k in range(4, 8)])
+# Case 4 (24 x 24, 52 masked pixels) once ended its GPU run with a memory
+# fault.  The cause, found by running the kernels on the host under
+# AddressSanitizer (tests/hostemu): with few masked rays the quantile
+# selection's target ranks floor(h_k) + {0, 1} were not in ascending order,
+# so a histogram bin appeared in two runs of targets, one run's candidate
+# slots in LDS were never written, and an uninitialised key's low word was
+# used as a ray index into global memory.  The selection now takes the
+# distinct ranks in ascending order.
+@pytest.mark.parametrize("k", range(8))
 def test_sweep_parity(k):
     g, rank_two, seed = _case(k)
     say(f"[gpu] sweep {k}: {g.n_img}x{g.n_img} ss={g.supersample} n_src={g.n_src} psf={g.psf_size}"

@@ -1,0 +1,116 @@
+"""The library's kernels and runtime compiled for the host with
+AddressSanitizer (tests/hostemu): every memory access of a full evaluation is
+bounds-checked against its buffer, and the outputs are compared with the FP64
+oracle at the parity tolerances.  The cases are the ones where out-of-range
+indices come from the data: the 24 x 24 image with 52 masked pixels, 3 x 3
+sub-rays, a 128 x 128 source in global memory, a rank-two PSF and lens light
+(once a GPU memory fault: the quantile selection's target ranks were out of
+order for few masked rays); masks of 10 and 52 pixels with both selections;
+the allocation-free entry point.  CPU only."""
+import os
+import struct
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import rtu_oracle as O
+from paper_2606_30620_amd import synth
+from tests.hostemu import build as hb
+
+TOL_IMG, TOL_GRAD = 1e-4, 1e-3
+
+pytestmark = pytest.mark.skipif(not hb.available(), reason="no host clang++ with AddressSanitizer")
+
+
+@pytest.fixture(scope="module")
+def driver():
+    return hb.build()
+
+
+def _write(p, path):
+    g = p.geom
+    with open(path, "wb") as f:
+        f.write(struct.pack("<9i2f", g.n_img, g.supersample, g.n_src, g.psf_size, g.n_sub_max, g.n_gauss,
+                            p.batch, p.lens.shape[1], 0, float(np.float32(g.pixel_scale)), float(g.tnfw_tau)))
+        for a, dt in ((p.image, np.float32), (p.noise_sigma, np.float32), (p.psf, np.float32), (p.mask, np.uint8),
+                      (p.lens, np.float32), (p.ps, np.float32), (p.latent, np.float32), (p.n_sub, np.int32)):
+            f.write(np.ascontiguousarray(a, dtype=dt).tobytes())
+
+
+def _run(driver, p, mode=0, flags=0):
+    g = p.geom
+    B, nl, n, N = p.batch, p.lens.shape[1], g.n_src, g.n_img
+    with tempfile.TemporaryDirectory() as d:
+        fi, fo = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
+        _write(p, fi)
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
+        r = subprocess.run([driver, fi, fo, str(mode), str(flags)], capture_output=True, text=True, timeout=600,
+                           env=env)
+        assert "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
+        assert r.returncode == 0, (r.returncode, r.stderr[-2000:])
+        raw = open(fo, "rb").read()
+    off = 0
+
+    def take(dt, cnt):
+        nonlocal off
+        a = np.frombuffer(raw, dtype=dt, count=cnt, offset=off)
+        off += a.nbytes
+        return a
+
+    out = {"loss": take(np.float64, B), "chi2_mask": take(np.float64, B), "status": take(np.uint32, B),
+           "grad_lens": take(np.float32, B * nl).reshape(B, nl), "grad_ps": take(np.float32, B * 4).reshape(B, 4),
+           "grad_latent": take(np.float32, B * n * n).reshape(B, n, n),
+           "model": take(np.float32, B * N * N).reshape(B, N, N)}
+    assert off == len(raw)
+    return out
+
+
+def _relinf(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    s = np.abs(b).max()
+    return np.abs(a - b).max() / s if s > 0 else np.abs(a - b).max()
+
+
+def _compare(out, p):
+    for b in range(p.batch):
+        ref = O.loss_grad_problem(p, b)
+        assert abs(out["loss"][b] - float(ref["loss"].detach())) <= TOL_IMG * abs(float(ref["loss"].detach()))
+        assert _relinf(out["model"][b], ref["model"].detach().numpy()) <= TOL_IMG
+        assert int(out["status"][b]) == int(ref["status"])
+        assert _relinf(out["grad_ps"][b], ref["grad_ps"].numpy()) <= TOL_GRAD
+        assert _relinf(out["grad_latent"][b], ref["grad_latent"].numpy()) <= TOL_GRAD
+        ns, g = int(p.n_sub[b]), p.geom
+        act = np.r_[0:7 + 4 * ns, 7 + 4 * g.n_sub_max:p.lens.shape[1]]
+        assert _relinf(out["grad_lens"][b][act], ref["grad_lens"].numpy()[act]) <= TOL_GRAD
+
+
+def _case4():
+    from tests.test_gpu_parity import _rank_two_psf
+    from tests.test_gpu_sweep import _case
+    g, rank_two, seed = _case(4)
+    p = synth.make_problem("X", batch=2, seed=seed, geom=g)
+    assert rank_two and int(p.mask.sum()) == 52
+    p.psf = _rank_two_psf(p.psf)
+    return p
+
+
+def _small_mask(npix):
+    p = synth.make_problem("C1")
+    m = np.zeros_like(p.mask)
+    m.reshape(-1)[500:500 + npix] = 1
+    p.mask = m
+    return p
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_sweep_case_with_52_masked_pixels(driver, mode):
+    p = _case4()
+    _compare(_run(driver, p, mode=mode), p)
+
+
+@pytest.mark.parametrize("npix, flags", [(10, 0), (10, 1), (52, 0), (52, 1)])
+def test_small_masks_both_selections(driver, npix, flags):
+    p = _small_mask(npix)
+    _compare(_run(driver, p, flags=flags), p)
