@@ -236,22 +236,32 @@ int rtu_profile_end(rtu_plan p, double* stage_ms, int32_t* launches);
  * epsilon 1e-8) on (mu, rho) to maximise it.  State stays on the device. */
 typedef struct rtu_fit_s* rtu_fit;
 
+/* Lens parameters whose guide lives in log space, as a bit mask over the lens
+ * parameter index i (word i / 32, bit i % 32): their sample is z = exp(u),
+ * u = mu + exp(rho) eps, the gradient is chained through z, and the prior is
+ * flat in u (log-uniform in z; for positive parameters such as a subhalo's
+ * kappa_s and r_s, which then never reach zero).  mu and rho of such a
+ * parameter are those of u. */
+#define RTU_LOG_MASK_WORDS 3
+
 /* Creates a fit on plan p (which must hold an observation) with S samples per
  * step (S <= the plan's max_batch), initial guide mu0, rho0 (host, [dim]),
- * learning rate lr, Philox seed, room for max_steps ELBO values, and n_sub
- * active subhaloes.  dim = n_lens + 4 + n_src^2. */
+ * learning rate lr, Philox seed, room for max_steps ELBO values, n_sub
+ * active subhaloes and the log-space mask (host [RTU_LOG_MASK_WORDS], or NULL
+ * for none).  dim = n_lens + 4 + n_src^2. */
 int rtu_fit_create(rtu_plan p, int32_t samples, const float* mu0, const float* rho0, float lr,
-                   uint64_t seed, int32_t max_steps, int32_t n_sub, rtu_fit* out);
+                   uint64_t seed, int32_t max_steps, int32_t n_sub, const uint32_t* log_mask, rtu_fit* out);
 int rtu_fit_destroy(rtu_fit f);
 int32_t rtu_fit_dim(rtu_fit f);
 /* Queues n_steps fit steps on `stream`.  eps (device, [n_steps][S][dim]) or
  * NULL to draw from Philox.  RTU_EINVAL if the trace would overflow. */
 int rtu_fit_step(rtu_fit f, int32_t n_steps, const float* eps, void* stream);
-/* Copies the guide (host mu[dim], rho[dim], either may be NULL) and the ELBO
- * trace (host elbo[max_trace]) out; *n_trace = steps taken.  Synchronises
- * `stream`. */
+/* Copies the guide (host mu[dim], rho[dim], either may be NULL), the ELBO
+ * trace (host elbo[max_trace]) and the OR of every sample's status word over
+ * every step taken (host *status, may be NULL) out; *n_trace = steps taken.
+ * Synchronises `stream`. */
 int rtu_fit_read(rtu_fit f, float* mu, float* rho, double* elbo, int32_t max_trace,
-                 int32_t* n_trace, void* stream);
+                 int32_t* n_trace, uint32_t* status, void* stream);
 /* Checkpoint / resume: the full optimiser state as host float[6][dim] in the
  * order mu, rho, Adam m(mu), v(mu), m(rho), v(rho), plus the number of steps
  * taken (the Philox counter and Adam's bias correction continue from it).
@@ -292,6 +302,7 @@ typedef struct {
   int32_t n_sub;             /* active subhaloes (<= geom.n_sub_max) */
   float lr;
   uint64_t seed;             /* Philox key of the fit's draws */
+  uint32_t log_mask[RTU_LOG_MASK_WORDS];  /* log-space lens parameters (see rtu_fit_create) */
 } rtu_fit_request;
 
 /* Creates a fleet on `device` with an arena of hbm_budget bytes and at most

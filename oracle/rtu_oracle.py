@@ -624,24 +624,30 @@ def cell_edge_slack(lens, ps, w, obs, n_sub=0, tau=0.0, delta=None, side=0):
 
 
 # ------------------------------------------------------------------ ELBO (Sec. 4)
-def elbo_and_grad(mu, rho, eps, obs, n_lens: int, n_sub=0, tau=0.0):
+def elbo_and_grad(mu, rho, eps, obs, n_lens: int, n_sub=0, tau=0.0, log_params=()):
     """Stochastic ELBO of a mean-field Gaussian guide over z = (lens, ps, w)
     with location mu and scale exp(rho), estimated with the given standard-normal
     draws eps[S, dim]:  z_s = mu + exp(rho) eps_s,
         ELBO = -mean_s loss(z_s) - sum_p ln(sigma_p sqrt(2 pi)) - (n^2/2) ln 2 pi
                + sum(rho) + (dim/2)(1 + ln 2 pi),
     i.e. Gaussian likelihood, flat priors on lens and spectrum parameters, a
-    unit normal prior on the latent, and the guide entropy.  Returns the ELBO
-    and its gradient with respect to mu and rho."""
+    unit normal prior on the latent, and the guide entropy.  The lens
+    parameters listed in log_params have their guide over the logarithm:
+    z_i = exp(mu_i + exp(rho_i) eps_i), with a flat prior on the logarithm
+    (log-uniform on z_i), so the same formula holds.  Returns the ELBO and
+    its gradient with respect to mu and rho."""
     mu = _t(mu).clone().requires_grad_(True)
     rho = _t(rho).clone().requires_grad_(True)
     eps = _t(eps)
     S, dim = eps.shape
     nsrc2 = dim - n_lens - 4
     n = int(round(math.sqrt(nsrc2)))
+    is_log = torch.zeros(dim, dtype=torch.bool)
+    is_log[list(log_params)] = True
     total = torch.zeros((), dtype=DT)
     for s in range(S):
-        z = mu + torch.exp(rho) * eps[s]
+        u = mu + torch.exp(rho) * eps[s]
+        z = torch.where(is_log, torch.exp(torch.where(is_log, u, torch.zeros_like(u))), u)
         out = forward(z[:n_lens], z[n_lens:n_lens + 4], z[n_lens + 4:].reshape(n, n),
                       obs, n_sub, tau)
         total = total + out["loss"]

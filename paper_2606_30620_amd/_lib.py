@@ -34,10 +34,23 @@ class Geometry(C.Structure):
                 ("n_gauss", C.c_int32)]
 
 
+LOG_MASK_WORDS = 3
+
+
 class FitRequest(C.Structure):
     _fields_ = [("geom", Geometry), ("image", C.c_void_p), ("noise_sigma", C.c_void_p), ("psf", C.c_void_p),
                 ("arc_mask", C.c_void_p), ("mu0", C.c_void_p), ("rho0", C.c_void_p), ("samples", C.c_int32),
-                ("steps", C.c_int32), ("n_sub", C.c_int32), ("lr", C.c_float), ("seed", C.c_uint64)]
+                ("steps", C.c_int32), ("n_sub", C.c_int32), ("lr", C.c_float), ("seed", C.c_uint64),
+                ("log_mask", C.c_uint32 * LOG_MASK_WORDS)]
+
+
+def log_mask_of(indices) -> "C.Array":
+    """Bit mask (RTU_LOG_MASK_WORDS words) of the lens parameters whose guide
+    lives in log space."""
+    m = (C.c_uint32 * LOG_MASK_WORDS)()
+    for i in indices or ():
+        m[i // 32] |= 1 << (i % 32)
+    return m
 
 
 class RTUError(RuntimeError):
@@ -70,12 +83,12 @@ def _load():
     lib.rtu_debug_fetch.argtypes = [P, I32, I32, VP, SZ, VP]
     lib.rtu_profile_begin.argtypes = [P, I32, C.c_uint32]
     lib.rtu_profile_end.argtypes = [P, VP, VP]
-    lib.rtu_fit_create.argtypes = [P, I32, VP, VP, C.c_float, C.c_uint64, I32, I32, C.POINTER(P)]
+    lib.rtu_fit_create.argtypes = [P, I32, VP, VP, C.c_float, C.c_uint64, I32, I32, VP, C.POINTER(P)]
     lib.rtu_fit_destroy.argtypes = [P]
     lib.rtu_fit_dim.argtypes = [P]
     lib.rtu_fit_dim.restype = I32
     lib.rtu_fit_step.argtypes = [P, I32, VP, VP]
-    lib.rtu_fit_read.argtypes = [P, VP, VP, VP, I32, C.POINTER(I32), VP]
+    lib.rtu_fit_read.argtypes = [P, VP, VP, VP, I32, C.POINTER(I32), VP, VP]
     lib.rtu_fit_last_outputs.argtypes = [P, C.POINTER(VP), C.POINTER(VP)]
     lib.rtu_fit_get_state.argtypes = [P, VP, C.POINTER(I32), VP]
     lib.rtu_fit_samples.argtypes = [P, VP, VP]
@@ -225,13 +238,18 @@ class Plan:
 class Fit:
     """An rtu_fit: Gaussian guide over (lens, ps, latent) with Adam, on a plan."""
 
-    def __init__(self, plan: Plan, samples: int, mu0, rho0, lr=1e-2, seed=0, max_steps=1000, n_sub=0):
+    def __init__(self, plan: Plan, samples: int, mu0, rho0, lr=1e-2, seed=0, max_steps=1000, n_sub=0,
+                 log_params=None):
+        """log_params: lens parameter indices whose guide lives in log space
+        (mu0, rho0 of those are of the logarithm)."""
         self.plan = plan
         mu0 = np.ascontiguousarray(mu0, dtype=np.float32)
         rho0 = np.ascontiguousarray(rho0, dtype=np.float32)
         h = C.c_void_p()
+        mask = log_mask_of(log_params)
         check(LIB.rtu_fit_create(plan._h, int(samples), mu0.ctypes.data, rho0.ctypes.data, float(lr),
-                                 int(seed), int(max_steps), int(n_sub), C.byref(h)), "rtu_fit_create")
+                                 int(seed), int(max_steps), int(n_sub), C.addressof(mask), C.byref(h)),
+              "rtu_fit_create")
         self._h = h
         self.dim = LIB.rtu_fit_dim(h)
         assert self.dim == mu0.size
@@ -255,12 +273,20 @@ class Fit:
         mu = np.zeros(self.dim, np.float32)
         rho = np.zeros(self.dim, np.float32)
         n = C.c_int32()
-        check(LIB.rtu_fit_read(self._h, mu.ctypes.data, rho.ctypes.data, None, 0, C.byref(n),
+        check(LIB.rtu_fit_read(self._h, mu.ctypes.data, rho.ctypes.data, None, 0, C.byref(n), None,
                                _stream_ptr(stream)), "rtu_fit_read")
         tr = np.zeros(max(n.value, 1), np.float64)
-        check(LIB.rtu_fit_read(self._h, None, None, tr.ctypes.data, n.value, C.byref(n),
+        check(LIB.rtu_fit_read(self._h, None, None, tr.ctypes.data, n.value, C.byref(n), None,
                                _stream_ptr(stream)), "rtu_fit_read")
         return mu, rho, tr[:n.value]
+
+    def status_acc(self, stream=None) -> int:
+        """OR of every sample's status word over every step taken."""
+        n = C.c_int32()
+        st = C.c_uint32()
+        check(LIB.rtu_fit_read(self._h, None, None, None, 0, C.byref(n), C.byref(st), _stream_ptr(stream)),
+              "rtu_fit_read")
+        return st.value
 
     def get_state(self, stream=None):
         """(state[6, dim]: mu, rho, m_mu, v_mu, m_rho, v_rho; steps taken)."""
@@ -305,12 +331,13 @@ class Fleet:
             pass
 
     @staticmethod
-    def _request(geom: Geometry, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub=0, lr=1e-2, seed=0):
+    def _request(geom: Geometry, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub=0, lr=1e-2, seed=0,
+                 log_params=None):
         arrs = [np.ascontiguousarray(image, np.float32), np.ascontiguousarray(sigma, np.float32),
                 np.ascontiguousarray(psf, np.float32), np.ascontiguousarray(mask, np.uint8),
                 np.ascontiguousarray(mu0, np.float32), np.ascontiguousarray(rho0, np.float32)]
         req = FitRequest(geom, *[a.ctypes.data for a in arrs], int(samples), int(steps), int(n_sub), float(lr),
-                         int(seed))
+                         int(seed), log_mask_of(log_params))
         return req, arrs
 
     @staticmethod
@@ -318,8 +345,10 @@ class Fleet:
         req, keep = Fleet._request(geom, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub)
         return LIB.rtu_fleet_request_bytes(C.byref(req))
 
-    def submit(self, geom, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub=0, lr=1e-2, seed=0) -> int:
-        req, keep = self._request(geom, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub, lr, seed)
+    def submit(self, geom, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub=0, lr=1e-2, seed=0,
+               log_params=None) -> int:
+        req, keep = self._request(geom, image, sigma, psf, mask, mu0, rho0, samples, steps, n_sub, lr, seed,
+                                  log_params)
         t = C.c_int64()
         check(LIB.rtu_fleet_submit(self._h, C.byref(req), C.byref(t)), "rtu_fleet_submit")
         self._dims[t.value] = (keep[4].size, int(steps))

@@ -38,20 +38,31 @@ __device__ __forceinline__ float eps_at(const FitDev& F, const float* eps, int s
   return eps ? eps[(size_t)s * F.dim + i] : normal_draw(F, step, s, i);
 }
 
-// z_s = mu + exp(rho) eps_s, scattered into the plan's per-sample inputs; the
-// draw is kept for the Adam update of rho
+__device__ __forceinline__ bool is_log(const FitDev& F, int i) {
+  return i < F.n_lens && ((F.log_mask[i >> 5] >> (i & 31)) & 1u);
+}
+
+// z_s = mu + exp(rho) eps_s (z = exp of that for a log-space parameter),
+// scattered into the plan's per-sample inputs; the draw is kept for the Adam
+// update of rho
 __device__ __forceinline__ void sample_body(const FitDev& F, const float* eps, int step, int s, int i) {
   if (i >= F.dim) return;
   const float e = eps_at(F, eps, step, s, i);
   F.eps_s[(size_t)s * F.dim + i] = e;
-  const float z = F.mu[i] + __expf(F.rho[i]) * e;
+  float z = F.mu[i] + __expf(F.rho[i]) * e;
+  if (is_log(F, i)) z = __expf(z);
   if (i < F.n_lens) F.z_lens[(size_t)s * F.n_lens + i] = z;
   else if (i < F.n_lens + 4) F.z_ps[(size_t)s * 4 + (i - F.n_lens)] = z;
   else F.z_lat[(size_t)s * F.n_src2 + (i - F.n_lens - 4)] = z;
 }
 
+// d loss / d u of sample s: the evaluation's gradient, times z for a
+// log-space parameter (z = exp(u))
 __device__ __forceinline__ float grad_at(const FitDev& F, int s, int i) {
-  if (i < F.n_lens) return F.g_lens[(size_t)s * F.n_lens + i];
+  if (i < F.n_lens) {
+    const float g = F.g_lens[(size_t)s * F.n_lens + i];
+    return is_log(F, i) ? g * F.z_lens[(size_t)s * F.n_lens + i] : g;
+  }
   if (i < F.n_lens + 4) return F.g_ps[(size_t)s * 4 + (i - F.n_lens)];
   return F.g_lat[(size_t)s * F.n_src2 + (i - F.n_lens - 4)];
 }

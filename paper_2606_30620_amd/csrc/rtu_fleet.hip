@@ -68,6 +68,7 @@ struct Entry {
   int S = 0, steps = 0, n_sub = 0;
   float lr = 0.f;
   uint64_t seed = 0;
+  uint32_t log_mask[RTU_LOG_MASK_WORDS] = {0, 0, 0};
   std::vector<float> image, sigma, psf, mu0, rho0;
   std::vector<uint8_t> mask;
   ObsHost obs;
@@ -260,6 +261,7 @@ int admit_one(rtu_fleet f, hipStream_t s) {
   F.lr = e.lr;
   F.seed_lo = (uint32_t)e.seed;
   F.seed_hi = (uint32_t)(e.seed >> 32);
+  for (int w = 0; w < RTU_LOG_MASK_WORDS; ++w) F.log_mask[w] = e.log_mask[w];
   F.elbo_const = elbo_constant(e.obs.inv_var, F.n_src2, F.dim);
   if (upload_observation(h, e.image.data(), e.psf.data(), e.mask.data(), e.obs, s) != hipSuccess) return -1;
   if (init_fit_state(F, e.mu0.data(), e.rho0.data(), e.n_sub, s) != hipSuccess) return -1;
@@ -362,6 +364,7 @@ int rtu_fleet_submit(rtu_fleet f, const rtu_fit_request* r, int64_t* ticket) {
   e.n_sub = r->n_sub;
   e.lr = r->lr;
   e.seed = r->seed;
+  for (int w = 0; w < RTU_LOG_MASK_WORDS; ++w) e.log_mask[w] = r->log_mask[w];
   const size_t N2 = (size_t)r->geom.n_img * r->geom.n_img, K2 = (size_t)r->geom.psf_size * r->geom.psf_size;
   SysDev tmp;
   fill_geometry(&r->geom, tmp);

@@ -125,6 +125,7 @@ struct FitDev {
   int round0, nsteps;         // serving: step = round - round0, active while < nsteps
   float lr;
   uint32_t seed_lo, seed_hi;
+  uint32_t log_mask[RTU_LOG_MASK_WORDS];   // lens parameter i has a log-space guide if bit i is set
   double elbo_const;          // data and prior normalisation + guide entropy constant
   float *mu, *rho, *m_mu, *v_mu, *m_rho, *v_rho;   // [dim]
   float *z_lens, *z_ps, *z_lat;                    // [S][...] samples (evaluation inputs)

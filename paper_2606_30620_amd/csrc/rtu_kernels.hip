@@ -479,19 +479,26 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
     // floor(h_{k+1}): merge them into one ascending list of distinct ranks
     // (the selections need ascending targets) and record where each node's
     // pair went.
-    if (tid == 0) {
-      auto clampM = [&](int r) { return r < 0 ? 0 : (r > M - 1 ? M - 1 : r); };
-      int ia = 0, ib = 0, nu = 0, last = -1;
-      while (ia < K || ib < K) {
-        const int a = ia < K ? clampM(S.rank_j[ia]) : 0x7fffffff;
-        const int c = ib < K ? clampM(S.rank_j[ib] + 1) : 0x7fffffff;
-        const bool fa = a <= c;
-        const int v = fa ? a : c;
-        const int t = fa ? 2 * ia++ : 2 * ib++ + 1;
-        if (v != last) { L.trank[nu++] = v; last = v; }
-        L.tmap[t] = nu - 1;
+    // One wave, lane t for target t: a rank is kept at its first lane, and its
+    // place in the list is the number of kept ranks below it.
+    if (tid < 64) {
+      const int t = tid;
+      int r = t < 2 * K ? S.rank_j[t >> 1] + (t & 1) : 0x7fffffff;
+      r = t < 2 * K ? (r < 0 ? 0 : (r > M - 1 ? M - 1 : r)) : r;
+      bool first = t < 2 * K;
+      for (int s = 0; s < 2 * K; ++s) {
+        const int rs = lane_value(r, s);       // every lane reads every lane (no divergence)
+        first = first && !(s < t && rs == r);
       }
-      L.ntgt = nu;
+      const unsigned long long keep = __ballot(first);
+      int below = 0;
+      for (int s = 0; s < 2 * K; ++s) {
+        const int rs = lane_value(r, s);
+        below += (((keep >> s) & 1ull) && rs < r) ? 1 : 0;
+      }
+      if (first) L.trank[below] = r;
+      if (t < 2 * K) L.tmap[t] = below;
+      if (t == 0) L.ntgt = __popcll(keep);
     }
     __syncthreads();
     if (S.sel_radix || !select_by_counting(L, zb, M, vmin, vmax)) select_by_radix(L, zb, M, umin, umax);

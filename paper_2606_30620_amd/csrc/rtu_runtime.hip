@@ -608,7 +608,7 @@ int rtu_profile_end(rtu_plan p, double* stage_ms, int32_t* launches) {
 }
 
 int rtu_fit_create(rtu_plan p, int32_t samples, const float* mu0, const float* rho0, float lr,
-                   uint64_t seed, int32_t max_steps, int32_t n_sub, rtu_fit* out) {
+                   uint64_t seed, int32_t max_steps, int32_t n_sub, const uint32_t* log_mask, rtu_fit* out) {
   if (!p || !out || !mu0 || !rho0 || samples < 1 || max_steps < 1) return RTU_EINVAL;
   if (samples > p->max_batch) return RTU_EBATCH;
   if (p->M < 0) return RTU_ESTATE;
@@ -628,6 +628,7 @@ int rtu_fit_create(rtu_plan p, int32_t samples, const float* mu0, const float* r
   F.lr = lr;
   F.seed_lo = (uint32_t)seed;
   F.seed_hi = (uint32_t)(seed >> 32);
+  for (int w = 0; w < RTU_LOG_MASK_WORDS; ++w) F.log_mask[w] = log_mask ? log_mask[w] : 0u;
   F.round0 = 0;
   F.nsteps = max_steps;
   F.elbo_const = elbo_constant(p->inv_var, n2, F.dim);
@@ -701,7 +702,7 @@ int rtu_fit_step(rtu_fit f, int32_t n_steps, const float* eps, void* stream) {
 }
 
 int rtu_fit_read(rtu_fit f, float* mu, float* rho, double* elbo, int32_t max_trace, int32_t* n_trace,
-                 void* stream) {
+                 uint32_t* status, void* stream) {
   if (!f) return RTU_EINVAL;
   if (hipSetDevice(f->plan->device) != hipSuccess) return RTU_EHIP;
   if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return RTU_EHIP;
@@ -711,6 +712,7 @@ int rtu_fit_read(rtu_fit f, float* mu, float* rho, double* elbo, int32_t max_tra
   if (e == hipSuccess && rho) e = hipMemcpy(rho, F.rho, (size_t)F.dim * 4, hipMemcpyDeviceToHost);
   const int nt = f->steps < max_trace ? f->steps : max_trace;
   if (e == hipSuccess && elbo && nt > 0) e = hipMemcpy(elbo, F.trace, (size_t)nt * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && status) e = hipMemcpy(status, F.status_acc, 4, hipMemcpyDeviceToHost);
   if (n_trace) *n_trace = f->steps;
   return e == hipSuccess ? RTU_OK : RTU_EHIP;
 }

@@ -36,14 +36,26 @@ class Request:
         return self.problem.geom
 
 
+def log_params(problem: synth.Problem) -> List[int]:
+    """Lens parameters fitted in log space: every active subhalo's kappa_s
+    and r_s (positive scales; a log-space guide keeps them positive through
+    every sample and step)."""
+    return [synth.N_LENS_BASE + synth.N_PER_SUB * j + k for j in range(int(problem.n_sub[0])) for k in (0, 1)]
+
+
 def guide_init(problem: synth.Problem):
     """Initial guide of a request: location at the request's parameter sample
-    (lens, spectrum) and the latent prior mean; scales 0.01 (lens, spectrum)
-    and 1 (latent, the prior's)."""
+    (lens, spectrum; the logarithm for the log-space subhalo scales) and the
+    latent prior mean; scales 0.01 (lens, spectrum), 0.05 on the logarithm of
+    a subhalo scale (5 %) and 1 (latent, the prior's)."""
     g = problem.geom
-    mu = np.concatenate([problem.lens[0], problem.ps[0], np.zeros(g.n_src * g.n_src)]).astype(np.float32)
-    rho = np.zeros(mu.size, np.float32)
-    rho[:problem.lens.shape[1] + 4] = math.log(0.01)
+    lens = problem.lens[0].astype(np.float64).copy()
+    rho = np.zeros(lens.size + 4 + g.n_src * g.n_src, np.float32)
+    rho[:lens.size + 4] = math.log(0.01)
+    for i in log_params(problem):
+        lens[i] = math.log(lens[i])
+        rho[i] = math.log(0.05)
+    mu = np.concatenate([lens, problem.ps[0], np.zeros(g.n_src * g.n_src)]).astype(np.float32)
     return mu, rho
 
 
@@ -73,11 +85,30 @@ class ServeResult:
     def fits_per_s(self) -> float:
         return len(self.latency) / self.makespan
 
+    def valid(self) -> Optional[int]:
+        """Fits whose samples never left the parameter domain (status bit 8)
+        nor gave a non-finite loss or gradient (bit 1), and whose ELBO trace is
+        finite; None when the results were not kept.  Bits 2 (smoothed CDF
+        not monotone: slopes clamped) and 4 (small mask) are conditions the
+        evaluation handles, not failures."""
+        if not self.results:
+            return None
+        return sum(1 for (_, _, tr, st) in self.results.values() if not (st & 9) and np.all(np.isfinite(tr)))
+
+    def status_counts(self) -> dict:
+        """Fits with each status bit set in some sample of some step."""
+        return {str(b): sum(1 for r in self.results.values() if r[3] & b) for b in (1, 2, 4, 8)}
+
     def summary(self) -> dict:
-        return {"n": int(len(self.latency)), "fits_per_s": round(self.fits_per_s, 2),
-                "p50_ms": round(1e3 * float(np.percentile(self.latency, 50)), 2),
-                "p99_ms": round(1e3 * float(np.percentile(self.latency, 99)), 2),
-                "makespan_s": round(self.makespan, 3)}
+        out = {"n": int(len(self.latency)), "fits_per_s": round(self.fits_per_s, 2),
+               "p50_ms": round(1e3 * float(np.percentile(self.latency, 50)), 2),
+               "p99_ms": round(1e3 * float(np.percentile(self.latency, 99)), 2),
+               "makespan_s": round(self.makespan, 3)}
+        v = self.valid()
+        if v is not None:
+            out["valid_fits"] = v
+            out["fits_with_status_bit"] = self.status_counts()
+        return out
 
 
 def serve_fleet(requests: List[Request], hbm_budget: int = 8 << 30, max_fits: int = 512, sync_every: int = 4,
@@ -103,7 +134,7 @@ def serve_fleet(requests: List[Request], hbm_budget: int = 8 << 30, max_fits: in
             mu, rho = guide_init(r.problem)
             p = r.problem
             t = fleet.submit(_geometry(lib_mod, p.geom), p.image, p.noise_sigma, p.psf, p.mask, mu, rho,
-                             r.samples, r.steps, int(p.n_sub[0]), r.lr, r.seed)
+                             r.samples, r.steps, int(p.n_sub[0]), r.lr, r.seed, log_params(p))
             ticket_of[t] = r.rid
             nxt += 1
         st = fleet.stats()
@@ -139,12 +170,13 @@ def serve_sequential(requests: List[Request], clock: Callable[[], float] = time.
         plan = _lib.Plan(_geometry(_lib, p.geom), r.samples)
         plan.set_observation(p.image, p.noise_sigma, p.psf, p.mask)
         mu, rho = guide_init(p)
-        fit = _lib.Fit(plan, r.samples, mu, rho, lr=r.lr, seed=r.seed, max_steps=r.steps, n_sub=int(p.n_sub[0]))
+        fit = _lib.Fit(plan, r.samples, mu, rho, lr=r.lr, seed=r.seed, max_steps=r.steps, n_sub=int(p.n_sub[0]),
+                       log_params=log_params(p))
         fit.step(r.steps)
         m, rh, tr = fit.read()
         done[r.rid] = clock() - t0
         if keep_results:
-            results[r.rid] = (m, rh, tr, 0)
+            results[r.rid] = (m, rh, tr, fit.status_acc())
         fit.close()
         plan.close()
     lat = np.array([done[r.rid] - r.arrival for r in sorted(reqs, key=lambda r: r.rid)])

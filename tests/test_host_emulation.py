@@ -46,7 +46,7 @@ def _run(driver, p, mode=0, flags=0):
         fi, fo = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
         _write(p, fi)
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0")
-        r = subprocess.run([driver, fi, fo, str(mode), str(flags)], capture_output=True, text=True, timeout=600,
+        r = subprocess.run([driver, fi, fo, str(mode), str(flags)], capture_output=True, text=True, timeout=300,
                            env=env)
         assert "AddressSanitizer" not in r.stderr, r.stderr[-4000:]
         assert r.returncode == 0, (r.returncode, r.stderr[-2000:])

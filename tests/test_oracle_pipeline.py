@@ -430,6 +430,36 @@ def test_gradient_matches_central_differences(n_sub):
         assert abs(cen - float(r["grad_latent"][a, b])) < 1e-5 * max(abs(cen), 1.0)
 
 
+def test_elbo_with_log_space_parameters():
+    """A log-space guide parameter: the loss is taken at z = exp(mu + e^rho eps)
+    (the ELBO formula unchanged, flat prior on the logarithm), and the
+    gradient in mu agrees with central differences."""
+    g = synth.Geometry(48, 0.08, 1, 16, 9, 1.0, n_sub_max=1, tnfw_tau=10.0)
+    p = synth.make_problem("X", batch=1, seed=4, geom=g)     # a monotone smoothed CDF (status 0)
+    obs = O.obs_from_problem(p)
+    n, nl = g.n_src, g.n_lens
+    lens = p.lens[0].astype(np.float64).copy()
+    logp = [7, 8]
+    lens[logp] = np.log(lens[logp])
+    mu = np.concatenate([lens, p.ps[0], p.latent[0].reshape(-1)]).astype(np.float64)
+    rho = np.full(mu.size, math.log(1e-3))
+    eps = np.random.default_rng(13).standard_normal((1, mu.size))
+    elbo, gmu, _ = O.elbo_and_grad(mu, rho, eps, obs, nl, 1, g.tnfw_tau, log_params=logp)
+    z = mu + np.exp(rho) * eps[0]
+    z[logp] = np.exp(z[logp])
+    loss = float(O.loss_grad(z[:nl], z[nl:nl + 4], z[nl + 4:].reshape(n, n), obs, 1, g.tnfw_tau,
+                             want_grad=False)["loss"])
+    sig = p.noise_sigma.astype(np.float64)
+    ref = (-loss - np.log(sig * math.sqrt(2 * math.pi)).sum() - 0.5 * n * n * math.log(2 * math.pi)
+           + rho.sum() + 0.5 * mu.size * (1 + math.log(2 * math.pi)))
+    assert abs(float(elbo) - ref) < 1e-9 * abs(ref)
+    assert O.loss_grad(z[:nl], z[nl:nl + 4], z[nl + 4:].reshape(n, n), obs, 1, g.tnfw_tau, want_grad=False)["status"] == 0
+    for i in logp:
+        cen = _fd(lambda m_: float(O.elbo_and_grad(m_, rho, eps, obs, nl, 1, g.tnfw_tau, log_params=logp)[0]),
+                  mu, i, 1e-6)
+        assert abs(cen - float(gmu[i])) < 1e-5 * max(1.0, abs(cen)), (i, cen, float(gmu[i]))
+
+
 def test_elbo_gradient_and_adam():
     p = synth.make_problem("C1")
     obs = O.obs_from_problem(p)

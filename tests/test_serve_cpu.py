@@ -25,7 +25,7 @@ class MockFleet:
         self.queue, self.active, self.done, self.next = [], {}, [], 1
         self.max_active_seen = 0
 
-    def submit(self, geom, image, sigma, psf, mask, mu, rho, samples, steps, n_sub, lr, seed):
+    def submit(self, geom, image, sigma, psf, mask, mu, rho, samples, steps, n_sub, lr, seed, log_params=None):
         t = self.next
         self.next += 1
         self.queue.append((t, steps))
