@@ -60,6 +60,7 @@ struct Sie {
   float the, x0, y0, g1, g2;
   float c, s;        // cos, sin of the position angle phi = atan2(e2, e1)/2
   float q, f, P;     // axis ratio, f = sqrt(1-q^2), P = theta_E sqrt(q)
+  float q2;          // q^2
   float invf;        // 1/f
   float e1, e2, e;
   bool round;        // e < E_ROUND: the angle-free gradient
@@ -77,6 +78,7 @@ __device__ __forceinline__ Sie make_sie(const float* L) {
   sincosf(phi, &o.s, &o.c);
   o.f = 2.f * sqrtf(o.e) / (1.f + o.e);   // sqrt(1 - q^2) without cancellation
   o.P = o.the * sqrtf(o.q);
+  o.q2 = o.q * o.q;
   o.invf = o.f > 0.f ? 1.f / o.f : 0.f;
   o.round = o.e < E_ROUND;
   const float ie = 1.f / (1.f + o.e);
@@ -122,12 +124,14 @@ __device__ __forceinline__ float poly_atanh_d(float t) {
   return p;
 }
 
-// atan(f a)/f with d/da and d/df: the polynomial in (f a)^2 for |f a| <= 1,
-// else pi/2 - atan(1/|f a|) with the same polynomial.  The second form is
-// evaluated only when a lane of the wave needs it (a wave-uniform branch),
-// and then selected per lane.
+// atan(f a)/f and, with D, its derivative 1/(1 + (f a)^2) in a: the polynomial
+// in (f a)^2 for |f a| <= 1, else pi/2 - atan(1/|f a|) with the same
+// polynomial.  The second form is evaluated only when a lane of the wave
+// needs it (a wave-uniform branch), and then selected per lane.  The
+// derivative in f is (a da - v)/f; the vector-Jacobian product forms it from
+// these two (sie_shear_vjp), so it needs no polynomial of its own.
 template <bool D>
-__device__ __forceinline__ void atan_over_f(float f, float invf, float a, float& v, float& da, float& df) {
+__device__ __forceinline__ void atan_over_f(float f, float invf, float a, float& v, float& da) {
   const float fa = f * a, t = fa * fa;
   const bool big = t > 1.f;
   const bool any_big = __any(big);
@@ -138,37 +142,30 @@ __device__ __forceinline__ void atan_over_f(float f, float invf, float a, float&
   }
   const float p = poly_atan(arg);
   v = a * p;
-  if (D) {
-    da = rcp(1.f + t);
-    df = 2.f * f * a * a * a * poly_atan_d(arg);
-  }
+  if (D) da = rcp(1.f + t);
   if (any_big) {
     const float vb = copysignf(1.5707963267948966f - r * p, fa) * invf;
     v = big ? vb : v;
-    if (D) df = big ? (a * da - vb) * invf : df;
   }
 }
-// atanh(f b)/f with d/db and d/df (|f b| < 1): the polynomial in (f b)^2 for
-// (f b)^2 <= 1/4, else the logarithm, evaluated when a lane of the wave needs it.
+// atanh(f b)/f and, with D, its derivative 1/(1 - (f b)^2) in b (|f b| < 1):
+// the polynomial in (f b)^2 for (f b)^2 <= 1/4, else the logarithm, evaluated
+// when a lane of the wave needs it.
 template <bool D>
-__device__ __forceinline__ void atanh_over_f(float f, float invf, float b, float& v, float& db, float& df) {
+__device__ __forceinline__ void atanh_over_f(float f, float invf, float b, float& v, float& db) {
   const float fb = f * b, t = fb * fb;
   const bool big = t > 0.25f;
   v = b * poly_atanh(t);
-  if (D) {
-    db = rcp(1.f - t);
-    df = 2.f * f * b * b * b * poly_atanh_d(t);
-  }
+  if (D) db = rcp(1.f - t);
   if (__any(big)) {
     const float vl = 0.5f * fln((1.f + fb) * rcp(1.f - fb)) * invf;
     v = big ? vl : v;
-    if (D) df = big ? (b * db - vl) * invf : df;
   }
 }
 
 // Per-ray intermediates of the SIE deflection, kept for the VJP.
 struct SieRay {
-  float xp, yp, ip, a, b, A, dA, fA, B, dB, fB;
+  float xp, yp, ip, a, b, A, dA, B, dB;
   bool ok;
 };
 
@@ -188,8 +185,8 @@ __device__ __forceinline__ void sie_shear_alpha(const Sie& L, float x, float y, 
   E.ip = __builtin_amdgcn_rsqf(fmaxf(psi2, 1e-30f));
   E.a = E.xp * E.ip;
   E.b = E.yp * E.ip;
-  atan_over_f<D>(L.f, L.invf, E.a, E.A, E.dA, E.fA);
-  atanh_over_f<D>(L.f, L.invf, E.b, E.B, E.dB, E.fB);
+  atan_over_f<D>(L.f, L.invf, E.a, E.A, E.dA);
+  atanh_over_f<D>(L.f, L.invf, E.b, E.B, E.dB);
   const float axp = E.ok ? L.P * E.A : 0.f;
   const float ayp = E.ok ? L.P * E.B : 0.f;
   ax = L.c * axp - L.s * ayp + L.g1 * x + L.g2 * y;
@@ -201,8 +198,22 @@ __device__ __forceinline__ void sie_shear_alpha(const Sie& L, float x, float y, 
   sie_shear_alpha<false>(L, x, y, ax, ay, E);
 }
 
-// Accumulators of the SIE + shear vector-Jacobian product; converted to
-// parameter gradients once per tile by sie_grad().
+// Accumulators of the SIE + shear vector-Jacobian product, summed over rays
+// and converted to parameter gradients once per sample by sie_grad_one().
+// Every factor that is constant per sample (P, q, 1/f, the rotation back to
+// the sky frame) is left to that conversion, so a ray adds only its own terms.
+// With abar' = R(-phi) abar the loss gradient in the lens frame, per ray:
+//   P   += abar'_x A + abar'_y B                    (d loss/d P)
+//   q   += psi' x' a,  psi' = -(a' a + b' b)/psi   (d loss/d q through psi, / (P q))
+//          with a' = abar'_x dA, b' = abar'_y dB
+//   f   += (a' a + b' b) - (abar'_x A + abar'_y B)  (d loss/d f, / (P/f): the
+//          derivative of atan(f a)/f in f is (a dA - A)/f, likewise for atanh)
+//   phi += abar'_y A - abar'_x B + x'' y' - y'' x'  (d loss/d phi, / P)
+//   x0, y0 += x'', y'',  x'' = (a' + psi' q^2 x')/psi, y'' = (b' + psi' y')/psi
+//          (d loss/d (x0, y0) = -P R(phi) (x0, y0) sums)
+//   g1, g2: the shear gradient itself.
+// A nearly round lens (sie_vjp_round) fills the same slots with the terms of
+// its own chain.
 struct SieAcc {
   float P, q, f, phi, x0, y0, g1, g2;
   __device__ __forceinline__ void zero() { P = q = f = phi = x0 = y0 = g1 = g2 = 0.f; }
@@ -273,75 +284,63 @@ __device__ __forceinline__ void sie_shear_vjp(const Sie& L, const SieRay& E, flo
     sie_vjp_round(L, E, x, y, abx, aby, acc);
     return;
   }
-  const float axp = L.P * E.A, ayp = L.P * E.B;
-  // rotation alpha = R(phi) alpha': d/dphi R(phi) alpha' = (-alpha_y, alpha_x) of the SIE part
-  const float rx = L.c * axp - L.s * ayp, ry = L.s * axp + L.c * ayp;
-  float phib = aby * rx - abx * ry;
-  const float axpb = L.c * abx + L.s * aby;
+  const float axpb = L.c * abx + L.s * aby;          // abar in the lens frame
   const float aypb = -L.s * abx + L.c * aby;
-  acc.P += axpb * E.A + aypb * E.B;
-  const float ab = axpb * L.P * E.dA;
-  const float bb = aypb * L.P * E.dB;
-  acc.f += L.P * (axpb * E.fA + aypb * E.fB);
-  const float psib = -(ab * E.a + bb * E.b) * E.ip;
-  acc.q += psib * L.q * E.xp * E.a;
-  const float xpb = (ab + psib * L.q * L.q * E.xp) * E.ip;
-  const float ypb = (bb + psib * E.yp) * E.ip;
-  phib += xpb * E.yp - ypb * E.xp;
-  acc.phi += phib;
-  acc.x0 -= L.c * xpb - L.s * ypb;
-  acc.y0 -= L.s * xpb + L.c * ypb;
+  const float pterm = axpb * E.A + aypb * E.B;
+  const float ab = axpb * E.dA, bb = aypb * E.dB;
+  const float sab = ab * E.a + bb * E.b;
+  const float psib = -sab * E.ip;
+  const float t1 = psib * E.xp;
+  const float xpb = fmaf(t1, L.q2, ab) * E.ip;
+  const float ypb = fmaf(psib, E.yp, bb) * E.ip;
+  acc.P += pterm;
+  acc.q = fmaf(t1, E.a, acc.q);
+  acc.f += sab - pterm;
+  acc.phi += (aypb * E.A - axpb * E.B) + (xpb * E.yp - ypb * E.xp);
+  acc.x0 += xpb;
+  acc.y0 += ypb;
 }
 
-// Convert summed accumulators (double) to d loss / d (theta_E, e1, e2, x0, y0, g1, g2).
-// Component q < 7 of the lens gradient from the SIE and shear sums a (the
-// same chain as sie_grad, one output).  A nearly round lens summed the
+// Component k < 7 of d loss / d (theta_E, e1, e2, x0, y0, g1, g2) from the
+// summed accumulators a (see SieAcc): the per-sample factors, then the chain
+// (P, q, f, phi) -> (theta_E, e) -> (e1, e2).  A nearly round lens summed the
 // angle-free terms of sie_vjp_round: theta_E enters through K = theta_E
 // sqrt(1 - e^2) alone.
-__device__ __forceinline__ double sie_grad_one(const Sie& L, const double* a, int q) {
+__device__ __forceinline__ double sie_grad_one(const Sie& L, const double* a, int k) {
   if (L.round) {
     const double ee = (double)L.e1 * L.e1 + (double)L.e2 * L.e2, r = sqrt(1.0 - ee);
     const double K = (double)L.the * r;
-    switch (q) {
+    switch (k) {
       case 0: return a[0] * r;
       case 1: return K * a[1] - a[0] * (double)L.the * (double)L.e1 / r;
       case 2: return K * a[2] - a[0] * (double)L.the * (double)L.e2 / r;
       case 3: return K * a[4];
       case 4: return K * a[5];
-      default: return a[q + 1];
+      default: return a[k + 1];
     }
   }
-  if (q == 0) return a[0] * sqrt((double)L.q);
-  if (q >= 3) return a[q + 1];
-  const double sq = sqrt((double)L.q);
-  const double e = (double)L.e;
-  const double qb = a[1] + a[0] * (double)L.the / (2.0 * sq);
+  const double q = L.q, sq = sqrt(q), e = (double)L.e, P = (double)L.the * sq;
+  const double c = L.c, s = L.s;
+  switch (k) {
+    case 0: return a[0] * sq;
+    case 3: return -P * (c * a[4] - s * a[5]);
+    case 4: return -P * (s * a[4] + c * a[5]);
+    case 5: return a[6];
+    case 6: return a[7];
+    default: break;
+  }
+  // d loss/d q (through psi and through P), d loss/d f, d loss/d phi
+  const double qb = P * q * a[1] + a[0] * (double)L.the / (2.0 * sq);
+  const double fb = P / (double)L.f * a[2];
+  const double phib = P * a[3];
   const double dqde = -2.0 / ((1.0 + e) * (1.0 + e));
   const double dfde = (1.0 - e) / (sqrt(e) * (1.0 + e) * (1.0 + e));
-  const double eb = qb * dqde + a[2] * dfde;
+  const double eb = qb * dqde + fb * dfde;
   const double e1 = L.e1, e2 = L.e2;
-  return q == 1 ? eb * e1 / e - a[3] * e2 / (2.0 * e * e) : eb * e2 / e + a[3] * e1 / (2.0 * e * e);
+  return k == 1 ? eb * e1 / e - phib * e2 / (2.0 * e * e) : eb * e2 / e + phib * e1 / (2.0 * e * e);
 }
 __device__ __forceinline__ void sie_grad(const Sie& L, const double* a, double* g) {
-  if (L.round) {
-    for (int q = 0; q < 7; ++q) g[q] = sie_grad_one(L, a, q);
-    return;
-  }
-  // a: P, q, f, phi, x0, y0, g1, g2
-  const double sq = sqrt((double)L.q);
-  const double e = (double)L.e;
-  g[0] = a[0] * sq;
-  const double qb = a[1] + a[0] * (double)L.the / (2.0 * sq);
-  const double dqde = -2.0 / ((1.0 + e) * (1.0 + e));
-  const double dfde = (1.0 - e) / (sqrt(e) * (1.0 + e) * (1.0 + e));
-  const double eb = qb * dqde + a[2] * dfde;
-  const double e1 = L.e1, e2 = L.e2;
-  g[1] = eb * e1 / e - a[3] * e2 / (2.0 * e * e);
-  g[2] = eb * e2 / e + a[3] * e1 / (2.0 * e * e);
-  g[3] = a[4];
-  g[4] = a[5];
-  g[5] = a[6];
-  g[6] = a[7];
+  for (int k = 0; k < 7; ++k) g[k] = sie_grad_one(L, a, k);
 }
 
 // ------------------------------------------------------------------ NFW (App. A.2)

@@ -10,7 +10,10 @@
 namespace rtu {
 
 constexpr int K = RTU_K_NODES;          // Chebyshev nodes (degree 21 + 1)
-constexpr int RAY_TILE = 16;            // ray kernels: 16x16 pixel tile per workgroup
+// ray kernels: a 16 x 16 pixel tile per workgroup, one pixel per thread, each
+// wave an 8 x 8 quarter of it (past an image edge at a multiple of 8 a whole
+// wave is outside and exits, instead of half the lanes of every wave idling)
+constexpr int RAY_TILE = 16;
 constexpr int RAY_THREADS = RAY_TILE * RAY_TILE;
 constexpr int PSF_TW = 64;              // PSF kernels: 64 x 16 output tile,
 constexpr int PSF_TH = 16;              // 256 threads x 4 columns each
@@ -59,7 +62,7 @@ struct SysDev {
   int n_img, ss, n_src, log2_src, psf_k, n_sub_max, n_lens, M;
   int n_gauss, light_off;     // lens-light Gaussians and their offset in the lens vector
   float pix, tau, inv_ss2;
-  int ray_tx, ray_tiles;      // 16x16 ray tiles per side / per sample
+  int ray_tx, ray_tiles;      // 16x16 ray tiles along x / per sample
   int psf_tx, psf_tiles;      // 64x16 PSF tiles along x / per sample
   int want_grad, batch;
   int round0, nsteps;         // serving: rounds [round0, round0 + nsteps) are this system's steps

@@ -668,6 +668,14 @@ __global__ void __launch_bounds__(PREP_THREADS) k_prep(SysDev S, int fft_cap) {
 }
 
 // ====================================================================== ray tiles
+// A workgroup takes a 16 x 16 tile of pixels, one pixel per thread.  Wave w
+// takes the 8 x 8 quarter (w / 2, w % 2) of the tile, lane l its row l / 8 and
+// column l % 8.
+__device__ __forceinline__ void ray_pixel(int ti, int tj, int& i, int& j) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  i = ti * RAY_TILE + 8 * (w >> 1) + (l >> 3);
+  j = tj * RAY_TILE + 8 * (w & 1) + (l & 7);
+}
 // Source grid staged in LDS with a one-cell zero border:
 // padded index (i + 1) * (n + 2) + (j + 1) for i, j in [-1, n].
 struct RayLdsHead : KnotTab {
@@ -756,7 +764,8 @@ template <bool BOX>
 __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* smem) {
   RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
   const int ti = tile / S.ray_tx, tj = tile - ti * S.ray_tx;
-  const int i = ti * RAY_TILE + (threadIdx.x >> 4), j = tj * RAY_TILE + (threadIdx.x & 15);
+  int i, j;
+  ray_pixel(ti, tj, i, j);
   load_knots(S, b, H);
   __syncthreads();
   const bool in = i < S.n_img && j < S.n_img;
@@ -837,7 +846,8 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   double* red = reinterpret_cast<double*>(smem + off);     // [8 * 4]
   int* bbox = reinterpret_cast<int*>(red + 8 * 4);
   const int ti = tile / S.ray_tx, tj = tile - ti * S.ray_tx;
-  const int i = ti * RAY_TILE + (threadIdx.x >> 4), j = tj * RAY_TILE + (threadIdx.x & 15);
+  int i, j;
+  ray_pixel(ti, tj, i, j);
   load_knots(S, b, H);
   if (LDSGRID)
     for (int q = threadIdx.x; q < np * np; q += blockDim.x) gb[q] = 0.0;

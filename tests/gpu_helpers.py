@@ -87,8 +87,9 @@ def compare(plan, problem, b, res, ref, check_stages=True):
             lens = torch.as_tensor(problem.lens[b].astype(np.float64))
             bxm, bym = O.ray_shoot(xs[m], ys[m], lens, int(problem.n_sub[b]), problem.geom.tnfw_tau)
             same_sel = selection_agrees(sel, tr, [bxm.numpy(), bym.numpy()])
-            out["std"] = max(abs(std[0] - float(tr["mu"][0])), abs(std[1] - float(tr["mu"][1])),
-                             abs(std[2] - float(tr["s"])) / float(tr["s"]))
+            mu_o = [float(torch.as_tensor(v).detach()) for v in tr["mu"]]
+            s_o = float(torch.as_tensor(tr["s"]).detach())
+            out["std"] = max(abs(std[0] - float(mu_o[0])), abs(std[1] - float(mu_o[1])), abs(std[2] - s_o) / s_o)
             assert out["std"] < 1e-5, ("std", std, tr["mu"], tr["s"])
             for ax in range(2):
                 out[f"X{ax}"] = relinf(kn[ax, 0], tr["X"][ax].detach().numpy())
