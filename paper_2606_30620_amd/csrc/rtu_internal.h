@@ -197,10 +197,9 @@ struct FleetLaunch {
   const FitDev* fit;          // device [n_slots]
   const Task *t_prep, *t_psf, *t_post, *t_param, *t_sample, *t_fit;
   int n_prep, n_psf, n_post, n_param, n_sample, n_fit;
-  // ray tiles by the adjoint's LDS mode, as t_adj; t_fwd[1] follows
-  // t_fwd[0] in the task table
-  const Task* t_fwd[2];
-  int n_fwd[2];
+  // forward ray tiles of every system
+  const Task* t_fwd;
+  int n_fwd;
   // adjoint ray tiles split by LDS mode: [0] d loss / d s in LDS, [1] in global memory
   const Task* t_adj[2];
   int n_adj[2];

@@ -757,10 +757,13 @@ __device__ __forceinline__ void bil_corners(const float* g, int n, const Bil& B,
 
 // The corner values are read from the zero-bordered grid in global memory
 // (through L1/L2): staging the grid in LDS per tile cost more than it saved.
-// With BOX each wave also records the range of source cells its sub-rays
-// fell in (tbox), which sizes the adjoint's LDS window when the source grid
-// does not fit in LDS.
-template <bool BOX>
+// Each wave also records a range of source cells that holds every cell its
+// sub-rays fell in (tbox): per pixel the range of its sub-rays' grid
+// coordinates, kept if it reaches within one cell of the zero-bordered grid
+// and clipped to it.  An empty range tells the adjoint that the wave's
+// sub-rays contribute nothing to the gradient but lens light (the one-cell
+// margin covers the adjoint's own rounding of the same rays); the range sizes
+// the adjoint's LDS window when the source grid does not fit in LDS.
 __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* smem) {
   RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
   const int ti = tile / S.ray_tx, tj = tile - ti * S.ray_tx;
@@ -769,7 +772,6 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
   load_knots(S, b, H);
   __syncthreads();
   const bool in = i < S.n_img && j < S.n_img;
-  if (!BOX && !in) return;
   int bi0 = 1 << 30, bj0 = 1 << 30, bi1 = -(1 << 30), bj1 = -(1 << 30);
   if (in) {
     const float* lensp = S.lens + (size_t)b * S.n_lens;
@@ -781,6 +783,7 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
     int kx = 0, ky = 0;
     float x0, y0, dxs;
     subray_origin(S, i, j, x0, y0, dxs);
+    float tx0 = INFINITY, tx1 = -INFINITY, ty0 = INFINITY, ty1 = -INFINITY;   // NaN ignored
     for (int a = 0; a < S.ss; ++a) {
       const float y = fmaf((float)a, dxs, y0);
       for (int cc = 0; cc < S.ss; ++cc) {
@@ -793,17 +796,20 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
         float tx, ty, dTx, dTy;
         const float Tx = cdf_grid<false>(H, 0, kx, bx, tx, dTx);
         const float Ty = cdf_grid<false>(H, 1, ky, by, ty, dTy);
+        tx0 = fminf(tx0, Tx); tx1 = fmaxf(tx1, Tx);
+        ty0 = fminf(ty0, Ty); ty1 = fmaxf(ty1, Ty);
         Bil B;
         if (bil_setup(Tx, Ty, n, B)) {
           float s00, s01, s10, s11;
           bil_corners(gsrc, n, B, s00, s01, s10, s11);
           acc += (1.f - B.fy) * ((1.f - B.fx) * s00 + B.fx * s01) + B.fy * ((1.f - B.fx) * s10 + B.fx * s11);
-          if (BOX) {
-            bi0 = min(bi0, B.i0); bj0 = min(bj0, B.j0);
-            bi1 = max(bi1, B.i0); bj1 = max(bj1, B.j0);
-          }
         }
       }
+    }
+    const float hi = (float)(n + 1), top = (float)(n - 1);
+    if (tx1 >= -2.f && tx0 < hi && ty1 >= -2.f && ty0 < hi) {
+      bi0 = (int)fminf(fmaxf(floorf(ty0), -1.f), top); bi1 = (int)fminf(fmaxf(floorf(ty1), -1.f), top);
+      bj0 = (int)fminf(fmaxf(floorf(tx0), -1.f), top); bj1 = (int)fminf(fmaxf(floorf(tx1), -1.f), top);
     }
     // lens light at the same sub-ray positions (not lensed)
     for (int g = 0; g < S.n_gauss; ++g) {
@@ -813,21 +819,19 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
     }
     S.u[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] = acc * S.inv_ss2;
   }
-  if (BOX) {   // every lane of the wave is here
-    bi0 = wave_min(bi0);
-    bj0 = wave_min(bj0);
-    bi1 = wave_max(bi1);
-    bj1 = wave_max(bj1);
-    if ((threadIdx.x & 63) == 0)
-      S.tbox[((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64) + (threadIdx.x >> 6)] = make_int4(bi0, bj0, bi1, bj1);
-  }
+  // every lane of the wave is here
+  bi0 = wave_min(bi0);
+  bj0 = wave_min(bj0);
+  bi1 = wave_max(bi1);
+  bj1 = wave_max(bj1);
+  if ((threadIdx.x & 63) == 0)
+    S.tbox[((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64) + (threadIdx.x >> 6)] = make_int4(bi0, bj0, bi1, bj1);
 }
 
-template <bool BOX>
 __global__ void __launch_bounds__(RAY_THREADS) k_rays_fwd(SysDev S) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x / S.ray_tiles;
-  rays_fwd_body<BOX>(S, b, blockIdx.x - b * S.ray_tiles, smem);
+  rays_fwd_body(S, b, blockIdx.x - b * S.ray_tiles, smem);
 }
 
 template <bool LDSGRID>
@@ -848,6 +852,25 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   const int ti = tile / S.ray_tx, tj = tile - ti * S.ray_tx;
   int i, j;
   ray_pixel(ti, tj, i, j);
+  // the cells the forward pass's sub-rays fell in, per wave: a wave whose
+  // range is empty has no sub-ray on (or near) the grid, whose d loss / d
+  // beta is zero; a tile of such waves without lens light only clears its
+  // partials
+  const int4* tb = S.tbox + ((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64);
+  int r0 = 1 << 30, c0 = 1 << 30, r1 = -(1 << 30), c1 = -(1 << 30);
+  for (int w = 0; w < RAY_THREADS / 64; ++w) {
+    const int4 v = tb[w];
+    r0 = min(r0, v.x); c0 = min(c0, v.y); r1 = max(r1, v.z); c1 = max(c1, v.w);
+  }
+  if (r0 > r1 && S.n_gauss == 0) {
+    double* lp = S.lpart + ((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64) * (S.n_lens + 1);
+    for (int q = threadIdx.x; q < (RAY_THREADS / 64) * (S.n_lens + 1); q += blockDim.x) lp[q] = 0.0;
+    double* kbo = S.kbar + ((size_t)b * S.ray_tiles + tile) * 4 * K;
+    for (int q = threadIdx.x; q < 4 * K; q += blockDim.x) kbo[q] = 0.0;
+    return;
+  }
+  const int4 wbox = tb[threadIdx.x >> 6];
+  const bool wave_on = wbox.x <= wbox.z;
   load_knots(S, b, H);
   if (LDSGRID)
     for (int q = threadIdx.x; q < np * np; q += blockDim.x) gb[q] = 0.0;
@@ -858,12 +881,6 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   // exceeds the capacity, is added to global memory at once
   int wr0 = 0, wc0 = 0, wrs = 0, wcs = 0;
   if (!LDSGRID) {
-    const int4* tb = S.tbox + ((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64);
-    int r0 = 1 << 30, c0 = 1 << 30, r1 = -(1 << 30), c1 = -(1 << 30);
-    for (int w = 0; w < RAY_THREADS / 64; ++w) {
-      const int4 v = tb[w];
-      r0 = min(r0, v.x); c0 = min(c0, v.y); r1 = max(r1, v.z); c1 = max(c1, v.w);
-    }
     r0 = max(r0, 0); c0 = max(c0, 0); r1 = min(r1 + 1, n - 1); c1 = min(c1 + 1, n - 1);   // cell corners
     if (r1 >= r0 && c1 >= c0 && (long)(r1 - r0 + 1) * (long)(c1 - c0 + 1) <= (long)S.adj_wcap) {
       wr0 = r0; wc0 = c0; wrs = r1 - r0 + 1; wcs = c1 - c0 + 1;
@@ -881,7 +898,7 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   SieAcc acc;
   acc.zero();
   int bi0 = 1 << 30, bj0 = 1 << 30, bi1 = -(1 << 30), bj1 = -(1 << 30);
-  if (i < S.n_img && j < S.n_img) {
+  if (wave_on && i < S.n_img && j < S.n_img) {
     const float vb = S.ubar[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] * S.inv_ss2;
     KnotMom cx{-1, 0.f, 0.f, 0.f, 0.f}, cy{-1, 0.f, 0.f, 0.f, 0.f};
     int kx = 0, ky = 0;
@@ -1701,13 +1718,7 @@ bool adj_lds_grid(const SysDev& h) {
 }
 
 hipError_t launch_rays_fwd(const SysDev& h, int batch, hipStream_t s) {
-  // the tile boxes size the adjoint's LDS window when the grid is in global memory
-  if (adj_lds_grid(h))
-    hipLaunchKernelGGL(k_rays_fwd<false>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS),
-                       ray_lds_bytes(h, false, false), s, h);
-  else
-    hipLaunchKernelGGL(k_rays_fwd<true>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS),
-                       ray_lds_bytes(h, false, false), s, h);
+  hipLaunchKernelGGL(k_rays_fwd, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), ray_lds_bytes(h, false, false), s, h);
   return hipGetLastError();
 }
 
@@ -1761,26 +1772,13 @@ __global__ void __launch_bounds__(PREP_THREADS) kf_prep(const SysDev* __restrict
   else prep_gp(S, t.y, smem, fft_cap);
 }
 
-template <bool BOX>
 __global__ void __launch_bounds__(RAY_THREADS) kf_rays_fwd(const SysDev* __restrict__ sys,
                                                            const Task* __restrict__ tasks, int round) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Task t = tasks[blockIdx.x];
   const SysDev S = sys[t.x];
   if (!sys_active(S, round)) return;
-  rays_fwd_body<BOX>(S, t.y, t.z, smem);
-}
-
-// both kinds of system in one launch (a mixed fleet): one launch instead of
-// two, in a larger kernel than either of the above
-__global__ void __launch_bounds__(RAY_THREADS) kf_rays_fwd_mixed(const SysDev* __restrict__ sys,
-                                                                 const Task* __restrict__ tasks, int round) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const Task t = tasks[blockIdx.x];
-  const SysDev S = sys[t.x];
-  if (!sys_active(S, round)) return;
-  if (S.lds_adj) rays_fwd_body<false>(S, t.y, t.z, smem);
-  else rays_fwd_body<true>(S, t.y, t.z, smem);
+  rays_fwd_body(S, t.y, t.z, smem);
 }
 
 template <bool LDSGRID>
@@ -1824,17 +1822,8 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
                            (int)(L.lds_prep / sizeof(float2)) - 128);
       break;
     case RTU_STAGE_RAYS_FWD:
-      // [1]: grids in global memory, whose tiles record their cell ranges;
-      // the two lists are adjacent in the task table
-      if (L.n_fwd[0] && L.n_fwd[1])
-        hipLaunchKernelGGL(kf_rays_fwd_mixed, dim3(L.n_fwd[0] + L.n_fwd[1]), dim3(RAY_THREADS), L.lds_rays_fwd, s,
-                           L.sys, L.t_fwd[0], round);
-      else if (L.n_fwd[0])
-        hipLaunchKernelGGL(kf_rays_fwd<false>, dim3(L.n_fwd[0]), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys,
-                           L.t_fwd[0], round);
-      else if (L.n_fwd[1])
-        hipLaunchKernelGGL(kf_rays_fwd<true>, dim3(L.n_fwd[1]), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys,
-                           L.t_fwd[1], round);
+      if (L.n_fwd)
+        hipLaunchKernelGGL(kf_rays_fwd, dim3(L.n_fwd), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys, L.t_fwd, round);
       break;
     case RTU_STAGE_PSF_FWD:
     case RTU_STAGE_PSF_ADJ:
