@@ -190,12 +190,17 @@ int rtu_loss_grad(rtu_plan p, int32_t batch,
  *   RTU_DBG_STD     double[3]: mean x, mean y, scale s of the masked rays
  *   RTU_DBG_SOURCE  float[n_src^2]: source grid s (eq. 3)
  *   RTU_DBG_PREPSF  float[N^2]: sub-ray mean image before the PSF
+ *   RTU_DBG_ONGRID  double[1]: number of sub-rays whose bilinear footprint
+ *                   touches the zero-bordered source grid (the ones with a
+ *                   nonzero adjoint), as the gradient pass counted them;
+ *                   RTU_ESTATE if the last call computed no gradient
  * RTU_EINVAL if `bytes` is smaller than the item. */
 #define RTU_DBG_KNOTS  1
 #define RTU_DBG_SELECT 2
 #define RTU_DBG_STD    3
 #define RTU_DBG_SOURCE 4
 #define RTU_DBG_PREPSF 5
+#define RTU_DBG_ONGRID 6
 int rtu_debug_fetch(rtu_plan p, int32_t what, int32_t sample, void* host_dst, size_t bytes,
                     void* stream);
 

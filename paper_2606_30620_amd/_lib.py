@@ -23,7 +23,7 @@ ST_NONFINITE, ST_NONMONOTONE, ST_MASK_SMALL, ST_DOMAIN = 1, 2, 4, 8
 K_NODES = 22
 N_LENS_BASE, N_PER_SUB, N_PS, MAX_SUB = 7, 4, 4, 10
 N_PER_GAUSS, MAX_GAUSS = 6, 8
-DBG_KNOTS, DBG_SELECT, DBG_STD, DBG_SOURCE, DBG_PREPSF = 1, 2, 3, 4, 5
+DBG_KNOTS, DBG_SELECT, DBG_STD, DBG_SOURCE, DBG_PREPSF, DBG_ONGRID = 1, 2, 3, 4, 5, 6
 STAGES = ("prep", "rays_fwd", "psf_fwd", "psf_adj", "rays_adj", "post", "sample", "adam")
 
 
@@ -214,6 +214,7 @@ class Plan:
             DBG_STD: ((3,), np.float64),
             DBG_SOURCE: ((g.n_src, g.n_src), np.float32),
             DBG_PREPSF: ((g.n_img, g.n_img), np.float32),
+            DBG_ONGRID: ((1,), np.float64),
         }[what]
         out = np.zeros(shape, dt)
         check(LIB.rtu_debug_fetch(self._h, what, sample, out.ctypes.data, out.nbytes, _stream_ptr(stream)),

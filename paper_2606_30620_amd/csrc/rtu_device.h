@@ -455,32 +455,42 @@ __device__ __forceinline__ void km_add(KnotMom& c, float yb, float t) {
   const float yt = yb * t, yt2 = yt * t;
   c.m0 += yb; c.m1 += yt; c.m2 += yt2; c.m3 = fmaf(yt2, t, c.m3);
 }
-// One code path for the Hermite intervals and the two linear continuations
-// (interval 0: g = u_0 + S_0 (z - X_0); interval K: the same at X_{K-1}), so
-// that lanes flushing different kinds of interval do not diverge.  du[l] =
-// u_{l+1} - u_l.
-__device__ __forceinline__ void km_flush(KnotMom& c, const float* X, const float* S, const float* ih,
-                                         const float* du_tab, double* kb /* dX[K], dS[K] */) {
+// The moments are linear in ybar, and so is the knot adjoint in them: a
+// lane adds its moments to the tile's sums of interval k (km, FP64 in LDS)
+// when it leaves the interval, and the knot adjoint is formed once per
+// interval from the tile's sums (km_knots).
+__device__ __forceinline__ void km_flush(KnotMom& c, double* km /* [K + 1][4] */) {
   if (c.k < 0) return;
-  const bool lin = c.k == 0 || c.k >= K;
-  const int l = lin ? (c.k == 0 ? 0 : K - 1) : c.k - 1;
-  const int r = min(l + 1, K - 1);
-  const float h = X[r] - X[l], ihh = ih[l], Sl = S[l], Sr = S[r], du = du_tab[l];
-  const float G10 = c.m3 - 2.f * c.m2 + c.m1;     // sum ybar (t^3 - 2t^2 + t)
-  const float G11 = c.m3 - c.m2;                  // sum ybar (t^3 - t^2)
-  const float gh = Sl * G10 + Sr * G11;           // sum ybar dg/dh at fixed t
-  const float a0 = h * Sl, a1 = 6.f * du - 4.f * h * Sl - 2.f * h * Sr, a2 = -6.f * du + 3.f * h * (Sl + Sr);
-  const float Atm1 = -a0 * c.m0 + (a0 - a1) * c.m1 + (a1 - a2) * c.m2 + a2 * c.m3;  // sum ybar dg/dt (t-1)
-  const float At = a0 * c.m1 + a1 * c.m2 + a2 * c.m3;                              // sum ybar dg/dt t
-  const float v0 = lin ? -Sl * c.m0 : Atm1 * ihh - gh;
-  const float v1 = lin ? 0.f : gh - At * ihh;
-  const float v2 = lin ? c.m1 : h * G10;
-  const float v3 = lin ? 0.f : h * G11;
-  atomicAdd(&kb[l], (double)v0);
-  atomicAdd(&kb[r], (double)v1);
-  atomicAdd(&kb[K + l], (double)v2);
-  atomicAdd(&kb[K + r], (double)v3);
+  double* m = km + 4 * c.k;
+  atomicAdd(&m[0], (double)c.m0);
+  atomicAdd(&m[1], (double)c.m1);
+  atomicAdd(&m[2], (double)c.m2);
+  atomicAdd(&m[3], (double)c.m3);
   c.m0 = c.m1 = c.m2 = c.m3 = 0.f;
+}
+// d loss / d (X_l, X_r, S_l, S_r) of interval k from its moment sums m
+// (l = k - 1, r = k for a Hermite interval; the linear continuations,
+// interval 0: g = u_0 + S_0 (z - X_0) and interval K: the same at X_{K-1},
+// depend on X_l and S_l only, with l = 0 and K - 1).  du[l] = u_{l+1} - u_l.
+__device__ __forceinline__ void km_knots(int k, const double* m, const float* X, const float* S, const float* ih,
+                                         const float* du_tab, double v[4]) {
+  if (k == 0 || k >= K) {
+    const int l = k == 0 ? 0 : K - 1;
+    v[0] = -(double)S[l] * m[0]; v[1] = 0.0; v[2] = m[1]; v[3] = 0.0;
+    return;
+  }
+  const int l = k - 1, r = k;
+  const double h = (double)X[r] - (double)X[l], ihh = ih[l], Sl = S[l], Sr = S[r], du = du_tab[l];
+  const double G10 = m[3] - 2.0 * m[2] + m[1];     // sum ybar (t^3 - 2t^2 + t)
+  const double G11 = m[3] - m[2];                  // sum ybar (t^3 - t^2)
+  const double gh = Sl * G10 + Sr * G11;           // sum ybar dg/dh at fixed t
+  const double a0 = h * Sl, a1 = 6.0 * du - 4.0 * h * Sl - 2.0 * h * Sr, a2 = -6.0 * du + 3.0 * h * (Sl + Sr);
+  const double Atm1 = -a0 * m[0] + (a0 - a1) * m[1] + (a1 - a2) * m[2] + a2 * m[3];  // sum ybar dg/dt (t-1)
+  const double At = a0 * m[1] + a1 * m[2] + a2 * m[3];                              // sum ybar dg/dt t
+  v[0] = Atm1 * ihh - gh;
+  v[1] = gh - At * ihh;
+  v[2] = h * G10;
+  v[3] = h * G11;
 }
 
 // ------------------------------------------------------------------ lens light
@@ -640,6 +650,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 __device__ __forceinline__ float wave_sum(float v) {
   return wave_reduce(v, [](float a, float b) { return a + b; });
+}
+__device__ __forceinline__ int wave_sum(int v) {
+  return wave_reduce(v, [](int a, int b) { return a + b; });
 }
 __device__ __forceinline__ float wave_min(float v) {
   return wave_reduce(v, [](float a, float b) { return fminf(a, b); });

@@ -117,7 +117,8 @@ struct SysDev {
   double* kbar;               // [B][ray_tiles][4K] per-tile dX, dS partials
   int4* tbox;                 // [B][ray_tiles][4 waves] source cells the forward's sub-rays fell in:
                               // (min row, min column, max row, max column) of the cell's lower corner
-  double* lpart;              // [B][ray_tiles][4 waves][n_lens + 1] per-wave raw lens-gradient partials
+  double* lpart;              // [B][ray_tiles][4 waves][n_lens + 2] per-wave raw lens-gradient partials,
+                              // then the number of the wave's sub-rays on the grid
   double* c2part;             // [B][psf_tiles][2] per-tile chi^2 partials (all, mask)
   uint32_t* st;               // [B][ST_WORDS] status words: selection x, y; parameter domain
 };

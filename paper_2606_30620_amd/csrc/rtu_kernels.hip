@@ -679,7 +679,8 @@ __device__ __forceinline__ void ray_pixel(int ti, int tj, int& i, int& j) {
 // Source grid staged in LDS with a one-cell zero border:
 // padded index (i + 1) * (n + 2) + (j + 1) for i, j in [-1, n].
 struct RayLdsHead : KnotTab {
-  double kb[4 * K];  // knot adjoint: dX (x), dS (x), dX (y), dS (y)
+  double km[2][K + 1][4];   // per axis and knot interval: the tile's knot moments, then
+                            // in place their knot adjoint (km_knots)
   Nfw nfw[RTU_MAX_SUB];
 };
 
@@ -694,7 +695,7 @@ __device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H
   const float4* src = reinterpret_cast<const float4*>(S.ktab + b);
   float4* dst = reinterpret_cast<float4*>(static_cast<KnotTab*>(&H));
   for (int i = threadIdx.x; i < (int)(sizeof(KnotTab) / 16); i += blockDim.x) dst[i] = src[i];
-  for (int i = threadIdx.x; i < 4 * K; i += blockDim.x) H.kb[i] = 0.0;
+  for (int i = threadIdx.x; i < 2 * (K + 1) * 4; i += blockDim.x) (&H.km[0][0][0])[i] = 0.0;
 }
 
 // Interval of z on axis ax (the number of knots <= z), trying the previous
@@ -844,11 +845,6 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   // padded grid (LDSGRID), else the tile's window of the grid
   double* gb = reinterpret_cast<double*>(smem + sizeof(RayLdsHead));
   float* subacc = reinterpret_cast<float*>(gb + (LDSGRID ? np * np : S.adj_wcap));   // [4 n_sub_max][256]
-  size_t off = sizeof(RayLdsHead) + (size_t)(LDSGRID ? np * np : S.adj_wcap) * 8 +
-               (size_t)4 * S.n_sub_max * RAY_THREADS * 4;
-  off = (off + 15) & ~(size_t)15;
-  double* red = reinterpret_cast<double*>(smem + off);     // [8 * 4]
-  int* bbox = reinterpret_cast<int*>(red + 8 * 4);
   const int ti = tile / S.ray_tx, tj = tile - ti * S.ray_tx;
   int i, j;
   ray_pixel(ti, tj, i, j);
@@ -863,8 +859,8 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
     r0 = min(r0, v.x); c0 = min(c0, v.y); r1 = max(r1, v.z); c1 = max(c1, v.w);
   }
   if (r0 > r1 && S.n_gauss == 0) {
-    double* lp = S.lpart + ((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64) * (S.n_lens + 1);
-    for (int q = threadIdx.x; q < (RAY_THREADS / 64) * (S.n_lens + 1); q += blockDim.x) lp[q] = 0.0;
+    double* lp = S.lpart + ((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64) * (S.n_lens + 2);
+    for (int q = threadIdx.x; q < (RAY_THREADS / 64) * (S.n_lens + 2); q += blockDim.x) lp[q] = 0.0;
     double* kbo = S.kbar + ((size_t)b * S.ray_tiles + tile) * 4 * K;
     for (int q = threadIdx.x; q < 4 * K; q += blockDim.x) kbo[q] = 0.0;
     return;
@@ -872,8 +868,17 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   const int4 wbox = tb[threadIdx.x >> 6];
   const bool wave_on = wbox.x <= wbox.z;
   load_knots(S, b, H);
-  if (LDSGRID)
-    for (int q = threadIdx.x; q < np * np; q += blockDim.x) gb[q] = 0.0;
+  // grid in LDS: the points of the cells in the forward's ranges widened by
+  // one cell on each side (the same rays, rounded in other code here, stay
+  // within), padded rows pr0 .. pr1 and columns pc0 .. pc1
+  const int pr0 = max(r0 - 1, -1) + 1, pr1 = min(r1 + 1, n - 1) + 2;
+  const int pc0 = max(c0 - 1, -1) + 1, pc1 = min(c1 + 1, n - 1) + 2;
+  const int pw = pc1 - pc0 + 1, ph = pr1 - pr0 + 1;
+  if (LDSGRID && r0 <= r1)
+    for (int q = threadIdx.x; q < ph * pw; q += blockDim.x) {
+      const int rr = q / pw;
+      gb[(pr0 + rr) * np + pc0 + q - rr * pw] = 0.0;
+    }
   // grid in global memory: d loss / d s of the grid points (rows wr0 .. wr0 +
   // wrs, columns wc0 .. wc0 + wcs) around the cells the forward's sub-rays of
   // this tile fell in is summed in LDS, and added to the sample's grid once;
@@ -888,7 +893,6 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
     for (int q = threadIdx.x; q < wrs * wcs; q += blockDim.x) gb[q] = 0.0;
   }
   for (int q = threadIdx.x; q < 4 * S.n_sub_max * RAY_THREADS; q += blockDim.x) subacc[q] = 0.f;
-  if (threadIdx.x == 0) { bbox[0] = bbox[1] = 1 << 30; bbox[2] = bbox[3] = -(1 << 30); }
   __syncthreads();
   const float* lensp = S.lens + (size_t)b * S.n_lens;
   const int nsub = n_sub_of(S, b);
@@ -897,7 +901,7 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   double* gsb = S.sbar + (size_t)b * n * n;
   SieAcc acc;
   acc.zero();
-  int bi0 = 1 << 30, bj0 = 1 << 30, bi1 = -(1 << 30), bj1 = -(1 << 30);
+  int ongrid = 0;   // sub-rays of this pixel on the grid
   if (wave_on && i < S.n_img && j < S.n_img) {
     const float vb = S.ubar[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] * S.inv_ss2;
     KnotMom cx{-1, 0.f, 0.f, 0.f, 0.f}, cy{-1, 0.f, 0.f, 0.f, 0.f};
@@ -909,18 +913,19 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
     float c00 = 0.f, c01 = 0.f, c10 = 0.f, c11 = 0.f;
     auto flush_cell = [&]() {
       if (ci < -1) return;
-      if (LDSGRID) {
+      if (LDSGRID && (unsigned)(ci + 1 - pr0) < (unsigned)(ph - 1) && (unsigned)(cj + 1 - pc0) < (unsigned)(pw - 1)) {
         const int p = (ci + 1) * np + (cj + 1);
         atomicAdd(&gb[p], (double)c00);
         atomicAdd(&gb[p + 1], (double)c01);
         atomicAdd(&gb[p + np], (double)c10);
         atomicAdd(&gb[p + np + 1], (double)c11);
-        bi0 = min(bi0, ci); bj0 = min(bj0, cj); bi1 = max(bi1, ci + 1); bj1 = max(bj1, cj + 1);
       } else {
+        // global-memory grid, or (never, by the window's construction) a
+        // cell outside the LDS window
         auto add = [&](int ii, int jj, float v) {
           if (ii >= 0 && ii < n && jj >= 0 && jj < n) {
             const int wi = ii - wr0, wj = jj - wc0;
-            if ((unsigned)wi < (unsigned)wrs && (unsigned)wj < (unsigned)wcs)
+            if (!LDSGRID && (unsigned)wi < (unsigned)wrs && (unsigned)wj < (unsigned)wcs)
               atomicAdd(&gb[wi * wcs + wj], (double)v);
             else
               atomicAdd(&gsb[ii * n + jj], (double)v);
@@ -949,6 +954,7 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         const float Ty = cdf_grid<true>(H, 1, ky, by, ty, dTy);
         Bil B;
         if (!bil_setup(Tx, Ty, n, B)) continue;
+        ++ongrid;
         float s00, s01, s10, s11;
         bil_corners(gsrc, n, B, s00, s01, s10, s11);
         // d loss / d s at the four corners
@@ -963,9 +969,9 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         const float Tby = vb * ((1.f - B.fx) * (s10 - s00) + B.fx * (s11 - s01));
         const float ybx = Tbx * (float)n, yby = Tby * (float)n;
         // knots and slopes of the CDF splines (moments per interval)
-        if (kx != cx.k) { km_flush(cx, H.X[0], H.Sl[0], H.ih[0], H.du, H.kb); cx.k = kx; }
+        if (kx != cx.k) { km_flush(cx, &H.km[0][0][0]); cx.k = kx; }
         km_add(cx, ybx, tx);
-        if (ky != cy.k) { km_flush(cy, H.X[1], H.Sl[1], H.ih[1], H.du, H.kb + 2 * K); cy.k = ky; }
+        if (ky != cy.k) { km_flush(cy, &H.km[1][0][0]); cy.k = ky; }
         km_add(cy, yby, ty);
         // d loss / d beta -> d loss / d alpha = -d loss / d beta
         const float abx = -Tbx * dTx, aby = -Tby * dTy;
@@ -979,20 +985,8 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
       }
     }
     flush_cell();
-    km_flush(cx, H.X[0], H.Sl[0], H.ih[0], H.du, H.kb);
-    km_flush(cy, H.X[1], H.Sl[1], H.ih[1], H.du, H.kb + 2 * K);
-  }
-  // the touched window: reduced within each wave first, so that the LDS
-  // atomics see one lane per wave (same-address atomics serialise)
-  if (LDSGRID) {
-    bi0 = wave_min(bi0);
-    bj0 = wave_min(bj0);
-    bi1 = wave_max(bi1);
-    bj1 = wave_max(bj1);
-    if ((threadIdx.x & 63) == 0) {
-      atomicMin(&bbox[0], bi0); atomicMin(&bbox[1], bj0);
-      atomicMax(&bbox[2], bi1); atomicMax(&bbox[3], bj1);
-    }
+    km_flush(cx, &H.km[0][0][0]);
+    km_flush(cy, &H.km[1][0][0]);
   }
   // ---- lens-gradient partials of this tile, one row per wave: the raw SIE
   //      and shear accumulators (P, q, f, phi, x0, y0, g1, g2), then the
@@ -1000,13 +994,16 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   //      is applied once per sample, after the sums
   {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double* lp = S.lpart + (((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64) + wave) * (S.n_lens + 1);
+    double* lp = S.lpart + (((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64) + wave) * (S.n_lens + 2);
     const float v[8] = {acc.P, acc.q, acc.f, acc.phi, acc.x0, acc.y0, acc.g1, acc.g2};
     float r[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) r[k] = wave_sum(v[k]);
-    if (lane == 0)
+    const int on = wave_sum(ongrid);
+    if (lane == 0) {
       for (int k = 0; k < 8; ++k) lp[k] = (double)r[k];
+      lp[S.n_lens + 1] = (double)on;
+    }
     for (int q = 0; q < 4 * S.n_sub_max; ++q) {
       const float sq = wave_sum(subacc[q * RAY_THREADS + threadIdx.x]);
       if (lane == 0) lp[8 + q] = (double)sq;
@@ -1034,12 +1031,30 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   }
   // every wave's knot-moment and window atomics are done before they are read
   __syncthreads();
-  // knot partials of this tile
+  // knot partials of this tile: the adjoint of each interval, then per knot
+  // the intervals it bounds (dX (x), dS (x), dX (y), dS (y))
+  if (threadIdx.x < 2 * (K + 1)) {
+    const int ax = threadIdx.x / (K + 1), k = threadIdx.x - ax * (K + 1);
+    double v[4];
+    km_knots(k, H.km[ax][k], H.X[ax], H.Sl[ax], H.ih[ax], H.du, v);
+    for (int c = 0; c < 4; ++c) H.km[ax][k][c] = v[c];
+  }
+  __syncthreads();
   double* kbo = S.kbar + ((size_t)b * S.ray_tiles + tile) * 4 * K;
-  for (int q = threadIdx.x; q < 4 * K; q += blockDim.x) kbo[q] = H.kb[q];
-  // d loss / d s: add the touched window of the LDS grid to the sample's grid
-  if (LDSGRID) {
-    const int i0 = max(bbox[0], 0), j0 = max(bbox[1], 0), i1 = min(bbox[2], n - 1), j1 = min(bbox[3], n - 1);
+  for (int q = threadIdx.x; q < 4 * K; q += blockDim.x) {
+    const int ax = q / (2 * K), rem = q - ax * 2 * K, o = rem >= K ? 2 : 0, j = rem - (o ? K : 0);
+    const double (*kv)[4] = H.km[ax];
+    double v = 0.0;
+    if (j <= K - 2) v += kv[j + 1][o];        // left knot of Hermite interval j + 1
+    if (j >= 1) v += kv[j][o + 1];            // right knot of Hermite interval j
+    if (j == 0) v += kv[0][o];                // linear continuation below X_0
+    if (j == K - 1) v += kv[K][o];            // linear continuation above X_{K-1}
+    kbo[q] = v;
+  }
+  // d loss / d s: add the window of the LDS grid (its points inside the
+  // grid) to the sample's grid
+  if (LDSGRID && r0 <= r1) {
+    const int i0 = max(pr0 - 1, 0), j0 = max(pc0 - 1, 0), i1 = min(pr1 - 1, n - 1), j1 = min(pc1 - 1, n - 1);
     const int wj = j1 - j0 + 1, wi = i1 - i0 + 1;
     if (wj > 0 && wi > 0) {
       for (int q = threadIdx.x; q < wi * wj; q += blockDim.x) {
@@ -1355,7 +1370,7 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
     // fixed order; then the chain from the SIE quantities to the lens
     // parameters, once
     const int rows = S.ray_tiles * (RAY_THREADS / 64);
-    reduce_columns(S.lpart + (size_t)b * rows * nc, rows, nc, nc, P.part,
+    reduce_columns(S.lpart + (size_t)b * rows * (nc + 1), rows, nc, nc + 1, P.part,
                    [&](int c, double v) { P.lsum[c] = v; });
     __syncthreads();
     reduce_columns(mp, 4 * K, nc, nc, P.part, [&](int c, double v) { P.lsum[c] += v; });
@@ -1700,7 +1715,7 @@ hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
 // 1-2k points).
 constexpr int ADJ_WCAP_MAX = 3072;
 int adj_window_cap(const SysDev& h) {
-  const long fixed = (long)sizeof(RayLdsHead) + 4L * h.n_sub_max * RAY_THREADS * 4 + 8 * 4 * 8 + 16 + 16;
+  const long fixed = (long)sizeof(RayLdsHead) + 4L * h.n_sub_max * RAY_THREADS * 4 + 16;
   const long room = (65536 - fixed) / 8;
   return (int)(std::max(0L, std::min((long)ADJ_WCAP_MAX, room)) & ~1L);
 }
@@ -1710,8 +1725,7 @@ size_t ray_lds_bytes(const SysDev& h, bool adjoint, bool lds_grid) {
   const size_t np = (size_t)(h.n_src + 2);
   size_t bytes = sizeof(RayLdsHead) + (lds_grid ? np * np * 8 : (size_t)h.adj_wcap * 8) +
                  (size_t)4 * h.n_sub_max * RAY_THREADS * 4;
-  bytes = (bytes + 15) & ~(size_t)15;
-  return bytes + 8 * 4 * 8 + 16;
+  return (bytes + 15) & ~(size_t)15;
 }
 bool adj_lds_grid(const SysDev& h) {
   return h.n_src <= GRID_LDS_MAX && ray_lds_bytes(h, true, true) <= 65536;

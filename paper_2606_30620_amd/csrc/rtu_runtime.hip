@@ -140,7 +140,7 @@ size_t carve_workspace(SysDev& h, int B, char* base) {
   h.sbar = c.take<double>(B * n2);
   h.kbar = c.take<double>((size_t)B * h.ray_tiles * 4 * K);
   h.tbox = c.take<int4>((size_t)B * h.ray_tiles * (RAY_THREADS / 64));
-  h.lpart = c.take<double>((size_t)B * h.ray_tiles * (RAY_THREADS / 64) * (h.n_lens + 1));
+  h.lpart = c.take<double>((size_t)B * h.ray_tiles * (RAY_THREADS / 64) * (h.n_lens + 2));
   h.c2part = c.take<double>((size_t)B * h.psf_tiles * 2);
   h.st = c.take<uint32_t>((size_t)B * ST_WORDS);
   return c.off + 256;
@@ -554,11 +554,25 @@ int rtu_debug_fetch(rtu_plan p, int32_t what, int32_t sample, void* host_dst, si
     case RTU_DBG_STD: src = h.stdv + (size_t)sample * 4; need = 3 * sizeof(double); break;
     case RTU_DBG_SOURCE: src = h.src + (size_t)sample * n2; need = n2 * sizeof(float); break;
     case RTU_DBG_PREPSF: src = h.u + (size_t)sample * N2; need = N2 * sizeof(float); break;
+    case RTU_DBG_ONGRID: need = sizeof(double); break;
     default: return RTU_EINVAL;
   }
   if (bytes < need) return RTU_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (hipStreamSynchronize(s) != hipSuccess) return RTU_EHIP;
+  if (what == RTU_DBG_ONGRID) {
+    if (!h.want_grad) return RTU_ESTATE;
+    // the last column of the sample's per-wave lens-gradient rows
+    const size_t ld = (size_t)h.n_lens + 2, rows = (size_t)h.ray_tiles * (RAY_THREADS / 64);
+    std::vector<double> v(rows * ld);
+    if (hipMemcpy(v.data(), h.lpart + (size_t)sample * rows * ld, v.size() * sizeof(double),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return RTU_EHIP;
+    double n = 0.0;
+    for (size_t r = 0; r < rows; ++r) n += v[r * ld + ld - 1];
+    *static_cast<double*>(host_dst) = n;
+    return RTU_OK;
+  }
   if (hipMemcpy(host_dst, src, need, hipMemcpyDeviceToHost) != hipSuccess) return RTU_EHIP;
   return RTU_OK;
 }

@@ -13,7 +13,7 @@ import pytest
 import torch
 
 from oracle import rtu_oracle as O
-from paper_2606_30620_amd import synth
+from paper_2606_30620_amd import _lib, synth
 from tests.gpu_helpers import compare, say
 
 pytestmark = pytest.mark.gpu
@@ -168,6 +168,29 @@ def test_forward_only_matches_forward_of_gradient_call():
     b = api.evaluate(plan, lens, ps, lat, nsub, want_grad=True, want_model=True)
     torch.cuda.synchronize()
     assert torch.equal(a.loss, b.loss) and torch.equal(a.model, b.model)
+
+
+@pytest.mark.parametrize("case", ["c2", "ragged"])
+def test_ongrid_count_matches_oracle(case):
+    """The gradient pass's count of sub-rays on the zero-bordered grid (grid
+    coordinates in [-1, n) on both axes) against the oracle's positions; a
+    sub-ray within 1e-3 cells of that boundary may fall either way."""
+    if case == "c2":
+        p = synth.make_problem("C2", batch=2)
+    else:
+        p = synth.make_problem("X", batch=2, seed=7, geom=synth.Geometry(72, 0.06, 3, 16, 9, 1.2))
+    say(f"[gpu] on-grid sub-ray count, {case}")
+    plan, res = _run(p)
+    n = p.geom.n_src
+    for b in range(2):
+        got = float(plan.debug_fetch(_lib.DBG_ONGRID, b)[0])
+        ref = O.loss_grad_problem(p, b, want_grad=False, return_all=True)
+        tx, ty = ref["gx"] * n - 0.5, ref["gy"] * n - 0.5
+        on = (tx >= -1) & (tx < n) & (ty >= -1) & (ty < n)
+        edge = torch.stack([tx + 1, tx - n, ty + 1, ty - n]).abs().amin(dim=0) < 1e-3
+        want, slack = int(on.sum()), int(edge.sum())
+        say(f"  sample {b}: gpu {got:.0f} oracle {want} (edge {slack})")
+        assert abs(got - want) <= slack
 
 
 @pytest.mark.parametrize("npix, flags", [(10, 0), (10, 1), (52, 0), (52, 1)])
