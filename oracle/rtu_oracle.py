@@ -336,6 +336,41 @@ def build_transform(bxm, bym, K: int = K_NODES, picks=None):
     return out
 
 
+def uniform_box_of(bxm, bym, picks=None):
+    """Sec. 2.1: the extent of the uniform grid, the smallest square box that
+    holds the masked rays.  Reading: the side L is the larger of the two
+    coordinate ranges (the x range on a tie), and the box is centred on the
+    rays' bounding box along both axes (along the longer axis it then spans the
+    range exactly).  The extremes are the order statistics of rank 0 and M - 1
+    (the type-7 quantiles at u = 0 and 1, ties by ray index) and are
+    differentiated as selections.  picks = per axis (index of the minimum,
+    index of the maximum) fixes which rays stand for them.  Fewer than two
+    masked rays, or a zero range on both axes: status bit 4 and the box of
+    side 1 at the rays' minimum (or at 0)."""
+    status = 0
+    M = bxm.shape[0]
+    ends = torch.tensor([0.0, 1.0], dtype=DT)
+    lo_hi, idx = [], []
+    for ax, z in enumerate((bxm, bym)):
+        if M == 0:
+            lo_hi.append((torch.zeros((), dtype=DT), torch.zeros((), dtype=DT)))
+            idx.append((torch.zeros(1, dtype=torch.long), torch.zeros(1, dtype=torch.long)))
+            continue
+        pk = None if picks is None else ([picks[ax][0], picks[ax][1]], [picks[ax][0], picks[ax][1]])
+        q, i0, _ = quantiles_type7(z, ends, pk)
+        lo_hi.append((q[0], q[1]))
+        idx.append((i0[:1], i0[1:]))
+    rx = lo_hi[0][1] - lo_hi[0][0]
+    ry = lo_hi[1][1] - lo_hi[1][0]
+    side = torch.where(rx >= ry, rx, ry)
+    if M < 2 or not bool(side > 0):
+        status |= ST_MASK_SMALL
+        return {"lo": (lo_hi[0][0].detach(), lo_hi[1][0].detach()), "side": torch.ones((), dtype=DT),
+                "idx": idx, "status": status}
+    lo = tuple(0.5 * (a + b) - 0.5 * side for a, b in lo_hi)
+    return {"lo": lo, "side": side, "idx": idx, "status": status}
+
+
 def rtu_transform(bx, by, tr):
     """Eq. (5): y = g(x) = (CDF_1(x_1), CDF_2(x_2)) on standardised coordinates."""
     zx = (bx - tr["mu"][0]) / tr["s"]
@@ -427,7 +462,9 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
     obs: dict with n_img, pix, ss, image[N,N], sigma[N,N], psf[K,K], mask[N,N],
     and optionally n_gauss: the last N_PER_GAUSS n_gauss entries of lens are
     lens-light Gaussians (mge_light), added to every sub-ray's value before the
-    sub-ray mean and the PSF.
+    sub-ray mean and the PSF; and grid = "uniform": the source grid spans the
+    smallest square box of the masked rays (Sec. 2.1, uniform_box_of) instead
+    of the RTU transform.
     uniform_box: if given as (x_lo, y_lo, side), the RTU transform is replaced by
     the plain affine map of that box onto the unit square (the paper's uniform
     grid, Sec. 2.1).
@@ -455,10 +492,17 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
     mflat = obs["mask"].reshape(-1).bool()
     xc, yc = pixel_centres(N, pix)
     M = int(mflat.sum())
-    if M < K_NODES + 1:
+    uniform = obs.get("grid", "rtu") == "uniform"
+    if M < (2 if uniform else K_NODES + 1):
         status |= ST_MASK_SMALL
     tr = None
-    if uniform_box is None:
+    if uniform:
+        bxm, bym = ray_shoot(xc[mflat], yc[mflat], lens, n_sub, tau)
+        tr = uniform_box_of(r32(bxm), r32(bym), picks=picks)
+        status |= tr["status"]
+        gx, gy = (bx - tr["lo"][0]) / tr["side"], (by - tr["lo"][1]) / tr["side"]
+        gx, gy = r32(gx), r32(gy)
+    elif uniform_box is None:
         bxm, bym = ray_shoot(xc[mflat], yc[mflat], lens, n_sub, tau)
         tr = build_transform(r32(bxm), r32(bym), picks=picks)
         status |= tr["status"]
@@ -495,7 +539,7 @@ def obs_from_problem(p) -> dict:
     return {"n_img": g.n_img, "pix": float(np.float32(g.pixel_scale)), "ss": g.supersample,
             "image": _t(p.image), "sigma": _t(p.noise_sigma), "psf": _t(p.psf),
             "mask": torch.as_tensor(p.mask.astype(np.int64)), "tau": g.tnfw_tau,
-            "n_gauss": getattr(g, "n_gauss", 0)}
+            "n_gauss": getattr(g, "n_gauss", 0), "grid": "uniform" if getattr(g, "uniform", False) else "rtu"}
 
 
 def loss_grad(lens, ps, w, obs, n_sub=0, tau=0.0, want_grad=True, return_all=False, cell_shift=0.0,

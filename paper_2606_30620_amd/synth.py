@@ -57,6 +57,7 @@ class Geometry:
     n_sub_max: int = 0
     tnfw_tau: float = 0.0   # truncation radius in units of r_s; 0 = none
     n_gauss: int = 0        # lens-light Gaussians; 0 = no lens light
+    uniform: bool = False   # source grid on the masked rays' square box instead of the RTU grid
 
     @property
     def n_lens(self) -> int:
