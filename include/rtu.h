@@ -53,7 +53,8 @@ extern "C" {
 /* ---- per-sample status bits (device uint32 words) -------------------- */
 #define RTU_ST_NONFINITE    1u  /* loss or a gradient is not finite                    */
 #define RTU_ST_NONMONOTONE  2u  /* QF slope p'(u_k) <= eps or tied knots: slopes clamped */
-#define RTU_ST_MASK_SMALL   4u  /* fewer masked pixels than nodes + 1                  */
+#define RTU_ST_MASK_SMALL   4u  /* fewer masked pixels than nodes + 1 (uniform grid:
+                                   fewer than 2, or a box of zero size)              */
 #define RTU_ST_DOMAIN       8u  /* theta_E <= 0, |e| >= 1, r_s <= 0 or spectrum <= 0   */
 
 /* Number of Chebyshev nodes of the quantile-function fit: degree 21 + 1
@@ -86,7 +87,7 @@ typedef struct {
   float    pixel_scale;  /* arcsec per image pixel, > 0                             */
   float    tnfw_tau;     /* subhalo projected-mass truncation in units of r_s;
                             0 = untruncated NFW                                     */
-  uint32_t flags;        /* 0 or RTU_GEOM_RADIX_SELECT                              */
+  uint32_t flags;        /* RTU_GEOM_* bits                                         */
   int32_t  n_gauss;      /* lens-light Gaussians per sample, 0..RTU_MAX_GAUSS
                             (0 = no lens light)                                     */
 } rtu_geometry;
@@ -96,6 +97,17 @@ typedef struct {
  * histogram cannot separate the target ranks.  Both selections return the
  * same rays (ties by index); the flag exists to exercise the fallback. */
 #define RTU_GEOM_RADIX_SELECT 1u
+/* Geometry flag: the uniform grid of Sec. 2.1 instead of the RTU grid.  The
+ * source grid spans the smallest square box that holds the masked rays (pixel
+ * centres, not supersampled): its side L is the larger of the two coordinate
+ * ranges (x on a tie) and it is centred on the rays' range along both axes;
+ * a ray maps to y = (beta - lo) / L.  The extremes are the masked rays of
+ * rank 0 and M - 1 (ties by ray index) and the gradient flows through them
+ * as selections.  Fewer than two masked rays, or zero ranges: status bit
+ * RTU_ST_MASK_SMALL and a box of side 1 at the rays' minimum.  In this mode
+ * RTU_DBG_SELECT holds per axis the indices of the minimum and the maximum in
+ * its first two slots, RTU_DBG_STD (lo_x, lo_y, L), and RTU_DBG_KNOTS zeros. */
+#define RTU_GEOM_UNIFORM 2u
 
 /* Number of lens parameters per sample: 7 + 4 n_sub_max + 6 n_gauss. */
 int32_t rtu_n_lens(const rtu_geometry* g);

@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Plan, make_geometry
+from ._lib import GEOM_UNIFORM, Plan, make_geometry
 
 
 @dataclasses.dataclass
@@ -30,6 +30,8 @@ class Result:
 def plan_for_problem(problem, max_batch: Optional[int] = None, device: int = 0, flags: int = 0) -> Plan:
     """Plan + observation for a problem from the seeded input generator."""
     g = problem.geom
+    if getattr(g, "uniform", False):
+        flags |= GEOM_UNIFORM
     geom = make_geometry(g.n_img, g.supersample, g.n_src, g.psf_size, g.pixel_scale,
                          g.n_sub_max, g.tnfw_tau, flags, g.n_gauss)
     plan = Plan(geom, max_batch or problem.batch, device)

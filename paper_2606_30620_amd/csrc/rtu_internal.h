@@ -69,6 +69,7 @@ struct SysDev {
   int lds_adj;                // the ray adjoint keeps d loss / d s in LDS (1) or adds to global memory (0)
   int adj_wcap;               // global mode: cells of the per-tile LDS window of d loss / d s
   int sel_radix;              // quantile selection: always the radix select (1)
+  int uniform;                // uniform grid on the masked rays' square box (1) instead of the RTU grid
   // observation (owned by the plan)
   const float* image;         // [N*N]
   const float* inv_var;       // [N*N] 1/sigma^2
@@ -108,7 +109,8 @@ struct SysDev {
   float* knots;               // [B][2][2][K] per axis: X_k, S_k in beta units
   float* kdbg;                // [B][2][2][K] per axis: X_k, S_k standardised
   int* sel;                   // [B][2][2][K] per axis: ray index at rank j, j+1
-  double* stdv;               // [B][4] mean x, mean y, s
+  double* stdv;               // [B][4] mean x, mean y, s, M (uniform grid: lo_x, lo_y, L,
+                              // the axis whose range is L)
   float* dp;                  // [B][2][K] p'(u_k) in beta units; <= 0: clamped
   float* u;                   // [B][N^2] sub-ray mean image
   float* r;                   // [B][N^2] (m - d)/sigma^2

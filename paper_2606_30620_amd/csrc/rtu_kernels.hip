@@ -86,6 +86,10 @@ __device__ __forceinline__ unsigned ord_key(float v) {
 __device__ __forceinline__ unsigned long long sel_key(float v, int m) {
   return ((unsigned long long)ord_key(v) << 32) | (unsigned)m;
 }
+// The value of an order key.
+__device__ __forceinline__ float ord_value(unsigned k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
 
 // ====================================================================== k_prep
 // The type-7 quantiles need the masked rays at 2K ranks of their sorted order
@@ -406,6 +410,74 @@ __device__ __forceinline__ void knot_table(const SysDev& S, int b, int ax, const
   if (ax == 0 && tid < 2) T.pad[tid] = 0.f;
 }
 
+// The uniform grid (Sec. 2.1) in the same tables: one interval [-inf, inf)
+// on which the grid coordinate is the affine T = n (z - lo) / L - 1/2, so the
+// ray kernels run unchanged and their knot moments of interval 0 are the sums
+// of ybar and ybar (z - lo) / L.
+__device__ __forceinline__ void knot_table_uniform(const SysDev& S, int b, int ax, float lo, float side) {
+  KnotTab& T = S.ktab[b];
+  const int tid = threadIdx.x;
+  if (tid < K) {
+    T.X[ax][tid] = lo; T.Sl[ax][tid] = 1.f / side; T.dp[ax][tid] = side; T.ih[ax][tid] = 0.f;
+    if (ax == 0) T.du[tid] = 0.f;
+  }
+  if (tid < 32) T.xs[ax][tid] = INFINITY;
+  if (tid <= K) {
+    T.kr[ax][tid] = tid == 0 ? make_float2(-INFINITY, INFINITY) : make_float2(INFINITY, INFINITY);
+    T.ct[ax][tid] = make_float2(lo, 1.f / side);
+    T.cq[ax][tid] = make_float4(-0.5f, (float)S.n_src, 0.f, 0.f);
+  }
+  if (ax == 0 && tid < 2) T.pad[tid] = 0.f;
+}
+
+// The uniform grid's box from the extremes of both axes (keys: value, ties by
+// index, per thread), for the axis of this workgroup.  Called by every
+// thread.
+__device__ void prep_uniform(const SysDev& S, int b, int axis, SelLds& L, const unsigned long long (&key)[4], int M,
+                             uint32_t st) {
+  const int tid = threadIdx.x;
+  if (tid < 2) { L.ulo[tid] = ~0ull; L.uhi[tid] = 0ull; }
+  __syncthreads();
+  atomicMin(&L.ulo[0], key[0]); atomicMax(&L.uhi[0], key[1]);
+  atomicMin(&L.ulo[1], key[2]); atomicMax(&L.uhi[1], key[3]);
+  __syncthreads();
+  double ext[2][2];
+  int idx[2][2];
+  for (int a = 0; a < 2; ++a) {
+    ext[a][0] = M > 0 ? (double)ord_value((unsigned)(L.ulo[a] >> 32)) : 0.0;
+    ext[a][1] = M > 0 ? (double)ord_value((unsigned)(L.uhi[a] >> 32)) : 0.0;
+    idx[a][0] = M > 0 ? (int)(unsigned)L.ulo[a] : 0;
+    idx[a][1] = M > 0 ? (int)(unsigned)L.uhi[a] : 0;
+  }
+  const double rx = ext[0][1] - ext[0][0], ry = ext[1][1] - ext[1][0];
+  double side = rx >= ry ? rx : ry, lo[2];
+  if (M < 2 || !(side > 0.0)) {
+    st |= RTU_ST_MASK_SMALL;
+    side = 1.0;
+    lo[0] = ext[0][0];
+    lo[1] = ext[1][0];
+  } else {
+    for (int a = 0; a < 2; ++a) lo[a] = 0.5 * (ext[a][0] + ext[a][1]) - 0.5 * side;
+  }
+  knot_table_uniform(S, b, axis, (float)lo[axis], (float)side);
+  float* kn = S.knots + ((size_t)b * 2 + axis) * 2 * K;
+  float* kd = S.kdbg + ((size_t)b * 2 + axis) * 2 * K;
+  int* sel = S.sel + ((size_t)b * 2 + axis) * 2 * K;
+  if (tid < 2 * K) {
+    kn[tid] = 0.f;
+    kd[tid] = 0.f;
+    sel[tid] = tid < 2 ? idx[axis][tid] : 0;
+  }
+  if (tid < K) S.dp[((size_t)b * 2 + axis) * K + tid] = -1.f;
+  if (tid == 0) {
+    if (axis == 0) {
+      double* sd = S.stdv + (size_t)b * 4;
+      sd[0] = lo[0]; sd[1] = lo[1]; sd[2] = side; sd[3] = rx >= ry ? 0.0 : 1.0;
+    }
+    S.st[b * ST_WORDS + axis] = st;
+  }
+}
+
 __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* smem) {
   SelLds& L = *reinterpret_cast<SelLds*>(smem);
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -416,7 +488,8 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
   const Sie sie = make_sie(lensp);
   float* zb = S.zbuf + ((size_t)b * 2 + axis) * M;
   uint32_t st = 0;
-  if (M < K + 1) st |= RTU_ST_MASK_SMALL;
+  if (M < (S.uniform ? 2 : K + 1)) st |= RTU_ST_MASK_SMALL;
+  unsigned long long ukey[4] = {~0ull, 0ull, ~0ull, 0ull};   // uniform grid: min x, max x, min y, max y
   if (tid == 0) L.stat = 0;
   if (tid < 2 * K) { L.tval[tid] = 0.f; L.tidx[tid] = 0; }
 
@@ -446,6 +519,11 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
     const unsigned u = ord_key(v);
     umin = min(umin, u);
     umax = max(umax, u);
+    if (S.uniform) {
+      const unsigned long long kx = sel_key(bx, m), ky = sel_key(by, m);
+      ukey[0] = min(ukey[0], kx); ukey[1] = max(ukey[1], kx);
+      ukey[2] = min(ukey[2], ky); ukey[3] = max(ukey[3], ky);
+    }
   }
   {
     double v4[4] = {sx, sy, sxx, syy};
@@ -464,6 +542,10 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
       umax = max(umax, L.ured[16 + w]);
     }
     __syncthreads();
+  }
+  if (S.uniform) {
+    prep_uniform(S, b, axis, L, ukey, M, st);
+    return;
   }
   const double Md = (double)(M > 0 ? M : 1);
   const double mux = sx / Md, muy = sy / Md;
@@ -1033,7 +1115,7 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   __syncthreads();
   // knot partials of this tile: the adjoint of each interval, then per knot
   // the intervals it bounds (dX (x), dS (x), dX (y), dS (y))
-  if (threadIdx.x < 2 * (K + 1)) {
+  if (!S.uniform && threadIdx.x < 2 * (K + 1)) {
     const int ax = threadIdx.x / (K + 1), k = threadIdx.x - ax * (K + 1);
     double v[4];
     km_knots(k, H.km[ax][k], H.X[ax], H.Sl[ax], H.ih[ax], H.du, v);
@@ -1041,7 +1123,12 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   }
   __syncthreads();
   double* kbo = S.kbar + ((size_t)b * S.ray_tiles + tile) * 4 * K;
-  for (int q = threadIdx.x; q < 4 * K; q += blockDim.x) {
+  if (S.uniform) {   // the raw moments m0, m1 of the one interval, per axis
+    for (int q = threadIdx.x; q < 4 * K; q += blockDim.x) {
+      const int ax = q / (2 * K), rem = q - ax * 2 * K;
+      kbo[q] = rem < 2 ? H.km[ax][0][rem] : 0.0;
+    }
+  } else for (int q = threadIdx.x; q < 4 * K; q += blockDim.x) {
     const int ax = q / (2 * K), rem = q - ax * 2 * K, o = rem >= K ? 2 : 0, j = rem - (o ? K : 0);
     const double (*kv)[4] = H.km[ax];
     double v = 0.0;
@@ -1277,6 +1364,7 @@ struct PostLds {
   double xbar[2][K];      // d loss / d X (beta units), after the slope chain
   double wk[2][K];        // -S_k^2 d loss / d S_k
   double lsum[RTU_MAX_LENS + 1];   // raw sums
+  double ub[4];           // uniform grid: d loss / d (x_min, x_max, y_min, y_max)
   uint32_t stat;
 };
 
@@ -1315,13 +1403,32 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
                    P.part, [&](int c, double v) { P.red[c] = v; });
     __syncthreads();
     // the factors -S_k^2 dS_k, one thread per (axis, k); then the sums over k
-    if (tid < 2 * K) {
+    if (!S.uniform && tid < 2 * K) {
       const int ax = tid / K, k = tid - ax * K;
       const double d = S.dp[((size_t)b * 2 + ax) * K + k];
       P.wk[ax][k] = d > 0.0 ? -P.red[ax * 2 * K + K + k] / (d * d) : 0.0;
     }
+    // uniform grid: y = (beta - lo) / L with the moment sums m0 = sum ybar,
+    // m1 = sum ybar y per axis gives d/d lo_a = -m0_a / L and
+    // d/d L = -(m1_x + m1_y) / L; lo_a = (min_a + max_a)/2 - L/2 and L the
+    // longer range (x on a tie) carry them to the four extremes.  A
+    // degenerate box (status bit 4) is a constant.
+    if (S.uniform && tid == 0) {
+      const double* sd = S.stdv + (size_t)b * 4;
+      const double side = sd[2];
+      const bool degen = (S.st[b * ST_WORDS] & RTU_ST_MASK_SMALL) != 0;
+      const double glo[2] = {-P.red[0] / side, -P.red[2 * K] / side};
+      const double gL = -(P.red[1] + P.red[2 * K + 1]) / side;
+      const double gc = gL - 0.5 * (glo[0] + glo[1]);
+      const int lax = (int)sd[3];   // the axis whose range is L
+      for (int a = 0; a < 2; ++a) {
+        const double dl = a == lax ? 1.0 : 0.0;
+        P.ub[2 * a] = degen ? 0.0 : 0.5 * glo[a] - gc * dl;
+        P.ub[2 * a + 1] = degen ? 0.0 : 0.5 * glo[a] + gc * dl;
+      }
+    }
     __syncthreads();
-    if (tid < 2 * K) {
+    if (!S.uniform && tid < 2 * K) {
       const int ax = tid / K, l = tid - ax * K;
       double xb = P.red[ax * 2 * K + l];
 #pragma unroll
@@ -1336,13 +1443,22 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
     if (tid < 4 * K) {
       double* row = mp + tid * nc;
       for (int q = 0; q < nc; ++q) row[q] = 0.0;
-      const int ax = tid / (2 * K), r = tid - ax * 2 * K, k = r >> 1;
-      const double t = S.rank_t[k];
-      const double wgt = (r & 1) ? t : 1.0 - t;
-      int m = S.sel[((size_t)b * 2 + ax) * 2 * K + r];
+      int ax, m;
+      double bb;
+      if (S.uniform) {   // rows 0..3: the minimum and maximum of x, then of y
+        ax = (tid >> 1) & 1;
+        m = S.sel[((size_t)b * 2 + ax) * 2 * K + (tid & 1)];
+        bb = tid < 4 ? P.ub[tid] : 0.0;
+      } else {
+        ax = tid / (2 * K);
+        const int r = tid - ax * 2 * K, k = r >> 1;
+        const double t = S.rank_t[k];
+        const double wgt = (r & 1) ? t : 1.0 - t;
+        m = S.sel[((size_t)b * 2 + ax) * 2 * K + r];
+        bb = wgt * P.xbar[ax][k];
+      }
       const int M = obs_M(S);
       m = m < 0 ? 0 : (m >= M ? M - 1 : m);
-      const double bb = wgt * P.xbar[ax][k];
       if (bb != 0.0 && M > 0) {
         const int p = S.mask_idx[m];
         const int i = p / S.n_img, j = p - i * S.n_img;

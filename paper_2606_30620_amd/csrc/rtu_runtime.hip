@@ -77,7 +77,7 @@ bool valid_geometry(const rtu_geometry* g) {
   if (g->n_sub_max < 0 || g->n_sub_max > RTU_MAX_SUB) return false;
   if (g->n_gauss < 0 || g->n_gauss > RTU_MAX_GAUSS) return false;
   if (g->k_nodes != RTU_K_NODES) return false;
-  if (!(g->pixel_scale > 0.f) || !(g->tnfw_tau >= 0.f) || (g->flags & ~RTU_GEOM_RADIX_SELECT) != 0) return false;
+  if (!(g->pixel_scale > 0.f) || !(g->tnfw_tau >= 0.f) || (g->flags & ~(RTU_GEOM_RADIX_SELECT | RTU_GEOM_UNIFORM)) != 0) return false;
   return true;
 }
 
@@ -112,6 +112,7 @@ void fill_geometry(const rtu_geometry* g, SysDev& h) {
   h.tau = g->tnfw_tau;
   h.inv_ss2 = 1.f / (float)(g->supersample * g->supersample);
   h.sel_radix = (g->flags & RTU_GEOM_RADIX_SELECT) ? 1 : 0;
+  h.uniform = (g->flags & RTU_GEOM_UNIFORM) ? 1 : 0;
   h.ray_tx = (g->n_img + RAY_TILE - 1) / RAY_TILE;
   h.ray_tiles = h.ray_tx * h.ray_tx;
   h.adj_wcap = adj_window_cap(h);

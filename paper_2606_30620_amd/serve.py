@@ -72,7 +72,7 @@ def make_requests(n: int, rate: float, steps: int = 200, samples: int = 1, seed:
 
 def _geometry(lib, g: synth.Geometry):
     return lib.make_geometry(g.n_img, g.supersample, g.n_src, g.psf_size, g.pixel_scale, g.n_sub_max,
-                             g.tnfw_tau, n_gauss=g.n_gauss)
+                             g.tnfw_tau, flags=lib.GEOM_UNIFORM if g.uniform else 0, n_gauss=g.n_gauss)
 
 
 @dataclasses.dataclass

@@ -54,6 +54,8 @@ inline unsigned min(unsigned a, unsigned b) { return a < b ? a : b; }
 inline unsigned max(unsigned a, unsigned b) { return a > b ? a : b; }
 inline long min(long a, long b) { return a < b ? a : b; }
 inline long max(long a, long b) { return a > b ? a : b; }
+inline unsigned long long min(unsigned long long a, unsigned long long b) { return a < b ? a : b; }
+inline unsigned long long max(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
 using std::isfinite;
 using std::isinf;
 using std::isnan;
@@ -156,6 +158,7 @@ inline unsigned __umulhi(unsigned a, unsigned b) { return (unsigned)(((uint64_t)
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
 inline int __clz(int v) { return v ? __builtin_clz((unsigned)v) : 32; }
 inline float __int_as_float(int v) { float f; memcpy(&f, &v, 4); return f; }
+inline float __uint_as_float(unsigned v) { float f; memcpy(&f, &v, 4); return f; }
 inline int __float_as_int(float f) { int v; memcpy(&v, &f, 4); return v; }
 inline unsigned __float_as_uint(float f) { unsigned v; memcpy(&v, &f, 4); return v; }
 inline double __hiloint2double(int hi, int lo) {

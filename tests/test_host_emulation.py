@@ -114,3 +114,14 @@ def test_sweep_case_with_52_masked_pixels(driver, mode):
 def test_small_masks_both_selections(driver, npix, flags):
     p = _small_mask(npix)
     _compare(_run(driver, p, flags=flags), p)
+
+
+@pytest.mark.parametrize("case", ["case4", "mask10", "mask1"])
+def test_uniform_grid_mode(driver, case):
+    """RTU_GEOM_UNIFORM: the box from the masked rays' extremes and its
+    adjoint, on the same data-dependent cases (one masked pixel: the
+    degenerate box)."""
+    import dataclasses
+    p = _case4() if case == "case4" else _small_mask(10 if case == "mask10" else 1)
+    p = dataclasses.replace(p, geom=dataclasses.replace(p.geom, uniform=True))
+    _compare(_run(driver, p, flags=2), p)
