@@ -368,6 +368,7 @@ def main():
     ap.add_argument("--no-light", action="store_true", help="skip the lens-light section")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the RTU vs uniform grid N_src sweep")
     ap.add_argument("--c4-iters", type=int, default=500)
     ap.add_argument("--serve-only", action="store_true", help="only the serving section (for profiling)")
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -417,6 +418,10 @@ def main():
         line["serving"] = serving_bench(args.serve_requests, args.serve_steps)
     if not args.no_light:
         line["lens_light"] = light_bench(20, 5)
+    if not args.no_sweep:
+        from paper_2606_30620_amd import sweep
+        note("N_src sweep, RTU and uniform grids")
+        line["nsrc_sweep"] = sweep.nsrc_sweep()
     if args.calib_copy:
         src = torch.ones(args.calib_copy // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -253,12 +253,13 @@ int rtu_profile_end(rtu_plan p, double* stage_ms, int32_t* launches);
  * epsilon 1e-8) on (mu, rho) to maximise it.  State stays on the device. */
 typedef struct rtu_fit_s* rtu_fit;
 
-/* Lens parameters whose guide lives in log space, as a bit mask over the lens
- * parameter index i (word i / 32, bit i % 32): their sample is z = exp(u),
- * u = mu + exp(rho) eps, the gradient is chained through z, and the prior is
- * flat in u (log-uniform in z; for positive parameters such as a subhalo's
- * kappa_s and r_s, which then never reach zero).  mu and rho of such a
- * parameter are those of u. */
+/* Lens and power-spectrum parameters whose guide lives in log space, as a
+ * bit mask over the index i into (lens, ps) (word i / 32, bit i % 32; i <
+ * n_lens + 4): their sample is z = exp(u), u = mu + exp(rho) eps, the
+ * gradient is chained through z, and the prior is flat in u (log-uniform in
+ * z; for positive parameters such as a subhalo's kappa_s and r_s or the
+ * spectrum's sigma and zeta, which then never reach zero).  mu and rho of
+ * such a parameter are those of u.  Bits at latent indices are ignored. */
 #define RTU_LOG_MASK_WORDS 3
 
 /* Creates a fit on plan p (which must hold an observation) with S samples per

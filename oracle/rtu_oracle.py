@@ -675,8 +675,9 @@ def elbo_and_grad(mu, rho, eps, obs, n_lens: int, n_sub=0, tau=0.0, log_params=(
         ELBO = -mean_s loss(z_s) - sum_p ln(sigma_p sqrt(2 pi)) - (n^2/2) ln 2 pi
                + sum(rho) + (dim/2)(1 + ln 2 pi),
     i.e. Gaussian likelihood, flat priors on lens and spectrum parameters, a
-    unit normal prior on the latent, and the guide entropy.  The lens
-    parameters listed in log_params have their guide over the logarithm:
+    unit normal prior on the latent, and the guide entropy.  The lens and
+    spectrum parameters listed in log_params (indices into z) have their
+    guide over the logarithm:
     z_i = exp(mu_i + exp(rho_i) eps_i), with a flat prior on the logarithm
     (log-uniform on z_i), so the same formula holds.  Returns the ELBO and
     its gradient with respect to mu and rho."""

@@ -45,8 +45,8 @@ class FitRequest(C.Structure):
 
 
 def log_mask_of(indices) -> "C.Array":
-    """Bit mask (RTU_LOG_MASK_WORDS words) of the lens parameters whose guide
-    lives in log space."""
+    """Bit mask (RTU_LOG_MASK_WORDS words) of the lens and power-spectrum
+    parameters (indices into (lens, ps)) whose guide lives in log space."""
     m = (C.c_uint32 * LOG_MASK_WORDS)()
     for i in indices or ():
         m[i // 32] |= 1 << (i % 32)

@@ -39,7 +39,7 @@ __device__ __forceinline__ float eps_at(const FitDev& F, const float* eps, int s
 }
 
 __device__ __forceinline__ bool is_log(const FitDev& F, int i) {
-  return i < F.n_lens && ((F.log_mask[i >> 5] >> (i & 31)) & 1u);
+  return i < F.n_lens + 4 && ((F.log_mask[i >> 5] >> (i & 31)) & 1u);
 }
 
 // z_s = mu + exp(rho) eps_s (z = exp of that for a log-space parameter),
@@ -63,7 +63,10 @@ __device__ __forceinline__ float grad_at(const FitDev& F, int s, int i) {
     const float g = F.g_lens[(size_t)s * F.n_lens + i];
     return is_log(F, i) ? g * F.z_lens[(size_t)s * F.n_lens + i] : g;
   }
-  if (i < F.n_lens + 4) return F.g_ps[(size_t)s * 4 + (i - F.n_lens)];
+  if (i < F.n_lens + 4) {
+    const float g = F.g_ps[(size_t)s * 4 + (i - F.n_lens)];
+    return is_log(F, i) ? g * F.z_ps[(size_t)s * 4 + (i - F.n_lens)] : g;
+  }
   return F.g_lat[(size_t)s * F.n_src2 + (i - F.n_lens - 4)];
 }
 

@@ -44,6 +44,15 @@ def test_elbo_step_with_log_space_subhalo_scales_matches_oracle():
                          "latent": slice(19, None)}, log_params=[7, 8, 11, 12], n_sub=2)
 
 
+def test_elbo_step_with_log_space_spectrum_matches_oracle():
+    """The power spectrum's sigma and zeta in log space as well."""
+    say("[gpu] fit: one ELBO+Adam step, log-space spectrum sigma and zeta, 48x48 ss=2 n_src=16, S=2")
+    g = synth.Geometry(48, 0.08, 2, 16, 15, 1.0)
+    p = synth.make_problem("X", batch=1, seed=35, geom=g)
+    _elbo_step_check(p, {"lens": slice(0, 7), "ps": slice(7, 11), "latent": slice(11, None)},
+                     log_params=[7, 9])
+
+
 def _elbo_step_check(p, groups, log_params=(), n_sub=0):
     from paper_2606_30620_amd import _lib, api
     plan = api.plan_for_problem(p, max_batch=2)
