@@ -225,12 +225,19 @@ def chebyshev_nodes(K: int = K_NODES):
     return 0.5 * (1.0 - torch.cos((2.0 * k - 1.0) * math.pi / (2.0 * K)))
 
 
-def standardise(bx, by):
+def standardise(bx, by, w=None):
     """App. C step (i): subtract the mean per axis and divide by the smaller of
-    the two (population) standard deviations."""
-    mx, my = bx.mean(), by.mean()
-    sx = torch.sqrt(((bx - mx) ** 2).mean())
-    sy = torch.sqrt(((by - my) ** 2).mean())
+    the two (population) standard deviations.  With ray weights w (Sec. 6.3)
+    the moments are weighted (a ray of integer weight k counts as k rays)."""
+    if w is None:
+        mx, my = bx.mean(), by.mean()
+        sx = torch.sqrt(((bx - mx) ** 2).mean())
+        sy = torch.sqrt(((by - my) ** 2).mean())
+    else:
+        W = w.sum()
+        mx, my = (w * bx).sum() / W, (w * by).sum() / W
+        sx = torch.sqrt((w * (bx - mx) ** 2).sum() / W)
+        sy = torch.sqrt((w * (by - my) ** 2).sum() / W)
     s = torch.minimum(sx, sy)
     return mx, my, s
 
@@ -257,6 +264,30 @@ def quantiles_type7(z, u, picks=None):
     j1 = torch.clamp(j + 1, max=M - 1)
     q = (1.0 - t) * zs[j] + t * zs[j1]
     return q, order[j], order[j1]
+
+
+def quantiles_weighted(z, w, u, picks=None):
+    """Quantiles of rays with weights (Sec. 6.3, the weighted RTU grid).
+    Reading: a weight counts rays, so that a ray of integer weight k stands for
+    k copies of itself: in sorted order (ties by ray index) ray i holds the
+    cumulative-weight interval [C_{i-1}, C_i), E(r) is the ray holding
+    position r, and with h = (W - 1) u, W = sum w, j = floor h,
+        Q(u) = (1 - (h - j)) z_E(j) + (h - j) z_E(j+1),
+    E clamped to the last ray.  Unit weights give type 7 (quantiles_type7);
+    rays of weight 0 are never picked.  picks as for quantiles_type7."""
+    W = w.sum()
+    h = (W - 1.0) * u
+    j = torch.floor(h)
+    t = h - j
+    if picks is not None:
+        i0, i1 = (torch.as_tensor(np.asarray(p), dtype=torch.long) for p in picks)
+        return (1.0 - t) * z[i0] + t * z[i1], i0, i1
+    zs, order = torch.sort(z, stable=True)
+    C = torch.cumsum(w[order], 0)
+    M = z.shape[0]
+    e0 = torch.clamp(torch.searchsorted(C, j, right=True), max=M - 1)
+    e1 = torch.clamp(torch.searchsorted(C, j + 1.0, right=True), max=M - 1)
+    return (1.0 - t) * zs[e0] + t * zs[e1], order[e0], order[e1]
 
 
 def chebyshev_T_U(tn, D: int):
@@ -310,18 +341,20 @@ def cdf_spline(z, X, S, u):
     return torch.where(k == 0, g_lo, torch.where(k >= K, g_hi, g_in))
 
 
-def build_transform(bxm, bym, K: int = K_NODES, picks=None):
+def build_transform(bxm, bym, K: int = K_NODES, picks=None, weights=None):
     """RTU transform from the masked rays (Sec. 2.2; App. C steps i-iv).
     Returns a dict with mu, s, knots X[2][K], slopes S[2][K], nodes u, the
     selected ray indices and the status bits.  picks (optional, per axis the
     pair (i0, i1) of quantiles_type7) fixes which rays stand for the order
-    statistics."""
+    statistics.  weights (optional, per masked ray): the weighted RTU grid of
+    Sec. 6.3 (quantiles_weighted, weighted standardisation)."""
     u = chebyshev_nodes(K)
-    mx, my, s = standardise(bxm, bym)
+    mx, my, s = standardise(bxm, bym, weights)
     out = {"u": u, "mu": (mx, my), "s": s, "status": 0}
     X, S, idx = [], [], []
     for ax, zc in enumerate(((bxm - mx) / s, (bym - my) / s)):
-        q, i0, i1 = quantiles_type7(zc, u, None if picks is None else picks[ax])
+        pk = None if picks is None else picks[ax]
+        q, i0, i1 = quantiles_type7(zc, u, pk) if weights is None else quantiles_weighted(zc, weights, u, pk)
         dp = qf_polynomial(q, u)
         # X_k = p(u_k) equals q_k exactly (interpolation); q_k is used directly.
         eps = 1e-6 * (q[-1] - q[0]).detach()
@@ -462,9 +495,10 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
     obs: dict with n_img, pix, ss, image[N,N], sigma[N,N], psf[K,K], mask[N,N],
     and optionally n_gauss: the last N_PER_GAUSS n_gauss entries of lens are
     lens-light Gaussians (mge_light), added to every sub-ray's value before the
-    sub-ray mean and the PSF; and grid = "uniform": the source grid spans the
+    sub-ray mean and the PSF; grid = "uniform": the source grid spans the
     smallest square box of the masked rays (Sec. 2.1, uniform_box_of) instead
-    of the RTU transform.
+    of the RTU transform; ray_weights[N,N]: per-pixel weights of the masked
+    rays for the weighted RTU grid (Sec. 6.3, quantiles_weighted).
     uniform_box: if given as (x_lo, y_lo, side), the RTU transform is replaced by
     the plain affine map of that box onto the unit square (the paper's uniform
     grid, Sec. 2.1).
@@ -504,7 +538,9 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
         gx, gy = r32(gx), r32(gy)
     elif uniform_box is None:
         bxm, bym = ray_shoot(xc[mflat], yc[mflat], lens, n_sub, tau)
-        tr = build_transform(r32(bxm), r32(bym), picks=picks)
+        rw = obs.get("ray_weights")
+        rw = None if rw is None else _t(rw).reshape(-1)[mflat]
+        tr = build_transform(r32(bxm), r32(bym), picks=picks, weights=rw)
         status |= tr["status"]
         if round32:
             tr["X"] = [r32(x) for x in tr["X"]]
@@ -652,11 +688,18 @@ def cell_edge_slack(lens, ps, w, obs, n_sub=0, tau=0.0, delta=None, side=0):
     sel = torch.tensor([p[0] for p in picks])
     axes = torch.tensor([p[1] for p in picks])
 
+    rw = obs.get("ray_weights")
+    rw = None if rw is None else _t(rw).reshape(-1)[mflat]
+    uniform = obs.get("grid", "rtu") == "uniform"
+
     def g_of(lv):
         bxm, bym = ray_shoot(xc[mflat], yc[mflat], lv, n_sub, tau)
-        tr = build_transform(bxm, bym)
         bx, by = ray_shoot(xr[sel], yr[sel], lv, n_sub, tau)
-        g1, g2 = rtu_transform(bx, by, tr)
+        if uniform:
+            box = uniform_box_of(bxm, bym)
+            g1, g2 = (bx - box["lo"][0]) / box["side"], (by - box["lo"][1]) / box["side"]
+        else:
+            g1, g2 = rtu_transform(bx, by, build_transform(bxm, bym, weights=rw))
         return torch.where(axes == 0, g1, g2)
 
     J = torch.autograd.functional.jacobian(g_of, lens_t, vectorize=True)     # [picks, n_lens]
