@@ -142,6 +142,24 @@ int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma
 /* Number of masked pixels M of the current observation (-1 if none). */
 int32_t rtu_masked_count(rtu_plan p);
 
+/* Weighted RTU grid (Sec. 6.3, "Extension to weighted RTU grid"): per-pixel
+ * weights of the masked rays when the eCDFs are built (for example the
+ * observed brightness or SNR), host float [n_img][n_img]; only masked pixels
+ * are read.  A weight counts rays: a masked ray of weight w stands for w
+ * rays, so integer weights give the quantiles of the rays repeated that many
+ * times and unit weights the unweighted grid; with W the total weight, the
+ * order statistic at cumulative-weight position r is the ray whose interval
+ * of the weights summed in sorted order (ties by ray index) holds r, the
+ * quantile at node u_k interpolates linearly between positions
+ * floor((W-1) u_k) and that + 1, and the standardisation uses weighted
+ * moments.  The weights are constants (no gradient).  RTU_EINVAL for a
+ * negative or non-finite weight or W < 1; RTU_ESTATE before
+ * rtu_set_observation.  NULL restores the unweighted grid; a new observation
+ * drops the weights.  The copy is queued on `stream` through a pinned buffer
+ * (no device-wide sync unless the scratch array must grow).  Not available
+ * in rtu_loss_grad_noalloc and the fleet. */
+int rtu_set_ray_weights(rtu_plan p, const float* weights, void* stream);
+
 /* ---- allocation-free evaluation ----------------------------------------
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -575,7 +575,8 @@ def obs_from_problem(p) -> dict:
     return {"n_img": g.n_img, "pix": float(np.float32(g.pixel_scale)), "ss": g.supersample,
             "image": _t(p.image), "sigma": _t(p.noise_sigma), "psf": _t(p.psf),
             "mask": torch.as_tensor(p.mask.astype(np.int64)), "tau": g.tnfw_tau,
-            "n_gauss": getattr(g, "n_gauss", 0), "grid": "uniform" if getattr(g, "uniform", False) else "rtu"}
+            "n_gauss": getattr(g, "n_gauss", 0), "grid": "uniform" if getattr(g, "uniform", False) else "rtu",
+            "ray_weights": None if getattr(p, "ray_weights", None) is None else _t(p.ray_weights)}
 
 
 def loss_grad(lens, ps, w, obs, n_sub=0, tau=0.0, want_grad=True, return_all=False, cell_shift=0.0,

@@ -75,6 +75,7 @@ def _load():
     lib.rtu_plan_create.argtypes = [C.POINTER(Geometry), I32, I32, C.POINTER(P)]
     lib.rtu_plan_destroy.argtypes = [P]
     lib.rtu_set_observation.argtypes = [P, VP, VP, VP, VP, VP]
+    lib.rtu_set_ray_weights.argtypes = [P, VP, VP]
     lib.rtu_masked_count.argtypes = [P]
     lib.rtu_masked_count.restype = I32
     lib.rtu_loss_grad.argtypes = [P, I32] + [VP] * 11 + [VP]
@@ -105,7 +106,7 @@ def _load():
     lib.rtu_fleet_stats.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(SZ), C.POINTER(C.c_int64)]
     lib.rtu_strerror.argtypes = [C.c_int]
     lib.rtu_strerror.restype = C.c_char_p
-    for fn in ("rtu_plan_create", "rtu_plan_destroy", "rtu_set_observation", "rtu_loss_grad",
+    for fn in ("rtu_plan_create", "rtu_plan_destroy", "rtu_set_observation", "rtu_set_ray_weights", "rtu_loss_grad",
                "rtu_debug_fetch", "rtu_profile_begin", "rtu_profile_end", "rtu_fit_create",
                "rtu_fit_destroy", "rtu_fit_step", "rtu_fit_read", "rtu_fit_last_outputs",
                "rtu_fit_get_state", "rtu_fit_set_state", "rtu_fit_samples", "rtu_fleet_create",
@@ -198,6 +199,16 @@ class Plan:
         assert k.size == self.geom.psf_size ** 2
         check(LIB.rtu_set_observation(self._h, _ptr(a), _ptr(s), _ptr(k), _ptr(m), _stream_ptr(stream)),
               "rtu_set_observation")
+
+    def set_ray_weights(self, weights, stream=None) -> None:
+        """Per-pixel ray weights of the weighted RTU grid ([n_img, n_img]), or
+        None for the unweighted grid; after set_observation."""
+        if weights is None:
+            check(LIB.rtu_set_ray_weights(self._h, None, _stream_ptr(stream)), "rtu_set_ray_weights")
+            return
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        assert w.size == self.geom.n_img ** 2
+        check(LIB.rtu_set_ray_weights(self._h, _ptr(w), _stream_ptr(stream)), "rtu_set_ray_weights")
 
     def loss_grad(self, lens, ps, latent, n_sub=None, *, loss, status, chi2_mask=None, grad_lens=None,
                   grad_ps=None, grad_latent=None, model=None, stream=None) -> None:
@@ -390,7 +401,8 @@ class Fleet:
 def exported_symbols():
     """Names declared in include/rtu.h that the loaded library exports."""
     return [n for n in ("rtu_n_lens", "rtu_workspace_bytes", "rtu_plan_create", "rtu_plan_destroy",
-                        "rtu_set_observation", "rtu_masked_count", "rtu_loss_grad", "rtu_loss_grad_noalloc",
+                        "rtu_set_observation", "rtu_set_ray_weights", "rtu_masked_count", "rtu_loss_grad",
+                        "rtu_loss_grad_noalloc",
                         "rtu_debug_fetch",
                         "rtu_profile_begin", "rtu_profile_end", "rtu_fit_create", "rtu_fit_destroy",
                         "rtu_fit_dim", "rtu_fit_step", "rtu_fit_read", "rtu_fit_last_outputs",

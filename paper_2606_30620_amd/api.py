@@ -36,6 +36,8 @@ def plan_for_problem(problem, max_batch: Optional[int] = None, device: int = 0, 
                          g.n_sub_max, g.tnfw_tau, flags, g.n_gauss)
     plan = Plan(geom, max_batch or problem.batch, device)
     plan.set_observation(problem.image, problem.noise_sigma, problem.psf, problem.mask)
+    if getattr(problem, "ray_weights", None) is not None:
+        plan.set_ray_weights(problem.ray_weights)
     return plan
 
 

@@ -85,6 +85,13 @@ struct SysDev {
   const int* mask_idx;        // [M] row-major pixel index of each masked pixel
   const int* rank_j;          // [K] floor((M-1) u_k)
   const double* rank_t;       // [K] (M-1) u_k - rank_j
+  // weighted RTU grid (ray_w non-null): per masked ray its weight, the total
+  // W, per node floor((W-1) u_k) and its fraction, and sort scratch
+  const float* ray_w;         // [M]
+  double wsum;
+  const double* wr0;          // [K]
+  const double* wt;           // [K]
+  uint2* wsort;               // [B][2 axes][2][M] (order key, ray index)
   // per-call inputs
   const float* lens;          // [B][n_lens]
   const int* n_sub;           // [B] or null

@@ -378,6 +378,123 @@ __device__ void select_by_radix(SelLds& L, const float* zb, int M, unsigned umin
 // pieces g = u_l + du (3t^2 - 2t^3) + h S_l (t^3 - 2t^2 + t) + h S_r (t^3 - t^2)
 // as cubics in t, scaled to grid coordinates, with linear continuation by the
 // end slopes outside the knots.
+// ---- weighted RTU grid (Sec. 6.3): weights count rays, so the order
+// statistic at cumulative-weight position r is the ray whose interval
+// [C_{i-1}, C_i) of the weights summed in sorted order (ties by index) holds
+// r.  The masked rays are sorted by a stable least-significant-digit radix
+// sort of their 32-bit order keys (the index order of equal keys is kept) in
+// global scratch, then the weights are summed in that order in FP64 chunk by
+// chunk and each target position finds its ray.
+
+// Inclusive FP64 sum over the block of v (every thread calls); the block
+// total in *total.  wsum: one double per wave of LDS.
+__device__ __forceinline__ double block_scan_f64(double v, double* wsum, double* total) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  double incl = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const double t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  double off = 0.0, tot = 0.0;
+  for (int q = 0; q < nw; ++q) {
+    if (q < wv) off += wsum[q];
+    tot += wsum[q];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl;
+}
+
+// Stable sort of (order key, ray index) pairs of the M masked rays by key,
+// four passes of 8-bit digits between A and Bf; the result is in A.
+__device__ void weighted_sort(SelLds& L, uint2* A, uint2* Bf, int M) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  int* hist = L.c.hist;             // [256] digit counts, then the running bases
+  int* cnt = L.c.hist + 256;        // [nw][256] per-wave digit counts of a chunk
+  for (int pass = 0; pass < 4; ++pass) {
+    const int sh = 8 * pass;
+    for (int d = tid; d < 256; d += nt) hist[d] = 0;
+    __syncthreads();
+    for (int m = tid; m < M; m += nt) atomicAdd(&hist[(A[m].x >> sh) & 255], 1);
+    __syncthreads();
+    if (tid == 0) {
+      int run = 0;
+      for (int d = 0; d < 256; ++d) { const int c = hist[d]; hist[d] = run; run += c; }
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < M; c0 += nt) {
+      const int m = c0 + tid;
+      const bool valid = m < M;
+      const uint2 e = valid ? A[m] : make_uint2(0u, 0u);
+      const int d = (int)((e.x >> sh) & 255);
+      // lanes of this wave with the same digit: one ballot per digit bit
+      unsigned long long same = __ballot(valid);
+      for (int bit = 0; bit < 8; ++bit) {
+        const unsigned long long on = __ballot(((d >> bit) & 1) != 0);
+        same &= ((d >> bit) & 1) ? on : ~on;
+      }
+      const int local = __popcll(same & ((1ull << lane) - 1ull));
+      for (int q = tid; q < nw * 256; q += nt) cnt[q] = 0;
+      __syncthreads();
+      if (valid && local == 0) cnt[wv * 256 + d] = __popcll(same);
+      __syncthreads();
+      if (valid) {
+        int pos = hist[d] + local;
+        for (int q = 0; q < wv; ++q) pos += cnt[q * 256 + d];
+        Bf[pos] = e;
+      }
+      __syncthreads();
+      for (int dd = tid; dd < 256; dd += nt) {
+        int s = 0;
+        for (int q = 0; q < nw; ++q) s += cnt[q * 256 + dd];
+        hist[dd] += s;
+      }
+      __syncthreads();
+    }
+    uint2* t = A; A = Bf; Bf = t;
+  }
+}
+
+// The 2K order statistics of the weighted quantiles: target t of node t/2 at
+// position wr0[t/2] + (t & 1); results in L.tval / L.tidx with the identity
+// map L.tmap.  A target beyond the total weight takes the last ray in sorted
+// order.
+__device__ void select_weighted(const SysDev& S, SelLds& L, const float* zb, int M, int b, int axis) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  uint2* A = S.wsort + ((size_t)b * 2 + axis) * 2 * M;
+  uint2* Bf = A + M;
+  for (int m = tid; m < M; m += nt) A[m] = make_uint2(ord_key(zb[m]), (unsigned)m);
+  __syncthreads();
+  weighted_sort(L, A, Bf, M);
+  if (tid < 2 * K) { L.tidx[tid] = -1; L.tmap[tid] = tid; }
+  if (tid == 0) L.ntgt = 2 * K;
+  double* wsum = reinterpret_cast<double*>(L.c.cand);
+  double run = 0.0;
+  __syncthreads();
+  for (int c0 = 0; c0 < M; c0 += nt) {
+    const int m = c0 + tid;
+    const uint2 e = m < M ? A[m] : make_uint2(0u, 0u);
+    const double w = m < M ? (double)S.ray_w[e.y] : 0.0;
+    double tot;
+    const double hi = run + block_scan_f64(w, wsum, &tot), lo = hi - w;
+    if (m < M && w > 0.0)
+      for (int t = 0; t < 2 * K; ++t) {
+        const double r = S.wr0[t >> 1] + (double)(t & 1);
+        if (lo <= r && r < hi) { L.tidx[t] = (int)e.y; L.tval[t] = zb[e.y]; }
+      }
+    run += tot;
+  }
+  __syncthreads();
+  if (tid < 2 * K && L.tidx[tid] < 0 && M > 0) {
+    const uint2 e = A[M - 1];
+    L.tidx[tid] = (int)e.y;
+    L.tval[tid] = zb[e.y];
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void knot_table(const SysDev& S, int b, int ax, const float* X, const float* Sl,
                                            const float* dp) {
   KnotTab& T = S.ktab[b];
@@ -509,7 +626,8 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
     const float y = ((float)i - 0.5f * (float)(S.n_img - 1)) * S.pix;
     float bx, by;
     shoot(S, sie, lensp, nsub, x, y, bx, by);
-    sx += bx; sy += by; sxx += (double)bx * bx; syy += (double)by * by;
+    const double wm = S.ray_w ? (double)S.ray_w[m] : 1.0;   // weighted grid: weighted moments
+    sx += wm * bx; sy += wm * by; sxx += wm * bx * bx; syy += wm * by * by;
     const float v = (axis == 0 ? bx : by) + 0.0f;
     zb[m] = v;
     if (isfinite(v)) {
@@ -547,14 +665,16 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
     prep_uniform(S, b, axis, L, ukey, M, st);
     return;
   }
-  const double Md = (double)(M > 0 ? M : 1);
+  const double Md = S.ray_w ? (S.wsum > 0.0 ? S.wsum : 1.0) : (double)(M > 0 ? M : 1);
   const double mux = sx / Md, muy = sy / Md;
   const double sdx = sqrt(fmax(sxx / Md - mux * mux, 0.0));
   const double sdy = sqrt(fmax(syy / Md - muy * muy, 0.0));
   const double sc = fmin(sdx, sdy);
   const double mu = axis == 0 ? mux : muy;
 
-  if (M > 0) {
+  if (M > 0 && S.ray_w) {
+    select_weighted(S, L, zb, M, b, axis);
+  } else if (M > 0) {
     // target ranks floor(h_k) and floor(h_k) + 1, h_k = (M-1) u_k.  Each of
     // the two sequences is non-decreasing in k, but with few masked rays
     // neighbouring nodes share floor(h_k), so floor(h_k) + 1 can exceed
@@ -597,7 +717,7 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
     double qb;
     const int t0 = M > 0 ? L.tmap[2 * tid] : 0, t1 = M > 0 ? L.tmap[2 * tid + 1] : 0;
     if (M > 0) {
-      const double t = (double)S.rank_t[tid];
+      const double t = S.ray_w ? S.wt[tid] : S.rank_t[tid];
       qb = (1.0 - t) * (double)L.tval[t0] + t * (double)L.tval[t1];
     } else {
       qb = 0.0;
@@ -1452,7 +1572,7 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
       } else {
         ax = tid / (2 * K);
         const int r = tid - ax * 2 * K, k = r >> 1;
-        const double t = S.rank_t[k];
+        const double t = S.ray_w ? S.wt[k] : S.rank_t[k];
         const double wgt = (r & 1) ? t : 1.0 - t;
         m = S.sel[((size_t)b * 2 + ax) * 2 * K + r];
         bb = wgt * P.xbar[ax][k];

@@ -39,6 +39,15 @@ struct rtu_plan_s {
   bool have_last = false;
   Prof prof;
   std::vector<float> inv_var;     // host copy of 1/sigma^2 (ELBO constant)
+  std::vector<int> mask_idx;      // host copy of the masked pixels (ray weights)
+  // weighted RTU grid: device [M] weights, [K] positions, [K] fractions, sort
+  // scratch; its pinned staging copy and the event of its last upload
+  char* wdev = nullptr;
+  size_t wdev_bytes = 0;
+  char* wstage = nullptr;
+  size_t wstage_bytes = 0;
+  hipEvent_t wdone = nullptr;
+  bool wpending = false;
 };
 
 struct rtu_fit_s {
@@ -409,6 +418,9 @@ int rtu_plan_destroy(rtu_plan p) {
   if (p->obs_pool) (void)hipFree(p->obs_pool);
   if (p->stage) (void)hipHostFree(p->stage);
   if (p->stage_done) (void)hipEventDestroy(p->stage_done);
+  if (p->wdev) (void)hipFree(p->wdev);
+  if (p->wstage) (void)hipHostFree(p->wstage);
+  if (p->wdone) (void)hipEventDestroy(p->wdone);
   for (hipEvent_t e : p->prof.ev) (void)hipEventDestroy(e);
   delete p;
   return RTU_OK;
@@ -447,9 +459,74 @@ int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma
   p->stage_pending = true;
   h.M = M;
   h.psf_rank1 = o.rank1 ? 1 : 0;
+  // a new mask: the ray weights, if any, must be given again
+  h.ray_w = nullptr; h.wr0 = nullptr; h.wt = nullptr; h.wsort = nullptr; h.wsum = 0.0;
   p->h = h;
   p->M = M;
   p->inv_var = o.inv_var;
+  p->mask_idx = o.idx;
+  return RTU_OK;
+}
+
+int rtu_set_ray_weights(rtu_plan p, const float* weights, void* stream) {
+  if (!p) return RTU_EINVAL;
+  if (p->M < 0) return RTU_ESTATE;
+  if (hipSetDevice(p->device) != hipSuccess) return RTU_EHIP;
+  SysDev& h = p->h;
+  if (!weights) {
+    h.ray_w = nullptr; h.wr0 = nullptr; h.wt = nullptr; h.wsort = nullptr; h.wsum = 0.0;
+    return RTU_OK;
+  }
+  const int M = p->M;
+  double W = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const float w = weights[p->mask_idx[m]];
+    if (!(w >= 0.f) || !std::isfinite(w)) return RTU_EINVAL;
+    W += (double)w;
+  }
+  if (!(W >= 1.0)) return RTU_EINVAL;
+  // device layout: weights [M] (float), positions [K], fractions [K] (double),
+  // then the sort scratch [max_batch][2][2][M] (uint2)
+  const size_t off_r = (((size_t)M * 4 + 15) & ~(size_t)15), off_s = off_r + 2 * K * sizeof(double);
+  const size_t host_bytes = off_s, bytes = off_s + (size_t)p->max_batch * 4 * M * sizeof(uint2);
+  if (p->wpending && hipEventSynchronize(p->wdone) != hipSuccess) return RTU_EHIP;
+  p->wpending = false;
+  if (bytes > p->wdev_bytes) {
+    // the previous array may still be read by queued work
+    if (p->wdev && (hipDeviceSynchronize() != hipSuccess || hipFree(p->wdev) != hipSuccess)) return RTU_EHIP;
+    p->wdev = nullptr;
+    p->wdev_bytes = 0;
+    h.ray_w = nullptr;
+    if (hipMalloc(&p->wdev, bytes) != hipSuccess) return RTU_ENOMEM;
+    p->wdev_bytes = bytes;
+  }
+  if (host_bytes > p->wstage_bytes) {
+    if (p->wstage) (void)hipHostFree(p->wstage);
+    p->wstage = nullptr;
+    p->wstage_bytes = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->wstage), host_bytes, hipHostMallocDefault) != hipSuccess)
+      return RTU_ENOMEM;
+    p->wstage_bytes = host_bytes;
+  }
+  if (!p->wdone && hipEventCreateWithFlags(&p->wdone, hipEventDisableTiming) != hipSuccess) return RTU_EHIP;
+  float* hw = reinterpret_cast<float*>(p->wstage);
+  double* hr = reinterpret_cast<double*>(p->wstage + off_r);
+  for (int m = 0; m < M; ++m) hw[m] = weights[p->mask_idx[m]];
+  for (int k = 0; k < K; ++k) {
+    const double u = 0.5 * (1.0 - cos((2.0 * (k + 1) - 1.0) * M_PI / (2.0 * K)));
+    const double hh = (W - 1.0) * u, fl = floor(hh);
+    hr[k] = fl;
+    hr[K + k] = hh - fl;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(p->wdev, p->wstage, host_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return RTU_EHIP;
+  if (hipEventRecord(p->wdone, s) != hipSuccess) return RTU_EHIP;
+  p->wpending = true;
+  h.ray_w = reinterpret_cast<const float*>(p->wdev);
+  h.wr0 = reinterpret_cast<const double*>(p->wdev + off_r);
+  h.wt = h.wr0 + K;
+  h.wsort = reinterpret_cast<uint2*>(p->wdev + off_s);
+  h.wsum = W;
   return RTU_OK;
 }
 

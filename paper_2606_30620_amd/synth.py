@@ -145,6 +145,7 @@ class Problem:
     latent: np.ndarray       # float32 [B, n_src, n_src]
     lens_truth: np.ndarray   # float64 [n_lens]
     noise: Optional[np.ndarray] = None  # float32 [N, N] unit-free noise draw (C1)
+    ray_weights: Optional[np.ndarray] = None  # float32 [N, N] weights of the masked rays (weighted RTU grid)
 
     @property
     def batch(self) -> int:

@@ -3,6 +3,9 @@
 // output: loss[B], chi2_mask[B] (double), status[B] (uint32), grad_lens[B][nl],
 // grad_ps[B][4], grad_latent[B][n][n], model[B][N][N] (float).
 //   driver <inputs> <outputs> <mode: 0 plan, 1 allocation-free> <geometry flags>
+// (header word 8 = 1: per-pixel ray weights follow the inputs), then (plan
+// mode, zeros otherwise) the selected rays [B][2][2K] and the standardisation
+// [B][3] of RTU_DBG_SELECT and RTU_DBG_STD.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -42,6 +45,8 @@ int main(int argc, char** argv) {
   std::vector<int> nsub;
   rd(image, (size_t)N * N); rd(sigma, (size_t)N * N); rd(psf, (size_t)KP * KP); rd(mask, (size_t)N * N);
   rd(lens, (size_t)B * nl); rd(ps, (size_t)B * 4); rd(lat, (size_t)B * n * n); rd(nsub, (size_t)B);
+  std::vector<float> wts;
+  if (hi[8] == 1) rd(wts, (size_t)N * N);     // ray weights of the weighted grid
   fclose(f);
   const int mode = atoi(argv[3]);
   const unsigned flags = (unsigned)atoi(argv[4]);
@@ -58,11 +63,21 @@ int main(int argc, char** argv) {
   float* dw = dev(lat);
   int* dn = dev(nsub);
   int rc;
+  // plan mode: the selected rays and the standardisation of every sample too
+  std::vector<int> sel((size_t)B * 4 * RTU_K_NODES, 0);
+  std::vector<double> sd((size_t)B * 3, 0.0);
   if (mode == 0) {
     rtu_plan p;
     if ((rc = rtu_plan_create(&g, B, 0, &p))) return 70;
     if ((rc = rtu_set_observation(p, image.data(), sigma.data(), psf.data(), mask.data(), nullptr))) return 71;
+    if (!wts.empty() && (rc = rtu_set_ray_weights(p, wts.data(), nullptr))) return 74;
     if ((rc = rtu_loss_grad(p, B, dl, dn, dp, dw, loss, c2m, gl, gp, gw, model, st, nullptr))) return 72;
+    for (int b = 0; b < B; ++b) {
+      if (rtu_debug_fetch(p, RTU_DBG_SELECT, b, sel.data() + (size_t)b * 4 * RTU_K_NODES,
+                          4 * RTU_K_NODES * sizeof(int), nullptr) ||
+          rtu_debug_fetch(p, RTU_DBG_STD, b, sd.data() + (size_t)b * 3, 3 * sizeof(double), nullptr))
+        return 75;
+    }
     rtu_plan_destroy(p);
   } else {
     float* di = dev(image);
@@ -81,6 +96,8 @@ int main(int argc, char** argv) {
   fwrite(gp, 4, (size_t)B * 4, o);
   fwrite(gw, 4, (size_t)B * n * n, o);
   fwrite(model, 4, (size_t)B * N * N, o);
+  fwrite(sel.data(), 4, sel.size(), o);
+  fwrite(sd.data(), 8, sd.size(), o);
   fclose(o);
   return 0;
 }
