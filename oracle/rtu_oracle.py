@@ -122,6 +122,48 @@ def sie_deflection(x, y, theta_e, e1, e2, x0, y0):
     return torch.where(centre, zero, ax), torch.where(centre, zero, ay)
 
 
+def epl_deflection(x, y, theta_e, e1, e2, x0, y0, gamma, tol=1e-17):
+    """Deflection of the elliptical power law of App. A.1, eq. (A1):
+    kappa = (3 - gamma)/2 (theta_E / rho)^(gamma - 1), rho^2 = q x'^2 + y'^2/q.
+    Tessore & Metcalf (2015) give it in the lens frame as a hypergeometric
+    function of the elliptical angle.  With complex z = (x - x0) + i (y - y0),
+    eps = e1 + i e2, m = z - eps conj(z), u = m/|m| and t = gamma - 1 (the
+    frame change absorbed into eps as in sie_deflection) it reads
+        alpha = Lam^t |m|^(1 - t) u F(-conj(eps) u^2),  Lam = theta_E sqrt(1 - |eps|^2),
+        F(w) = 2F1(1, t/2; 2 - t/2; w) = sum_n c_n w^n,
+        c_0 = 1,  c_n = c_{n-1} (2n - 2 + t) / (2n + 2 - t),
+    the series summed until c_n |eps|^n < tol (|w| = |eps| < 1).  At gamma = 2
+    it is sie_deflection; it has no angle and is smooth in (e1, e2).  A ray on
+    the centre is not deflected."""
+    t = gamma - 1.0
+    dx, dy = x - x0, y - y0
+    centre = (dx == 0) & (dy == 0)
+    dx = torch.where(centre, torch.ones_like(dx), dx)
+    dy = torch.where(centre, torch.zeros_like(dy), dy)
+    z = torch.complex(dx, dy)
+    eps = torch.complex(e1 * torch.ones_like(dx), e2 * torch.ones_like(dx))
+    m = z - eps * z.conj()
+    am = m.abs()
+    u = m / am
+    w = -eps.conj() * u * u
+    e = float(torch.hypot(e1.detach(), e2.detach()))
+    F = torch.zeros_like(w)
+    c = torch.ones((), dtype=DT) + 0.0 * t
+    wn = torch.ones_like(w)
+    n = 0
+    while True:
+        F = F + c * wn
+        n += 1
+        c = c * (2.0 * n - 2.0 + t) / (2.0 * n + 2.0 - t)
+        wn = wn * w
+        if float(c.detach()) * e ** n < tol or n > 5000:
+            break
+    lam = theta_e * torch.sqrt(1.0 - (e1 * e1 + e2 * e2))
+    a = lam ** t * am ** (1.0 - t) * u * F
+    zero = torch.zeros_like(dx)
+    return torch.where(centre, zero, a.real), torch.where(centre, zero, a.imag)
+
+
 def shear_deflection(x, y, g1, g2):
     """External shear about the origin, potential (g1 (x^2 - y^2) + 2 g2 x y)/2."""
     return g1 * x + g2 * y, g2 * x - g1 * y
@@ -176,21 +218,31 @@ def nfw_deflection(x, y, ks, rs, xs, ys, tau: float = 0.0):
     return fac * dx, fac * dy
 
 
-def deflection(x, y, lens, n_sub: int = 0, tau: float = 0.0):
-    """Total deflection: SIE + external shear + n_sub NFW subhaloes."""
-    ax, ay = sie_deflection(x, y, lens[0], lens[1], lens[2], lens[3], lens[4])
+def lens_base(epl: bool = False) -> int:
+    """Lens parameters before the subhaloes: theta_E, e1, e2, x0, y0, gamma1,
+    gamma2, and with the EPL its slope gamma."""
+    return N_LENS_BASE + (1 if epl else 0)
+
+
+def deflection(x, y, lens, n_sub: int = 0, tau: float = 0.0, epl: bool = False):
+    """Total deflection: SIE (or with epl the EPL, slope lens[7]) + external
+    shear + n_sub NFW subhaloes."""
+    if epl:
+        ax, ay = epl_deflection(x, y, lens[0], lens[1], lens[2], lens[3], lens[4], lens[7])
+    else:
+        ax, ay = sie_deflection(x, y, lens[0], lens[1], lens[2], lens[3], lens[4])
     sx, sy = shear_deflection(x, y, lens[5], lens[6])
     ax, ay = ax + sx, ay + sy
     for j in range(n_sub):
-        b = N_LENS_BASE + N_PER_SUB * j
+        b = lens_base(epl) + N_PER_SUB * j
         nx, ny = nfw_deflection(x, y, lens[b], lens[b + 1], lens[b + 2], lens[b + 3], tau)
         ax, ay = ax + nx, ay + ny
     return ax, ay
 
 
-def ray_shoot(x, y, lens, n_sub=0, tau=0.0):
+def ray_shoot(x, y, lens, n_sub=0, tau=0.0, epl=False):
     """Lens equation beta = theta - alpha(theta)."""
-    ax, ay = deflection(x, y, lens, n_sub, tau)
+    ax, ay = deflection(x, y, lens, n_sub, tau, epl)
     return x - ax, y - ay
 
 
@@ -498,7 +550,9 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
     sub-ray mean and the PSF; grid = "uniform": the source grid spans the
     smallest square box of the masked rays (Sec. 2.1, uniform_box_of) instead
     of the RTU transform; ray_weights[N,N]: per-pixel weights of the masked
-    rays for the weighted RTU grid (Sec. 6.3, quantiles_weighted).
+    rays for the weighted RTU grid (Sec. 6.3, quantiles_weighted);
+    lens_model = "epl": the main deflector is the EPL with its slope as lens
+    parameter 7 (epl_deflection), the subhaloes following it.
     uniform_box: if given as (x_lo, y_lo, side), the RTU transform is replaced by
     the plain affine map of that box onto the unit square (the paper's uniform
     grid, Sec. 2.1).
@@ -507,13 +561,15 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
     evaluates the spline in binary32 with the quantile fit in binary64).
     picks: the masked rays standing for the order statistics (build_transform)."""
     N, pix, ss = obs["n_img"], obs["pix"], obs["ss"]
+    epl = obs.get("lens_model", "sie") == "epl"
     r32 = (lambda t: t.float().to(DT)) if round32 else (lambda t: t)
     status = 0
     lv, pv = lens.detach(), ps.detach()
     n_gauss = int(obs.get("n_gauss", 0))
     light = lens[lens.shape[0] - N_PER_GAUSS * n_gauss:] if n_gauss else None
     if float(lv[0]) <= 0 or float(torch.hypot(lv[1], lv[2])) >= 1 or \
-            any(float(lv[N_LENS_BASE + N_PER_SUB * j + 1]) <= 0 for j in range(n_sub)) or \
+            any(float(lv[lens_base(epl) + N_PER_SUB * j + 1]) <= 0 for j in range(n_sub)) or \
+            (epl and not (1.0 < float(lv[7]) < 3.0)) or \
             bool((pv[:3] <= 0).any()) or bool((obs["sigma"] <= 0).any()):
         status |= ST_DOMAIN
     if n_gauss:
@@ -521,7 +577,7 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
         if bool((lt[:, 1] <= 0).any()) or bool((torch.hypot(lt[:, 2], lt[:, 3]) >= 1).any()):
             status |= ST_DOMAIN
     xr, yr = subray_positions(N, pix, ss)
-    bx, by = ray_shoot(xr, yr, lens, n_sub, tau)
+    bx, by = ray_shoot(xr, yr, lens, n_sub, tau, epl)
     bx, by = r32(bx), r32(by)
     mflat = obs["mask"].reshape(-1).bool()
     xc, yc = pixel_centres(N, pix)
@@ -531,13 +587,13 @@ def forward(lens, ps, w, obs, n_sub=0, tau=0.0, uniform_box=None, return_all=Fal
         status |= ST_MASK_SMALL
     tr = None
     if uniform:
-        bxm, bym = ray_shoot(xc[mflat], yc[mflat], lens, n_sub, tau)
+        bxm, bym = ray_shoot(xc[mflat], yc[mflat], lens, n_sub, tau, epl)
         tr = uniform_box_of(r32(bxm), r32(bym), picks=picks)
         status |= tr["status"]
         gx, gy = (bx - tr["lo"][0]) / tr["side"], (by - tr["lo"][1]) / tr["side"]
         gx, gy = r32(gx), r32(gy)
     elif uniform_box is None:
-        bxm, bym = ray_shoot(xc[mflat], yc[mflat], lens, n_sub, tau)
+        bxm, bym = ray_shoot(xc[mflat], yc[mflat], lens, n_sub, tau, epl)
         rw = obs.get("ray_weights")
         rw = None if rw is None else _t(rw).reshape(-1)[mflat]
         tr = build_transform(r32(bxm), r32(bym), picks=picks, weights=rw)
@@ -576,7 +632,8 @@ def obs_from_problem(p) -> dict:
             "image": _t(p.image), "sigma": _t(p.noise_sigma), "psf": _t(p.psf),
             "mask": torch.as_tensor(p.mask.astype(np.int64)), "tau": g.tnfw_tau,
             "n_gauss": getattr(g, "n_gauss", 0), "grid": "uniform" if getattr(g, "uniform", False) else "rtu",
-            "ray_weights": None if getattr(p, "ray_weights", None) is None else _t(p.ray_weights)}
+            "ray_weights": None if getattr(p, "ray_weights", None) is None else _t(p.ray_weights),
+            "lens_model": "epl" if getattr(g, "epl", False) else "sie"}
 
 
 def loss_grad(lens, ps, w, obs, n_sub=0, tau=0.0, want_grad=True, return_all=False, cell_shift=0.0,
@@ -648,6 +705,7 @@ def cell_edge_slack(lens, ps, w, obs, n_sub=0, tau=0.0, delta=None, side=0):
     out = forward(lens_g, ps_t, w_t, obs, n_sub, tau, return_all=True)
     (dldu,) = torch.autograd.grad(out["loss"], [out["u"]])
     N, pix, ss = obs["n_img"], obs["pix"], obs["ss"]
+    epl = obs.get("lens_model", "sie") == "epl"
     gx, gy = out["gx"].detach(), out["gy"].detach()
     src = out["src"].detach()
     n = src.shape[0]
@@ -694,8 +752,8 @@ def cell_edge_slack(lens, ps, w, obs, n_sub=0, tau=0.0, delta=None, side=0):
     uniform = obs.get("grid", "rtu") == "uniform"
 
     def g_of(lv):
-        bxm, bym = ray_shoot(xc[mflat], yc[mflat], lv, n_sub, tau)
-        bx, by = ray_shoot(xr[sel], yr[sel], lv, n_sub, tau)
+        bxm, bym = ray_shoot(xc[mflat], yc[mflat], lv, n_sub, tau, epl)
+        bx, by = ray_shoot(xr[sel], yr[sel], lv, n_sub, tau, epl)
         if uniform:
             box = uniform_box_of(bxm, bym)
             g1, g2 = (bx - box["lo"][0]) / box["side"], (by - box["lo"][1]) / box["side"]
