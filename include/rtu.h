@@ -60,20 +60,23 @@ extern "C" {
 /* Number of Chebyshev nodes of the quantile-function fit: degree 21 + 1
  * (App. C step iii and Fig. C1). */
 #define RTU_K_NODES 22
-/* Lens parameters: theta_E, e1, e2, x0, y0, gamma1, gamma2, then per
- * subhalo kappa_s, r_s, x_s, y_s (App. A), then per lens-light Gaussian
+/* Lens parameters: theta_E, e1, e2, x0, y0, gamma1, gamma2 (SIE + external
+ * shear; with RTU_GEOM_EPL also the slope gamma of the elliptical power law,
+ * App. A.1, eq. A1), then per subhalo kappa_s, r_s, x_s, y_s (App. A), then
+ * per lens-light Gaussian
  * A, sigma, e1, e2, x_c, y_c (App. A, Multi Gaussian Expansion: the
  * component adds A/(2 pi) exp(-rho^2/(2 sigma^2)) to every sub-ray, with
  * rho^2 = q x'^2 + y'^2/q about (x_c, y_c) and q, angle from (e1, e2) as for
  * the mass).  Power-spectrum parameters: sigma_src, n_src, zeta_src,
  * alpha_src (eqs. 3-4). */
 #define RTU_N_LENS_BASE 7
+#define RTU_N_LENS_BASE_EPL 8
 #define RTU_N_PER_SUB   4
 #define RTU_N_PER_GAUSS 6
 #define RTU_N_PS        4
 #define RTU_MAX_SUB    10
 #define RTU_MAX_GAUSS   8
-#define RTU_MAX_LENS   (RTU_N_LENS_BASE + RTU_N_PER_SUB * RTU_MAX_SUB + RTU_N_PER_GAUSS * RTU_MAX_GAUSS)
+#define RTU_MAX_LENS   (RTU_N_LENS_BASE_EPL + RTU_N_PER_SUB * RTU_MAX_SUB + RTU_N_PER_GAUSS * RTU_MAX_GAUSS)
 
 typedef struct rtu_plan_s* rtu_plan;
 
@@ -108,6 +111,15 @@ typedef struct {
  * RTU_DBG_SELECT holds per axis the indices of the minimum and the maximum in
  * its first two slots, RTU_DBG_STD (lo_x, lo_y, L), and RTU_DBG_KNOTS zeros. */
 #define RTU_GEOM_UNIFORM 2u
+/* Geometry flag: the main deflector is the elliptical power law of App. A.1,
+ * eq. (A1), kappa = (3 - gamma)/2 (theta_E/rho)^(gamma - 1) with rho^2 =
+ * q x'^2 + y'^2/q, whose slope gamma (in (1, 3); status RTU_ST_DOMAIN
+ * outside) is lens parameter 7, the subhaloes and lens light following
+ * (RTU_N_LENS_BASE_EPL parameters before the subhaloes).  Its deflection is
+ * the hypergeometric series of Tessore & Metcalf (2015), summed to FP32
+ * precision with at most 48 terms (|e| <= 0.68 reaches it), and gamma gets
+ * its gradient.  At gamma = 2 it is the SIE. */
+#define RTU_GEOM_EPL 4u
 
 /* Number of lens parameters per sample: 7 + 4 n_sub_max + 6 n_gauss. */
 int32_t rtu_n_lens(const rtu_geometry* g);

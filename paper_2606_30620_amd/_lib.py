@@ -126,6 +126,7 @@ def check(rc: int, what: str = "") -> None:
 
 GEOM_RADIX_SELECT = 1
 GEOM_UNIFORM = 2
+GEOM_EPL = 4
 
 
 def make_geometry(n_img, supersample, n_src, psf_size, pixel_scale, n_sub_max=0, tnfw_tau=0.0,

@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import GEOM_UNIFORM, Plan, make_geometry
+from ._lib import GEOM_EPL, GEOM_UNIFORM, Plan, make_geometry
 
 
 @dataclasses.dataclass
@@ -32,6 +32,8 @@ def plan_for_problem(problem, max_batch: Optional[int] = None, device: int = 0, 
     g = problem.geom
     if getattr(g, "uniform", False):
         flags |= GEOM_UNIFORM
+    if getattr(g, "epl", False):
+        flags |= GEOM_EPL
     geom = make_geometry(g.n_img, g.supersample, g.n_src, g.psf_size, g.pixel_scale,
                          g.n_sub_max, g.tnfw_tau, flags, g.n_gauss)
     plan = Plan(geom, max_batch or problem.batch, device)

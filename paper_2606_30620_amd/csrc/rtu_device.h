@@ -343,6 +343,172 @@ __device__ __forceinline__ void sie_grad(const Sie& L, const double* a, double* 
   for (int k = 0; k < 7; ++k) g[k] = sie_grad_one(L, a, k);
 }
 
+// ------------------------------------------------------------------ EPL (App. A.1)
+// Elliptical power law, kappa = (3 - gamma)/2 (theta_E/rho)^(gamma - 1), in
+// the angle-free complex form of the Tessore & Metcalf (2015) deflection: with
+// z = (x - x0) + i (y - y0), eps = e1 + i e2, m = z - eps conj(z), u = m/|m|,
+// t = gamma - 1 and Lam = theta_E sqrt(1 - |eps|^2),
+//   alpha = Lam^t |m|^(-t) m F(w),  w = -conj(eps) u^2,
+//   F(w) = 2F1(1, t/2; 2 - t/2; w) = sum_n c_n w^n,  c_n = c_{n-1} (2n-2+t)/(2n+2-t),
+// summed by Horner's rule over the terms that reach FP32 precision (|w| =
+// |eps|).  It has no angle, so the gradient is smooth at eps = 0.
+constexpr int EPL_NMAX = 48;             // series terms at most (|eps| <= 0.68 reaches 1e-8)
+
+struct Epl {
+  float the, e1, e2, x0, y0, g1, g2, t;
+  float l2lam;     // log2 Lam
+  float hk;        // 1 / (2 (1 - |eps|^2))
+};
+// Per-sample coefficient tables: c_n (F), (n+1) c_{n+1} (F' = dF/dw) and
+// c_n s_n with s_n = d ln c_n / dt = sum_{k<=n} 1/(2k-2+t) + 1/(2k+2-t) (dF/dt).
+struct EplTab {
+  float c[EPL_NMAX], cd[EPL_NMAX], cs[EPL_NMAX];
+  int n;
+};
+
+__device__ __forceinline__ Epl make_epl(const float* L) {
+  Epl o;
+  o.the = L[0]; o.e1 = L[1]; o.e2 = L[2]; o.x0 = L[3]; o.y0 = L[4]; o.g1 = L[5]; o.g2 = L[6];
+  o.t = L[7] - 1.f;
+  const float omee = 1.f - (o.e1 * o.e1 + o.e2 * o.e2);
+  o.l2lam = log2f(o.the * sqrtf(omee));
+  o.hk = 0.5f / omee;
+  return o;
+}
+
+// The tables of one sample, by one thread (FP64, stored FP32).
+__device__ __forceinline__ void epl_table(const Epl& E, EplTab& T) {
+  const double t = E.t, e = sqrt((double)E.e1 * E.e1 + (double)E.e2 * E.e2);
+  double c = 1.0, sn = 0.0, en = 1.0;
+  int n = 0;
+  for (; n < EPL_NMAX; ++n) {
+    T.c[n] = (float)c;
+    T.cs[n] = (float)(c * sn);
+    if (n > 0) T.cd[n - 1] = (float)(n * c);
+    if (n > 0 && c * en < 1e-9) { ++n; break; }
+    const double a = 2.0 * n + t, bb = 2.0 * n + 4.0 - t;   // (2k-2+t), (2k+2-t) at k = n+1
+    c *= a / bb;
+    sn += 1.0 / a + 1.0 / bb;
+    en *= e;
+  }
+  T.n = n;
+  T.cd[n - 1] = 0.f;
+}
+
+// The per-ray quantities shared by the deflection and its vector-Jacobian
+// product.
+struct EplRay {
+  float dx, dy, mr, mi, ir, u2r, u2i, wr, wi, pw, Fr, Fi;
+  bool ok;
+};
+__device__ __forceinline__ void epl_ray(const Epl& L, const EplTab& T, float x, float y, EplRay& R) {
+  R.dx = x - L.x0; R.dy = y - L.y0;
+  R.mr = R.dx - (L.e1 * R.dx + L.e2 * R.dy);
+  R.mi = R.dy - (L.e2 * R.dx - L.e1 * R.dy);
+  const float r2 = R.mr * R.mr + R.mi * R.mi;
+  R.ok = r2 > 0.f;
+  R.ir = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+  const float ur = R.mr * R.ir, ui = R.mi * R.ir;
+  R.u2r = ur * ur - ui * ui;
+  R.u2i = 2.f * ur * ui;
+  R.wr = -(L.e1 * R.u2r + L.e2 * R.u2i);
+  R.wi = -(L.e1 * R.u2i - L.e2 * R.u2r);
+  // Lam^t |m|^-t
+  R.pw = exp2f(L.t * (L.l2lam + log2f(R.ir)));
+  float Fr = T.c[T.n - 1], Fi = 0.f;
+  for (int k = T.n - 2; k >= 0; --k) {
+    const float nr = fmaf(Fr, R.wr, fmaf(-Fi, R.wi, T.c[k]));
+    Fi = fmaf(Fr, R.wi, Fi * R.wr);
+    Fr = nr;
+  }
+  R.Fr = Fr; R.Fi = Fi;
+}
+
+__device__ __forceinline__ void epl_shear_alpha(const Epl& L, const EplTab& T, float x, float y, float& ax,
+                                                float& ay) {
+  EplRay R;
+  epl_ray(L, T, x, y, R);
+  const float s = R.ok ? R.pw : 0.f;
+  ax = s * (R.mr * R.Fr - R.mi * R.Fi) + L.g1 * x + L.g2 * y;
+  ay = s * (R.mr * R.Fi + R.mi * R.Fr) + L.g2 * x - L.g1 * y;
+}
+
+// Vector-Jacobian product of EPL + shear: given gbar = d loss/d alpha, adds
+// d loss/d (theta_E, e1, e2, x0, y0, gamma1, gamma2, gamma) to acc.  With
+// Wirtinger derivatives (alpha = Lam^t m^(1-t/2) conj(m)^(-t/2) F(-conj(eps) m/conj(m))):
+//   d alpha/d m       = pw [(1 - t/2) F - F' conj(eps) u^2]
+//   d alpha/d conj(m) = pw [-(t/2) F u^2 + F' conj(eps) u^4]
+//   d alpha/d conj(eps) at fixed m adds -pw m F' u^2, and through Lam
+//   d alpha/d eps = -t alpha conj(eps) / (2 (1 - |eps|^2)) (conjugate for conj(eps));
+// m = Delta - eps conj(Delta) with Delta = z - z0 carries them to z0 and eps,
+// and a real pair (p_x, p_y) of a complex parameter p gets
+//   d loss/d p_x = Re(conj(gbar) (D_p + D_conj(p))),  d loss/d p_y = -Im(conj(gbar) (D_p - D_conj(p))).
+__device__ __forceinline__ void epl_shear_vjp(const Epl& L, const EplTab& T, float x, float y, float gx,
+                                              float gy, float (&acc)[8]) {
+  EplRay R;
+  R.dx = x - L.x0; R.dy = y - L.y0;
+  R.mr = R.dx - (L.e1 * R.dx + L.e2 * R.dy);
+  R.mi = R.dy - (L.e2 * R.dx - L.e1 * R.dy);
+  const float r2 = R.mr * R.mr + R.mi * R.mi;
+  acc[5] += gx * x - gy * y;
+  acc[6] += gx * y + gy * x;
+  if (!(r2 > 0.f)) return;
+  R.ir = __builtin_amdgcn_rsqf(r2);
+  const float ur = R.mr * R.ir, ui = R.mi * R.ir;
+  R.u2r = ur * ur - ui * ui;
+  R.u2i = 2.f * ur * ui;
+  R.wr = -(L.e1 * R.u2r + L.e2 * R.u2i);
+  R.wi = -(L.e1 * R.u2i - L.e2 * R.u2r);
+  const float l2 = L.l2lam + log2f(R.ir);      // log2(Lam/|m|)
+  const float pw = exp2f(L.t * l2);
+  // F, F' and dF/dt by Horner's rule
+  float Fr = T.c[T.n - 1], Fi = 0.f, Dr = T.cd[T.n - 1], Di = 0.f, Sr = T.cs[T.n - 1], Si = 0.f;
+  for (int k = T.n - 2; k >= 0; --k) {
+    float nr = fmaf(Fr, R.wr, fmaf(-Fi, R.wi, T.c[k]));
+    Fi = fmaf(Fr, R.wi, Fi * R.wr);
+    Fr = nr;
+    nr = fmaf(Dr, R.wr, fmaf(-Di, R.wi, T.cd[k]));
+    Di = fmaf(Dr, R.wi, Di * R.wr);
+    Dr = nr;
+    nr = fmaf(Sr, R.wr, fmaf(-Si, R.wi, T.cs[k]));
+    Si = fmaf(Sr, R.wi, Si * R.wr);
+    Sr = nr;
+  }
+  const float t = L.t;
+  // alpha = pw m F;  A = pw m
+  const float Ar = pw * R.mr, Ai = pw * R.mi;
+  const float alr = Ar * Fr - Ai * Fi, ali = Ar * Fi + Ai * Fr;
+  // E = conj(eps) u^2 (complex), F' E, F' E u^2
+  const float Er = L.e1 * R.u2r + L.e2 * R.u2i, Ei = L.e1 * R.u2i - L.e2 * R.u2r;
+  const float DEr = Dr * Er - Di * Ei, DEi = Dr * Ei + Di * Er;
+  const float DE2r = DEr * R.u2r - DEi * R.u2i, DE2i = DEr * R.u2i + DEi * R.u2r;
+  const float FU2r = Fr * R.u2r - Fi * R.u2i, FU2i = Fr * R.u2i + Fi * R.u2r;
+  // P1 = d alpha/d m, P2 = d alpha/d conj(m)
+  const float P1r = pw * ((1.f - 0.5f * t) * Fr - DEr), P1i = pw * ((1.f - 0.5f * t) * Fi - DEi);
+  const float P2r = pw * (-0.5f * t * FU2r + DE2r), P2i = pw * (-0.5f * t * FU2i + DE2i);
+  // z0: D = -P1 + conj(eps) P2,  Db = eps P1 - P2
+  const float Dz_r = -P1r + (L.e1 * P2r + L.e2 * P2i), Dz_i = -P1i + (L.e1 * P2i - L.e2 * P2r);
+  const float Dzb_r = (L.e1 * P1r - L.e2 * P1i) - P2r, Dzb_i = (L.e1 * P1i + L.e2 * P1r) - P2i;
+  // eps: D = -conj(Delta) P1 - t hk alpha conj(eps)
+  //      Db = -Delta P2 - pw m F' u^2 - t hk alpha eps
+  const float th = t * L.hk;
+  const float De_r = -(R.dx * P1r + R.dy * P1i) - th * (alr * L.e1 + ali * L.e2);
+  const float De_i = -(R.dx * P1i - R.dy * P1r) - th * (ali * L.e1 - alr * L.e2);
+  const float Du2r = Dr * R.u2r - Di * R.u2i, Du2i = Dr * R.u2i + Di * R.u2r;   // F' u^2
+  const float Deb_r = -(R.dx * P2r - R.dy * P2i) - (Ar * Du2r - Ai * Du2i) - th * (alr * L.e1 - ali * L.e2);
+  const float Deb_i = -(R.dx * P2i + R.dy * P2r) - (Ar * Du2i + Ai * Du2r) - th * (ali * L.e1 + alr * L.e2);
+  // Re(conj(g) X) = gx Xr + gy Xi;  Im(conj(g) X) = gx Xi - gy Xr
+  acc[0] += L.the > 0.f ? t * (gx * alr + gy * ali) / L.the : 0.f;
+  acc[1] += gx * (De_r + Deb_r) + gy * (De_i + Deb_i);
+  acc[2] += -(gx * (De_i - Deb_i) - gy * (De_r - Deb_r));
+  acc[3] += gx * (Dz_r + Dzb_r) + gy * (Dz_i + Dzb_i);
+  acc[4] += -(gx * (Dz_i - Dzb_i) - gy * (Dz_r - Dzb_r));
+  // gamma: alpha ln(Lam/|m|) + A dF/dt
+  const float ln = 0.69314718f * l2;
+  const float Tr = alr * ln + (Ar * Sr - Ai * Si), Ti = ali * ln + (Ar * Si + Ai * Sr);
+  acc[7] += gx * Tr + gy * Ti;
+}
+
 // ------------------------------------------------------------------ NFW (App. A.2)
 // T(v) = atanh(sqrt v)/sqrt v (v > 0), atan(sqrt(-v))/sqrt(-v) (v < 0), 1 at 0:
 // Q(v) and P(-v) of the polynomials above where they apply.

@@ -115,7 +115,7 @@ namespace rtu {
 
 int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDev>& fit, FleetLaunch& L) {
   const size_t n = sys.size();
-  std::vector<Task> prep, psf, post, param, samp, fits, fwd, adj[2];
+  std::vector<Task> prep, psf, post, param, samp, fits, fwd[2], adj[2][2];
   size_t lds_f = 0, lds_a = 0, lds_p = 0, lds_pr = 0, lds_po = 0;
   for (size_t i = 0; i < n; ++i) {
     const SysDev& h = sys[i];
@@ -124,8 +124,8 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
     for (int b = 0; b < S; ++b) {
       for (int r = 0; r < 3; ++r) prep.push_back(make_int4(si, b, r, 0));
       for (int t = 0; t < h.ray_tiles; ++t) {
-        fwd.push_back(make_int4(si, b, t, 0));
-        adj[h.lds_adj ? 0 : 1].push_back(make_int4(si, b, t, 0));
+        fwd[h.epl ? 1 : 0].push_back(make_int4(si, b, t, 0));
+        adj[h.lds_adj ? 0 : 1][h.epl ? 1 : 0].push_back(make_int4(si, b, t, 0));
       }
       for (int t = 0; t < h.psf_tiles; ++t) psf.push_back(make_int4(si, b, t, 0));
       for (int r = 0; r < (h.want_grad ? 2 : 1); ++r) post.push_back(make_int4(si, b, r, 0));
@@ -143,9 +143,10 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
     lds_po = std::max(lds_po, post_lds_bytes(h.n_src, h.n_lens));
   }
   std::vector<Task> all;
-  size_t off[9];
-  std::vector<Task>* lists[9] = {&prep, &psf, &post, &param, &samp, &fits, &fwd, &adj[0], &adj[1]};
-  for (int k = 0; k < 9; ++k) {
+  size_t off[12];
+  std::vector<Task>* lists[12] = {&prep, &psf, &post, &param, &samp, &fits, &fwd[0], &fwd[1],
+                                  &adj[0][0], &adj[0][1], &adj[1][0], &adj[1][1]};
+  for (int k = 0; k < 12; ++k) {
     off[k] = all.size();
     all.insert(all.end(), lists[k]->begin(), lists[k]->end());
   }
@@ -177,9 +178,12 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
   L.t_param = d_tasks + off[3]; L.n_param = (int)param.size();
   L.t_sample = d_tasks + off[4]; L.n_sample = (int)samp.size();
   L.t_fit = d_tasks + off[5];   L.n_fit = (int)fits.size();
-  L.t_fwd = d_tasks + off[6];    L.n_fwd = (int)fwd.size();
   for (int k = 0; k < 2; ++k) {
-    L.t_adj[k] = d_tasks + off[7 + k]; L.n_adj[k] = (int)adj[k].size();
+    L.t_fwd[k] = d_tasks + off[6 + k]; L.n_fwd[k] = (int)fwd[k].size();
+    for (int e = 0; e < 2; ++e) {
+      L.t_adj[k][e] = d_tasks + off[8 + 2 * k + e];
+      L.n_adj[k][e] = (int)adj[k][e].size();
+    }
   }
   L.lds_rays_fwd = lds_f;
   L.lds_rays_adj = lds_a;

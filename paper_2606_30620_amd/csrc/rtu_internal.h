@@ -70,6 +70,8 @@ struct SysDev {
   int adj_wcap;               // global mode: cells of the per-tile LDS window of d loss / d s
   int sel_radix;              // quantile selection: always the radix select (1)
   int uniform;                // uniform grid on the masked rays' square box (1) instead of the RTU grid
+  int epl;                    // main deflector: EPL with free slope (1) or SIE (0)
+  int lens_base;              // lens parameters before the subhaloes: 7 (SIE), 8 (EPL)
   // observation (owned by the plan)
   const float* image;         // [N*N]
   const float* inv_var;       // [N*N] 1/sigma^2
@@ -207,12 +209,13 @@ struct FleetLaunch {
   const FitDev* fit;          // device [n_slots]
   const Task *t_prep, *t_psf, *t_post, *t_param, *t_sample, *t_fit;
   int n_prep, n_psf, n_post, n_param, n_sample, n_fit;
-  // forward ray tiles of every system
-  const Task* t_fwd;
-  int n_fwd;
-  // adjoint ray tiles split by LDS mode: [0] d loss / d s in LDS, [1] in global memory
-  const Task* t_adj[2];
-  int n_adj[2];
+  // forward ray tiles by main deflector: [0] SIE, [1] EPL
+  const Task* t_fwd[2];
+  int n_fwd[2];
+  // adjoint ray tiles by LDS mode ([0] d loss / d s in LDS, [1] in global
+  // memory), then by main deflector
+  const Task* t_adj[2][2];
+  int n_adj[2][2];
   size_t lds_rays_fwd, lds_rays_adj, lds_psf, lds_prep, lds_post;
 };
 // One stage (RTU_STAGE_*) of a shared launch; eps (device [S][dim] per fit,

@@ -55,22 +55,43 @@ __device__ __forceinline__ int n_sub_of(const SysDev& S, int b) {
   return v < 0 ? 0 : (v > S.n_sub_max ? S.n_sub_max : v);
 }
 
-// beta = theta - alpha(theta) for SIE + shear + subhaloes
-__device__ __forceinline__ void shoot(const SysDev& S, const Sie& L, const float* lensp, int nsub,
+// The main deflector with the external shear: the SIE (slope 2) or, with
+// the EPL geometry flag, the elliptical power law (its series tables in LDS).
+template <bool EPL> struct Main;
+template <> struct Main<false> {
+  Sie L;
+  __device__ __forceinline__ Main(const float* lensp, const EplTab*) : L(make_sie(lensp)) {}
+  __device__ __forceinline__ void alpha(float x, float y, float& ax, float& ay) const {
+    sie_shear_alpha(L, x, y, ax, ay);
+  }
+};
+template <> struct Main<true> {
+  Epl L;
+  const EplTab* T;
+  __device__ __forceinline__ Main(const float* lensp, const EplTab* t) : L(make_epl(lensp)), T(t) {}
+  __device__ __forceinline__ void alpha(float x, float y, float& ax, float& ay) const {
+    epl_shear_alpha(L, *T, x, y, ax, ay);
+  }
+};
+
+// beta = theta - alpha(theta) for the main deflector + shear + subhaloes
+template <class MAIN>
+__device__ __forceinline__ void shoot(const SysDev& S, const MAIN& L, const float* lensp, int nsub,
                                       float x, float y, float& bx, float& by) {
   float ax, ay;
-  sie_shear_alpha(L, x, y, ax, ay);
+  L.alpha(x, y, ax, ay);
   for (int j = 0; j < nsub; ++j) {
-    const Nfw N = make_nfw(lensp + RTU_N_LENS_BASE + RTU_N_PER_SUB * j, S.tau);
+    const Nfw N = make_nfw(lensp + S.lens_base + RTU_N_PER_SUB * j, S.tau);
     nfw_alpha(N, S.tau, x, y, ax, ay);
   }
   bx = x - ax;
   by = y - ay;
 }
-__device__ __forceinline__ void shoot(const SysDev& S, const Sie& L, const Nfw* nf, int nsub,
+template <class MAIN>
+__device__ __forceinline__ void shoot(const SysDev& S, const MAIN& L, const Nfw* nf, int nsub,
                                       float x, float y, float& bx, float& by) {
   float ax, ay;
-  sie_shear_alpha(L, x, y, ax, ay);
+  L.alpha(x, y, ax, ay);
   for (int j = 0; j < nsub; ++j) nfw_alpha(nf[j], S.tau, x, y, ax, ay);
   bx = x - ax;
   by = y - ay;
@@ -143,6 +164,7 @@ struct SelLds {
   double q[K];
   float kx[K], ks[K], kd[K];   // the knots, slopes and d p / d u as stored (FP32)
   uint32_t stat;
+  EplTab etab;                  // EPL deflector: the sample's series tables
 };
 
 // Exclusive scan of h[0, n) by the whole workgroup; h[n] = total.
@@ -602,7 +624,8 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
   const int M = obs_M(S);
   const float* lensp = S.lens + (size_t)b * S.n_lens;
   const int nsub = n_sub_of(S, b);
-  const Sie sie = make_sie(lensp);
+  if (S.epl && tid == 0) epl_table(make_epl(lensp), L.etab);
+  const Main<false> sie(lensp, nullptr);
   float* zb = S.zbuf + ((size_t)b * 2 + axis) * M;
   uint32_t st = 0;
   if (M < (S.uniform ? 2 : K + 1)) st |= RTU_ST_MASK_SMALL;
@@ -614,6 +637,7 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
   double sx = 0, sy = 0, sxx = 0, syy = 0;
   float vmin = INFINITY, vmax = -INFINITY;      // over the finite values
   unsigned umin = 0xffffffffu, umax = 0u;       // key range over all values
+  __syncthreads();   // the EPL tables
   // the mask index of the iteration after next is loaded ahead
   int p1 = tid < M ? S.mask_idx[tid] : 0;
   int p2 = tid + nt < M ? S.mask_idx[tid + nt] : 0;
@@ -625,7 +649,8 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
     const float x = ((float)j - 0.5f * (float)(S.n_img - 1)) * S.pix;
     const float y = ((float)i - 0.5f * (float)(S.n_img - 1)) * S.pix;
     float bx, by;
-    shoot(S, sie, lensp, nsub, x, y, bx, by);
+    if (S.epl) shoot(S, Main<true>(lensp, &L.etab), lensp, nsub, x, y, bx, by);
+    else shoot(S, sie, lensp, nsub, x, y, bx, by);
     const double wm = S.ray_w ? (double)S.ray_w[m] : 1.0;   // weighted grid: weighted moments
     sx += wm * bx; sy += wm * by; sxx += wm * bx * bx; syy += wm * by * by;
     const float v = (axis == 0 ? bx : by) + 0.0f;
@@ -784,9 +809,10 @@ __device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* s
     const float* L = S.lens + (size_t)b * S.n_lens;
     uint32_t st = 0;
     if (!(L[0] > 0.f) || !(L[1] * L[1] + L[2] * L[2] < 1.f)) st |= RTU_ST_DOMAIN;
+    if (S.epl && !(L[7] > 1.f && L[7] < 3.f)) st |= RTU_ST_DOMAIN;
     const int ns = n_sub_of(S, b);
     for (int j = 0; j < ns; ++j)
-      if (!(L[RTU_N_LENS_BASE + RTU_N_PER_SUB * j + 1] > 0.f)) st |= RTU_ST_DOMAIN;
+      if (!(L[S.lens_base + RTU_N_PER_SUB * j + 1] > 0.f)) st |= RTU_ST_DOMAIN;
     for (int g = 0; g < S.n_gauss; ++g) {
       const float* lg = L + S.light_off + RTU_N_PER_GAUSS * g;
       if (!(lg[1] > 0.f) || !(lg[2] * lg[2] + lg[3] * lg[3] < 1.f)) st |= RTU_ST_DOMAIN;
@@ -884,6 +910,7 @@ struct RayLdsHead : KnotTab {
   double km[2][K + 1][4];   // per axis and knot interval: the tile's knot moments, then
                             // in place their knot adjoint (km_knots)
   Nfw nfw[RTU_MAX_SUB];
+  EplTab epl;               // EPL deflector: series tables of the sample
 };
 
 // The sample's spline tables into LDS (one 16-byte load per thread), the
@@ -892,7 +919,8 @@ __device__ __forceinline__ void load_knots(const SysDev& S, int b, RayLdsHead& H
   {
     const int ns = n_sub_of(S, b);
     const float* lensp = S.lens + (size_t)b * S.n_lens;
-    if ((int)threadIdx.x < ns) H.nfw[threadIdx.x] = make_nfw(lensp + RTU_N_LENS_BASE + RTU_N_PER_SUB * threadIdx.x, S.tau);
+    if ((int)threadIdx.x < ns) H.nfw[threadIdx.x] = make_nfw(lensp + S.lens_base + RTU_N_PER_SUB * threadIdx.x, S.tau);
+    if (S.epl && threadIdx.x == 64) epl_table(make_epl(lensp), H.epl);
   }
   const float4* src = reinterpret_cast<const float4*>(S.ktab + b);
   float4* dst = reinterpret_cast<float4*>(static_cast<KnotTab*>(&H));
@@ -967,6 +995,7 @@ __device__ __forceinline__ void bil_corners(const float* g, int n, const Bil& B,
 // sub-rays contribute nothing to the gradient but lens light (the one-cell
 // margin covers the adjoint's own rounding of the same rays); the range sizes
 // the adjoint's LDS window when the source grid does not fit in LDS.
+template <bool EPL>
 __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* smem) {
   RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
   const int ti = tile / S.ray_tx, tj = tile - ti * S.ray_tx;
@@ -979,7 +1008,7 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
   if (in) {
     const float* lensp = S.lens + (size_t)b * S.n_lens;
     const int nsub = n_sub_of(S, b);
-    const Sie L = make_sie(lensp);
+    const Main<EPL> L(lensp, &H.epl);
     const int n = S.n_src;
     const float* gsrc = S.srcp + (size_t)b * (n + 2) * (n + 2);
     float acc = 0.f;
@@ -1031,13 +1060,14 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
     S.tbox[((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64) + (threadIdx.x >> 6)] = make_int4(bi0, bj0, bi1, bj1);
 }
 
+template <bool EPL>
 __global__ void __launch_bounds__(RAY_THREADS) k_rays_fwd(SysDev S) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x / S.ray_tiles;
-  rays_fwd_body(S, b, blockIdx.x - b * S.ray_tiles, smem);
+  rays_fwd_body<EPL>(S, b, blockIdx.x - b * S.ray_tiles, smem);
 }
 
-template <bool LDSGRID>
+template <bool LDSGRID, bool EPL>
 __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* smem) {
   RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
   const int n = S.n_src, np = n + 2;
@@ -1098,11 +1128,12 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   __syncthreads();
   const float* lensp = S.lens + (size_t)b * S.n_lens;
   const int nsub = n_sub_of(S, b);
-  const Sie L = make_sie(lensp);
+  const Main<EPL> M(lensp, &H.epl);
   const float* gsrc = S.srcp + (size_t)b * np * np;
   double* gsb = S.sbar + (size_t)b * n * n;
-  SieAcc acc;
+  SieAcc acc;                         // SIE: raw accumulators (sie_grad_one)
   acc.zero();
+  float eacc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // EPL: the parameter gradients
   int ongrid = 0;   // sub-rays of this pixel on the grid
   if (wave_on && i < S.n_img && j < S.n_img) {
     const float vb = S.ubar[(size_t)b * S.n_img * S.n_img + i * S.n_img + j] * S.inv_ss2;
@@ -1146,7 +1177,8 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         const float x = fmaf((float)c, dxs, x0);
         SieRay E;
         float ax, ay;
-        sie_shear_alpha<true>(L, x, y, ax, ay, E);
+        if constexpr (EPL) M.alpha(x, y, ax, ay);
+        else sie_shear_alpha<true>(M.L, x, y, ax, ay, E);
         for (int q = 0; q < nsub; ++q) nfw_alpha(H.nfw[q], S.tau, x, y, ax, ay);
         const float bx = x - ax, by = y - ay;
         kx = knot_find(H, 0, bx, kx);
@@ -1177,7 +1209,8 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         km_add(cy, yby, ty);
         // d loss / d beta -> d loss / d alpha = -d loss / d beta
         const float abx = -Tbx * dTx, aby = -Tby * dTy;
-        sie_shear_vjp(L, E, x, y, abx, aby, acc);
+        if constexpr (EPL) epl_shear_vjp(M.L, *M.T, x, y, abx, aby, eacc);
+        else sie_shear_vjp(M.L, E, x, y, abx, aby, acc);
         for (int q = 0; q < nsub; ++q) {
           float* sa = subacc + (4 * q) * RAY_THREADS + threadIdx.x;
           float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
@@ -1197,18 +1230,21 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double* lp = S.lpart + (((size_t)b * S.ray_tiles + tile) * (RAY_THREADS / 64) + wave) * (S.n_lens + 2);
-    const float v[8] = {acc.P, acc.q, acc.f, acc.phi, acc.x0, acc.y0, acc.g1, acc.g2};
+    float v[8] = {acc.P, acc.q, acc.f, acc.phi, acc.x0, acc.y0, acc.g1, acc.g2};
+    if constexpr (EPL)
+      for (int k = 0; k < 8; ++k) v[k] = eacc[k];
     float r[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) r[k] = wave_sum(v[k]);
     const int on = wave_sum(ongrid);
     if (lane == 0) {
       for (int k = 0; k < 8; ++k) lp[k] = (double)r[k];
+      if (EPL) lp[8] = 0.0;           // rows: the 8 model terms, then lens index + 1
       lp[S.n_lens + 1] = (double)on;
     }
     for (int q = 0; q < 4 * S.n_sub_max; ++q) {
       const float sq = wave_sum(subacc[q * RAY_THREADS + threadIdx.x]);
-      if (lane == 0) lp[8 + q] = (double)sq;
+      if (lane == 0) lp[S.lens_base + 1 + q] = (double)sq;
     }
     // lens-light gradients: every lane of the wave takes part in the sums,
     // a pixel outside the image with weight zero
@@ -1281,11 +1317,11 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   }
 }
 
-template <bool LDSGRID>
+template <bool LDSGRID, bool EPL>
 __global__ void __launch_bounds__(RAY_THREADS) k_rays_adj(SysDev S) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x / S.ray_tiles;
-  rays_adj_body<LDSGRID>(S, b, blockIdx.x - b * S.ray_tiles, smem);
+  rays_adj_body<LDSGRID, EPL>(S, b, blockIdx.x - b * S.ray_tiles, smem);
 }
 
 // ====================================================================== PSF
@@ -1486,6 +1522,7 @@ struct PostLds {
   double lsum[RTU_MAX_LENS + 1];   // raw sums
   double ub[4];           // uniform grid: d loss / d (x_min, x_max, y_min, y_max)
   uint32_t stat;
+  EplTab etab;            // EPL deflector: the sample's series tables
 };
 
 __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsigned char* fft_smem, int cap, PostLds& P) {
@@ -1517,6 +1554,7 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
     const float* lensp = S.lens + (size_t)b * nl;
     const int nsub = n_sub_of(S, b);
     const Sie L = make_sie(lensp);
+    if (S.epl && tid == 0) epl_table(make_epl(lensp), P.etab);   // read after the syncs below
     // ---- knot adjoint: sum the tile partials, then S_k = 1/p'_k with
     //      p'_k = sum_l D_kl X_l  ->  dX_l += sum_k (-S_k^2 dS_k) D_kl
     reduce_columns(S.kbar + (size_t)b * S.ray_tiles * 4 * K, S.ray_tiles, 4 * K, 4 * K,
@@ -1585,19 +1623,26 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
         const float x = ((float)j - 0.5f * (float)(S.n_img - 1)) * S.pix;
         const float y = ((float)i - 0.5f * (float)(S.n_img - 1)) * S.pix;
         const float abx = ax == 0 ? -(float)bb : 0.f, aby = ax == 1 ? -(float)bb : 0.f;
-        SieAcc a;
-        a.zero();
-        SieRay E;
-        float ax_, ay_;
-        sie_shear_alpha<true>(L, x, y, ax_, ay_, E);
-        sie_shear_vjp(L, E, x, y, abx, aby, a);
-        row[0] = a.P; row[1] = a.q; row[2] = a.f; row[3] = a.phi;
-        row[4] = a.x0; row[5] = a.y0; row[6] = a.g1; row[7] = a.g2;
+        if (S.epl) {     // the parameter gradients themselves (row 8 stays zero)
+          float ea[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+          epl_shear_vjp(make_epl(lensp), P.etab, x, y, abx, aby, ea);
+          for (int k = 0; k < 8; ++k) row[k] = ea[k];
+        } else {
+          SieAcc a;
+          a.zero();
+          SieRay E;
+          float ax_, ay_;
+          sie_shear_alpha<true>(L, x, y, ax_, ay_, E);
+          sie_shear_vjp(L, E, x, y, abx, aby, a);
+          row[0] = a.P; row[1] = a.q; row[2] = a.f; row[3] = a.phi;
+          row[4] = a.x0; row[5] = a.y0; row[6] = a.g1; row[7] = a.g2;
+        }
+        double* rs = row + S.lens_base + 1;   // lens index + 1 from the subhaloes on
         for (int q = 0; q < nsub; ++q) {
-          const Nfw N = make_nfw(lensp + RTU_N_LENS_BASE + RTU_N_PER_SUB * q, S.tau);
+          const Nfw N = make_nfw(lensp + S.lens_base + RTU_N_PER_SUB * q, S.tau);
           float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
           nfw_vjp(N, S.tau, x, y, abx, aby, g0, g1, g2, g3);
-          row[8 + 4 * q] = g0; row[9 + 4 * q] = g1; row[10 + 4 * q] = g2; row[11 + 4 * q] = g3;
+          rs[4 * q] = g0; rs[4 * q + 1] = g1; rs[4 * q + 2] = g2; rs[4 * q + 3] = g3;
         }
       }
     }
@@ -1612,7 +1657,8 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
     reduce_columns(mp, 4 * K, nc, nc, P.part, [&](int c, double v) { P.lsum[c] += v; });
     __syncthreads();
     if (tid < nl) {
-      const double v = tid < 7 ? sie_grad_one(L, P.lsum, tid) : P.lsum[tid + 1];
+      const double v = S.epl ? (tid < 8 ? P.lsum[tid] : P.lsum[tid + 1])
+                             : (tid < 7 ? sie_grad_one(L, P.lsum, tid) : P.lsum[tid + 1]);
       if (S.g_lens) S.g_lens[(size_t)b * nl + tid] = (float)v;
       if (!isfinite(v)) atomicOr(&P.stat, RTU_ST_NONFINITE);
     }
@@ -1968,17 +2014,23 @@ bool adj_lds_grid(const SysDev& h) {
 }
 
 hipError_t launch_rays_fwd(const SysDev& h, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_rays_fwd, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), ray_lds_bytes(h, false, false), s, h);
+  if (h.epl)
+    hipLaunchKernelGGL(k_rays_fwd<true>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), ray_lds_bytes(h, false, false),
+                       s, h);
+  else
+    hipLaunchKernelGGL(k_rays_fwd<false>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), ray_lds_bytes(h, false, false),
+                       s, h);
   return hipGetLastError();
 }
 
 hipError_t launch_rays_adj(const SysDev& h, int batch, hipStream_t s) {
   const bool lg = adj_lds_grid(h);
   const size_t lds = ray_lds_bytes(h, true, lg);
-  if (lg)
-    hipLaunchKernelGGL(k_rays_adj<true>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), lds, s, h);
-  else
-    hipLaunchKernelGGL(k_rays_adj<false>, dim3(batch * h.ray_tiles), dim3(RAY_THREADS), lds, s, h);
+  const dim3 g(batch * h.ray_tiles), t(RAY_THREADS);
+  if (lg && h.epl) hipLaunchKernelGGL((k_rays_adj<true, true>), g, t, lds, s, h);
+  else if (lg) hipLaunchKernelGGL((k_rays_adj<true, false>), g, t, lds, s, h);
+  else if (h.epl) hipLaunchKernelGGL((k_rays_adj<false, true>), g, t, lds, s, h);
+  else hipLaunchKernelGGL((k_rays_adj<false, false>), g, t, lds, s, h);
   return hipGetLastError();
 }
 
@@ -2022,23 +2074,24 @@ __global__ void __launch_bounds__(PREP_THREADS) kf_prep(const SysDev* __restrict
   else prep_gp(S, t.y, smem, fft_cap);
 }
 
+template <bool EPL>
 __global__ void __launch_bounds__(RAY_THREADS) kf_rays_fwd(const SysDev* __restrict__ sys,
                                                            const Task* __restrict__ tasks, int round) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Task t = tasks[blockIdx.x];
   const SysDev S = sys[t.x];
   if (!sys_active(S, round)) return;
-  rays_fwd_body(S, t.y, t.z, smem);
+  rays_fwd_body<EPL>(S, t.y, t.z, smem);
 }
 
-template <bool LDSGRID>
+template <bool LDSGRID, bool EPL>
 __global__ void __launch_bounds__(RAY_THREADS) kf_rays_adj(const SysDev* __restrict__ sys,
                                                            const Task* __restrict__ tasks, int round) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Task t = tasks[blockIdx.x];
   const SysDev S = sys[t.x];
   if (!sys_active(S, round)) return;
-  rays_adj_body<LDSGRID>(S, t.y, t.z, smem);
+  rays_adj_body<LDSGRID, EPL>(S, t.y, t.z, smem);
 }
 
 __global__ void __launch_bounds__(PSF_THREADS) kf_psf(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
@@ -2072,8 +2125,12 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
                            (int)(L.lds_prep / sizeof(float2)) - 128);
       break;
     case RTU_STAGE_RAYS_FWD:
-      if (L.n_fwd)
-        hipLaunchKernelGGL(kf_rays_fwd, dim3(L.n_fwd), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys, L.t_fwd, round);
+      if (L.n_fwd[0])
+        hipLaunchKernelGGL(kf_rays_fwd<false>, dim3(L.n_fwd[0]), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys,
+                           L.t_fwd[0], round);
+      if (L.n_fwd[1])
+        hipLaunchKernelGGL(kf_rays_fwd<true>, dim3(L.n_fwd[1]), dim3(RAY_THREADS), L.lds_rays_fwd, s, L.sys,
+                           L.t_fwd[1], round);
       break;
     case RTU_STAGE_PSF_FWD:
     case RTU_STAGE_PSF_ADJ:
@@ -2082,12 +2139,18 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
                            stage == RTU_STAGE_PSF_ADJ ? 1 : 0);
       break;
     case RTU_STAGE_RAYS_ADJ:
-      if (L.n_adj[0])
-        hipLaunchKernelGGL(kf_rays_adj<true>, dim3(L.n_adj[0]), dim3(RAY_THREADS), L.lds_rays_adj, s, L.sys,
-                           L.t_adj[0], round);
-      if (L.n_adj[1])
-        hipLaunchKernelGGL(kf_rays_adj<false>, dim3(L.n_adj[1]), dim3(RAY_THREADS), L.lds_rays_adj, s, L.sys,
-                           L.t_adj[1], round);
+      if (L.n_adj[0][0])
+        hipLaunchKernelGGL((kf_rays_adj<true, false>), dim3(L.n_adj[0][0]), dim3(RAY_THREADS), L.lds_rays_adj, s,
+                           L.sys, L.t_adj[0][0], round);
+      if (L.n_adj[0][1])
+        hipLaunchKernelGGL((kf_rays_adj<true, true>), dim3(L.n_adj[0][1]), dim3(RAY_THREADS), L.lds_rays_adj, s,
+                           L.sys, L.t_adj[0][1], round);
+      if (L.n_adj[1][0])
+        hipLaunchKernelGGL((kf_rays_adj<false, false>), dim3(L.n_adj[1][0]), dim3(RAY_THREADS), L.lds_rays_adj, s,
+                           L.sys, L.t_adj[1][0], round);
+      if (L.n_adj[1][1])
+        hipLaunchKernelGGL((kf_rays_adj<false, true>), dim3(L.n_adj[1][1]), dim3(RAY_THREADS), L.lds_rays_adj, s,
+                           L.sys, L.t_adj[1][1], round);
       break;
     case RTU_STAGE_POST:
       if (L.n_post)

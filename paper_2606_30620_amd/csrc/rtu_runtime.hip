@@ -86,7 +86,7 @@ bool valid_geometry(const rtu_geometry* g) {
   if (g->n_sub_max < 0 || g->n_sub_max > RTU_MAX_SUB) return false;
   if (g->n_gauss < 0 || g->n_gauss > RTU_MAX_GAUSS) return false;
   if (g->k_nodes != RTU_K_NODES) return false;
-  if (!(g->pixel_scale > 0.f) || !(g->tnfw_tau >= 0.f) || (g->flags & ~(RTU_GEOM_RADIX_SELECT | RTU_GEOM_UNIFORM)) != 0) return false;
+  if (!(g->pixel_scale > 0.f) || !(g->tnfw_tau >= 0.f) || (g->flags & ~(RTU_GEOM_RADIX_SELECT | RTU_GEOM_UNIFORM | RTU_GEOM_EPL)) != 0) return false;
   return true;
 }
 
@@ -115,13 +115,15 @@ void fill_geometry(const rtu_geometry* g, SysDev& h) {
   h.psf_k = g->psf_size;
   h.n_sub_max = g->n_sub_max;
   h.n_gauss = g->n_gauss;
-  h.light_off = RTU_N_LENS_BASE + RTU_N_PER_SUB * g->n_sub_max;
+  h.light_off = ((g->flags & RTU_GEOM_EPL) ? RTU_N_LENS_BASE_EPL : RTU_N_LENS_BASE) + RTU_N_PER_SUB * g->n_sub_max;
   h.n_lens = h.light_off + RTU_N_PER_GAUSS * g->n_gauss;
   h.pix = g->pixel_scale;
   h.tau = g->tnfw_tau;
   h.inv_ss2 = 1.f / (float)(g->supersample * g->supersample);
   h.sel_radix = (g->flags & RTU_GEOM_RADIX_SELECT) ? 1 : 0;
   h.uniform = (g->flags & RTU_GEOM_UNIFORM) ? 1 : 0;
+  h.epl = (g->flags & RTU_GEOM_EPL) ? 1 : 0;
+  h.lens_base = h.epl ? RTU_N_LENS_BASE_EPL : RTU_N_LENS_BASE;
   h.ray_tx = (g->n_img + RAY_TILE - 1) / RAY_TILE;
   h.ray_tiles = h.ray_tx * h.ray_tx;
   h.adj_wcap = adj_window_cap(h);
@@ -368,7 +370,9 @@ int run_eval(rtu_plan p, const SysDev& h, int batch, hipStream_t s) {
 extern "C" {
 
 int32_t rtu_n_lens(const rtu_geometry* g) {
-  return g ? RTU_N_LENS_BASE + RTU_N_PER_SUB * g->n_sub_max + RTU_N_PER_GAUSS * g->n_gauss : 0;
+  return g ? ((g->flags & RTU_GEOM_EPL) ? RTU_N_LENS_BASE_EPL : RTU_N_LENS_BASE) + RTU_N_PER_SUB * g->n_sub_max +
+                 RTU_N_PER_GAUSS * g->n_gauss
+           : 0;
 }
 
 size_t rtu_workspace_bytes(const rtu_geometry* g, int32_t max_batch) {

@@ -40,7 +40,8 @@ def log_params(problem: synth.Problem) -> List[int]:
     """Lens parameters fitted in log space: every active subhalo's kappa_s
     and r_s (positive scales; a log-space guide keeps them positive through
     every sample and step)."""
-    return [synth.N_LENS_BASE + synth.N_PER_SUB * j + k for j in range(int(problem.n_sub[0])) for k in (0, 1)]
+    base = synth.N_LENS_BASE + (1 if problem.geom.epl else 0)
+    return [base + synth.N_PER_SUB * j + k for j in range(int(problem.n_sub[0])) for k in (0, 1)]
 
 
 def guide_init(problem: synth.Problem):
@@ -72,7 +73,8 @@ def make_requests(n: int, rate: float, steps: int = 200, samples: int = 1, seed:
 
 def _geometry(lib, g: synth.Geometry):
     return lib.make_geometry(g.n_img, g.supersample, g.n_src, g.psf_size, g.pixel_scale, g.n_sub_max,
-                             g.tnfw_tau, flags=lib.GEOM_UNIFORM if g.uniform else 0, n_gauss=g.n_gauss)
+                             g.tnfw_tau, flags=(lib.GEOM_UNIFORM if g.uniform else 0) | (lib.GEOM_EPL if g.epl else 0),
+                             n_gauss=g.n_gauss)
 
 
 @dataclasses.dataclass

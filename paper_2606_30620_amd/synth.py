@@ -58,10 +58,11 @@ class Geometry:
     tnfw_tau: float = 0.0   # truncation radius in units of r_s; 0 = none
     n_gauss: int = 0        # lens-light Gaussians; 0 = no lens light
     uniform: bool = False   # source grid on the masked rays' square box instead of the RTU grid
+    epl: bool = False       # main deflector: elliptical power law, its slope as lens parameter 7
 
     @property
     def n_lens(self) -> int:
-        return N_LENS_BASE + N_PER_SUB * self.n_sub_max + N_PER_GAUSS * self.n_gauss
+        return N_LENS_BASE + (1 if self.epl else 0) + N_PER_SUB * self.n_sub_max + N_PER_GAUSS * self.n_gauss
 
 
 def e_from_q_phi(q: float, phi: float):
@@ -295,6 +296,19 @@ def make_problem(name: str, batch: Optional[int] = None, seed: Optional[int] = N
     sigma = np.full((N, N), sig)
     return Problem(geom, _f32(image), _f32(sigma), _f32(psf), mask,
                    _f32(lens), n_sub, _f32(ps), _f32(latent), truth)
+
+
+def with_epl(problem: Problem, slope_mean: float = 2.1, slope_spread: float = 0.05, seed: int = 77) -> Problem:
+    """The same system with the EPL deflector: a slope per sample (drawn
+    around slope_mean) inserted as lens parameter 7, the subhaloes and lens
+    light moved up by one."""
+    rng = np.random.default_rng(seed)
+    B = problem.batch
+    g = rng.normal(slope_mean, slope_spread, B)
+    lens = np.concatenate([problem.lens[:, :N_LENS_BASE], g[:, None], problem.lens[:, N_LENS_BASE:]], axis=1)
+    truth = np.concatenate([problem.lens_truth[:N_LENS_BASE], [slope_mean], problem.lens_truth[N_LENS_BASE:]])
+    return dataclasses.replace(problem, geom=dataclasses.replace(problem.geom, epl=True), lens=_f32(lens),
+                               lens_truth=truth)
 
 
 # ---------------------------------------------------------------- serving mix

@@ -85,7 +85,8 @@ def compare(plan, problem, b, res, ref, check_stages=True):
             xs, ys = O.pixel_centres(problem.geom.n_img, float(np.float32(problem.geom.pixel_scale)))
             m = torch.as_tensor(problem.mask.reshape(-1).astype(bool))
             lens = torch.as_tensor(problem.lens[b].astype(np.float64))
-            bxm, bym = O.ray_shoot(xs[m], ys[m], lens, int(problem.n_sub[b]), problem.geom.tnfw_tau)
+            bxm, bym = O.ray_shoot(xs[m], ys[m], lens, int(problem.n_sub[b]), problem.geom.tnfw_tau,
+                                   getattr(problem.geom, "epl", False))
             same_sel = selection_agrees(sel, tr, [bxm.numpy(), bym.numpy()])
             mu_o = [float(torch.as_tensor(v).detach()) for v in tr["mu"]]
             s_o = float(torch.as_tensor(tr["s"]).detach())
@@ -107,10 +108,11 @@ def compare(plan, problem, b, res, ref, check_stages=True):
         # first n_sub are active), lens-light Gaussians (6 n_gauss)
         ns = int(problem.n_sub[b])
         g = problem.geom
-        lo = 7 + 4 * g.n_sub_max
-        act = np.r_[0:7 + 4 * ns]
+        base = 8 if getattr(g, "epl", False) else 7
+        lo = base + 4 * g.n_sub_max
+        act = np.r_[0:base + 4 * ns]
         light = np.r_[lo:lo + 6 * getattr(g, "n_gauss", 0)]
-        inact = np.r_[7 + 4 * ns:lo]
+        inact = np.r_[base + 4 * ns:lo]
         out["g_ps"] = relinf(res.grad_ps[b].cpu().numpy(), ref["grad_ps"].numpy())
         out["g_latent"] = relinf(res.grad_latent[b].cpu().numpy(), ref["grad_latent"].numpy())
         assert out["g_ps"] <= TOL_GRAD, ("grad_ps", res.grad_ps[b].cpu().numpy(), ref["grad_ps"].numpy())

@@ -36,7 +36,9 @@ def test_host_validation_without_gpu():
     assert L.rtu_workspace_bytes(ok, 1) == L.rtu_workspace_bytes(g, 1)
     uni = _lib.make_geometry(64, 1, 32, 15, 0.05, flags=_lib.GEOM_UNIFORM)
     assert L.rtu_workspace_bytes(uni, 1) == L.rtu_workspace_bytes(g, 1)
-    bad = _lib.make_geometry(64, 1, 32, 15, 0.05, flags=4)     # unknown flag
+    epl = _lib.make_geometry(64, 1, 32, 15, 0.05, flags=_lib.GEOM_EPL)
+    assert L.rtu_workspace_bytes(epl, 1) > 0 and L.rtu_n_lens(epl) == 8
+    bad = _lib.make_geometry(64, 1, 32, 15, 0.05, flags=8)     # unknown flag
     assert L.rtu_workspace_bytes(bad, 1) == 0
     lit = _lib.make_geometry(64, 1, 32, 15, 0.05, n_sub_max=2, n_gauss=5)
     assert L.rtu_n_lens(lit) == 7 + 4 * 2 + 6 * 5

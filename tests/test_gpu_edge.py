@@ -56,12 +56,13 @@ def test_gradient_matches_central_differences_of_the_gpu_loss():
     difference actually taken, so the first-order prediction is
     sum_i g_i (x+ - x-)_i.
 
-    Step: h = 1e-4 where that changes the loss by at least 10, else the step
+    Step: h = 1e-4 where that changes the loss by at least 20, else the step
     that does (at most 5 % of the parameter).  The loss, an FP64 sum of FP32
-    pixel terms of about 2e4 at C2, carries rounding noise of about 1e-2
-    (measured: 1e-4 steps of the spectrum slope n change it by 0.26 and the
-    difference missed by 0.005), so a change of 10 resolves the derivative to
-    about 1e-3; the truncation error of the larger steps is O(h^2), below that."""
+    pixel terms of about 2e4 at C2, carries rounding noise of 1e-2 to 3e-2
+    (measured: central differences of a change of 10 missed by up to 0.03,
+    depending on how the compiler orders the forward's FP32 arithmetic), so a
+    change of 20 resolves the derivative to about 1e-3; the truncation error
+    of the larger steps is O(h^2), below that."""
     from paper_2606_30620_amd import api
     p = synth.make_problem("C2", batch=2)
     plan = api.plan_for_problem(p)
@@ -85,7 +86,7 @@ def test_gradient_matches_central_differences_of_the_gpu_loss():
             e = (v / v.norm(dim=(1, 2), keepdim=True)).float()
             gdir = (g * e.double()).sum(dim=(1, 2))
             scale = torch.ones_like(gdir)
-        h = torch.clamp(torch.maximum(torch.full_like(gdir, 1e-4), 5.0 / gdir.abs()), max=0.05 * scale).float()
+        h = torch.clamp(torch.maximum(torch.full_like(gdir, 1e-4), 20.0 / gdir.abs()), max=0.05 * scale).float()
         hb = h.view(-1, *([1] * (e.dim() - 1)))
         xp_, xm_ = ((ps + hb * e, ps - hb * e) if d < 4 else (lat + hb * e, lat - hb * e))
         if d < 4:

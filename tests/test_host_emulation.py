@@ -185,3 +185,18 @@ def test_weighted_grid(driver, case):
             assert abs(out["loss"][b] - float(ref["loss"].detach())) <= allow
     else:
         _compare(out, p)
+
+
+@pytest.mark.parametrize("case", ["c1", "case4", "subhaloes"])
+def test_epl_deflector(driver, case):
+    """RTU_GEOM_EPL: the series tables and the complex vector-Jacobian product
+    of the elliptical power law in every kernel (slopes around 2.1; lens
+    light and a 128 x 128 grid in global memory with case4; two subhaloes)."""
+    if case == "c1":
+        p = synth.with_epl(synth.make_problem("C1"))
+    elif case == "case4":
+        p = synth.with_epl(_case4(), slope_mean=2.3)
+    else:
+        g = synth.Geometry(40, 0.08, 2, 16, 9, 1.0, n_sub_max=2, tnfw_tau=10.0)
+        p = synth.with_epl(synth.make_problem("X", batch=2, seed=12, geom=g), slope_mean=1.85)
+    _compare(_run(driver, p, flags=4), p)
