@@ -254,7 +254,8 @@ int rtu_debug_fetch(rtu_plan p, int32_t what, int32_t sample, void* host_dst, si
 #define RTU_STAGE_PSF_ADJ   3   /* PSF adjoint                                    */
 #define RTU_STAGE_RAYS_ADJ  4   /* ray adjoint: source, knot, lens gradients      */
 #define RTU_STAGE_POST      5   /* knot adjoint, reductions, GP adjoint           */
-#define RTU_STAGE_SAMPLE    6   /* fit: draw z = mu + exp(rho) eps                */
+#define RTU_STAGE_SAMPLE    6   /* fit: draw z = mu + exp(rho) eps (first step,
+                                       restored state, given draws; else in ADAM) */
 #define RTU_STAGE_ADAM      7   /* fit: ELBO value and Adam update                */
 #define RTU_N_STAGES        8
 
@@ -317,7 +318,10 @@ int rtu_fit_read(rtu_fit f, float* mu, float* rho, double* elbo, int32_t max_tra
 int rtu_fit_get_state(rtu_fit f, float* state, int32_t* steps, void* stream);
 int rtu_fit_set_state(rtu_fit f, const float* state, int32_t steps);
 
-/* Copies the last step's samples z_s to host z[S][dim] (synchronises `stream`). */
+/* Copies the fit's sample buffers z_s to host z[S][dim] (synchronises
+ * `stream`): after a step with given draws, that step's samples; with Philox
+ * draws the Adam update of a step already draws the next step's samples (so
+ * that no separate sampling launch is needed), and the buffers hold those. */
 int rtu_fit_samples(rtu_fit f, float* z, void* stream);
 
 /* Device pointers of the last step's per-sample loss [S] (double) and status

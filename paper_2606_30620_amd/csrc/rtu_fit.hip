@@ -24,14 +24,24 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
   return c;
 }
 
-// Standard normal draw for (step, sample, parameter) by Box-Muller on two
-// 32-bit uniforms of one Philox block.
-__device__ __forceinline__ float normal_draw(const FitDev& F, int step, int s, int i) {
-  const uint4 r = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)s, (uint32_t)step, 0x52545547u),
+// Standard normal draws of samples 4c .. 4c + 3 of (step, parameter): one
+// Philox block (counter: parameter, c, step, a constant) gives four 32-bit
+// uniforms, and Box-Muller turns each pair into two normals (cosine and sine
+// branch).
+__device__ __forceinline__ void normal_draw4(const FitDev& F, int step, int c, int i, float (&z)[4]) {
+  const uint4 r = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)c, (uint32_t)step, 0x52545547u),
                                 make_uint2(F.seed_lo, F.seed_hi));
-  const float u1 = ((float)r.x + 0.5f) * 2.3283064365386963e-10f;   // (0, 1)
-  const float u2 = (float)r.y * 2.3283064365386963e-10f;
-  return sqrtf(-2.f * __logf(u1)) * __cosf(6.283185307179586f * u2);
+  const float k = 2.3283064365386963e-10f;          // 2^-32
+  const float ra = sqrtf(-2.f * __logf(((float)r.x + 0.5f) * k)), ta = 6.283185307179586f * (float)r.y * k;
+  const float rb = sqrtf(-2.f * __logf(((float)r.z + 0.5f) * k)), tb = 6.283185307179586f * (float)r.w * k;
+  z[0] = ra * __cosf(ta); z[1] = ra * __sinf(ta);
+  z[2] = rb * __cosf(tb); z[3] = rb * __sinf(tb);
+}
+__device__ __forceinline__ float normal_draw(const FitDev& F, int step, int s, int i) {
+  float z[4];
+  normal_draw4(F, step, s >> 2, i, z);
+  const int k = s & 3;
+  return k == 0 ? z[0] : (k == 1 ? z[1] : (k == 2 ? z[2] : z[3]));
 }
 
 __device__ __forceinline__ float eps_at(const FitDev& F, const float* eps, int step, int s, int i) {
@@ -44,12 +54,10 @@ __device__ __forceinline__ bool is_log(const FitDev& F, int i) {
 
 // z_s = mu + exp(rho) eps_s (z = exp of that for a log-space parameter),
 // scattered into the plan's per-sample inputs; the draw is kept for the Adam
-// update of rho
-__device__ __forceinline__ void sample_body(const FitDev& F, const float* eps, int step, int s, int i) {
-  if (i >= F.dim) return;
-  const float e = eps_at(F, eps, step, s, i);
+// update of rho.  mu, sig = exp(rho) of parameter i.
+__device__ __forceinline__ void sample_store(const FitDev& F, int s, int i, float mu, float sig, float e) {
   F.eps_s[(size_t)s * F.dim + i] = e;
-  float z = F.mu[i] + __expf(F.rho[i]) * e;
+  float z = mu + sig * e;
   if (is_log(F, i)) z = __expf(z);
   if (i < F.n_lens) F.z_lens[(size_t)s * F.n_lens + i] = z;
   else if (i < F.n_lens + 4) F.z_ps[(size_t)s * 4 + (i - F.n_lens)] = z;
@@ -75,8 +83,10 @@ __device__ __forceinline__ float grad_at(const FitDev& F, int s, int i) {
 // A workgroup takes ADAM_P parameters; its ADAM_G groups of threads each sum
 // every ADAM_G-th sample of a parameter, and group 0 adds the group sums in
 // group order (so that more workgroups share the memory latency of the
-// S gradient and draw loads).  Called by every thread of the workgroup.
-__device__ __forceinline__ void adam_body(const FitDev& F, int t, int i, int g, float* red) {
+// S gradient and draw loads) and leaves the new mu and exp(rho) in nmu,
+// nsig.  Called by every thread of the workgroup.
+__device__ __forceinline__ void adam_body(const FitDev& F, int t, int i, int g, float* red, float* nmu,
+                                          float* nsig) {
   const int p = threadIdx.x % ADAM_P;
   float gm = 0.f, gr = 0.f;
   if (i < F.dim) {
@@ -112,7 +122,10 @@ __device__ __forceinline__ void adam_body(const FitDev& F, int t, int i, int g, 
   v = b2 * F.v_rho[i] + (1.f - b2) * gr * gr;
   F.m_rho[i] = m;
   F.v_rho[i] = v;
-  F.rho[i] -= F.lr * (m * c1) / (sqrtf(v * c2) + e);
+  const float rho = F.rho[i] - F.lr * (m * c1) / (sqrtf(v * c2) + e);
+  F.rho[i] = rho;
+  nmu[p] = F.mu[i];
+  nsig[p] = __expf(rho);
 }
 
 // ---- shared launches over many fits (serving); step = round - round0
@@ -121,47 +134,68 @@ __device__ __forceinline__ bool fit_step(const FitDev& F, int round, int& step) 
   return step >= 0 && step < F.nsteps;
 }
 
-// The blocks of sample 0 also sum the guide's rho over their 256 parameters
-// (the ELBO's entropy term, before this step's update) into rho_part.
+// rho_part[step & 1][j]: the sum of rho over parameter block j of ADAM_P at
+// the time the samples of `step` were drawn (the ELBO's entropy term).
+__device__ __forceinline__ double* rho_part_of(const FitDev& F, int step) {
+  return F.rho_part + (size_t)(step & 1) * ((F.dim + ADAM_P - 1) / ADAM_P);
+}
+
+// The samples of a step: a fit's first step, one after a restored state, and
+// every step with given draws.  (With Philox draws the Adam update of a step
+// draws the next step's samples.)  The blocks of sample 0 also write the
+// rho sums of their ADAM_P-blocks (one wave each).
 __global__ void __launch_bounds__(FIT_THREADS) kf_sample(const FitDev* __restrict__ fits,
                                                          const Task* __restrict__ tasks, int round,
                                                          const float* eps) {
-  __shared__ double red[FIT_THREADS / 64];
   const Task t = tasks[blockIdx.x];      // x fit, y parameter block, z sample
   const FitDev& F = fits[t.x];
   int step;
   if (!fit_step(F, round, step)) return;
   const int i = t.y * FIT_THREADS + threadIdx.x;
-  sample_body(F, eps, step, t.z, i);
+  if (i < F.dim) sample_store(F, t.z, i, F.mu[i], __expf(F.rho[i]), eps_at(F, eps, step, t.z, i));
   if (t.z == 0) {
+    static_assert(FIT_THREADS % ADAM_P == 0 && ADAM_P == 64, "one wave per rho block");
     const double r = wave_sum(i < F.dim ? (double)F.rho[i] : 0.0);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double part = 0.0;
-      for (int w = 0; w < FIT_THREADS / 64; ++w) part += red[w];
-      F.rho_part[t.y] = part;
-    }
+    const int j = i / ADAM_P;
+    if ((threadIdx.x & 63) == 0 && j * ADAM_P < F.dim) rho_part_of(F, step)[j] = r;
   }
 }
 
-// Adam; block 0 of each fit also writes the ELBO of this step from the
-// sampling kernel's rho sums (taken before the update), the losses and the
-// status words, each summed in a fixed order.
+// Adam; with draw set (Philox draws) each block then draws the next step's
+// samples of its parameters from the updated guide and their rho sum.  Block
+// 0 of each fit also writes the ELBO of this step from the rho sums taken
+// when this step's samples were drawn, the losses and the status words, each
+// summed in a fixed order.
 __global__ void __launch_bounds__(FIT_THREADS) kf_adam(const FitDev* __restrict__ fits,
-                                                       const Task* __restrict__ tasks, int round) {
+                                                       const Task* __restrict__ tasks, int round, int draw) {
   __shared__ float red[2 * FIT_THREADS];
+  __shared__ float nmu[ADAM_P], nsig[ADAM_P];
   const Task t = tasks[blockIdx.x];      // x fit, y block of ADAM_P parameters
   const FitDev& F = fits[t.x];
   int step;
   if (!fit_step(F, round, step)) return;
-  adam_body(F, step + 1, t.y * ADAM_P + threadIdx.x % ADAM_P, threadIdx.x / ADAM_P, red);
+  const int p = threadIdx.x % ADAM_P, g = threadIdx.x / ADAM_P, i = t.y * ADAM_P + p;
+  adam_body(F, step + 1, i, g, red, nmu, nsig);
+  __syncthreads();
+  if (draw) {
+    if (i < F.dim)
+      for (int c = g; 4 * c < F.S; c += ADAM_G) {   // four samples per Philox block
+        float z[4];
+        normal_draw4(F, step + 1, c, i, z);
+        for (int k = 0; k < 4 && 4 * c + k < F.S; ++k) sample_store(F, 4 * c + k, i, nmu[p], nsig[p], z[k]);
+      }
+    if (g == 0) {
+      const double r = wave_sum(i < F.dim ? (double)F.rho[i] : 0.0);
+      if (p == 0) rho_part_of(F, step + 1)[t.y] = r;
+    }
+  }
   if (t.y != 0 || threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
-  const int nblk = (F.dim + FIT_THREADS - 1) / FIT_THREADS;
+  const int nblk = (F.dim + ADAM_P - 1) / ADAM_P;
+  const double* rp = rho_part_of(F, step);
   double a = 0.0, ls = 0.0;
   uint32_t st = 0;
-  for (int j0 = 0; j0 < nblk; j0 += 64) a += wave_sum(j0 + lane < nblk ? F.rho_part[j0 + lane] : 0.0);
+  for (int j0 = 0; j0 < nblk; j0 += 64) a += wave_sum(j0 + lane < nblk ? rp[j0 + lane] : 0.0);
   for (int s0 = 0; s0 < F.S; s0 += 64) {
     ls += wave_sum(s0 + lane < F.S ? F.loss[s0 + lane] : 0.0);
     const int v = s0 + lane < F.S ? (int)F.status[s0 + lane] : 0;
@@ -179,7 +213,8 @@ hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, co
                                       round, eps);
   } else if (stage == RTU_STAGE_ADAM) {
     if (L.n_param)
-      hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(FIT_THREADS), 0, s, L.fit, L.t_param, round);
+      hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(FIT_THREADS), 0, s, L.fit, L.t_param, round,
+                         eps ? 0 : 1);
   }
   return hipGetLastError();
 }

@@ -409,14 +409,21 @@ int rtu_fleet_run(rtu_fleet f, int32_t rounds, void* stream) {
       for (const Entry& e : f->active) running += !finished(f, e);
     }
     if (running == 0) break;
+    // new tables (fits admitted or retired): the sampling launch draws the
+    // first samples of the new fits (and again, identically, those of the
+    // others); otherwise every fit's samples come from its last Adam update
+    bool fresh = false;
     if (f->dirty) {
       int rc = upload_tables(f);
       if (rc) return rc;
+      fresh = true;
     }
     const int order[] = {RTU_STAGE_SAMPLE, RTU_STAGE_PREP, RTU_STAGE_RAYS_FWD, RTU_STAGE_PSF_FWD,
                          RTU_STAGE_PSF_ADJ, RTU_STAGE_RAYS_ADJ, RTU_STAGE_POST, RTU_STAGE_ADAM};
-    for (int st : order)
+    for (int st : order) {
+      if (st == RTU_STAGE_SAMPLE && !fresh) continue;
       if (launch_fleet_stage(f->L, st, f->round, nullptr, s) != hipSuccess) return RTU_EHIP;
+    }
     f->round++;
     f->since_sync++;
     f->rounds_run++;

@@ -483,7 +483,7 @@ __device__ void weighted_sort(SelLds& L, uint2* A, uint2* Bf, int M) {
 // position wr0[t/2] + (t & 1); results in L.tval / L.tidx with the identity
 // map L.tmap.  A target beyond the total weight takes the last ray in sorted
 // order.
-__device__ void select_weighted(const SysDev& S, SelLds& L, const float* zb, int M, int b, int axis) {
+__device__ __forceinline__ void select_weighted(const SysDev& S, SelLds& L, const float* zb, int M, int b, int axis) {
   const int tid = threadIdx.x, nt = blockDim.x;
   uint2* A = S.wsort + ((size_t)b * 2 + axis) * 2 * M;
   uint2* Bf = A + M;
@@ -572,72 +572,63 @@ __device__ __forceinline__ void knot_table_uniform(const SysDev& S, int b, int a
 // The uniform grid's box from the extremes of both axes (keys: value, ties by
 // index, per thread), for the axis of this workgroup.  Called by every
 // thread.
-__device__ void prep_uniform(const SysDev& S, int b, int axis, SelLds& L, const unsigned long long (&key)[4], int M,
+__device__ __forceinline__ void prep_uniform(const SysDev& S, int b, int axis, SelLds& L, unsigned long long kx0,
+                             unsigned long long kx1, unsigned long long ky0, unsigned long long ky1, int M,
                              uint32_t st) {
   const int tid = threadIdx.x;
   if (tid < 2) { L.ulo[tid] = ~0ull; L.uhi[tid] = 0ull; }
   __syncthreads();
-  atomicMin(&L.ulo[0], key[0]); atomicMax(&L.uhi[0], key[1]);
-  atomicMin(&L.ulo[1], key[2]); atomicMax(&L.uhi[1], key[3]);
+  atomicMin(&L.ulo[0], kx0); atomicMax(&L.uhi[0], kx1);
+  atomicMin(&L.ulo[1], ky0); atomicMax(&L.uhi[1], ky1);
   __syncthreads();
-  double ext[2][2];
-  int idx[2][2];
-  for (int a = 0; a < 2; ++a) {
-    ext[a][0] = M > 0 ? (double)ord_value((unsigned)(L.ulo[a] >> 32)) : 0.0;
-    ext[a][1] = M > 0 ? (double)ord_value((unsigned)(L.uhi[a] >> 32)) : 0.0;
-    idx[a][0] = M > 0 ? (int)(unsigned)L.ulo[a] : 0;
-    idx[a][1] = M > 0 ? (int)(unsigned)L.uhi[a] : 0;
-  }
-  const double rx = ext[0][1] - ext[0][0], ry = ext[1][1] - ext[1][0];
-  double side = rx >= ry ? rx : ry, lo[2];
+  const double x0 = M > 0 ? (double)ord_value((unsigned)(L.ulo[0] >> 32)) : 0.0;
+  const double x1 = M > 0 ? (double)ord_value((unsigned)(L.uhi[0] >> 32)) : 0.0;
+  const double y0 = M > 0 ? (double)ord_value((unsigned)(L.ulo[1] >> 32)) : 0.0;
+  const double y1 = M > 0 ? (double)ord_value((unsigned)(L.uhi[1] >> 32)) : 0.0;
+  const unsigned long long klo = axis == 0 ? L.ulo[0] : L.ulo[1], khi = axis == 0 ? L.uhi[0] : L.uhi[1];
+  const double rx = x1 - x0, ry = y1 - y0;
+  double side = rx >= ry ? rx : ry, lox, loy;
   if (M < 2 || !(side > 0.0)) {
     st |= RTU_ST_MASK_SMALL;
     side = 1.0;
-    lo[0] = ext[0][0];
-    lo[1] = ext[1][0];
+    lox = x0;
+    loy = y0;
   } else {
-    for (int a = 0; a < 2; ++a) lo[a] = 0.5 * (ext[a][0] + ext[a][1]) - 0.5 * side;
+    lox = 0.5 * (x0 + x1) - 0.5 * side;
+    loy = 0.5 * (y0 + y1) - 0.5 * side;
   }
-  knot_table_uniform(S, b, axis, (float)lo[axis], (float)side);
+  knot_table_uniform(S, b, axis, (float)(axis == 0 ? lox : loy), (float)side);
   float* kn = S.knots + ((size_t)b * 2 + axis) * 2 * K;
   float* kd = S.kdbg + ((size_t)b * 2 + axis) * 2 * K;
   int* sel = S.sel + ((size_t)b * 2 + axis) * 2 * K;
   if (tid < 2 * K) {
     kn[tid] = 0.f;
     kd[tid] = 0.f;
-    sel[tid] = tid < 2 ? idx[axis][tid] : 0;
+    sel[tid] = M > 0 && tid < 2 ? (int)(unsigned)(tid == 0 ? klo : khi) : 0;
   }
   if (tid < K) S.dp[((size_t)b * 2 + axis) * K + tid] = -1.f;
   if (tid == 0) {
     if (axis == 0) {
       double* sd = S.stdv + (size_t)b * 4;
-      sd[0] = lo[0]; sd[1] = lo[1]; sd[2] = side; sd[3] = rx >= ry ? 0.0 : 1.0;
+      sd[0] = lox; sd[1] = loy; sd[2] = side; sd[3] = rx >= ry ? 0.0 : 1.0;
     }
     S.st[b * ST_WORDS + axis] = st;
   }
 }
 
-__device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* smem) {
-  SelLds& L = *reinterpret_cast<SelLds*>(smem);
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-  const int M = obs_M(S);
-  const float* lensp = S.lens + (size_t)b * S.n_lens;
-  const int nsub = n_sub_of(S, b);
-  if (S.epl && tid == 0) epl_table(make_epl(lensp), L.etab);
-  const Main<false> sie(lensp, nullptr);
-  float* zb = S.zbuf + ((size_t)b * 2 + axis) * M;
-  uint32_t st = 0;
-  if (M < (S.uniform ? 2 : K + 1)) st |= RTU_ST_MASK_SMALL;
-  unsigned long long ukey[4] = {~0ull, 0ull, ~0ull, 0ull};   // uniform grid: min x, max x, min y, max y
-  if (tid == 0) L.stat = 0;
-  if (tid < 2 * K) { L.tval[tid] = 0.f; L.tidx[tid] = 0; }
-
-  // ---- masked rays at the observed pixel centres (not supersampled)
-  double sx = 0, sy = 0, sxx = 0, syy = 0;
+// The masked rays at the observed pixel centres (not supersampled): their
+// coordinate on this workgroup's axis into zb, the (weighted) moments of
+// both axes, the value and key ranges, and the uniform grid's extremes.
+struct MaskedRays {
+  double sx = 0.0, sy = 0.0, sxx = 0.0, syy = 0.0;
   float vmin = INFINITY, vmax = -INFINITY;      // over the finite values
   unsigned umin = 0xffffffffu, umax = 0u;       // key range over all values
-  __syncthreads();   // the EPL tables
+  unsigned long long kx0 = ~0ull, kx1 = 0ull, ky0 = ~0ull, ky1 = 0ull;
+};
+template <class MAIN>
+__device__ __forceinline__ void masked_rays(const SysDev& S, const MAIN& ML, const float* lensp, int nsub, int axis,
+                                            int M, float* zb, MaskedRays& R) {
+  const int tid = threadIdx.x, nt = blockDim.x;
   // the mask index of the iteration after next is loaded ahead
   int p1 = tid < M ? S.mask_idx[tid] : 0;
   int p2 = tid + nt < M ? S.mask_idx[tid + nt] : 0;
@@ -649,25 +640,51 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
     const float x = ((float)j - 0.5f * (float)(S.n_img - 1)) * S.pix;
     const float y = ((float)i - 0.5f * (float)(S.n_img - 1)) * S.pix;
     float bx, by;
-    if (S.epl) shoot(S, Main<true>(lensp, &L.etab), lensp, nsub, x, y, bx, by);
-    else shoot(S, sie, lensp, nsub, x, y, bx, by);
-    const double wm = S.ray_w ? (double)S.ray_w[m] : 1.0;   // weighted grid: weighted moments
-    sx += wm * bx; sy += wm * by; sxx += wm * bx * bx; syy += wm * by * by;
+    shoot(S, ML, lensp, nsub, x, y, bx, by);
+    if (S.ray_w) {   // weighted grid: weighted moments
+      const double wm = (double)S.ray_w[m];
+      R.sx += wm * bx; R.sy += wm * by; R.sxx += wm * bx * bx; R.syy += wm * by * by;
+    } else {
+      R.sx += bx; R.sy += by; R.sxx += (double)bx * bx; R.syy += (double)by * by;
+    }
     const float v = (axis == 0 ? bx : by) + 0.0f;
     zb[m] = v;
     if (isfinite(v)) {
-      vmin = fminf(vmin, v);
-      vmax = fmaxf(vmax, v);
+      R.vmin = fminf(R.vmin, v);
+      R.vmax = fmaxf(R.vmax, v);
     }
     const unsigned u = ord_key(v);
-    umin = min(umin, u);
-    umax = max(umax, u);
+    R.umin = min(R.umin, u);
+    R.umax = max(R.umax, u);
     if (S.uniform) {
       const unsigned long long kx = sel_key(bx, m), ky = sel_key(by, m);
-      ukey[0] = min(ukey[0], kx); ukey[1] = max(ukey[1], kx);
-      ukey[2] = min(ukey[2], ky); ukey[3] = max(ukey[3], ky);
+      R.kx0 = min(R.kx0, kx); R.kx1 = max(R.kx1, kx);
+      R.ky0 = min(R.ky0, ky); R.ky1 = max(R.ky1, ky);
     }
   }
+}
+
+__device__ __forceinline__ void prep_select(const SysDev& S, int b, int axis, unsigned char* smem) {
+  SelLds& L = *reinterpret_cast<SelLds*>(smem);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  const int M = obs_M(S);
+  const float* lensp = S.lens + (size_t)b * S.n_lens;
+  const int nsub = n_sub_of(S, b);
+  if (S.epl && tid == 0) epl_table(make_epl(lensp), L.etab);
+  float* zb = S.zbuf + ((size_t)b * 2 + axis) * M;
+  uint32_t st = 0;
+  if (M < (S.uniform ? 2 : K + 1)) st |= RTU_ST_MASK_SMALL;
+  if (tid == 0) L.stat = 0;
+  if (tid < 2 * K) { L.tval[tid] = 0.f; L.tidx[tid] = 0; }
+  __syncthreads();   // the EPL tables
+
+  MaskedRays R;
+  if (S.epl) masked_rays(S, Main<true>(lensp, &L.etab), lensp, nsub, axis, M, zb, R);
+  else masked_rays(S, Main<false>(lensp, nullptr), lensp, nsub, axis, M, zb, R);
+  double sx = R.sx, sy = R.sy, sxx = R.sxx, syy = R.syy;
+  float vmin = R.vmin, vmax = R.vmax;
+  unsigned umin = R.umin, umax = R.umax;
   {
     double v4[4] = {sx, sy, sxx, syy};
     block_sum<4>(v4, L.red);
@@ -687,7 +704,7 @@ __device__ void prep_select(const SysDev& S, int b, int axis, unsigned char* sme
     __syncthreads();
   }
   if (S.uniform) {
-    prep_uniform(S, b, axis, L, ukey, M, st);
+    prep_uniform(S, b, axis, L, R.kx0, R.kx1, R.ky0, R.ky1, M, st);
     return;
   }
   const double Md = S.ray_w ? (S.wsum > 0.0 ? S.wsum : 1.0) : (double)(M > 0 ? M : 1);

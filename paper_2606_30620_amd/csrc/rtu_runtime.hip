@@ -55,6 +55,7 @@ struct rtu_fit_s {
   FitDev F;
   char* pool = nullptr;
   int max_steps = 0, steps = 0;
+  bool drawn = false;             // the next step's samples are drawn (by the last Adam update)
   int n_sub = 0;
   // the fit runs the shared-launch kernels of the serving fleet on a one-fit
   // table, so a fit alone and a fit in a fleet execute the same code
@@ -271,7 +272,7 @@ size_t carve_fit(FitDev& F, int S, int max_steps, char* base) {
   F.status = cv.take<uint32_t>(S); F.n_sub = cv.take<int>(S);
   F.trace = cv.take<double>(max_steps);
   F.status_acc = cv.take<uint32_t>(1);
-  F.rho_part = cv.take<double>(((size_t)F.dim + 255) / 256);
+  F.rho_part = cv.take<double>(2 * (((size_t)F.dim + ADAM_P - 1) / ADAM_P));
   return cv.off + 256;
 }
 
@@ -788,10 +789,12 @@ int rtu_fit_step(rtu_fit f, int32_t n_steps, const float* eps, void* stream) {
     const float* ek = eps ? eps + (size_t)k * F.S * F.dim : nullptr;
     prof_call_begin(p);
     for (int st : order) {
+      if (st == RTU_STAGE_SAMPLE && f->drawn && !ek) continue;
       prof_stage(p, st, false, s);
       if (launch_fleet_stage(f->L, st, step, ek, s) != hipSuccess) return RTU_EHIP;
       prof_stage(p, st, true, s);
     }
+    f->drawn = ek == nullptr;      // Philox draws: the Adam update drew the next step's samples
     f->steps++;
   }
   return RTU_OK;
@@ -836,6 +839,7 @@ int rtu_fit_set_state(rtu_fit f, const float* state, int32_t steps) {
     if (hipMemcpy(dst[k], state + (size_t)k * F.dim, (size_t)F.dim * 4, hipMemcpyHostToDevice) != hipSuccess)
       return RTU_EHIP;
   f->steps = steps;
+  f->drawn = false;
   return RTU_OK;
 }
 
