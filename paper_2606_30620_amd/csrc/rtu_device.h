@@ -56,18 +56,7 @@ __device__ __forceinline__ SoftplusTerms softplus_terms(float x) {
 // e = 0, and its derivative terms cancel to O(e) in FP32 near it.
 constexpr float E_ROUND = 0.02f;
 
-struct Sie {
-  float the, x0, y0, g1, g2;
-  float c, s;        // cos, sin of the position angle phi = atan2(e2, e1)/2
-  float q, f, P;     // axis ratio, f = sqrt(1-q^2), P = theta_E sqrt(q)
-  float q2;          // q^2
-  float invf;        // 1/f
-  float e1, e2, e;
-  bool round;        // e < E_ROUND: the angle-free gradient
-  float cpe, spe;    // c/(1+e), s/(1+e)
-  float cq, sq;      // c q, s q
-  float im2f;        // 1/(1+e)^2
-};
+// (struct Sie: rtu_internal.h, where the per-sample copies live)
 
 __device__ __forceinline__ Sie make_sie(const float* L) {
   Sie o;
@@ -85,6 +74,8 @@ __device__ __forceinline__ Sie make_sie(const float* L) {
   o.cpe = o.c * ie; o.spe = o.s * ie;
   o.cq = o.c * o.q; o.sq = o.s * o.q;
   o.im2f = ie * ie;
+  o.jb = fabsf(o.the) / sqrtf(o.q);
+  o.gam = sqrtf(o.g1 * o.g1 + o.g2 * o.g2);
   return o;
 }
 

@@ -51,9 +51,29 @@ struct KnotTab {
   float xs[2][32];      // knots, then +inf (branch-free search)
   float X[2][K], Sl[2][K], ih[2][K], dp[2][K];
   float du[K];          // u_{l+1} - u_l (0 for l = K-1)
+  float zr[2][2];       // per axis: the z below which T < -2.25 and above which
+                        // T > n + 1.25 (the affine end pieces; -inf / +inf if
+                        // their slope is not positive)
   float pad[2];
 };
 static_assert(sizeof(KnotTab) % 16 == 0, "KnotTab is copied as float4");
+
+// Per-sample constants of the singular isothermal ellipsoid (eq. A1 at slope
+// 2) and the external shear, made once per sample by the selection workgroup
+// of axis 0 and read by the ray kernels.
+struct Sie {
+  float the, x0, y0, g1, g2;
+  float c, s;        // cos, sin of the position angle phi = atan2(e2, e1)/2
+  float q, f, P;     // axis ratio, f = sqrt(1-q^2), P = theta_E sqrt(q)
+  float q2;          // q^2
+  float invf;        // 1/f
+  float e1, e2, e;
+  bool round;        // e < E_ROUND: the angle-free gradient
+  float cpe, spe;    // c/(1+e), s/(1+e)
+  float cq, sq;      // c q, s q
+  float im2f;        // 1/(1+e)^2
+  float jb, gam;     // |theta_E| / sqrt(q); shear modulus gamma
+};
 
 // Everything a kernel needs about one lens system and the samples of a call.
 // Sample b of a per-sample array starts at base + b * (its per-sample size).
@@ -111,6 +131,7 @@ struct SysDev {
   float* src;                 // [B][n^2] source brightness s
   float* srcp;                // [B][(n+2)^2] s with a one-cell zero border (corner reads need no bounds checks)
   KnotTab* ktab;              // [B] spline tables for the ray kernels
+  Sie* sie;                   // [B] SIE + shear constants for the ray kernels
   float* fld;                 // [B][n^2] GP field f
   float2* F;                  // [B][n^2] DFT of the latent
   float2* tmp;                // [B][n^2] FFT scratch

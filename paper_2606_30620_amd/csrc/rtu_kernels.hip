@@ -61,9 +61,18 @@ template <bool EPL> struct Main;
 template <> struct Main<false> {
   Sie L;
   __device__ __forceinline__ Main(const float* lensp, const EplTab*) : L(make_sie(lensp)) {}
+  __device__ __forceinline__ explicit Main(const Sie& c) : L(c) {}
   __device__ __forceinline__ void alpha(float x, float y, float& ax, float& ay) const {
     sie_shear_alpha(L, x, y, ax, ay);
   }
+  // A bound on the spectral norm of d alpha/d theta at distance >= r from the
+  // centre: the SIE potential is homogeneous of degree one, so its Hessian
+  // has the eigenvalues 0 and 2 kappa = theta_E / rho <= theta_E / (sqrt(q) r)
+  // (rho^2 = q x'^2 + y'^2 / q >= q r^2 for q <= 1); the shear adds gamma.
+  // Infinite or NaN where no bound holds (r = 0, q <= 0).
+  __device__ __forceinline__ float jac_bound(float r) const { return L.jb * rcp(r) + L.gam; }
+  __device__ __forceinline__ float cx() const { return L.x0; }
+  __device__ __forceinline__ float cy() const { return L.y0; }
 };
 template <> struct Main<true> {
   Epl L;
@@ -72,7 +81,25 @@ template <> struct Main<true> {
   __device__ __forceinline__ void alpha(float x, float y, float& ax, float& ay) const {
     epl_shear_alpha(L, *T, x, y, ax, ay);
   }
+  // no bound is used for the power law: its rays are never skipped
+  __device__ __forceinline__ float jac_bound(float) const { return INFINITY; }
+  __device__ __forceinline__ float cx() const { return L.x0; }
+  __device__ __forceinline__ float cy() const { return L.y0; }
 };
+
+// The main deflector of sample b in a ray kernel: the SIE from the constants
+// its selection workgroup stored, the power law from the lens vector and the
+// series tables in LDS.
+template <bool EPL>
+__device__ __forceinline__ Main<EPL> main_of(const SysDev& S, int b, const float* lensp, const EplTab* t);
+template <>
+__device__ __forceinline__ Main<false> main_of<false>(const SysDev& S, int b, const float*, const EplTab*) {
+  return Main<false>(S.sie[b]);
+}
+template <>
+__device__ __forceinline__ Main<true> main_of<true>(const SysDev&, int, const float* lensp, const EplTab* t) {
+  return Main<true>(lensp, t);
+}
 
 // beta = theta - alpha(theta) for the main deflector + shear + subhaloes
 template <class MAIN>
@@ -517,6 +544,17 @@ __device__ __forceinline__ void select_weighted(const SysDev& S, SelLds& L, cons
   __syncthreads();
 }
 
+// On an affine end piece T = c.x + c.y (z - p.x) p.y: the z at which T
+// reaches -2.25 (low end) or n + 1.25 (high end), moved to the piece's own
+// side of p.x; -inf / +inf if the slope is not positive.  Every z below (above)
+// it has T below (above) that level.
+__device__ __forceinline__ float grid_reach(float4 c, float2 p, bool hi, float n) {
+  const float sl = c.y * p.y, Tl = hi ? n + 1.25f : -2.25f;
+  if (!(sl > 0.f)) return hi ? INFINITY : -INFINITY;
+  const float z = p.x + (Tl - c.x) / sl;
+  return hi ? fmaxf(z, p.x) : fminf(z, p.x);
+}
+
 __device__ __forceinline__ void knot_table(const SysDev& S, int b, int ax, const float* X, const float* Sl,
                                            const float* dp) {
   KnotTab& T = S.ktab[b];
@@ -546,6 +584,11 @@ __device__ __forceinline__ void knot_table(const SysDev& S, int b, int ax, const
                                 n * (hs0 + hs1 - 2.f * du));
     }
   }
+  if (tid == 0 || tid == K) {
+    const float4 c = T.cq[ax][tid];
+    const float2 p = T.ct[ax][tid];
+    T.zr[ax][tid == K] = grid_reach(c, p, tid == K, n);
+  }
   if (ax == 0 && tid < 2) T.pad[tid] = 0.f;
 }
 
@@ -565,6 +608,7 @@ __device__ __forceinline__ void knot_table_uniform(const SysDev& S, int b, int a
     T.kr[ax][tid] = tid == 0 ? make_float2(-INFINITY, INFINITY) : make_float2(INFINITY, INFINITY);
     T.ct[ax][tid] = make_float2(lo, 1.f / side);
     T.cq[ax][tid] = make_float4(-0.5f, (float)S.n_src, 0.f, 0.f);
+    if (tid < 2) T.zr[ax][tid] = grid_reach(T.cq[ax][tid], T.ct[ax][tid], tid == 1, (float)S.n_src);
   }
   if (ax == 0 && tid < 2) T.pad[tid] = 0.f;
 }
@@ -672,6 +716,7 @@ __device__ __forceinline__ void prep_select(const SysDev& S, int b, int axis, un
   const float* lensp = S.lens + (size_t)b * S.n_lens;
   const int nsub = n_sub_of(S, b);
   if (S.epl && tid == 0) epl_table(make_epl(lensp), L.etab);
+  if (!S.epl && axis == 0 && tid == 64) S.sie[b] = make_sie(lensp);   // for the ray kernels
   float* zb = S.zbuf + ((size_t)b * 2 + axis) * M;
   uint32_t st = 0;
   if (M < (S.uniform ? 2 : K + 1)) st |= RTU_ST_MASK_SMALL;
@@ -1012,6 +1057,49 @@ __device__ __forceinline__ void bil_corners(const float* g, int n, const Bil& B,
 // sub-rays contribute nothing to the gradient but lens light (the one-cell
 // margin covers the adjoint's own rounding of the same rays); the range sizes
 // the adjoint's LDS window when the source grid does not fit in LDS.
+// Whether every sub-ray of pixel (i, j) lands off the source grid.  Along a
+// segment that keeps a distance >= r from every deflector's centre, beta =
+// theta - alpha(theta) moves by at most (1 + ||d alpha/d theta||) times the
+// segment's length.  The main deflector bounds its part (jac_bound); a
+// subhalo, axisymmetric with a convergence that does not increase outwards,
+// has the Hessian eigenvalues kappa_bar and 2 kappa - kappa_bar, both at most
+// kappa_bar(r) = |alpha(r)| / r in size, and kappa_bar does not increase with r.
+// The sub-rays lie in the pixel square, so all of them land within R = (half
+// diagonal) (1 + bound) of the pixel centre's beta.  If that disc lies beyond
+// T = -2.25 or T = n + 1.25 on one axis (KnotTab::zr: a quarter cell past the
+// per-pixel range test below), every sub-ray falls outside the zero-bordered grid and
+// fails that test: the sub-ray loop would add nothing and record nothing.
+// (1.001 R + 1e-5 and the quarter cell absorb the FP32 rounding of both
+// sides.)  Any NaN leaves the pixel to the loop.
+template <bool EPL>
+__device__ __forceinline__ bool pixel_off_grid(const SysDev& S, const RayLdsHead& H, const Main<EPL>& L, int nsub,
+                                               int i, int j) {
+  if (EPL) return false;
+  const float h = 0.5f * S.pix;
+  const float xc = ((float)j + 0.5f - 0.5f * (float)S.n_img) * S.pix;
+  const float yc = ((float)i + 0.5f - 0.5f * (float)S.n_img) * S.pix;
+  auto dist = [&](float cx, float cy) {
+    const float dx = fmaxf(fabsf(xc - cx) - h, 0.f), dy = fmaxf(fabsf(yc - cy) - h, 0.f);
+    return fsqrt(dx * dx + dy * dy);
+  };
+  const float r = dist(L.cx(), L.cy());
+  float bound = r > 0.f ? 1.f + L.jac_bound(r) : INFINITY;
+  for (int q = 0; q < nsub; ++q) {
+    const Nfw& N = H.nfw[q];
+    // kappa_bar taken a little inside, at 0.99 rs (the FP32 offset from the
+    // centre then stays below rs), times 1.01
+    const float rs = dist(N.xs, N.ys);
+    if (!(rs > 1e-3f)) return false;
+    float ax = 0.f, ay = 0.f;
+    nfw_alpha(N, S.tau, N.xs + 0.99f * rs, N.ys, ax, ay);
+    bound += 1.0203f * fabsf(ax) * rcp(rs);
+  }
+  const float R = fmaf(0.70710678f * S.pix * bound, 1.001f, 1e-5f);
+  float bx, by;
+  shoot(S, L, H.nfw, nsub, xc, yc, bx, by);
+  return bx + R < H.zr[0][0] || bx - R > H.zr[0][1] || by + R < H.zr[1][0] || by - R > H.zr[1][1];
+}
+
 template <bool EPL>
 __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* smem) {
   RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
@@ -1025,7 +1113,7 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
   if (in) {
     const float* lensp = S.lens + (size_t)b * S.n_lens;
     const int nsub = n_sub_of(S, b);
-    const Main<EPL> L(lensp, &H.epl);
+    const Main<EPL> L = main_of<EPL>(S, b, lensp, &H.epl);
     const int n = S.n_src;
     const float* gsrc = S.srcp + (size_t)b * (n + 2) * (n + 2);
     float acc = 0.f;
@@ -1033,7 +1121,8 @@ __device__ void rays_fwd_body(const SysDev& S, int b, int tile, unsigned char* s
     float x0, y0, dxs;
     subray_origin(S, i, j, x0, y0, dxs);
     float tx0 = INFINITY, tx1 = -INFINITY, ty0 = INFINITY, ty1 = -INFINITY;   // NaN ignored
-    for (int a = 0; a < S.ss; ++a) {
+    const int nss = pixel_off_grid<EPL>(S, H, L, nsub, i, j) ? 0 : S.ss;
+    for (int a = 0; a < nss; ++a) {
       const float y = fmaf((float)a, dxs, y0);
       for (int cc = 0; cc < S.ss; ++cc) {
         const int c = (a & 1) ? S.ss - 1 - cc : cc;   // serpentine: neighbouring sub-rays in turn
@@ -1145,7 +1234,7 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
   __syncthreads();
   const float* lensp = S.lens + (size_t)b * S.n_lens;
   const int nsub = n_sub_of(S, b);
-  const Main<EPL> M(lensp, &H.epl);
+  const Main<EPL> M = main_of<EPL>(S, b, lensp, &H.epl);
   const float* gsrc = S.srcp + (size_t)b * np * np;
   double* gsb = S.sbar + (size_t)b * n * n;
   SieAcc acc;                         // SIE: raw accumulators (sie_grad_one)

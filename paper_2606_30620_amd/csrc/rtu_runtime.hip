@@ -143,6 +143,7 @@ size_t carve_workspace(SysDev& h, int B, char* base) {
   h.tmp = c.take<float2>(B * n2);
   h.knots = c.take<float>((size_t)B * 4 * K);
   h.ktab = c.take<KnotTab>((size_t)B);
+  h.sie = c.take<Sie>((size_t)B);
   h.kdbg = c.take<float>((size_t)B * 4 * K);
   h.sel = c.take<int>((size_t)B * 4 * K);
   h.stdv = c.take<double>((size_t)B * 4);

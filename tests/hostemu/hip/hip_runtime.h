@@ -154,6 +154,7 @@ inline float __builtin_amdgcn_exp2f(float x) { return exp2f(x); }
 inline float __expf(float x) { return expf(x); }
 inline float __logf(float x) { return logf(x); }
 inline float __cosf(float x) { return cosf(x); }
+inline float __sinf(float x) { return sinf(x); }
 inline unsigned __umulhi(unsigned a, unsigned b) { return (unsigned)(((uint64_t)a * b) >> 32); }
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
 inline int __clz(int v) { return v ? __builtin_clz((unsigned)v) : 32; }
