@@ -1087,19 +1087,21 @@ __device__ __forceinline__ void batched_copy(int tot, LD ld, ST st) {
 // with sign1, handed to `mid(row, col, value)` (which may rescale it), then
 // transformed with sign2 if `twice`, and written through `st(row, col, value)`.
 // Lines are processed in chunks that fit the cap float2 slots of the LDS
-// buffer, which holds 128 more slots after them for the twiddle table.  The
-// global loads and stores go U per thread at a time.
+// buffer, which holds 128 more slots after them for the twiddle table; with
+// lend > 0 only the lines [lbeg, lend) are.  The global loads and stores go U
+// per thread at a time.
 template <int U = 8, class LD, class MID, class ST>
 __device__ __forceinline__ void fft_pass(float2* lds, int cap, int n, int logn, bool cols, float sign1, bool twice, float sign2,
-                         LD ld, MID mid, ST st) {
+                         LD ld, MID mid, ST st, int lbeg = 0, int lend = 0) {
   float2* tw = lds + cap;
   for (int k = threadIdx.x; k < 128; k += blockDim.x) tw[k] = c_tw[k];
   const int ls = n + 1;
   const int nt = blockDim.x;
+  const int le = lend > 0 ? lend : n;   // lines [lbeg, le) only
   int chunk = cap / ls;
   if (chunk > n) chunk = n;
-  for (int l0 = 0; l0 < n; l0 += chunk) {
-    const int nl = min(chunk, n - l0);
+  for (int l0 = lbeg; l0 < le; l0 += chunk) {
+    const int nl = min(chunk, le - l0);
     const int tot = nl * n;
     // element idx of the chunk: its line l, its index i along the line, and
     // its (row, col) in the array

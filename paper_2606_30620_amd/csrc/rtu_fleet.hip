@@ -115,14 +115,16 @@ namespace rtu {
 
 int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDev>& fit, FleetLaunch& L) {
   const size_t n = sys.size();
-  std::vector<Task> prep, psf, post, param, samp, fits, fwd[2], adj[2][2];
-  size_t lds_f = 0, lds_a = 0, lds_p = 0, lds_pr = 0, lds_po = 0;
+  std::vector<Task> prep, psf, post, param, samp, fits, gp, fwd[2], adj[2][2];
+  size_t lds_f = 0, lds_a = 0, lds_p = 0, lds_pr = 0, lds_po = 0, lds_g = 0;
   for (size_t i = 0; i < n; ++i) {
     const SysDev& h = sys[i];
     const FitDev& F = fit[i];
     const int si = (int)i, S = h.batch;
     for (int b = 0; b < S; ++b) {
       for (int r = 0; r < 3; ++r) prep.push_back(make_int4(si, b, r, 0));
+      if (gp_split(h.n_src))
+        for (int g = 0; g < h.n_src / GP_LINES; ++g) gp.push_back(make_int4(si, b, g, 0));
       for (int t = 0; t < h.ray_tiles; ++t) {
         fwd[h.epl ? 1 : 0].push_back(make_int4(si, b, t, 0));
         adj[h.lds_adj ? 0 : 1][h.epl ? 1 : 0].push_back(make_int4(si, b, t, 0));
@@ -141,12 +143,13 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
     lds_p = std::max(lds_p, psf_lds_bytes(h.psf_k));
     lds_pr = std::max(lds_pr, prep_lds_bytes(h.n_src));
     lds_po = std::max(lds_po, post_lds_bytes(h.n_src, h.n_lens));
+    if (gp_split(h.n_src)) lds_g = std::max(lds_g, gp_lds_bytes(h.n_src));
   }
   std::vector<Task> all;
-  size_t off[12];
-  std::vector<Task>* lists[12] = {&prep, &psf, &post, &param, &samp, &fits, &fwd[0], &fwd[1],
-                                  &adj[0][0], &adj[0][1], &adj[1][0], &adj[1][1]};
-  for (int k = 0; k < 12; ++k) {
+  size_t off[13];
+  std::vector<Task>* lists[13] = {&prep, &psf, &post, &param, &samp, &fits, &fwd[0], &fwd[1],
+                                  &adj[0][0], &adj[0][1], &adj[1][0], &adj[1][1], &gp};
+  for (int k = 0; k < 13; ++k) {
     off[k] = all.size();
     all.insert(all.end(), lists[k]->begin(), lists[k]->end());
   }
@@ -178,6 +181,8 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
   L.t_param = d_tasks + off[3]; L.n_param = (int)param.size();
   L.t_sample = d_tasks + off[4]; L.n_sample = (int)samp.size();
   L.t_fit = d_tasks + off[5];   L.n_fit = (int)fits.size();
+  L.t_gp = d_tasks + off[12];   L.n_gp = (int)gp.size();
+  L.lds_gp = lds_g;
   for (int k = 0; k < 2; ++k) {
     L.t_fwd[k] = d_tasks + off[6 + k]; L.n_fwd[k] = (int)fwd[k].size();
     for (int e = 0; e < 2; ++e) {

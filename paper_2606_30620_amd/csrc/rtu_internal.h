@@ -21,8 +21,14 @@ constexpr int PSF_THREADS = 256;
 constexpr int ST_WORDS = 8;
 constexpr int PREP_THREADS = 512;       // quantile selection and FFT workgroups
 constexpr int GRID_LDS_MAX = 64;        // n_src <= this: the ray adjoint keeps d loss / d s in LDS
-constexpr int FFT_LDS_MAX = 128 * 129;  // FFT line buffer (float2): 128 lines of 128 + 1 pad = 129 KB
 constexpr int KBAR = 4 * K;
+// GP transforms of source grids of at least GP_SPLIT_N per side run as three
+// line passes (rows, columns, rows) through the workspace, each pass a launch
+// of GP_LINES lines per workgroup
+constexpr int GP_LINES = 16;
+constexpr int GP_SPLIT_N = 256;
+constexpr int GP_THREADS = 256;
+__host__ __device__ constexpr bool gp_split(int n) { return n >= GP_SPLIT_N; }
 constexpr int FIT_THREADS = 256;        // fit kernels: sampling blocks of 256 parameters,
 constexpr int ADAM_P = 64;              // Adam blocks of 64 parameters x 4 sample groups
 constexpr int ADAM_G = FIT_THREADS / ADAM_P;
@@ -135,6 +141,7 @@ struct SysDev {
   float* fld;                 // [B][n^2] GP field f
   float2* F;                  // [B][n^2] DFT of the latent
   float2* tmp;                // [B][n^2] FFT scratch
+  double* gpp;                // [B][n / GP_LINES][4] split GP adjoint: spectrum-gradient partials per workgroup
   float* zbuf;                // [B][2][M] masked-ray beta per axis
   float* knots;               // [B][2][2][K] per axis: X_k, S_k in beta units
   float* kdbg;                // [B][2][2][K] per axis: X_k, S_k standardised
@@ -221,6 +228,7 @@ int adj_window_cap(const SysDev& h);
 bool adj_lds_grid(const SysDev& h);
 size_t psf_lds_bytes(int KP);
 int fft_lds_cap(int n_src);          // float2 slots of the FFT line buffer for this grid
+size_t gp_lds_bytes(int n_src);      // dynamic LDS of a split GP line pass
 size_t prep_lds_bytes(int n_src);
 size_t post_lds_bytes(int n_src, int n_lens);
 
@@ -228,8 +236,8 @@ size_t post_lds_bytes(int n_src, int n_lens);
 struct FleetLaunch {
   const SysDev* sys;          // device [n_slots]
   const FitDev* fit;          // device [n_slots]
-  const Task *t_prep, *t_psf, *t_post, *t_param, *t_sample, *t_fit;
-  int n_prep, n_psf, n_post, n_param, n_sample, n_fit;
+  const Task *t_prep, *t_psf, *t_post, *t_param, *t_sample, *t_fit, *t_gp;
+  int n_prep, n_psf, n_post, n_param, n_sample, n_fit, n_gp;   // t_gp: split GP line groups
   // forward ray tiles by main deflector: [0] SIE, [1] EPL
   const Task* t_fwd[2];
   int n_fwd[2];
@@ -237,7 +245,7 @@ struct FleetLaunch {
   // memory), then by main deflector
   const Task* t_adj[2][2];
   int n_adj[2][2];
-  size_t lds_rays_fwd, lds_rays_adj, lds_psf, lds_prep, lds_post;
+  size_t lds_rays_fwd, lds_rays_adj, lds_psf, lds_prep, lds_post, lds_gp;
 };
 // One stage (RTU_STAGE_*) of a shared launch; eps (device [S][dim] per fit,
 // only for a single-fit table) replaces the Philox draws when not null.

@@ -843,15 +843,24 @@ __device__ __forceinline__ void prep_select(const SysDev& S, int b, int axis, un
   }
 }
 
+// The field value f at point q of sample b and the source s = (s0
+// softplus(f/s0))^alpha, s0 = 0.01 (eqs. 1-4), also into the zero-bordered copy.
+__device__ __forceinline__ void gp_source(const SysDev& S, int b, int q, float f, float alpha) {
+  const int n = S.n_src, logn = S.log2_src;
+  const size_t n2 = (size_t)n * n;
+  S.fld[(size_t)b * n2 + q] = f;
+  const float x = f * 100.f;   // f / s0
+  const float s = __expf(alpha * (-4.605170186f + log_softplus_f(x)));
+  S.src[(size_t)b * n2 + q] = s;
+  S.srcp[(size_t)b * (n + 2) * (n + 2) + ((q >> logn) + 1) * (n + 2) + (q & (n - 1)) + 1] = s;
+}
+
 // GP source (eqs. 1-4): F = DFT(w); f = Re IDFT(sqrt(P) F)/n^2; s = (s0 softplus(f/s0))^alpha
 __device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* smem, int cap) {
   float2* lds = reinterpret_cast<float2*>(smem);
   const int n = S.n_src, logn = S.log2_src, n2 = n * n;
   const float* w = S.latent + (size_t)b * n2;
   float2* F = S.F + (size_t)b * n2;
-  float2* T = S.tmp + (size_t)b * n2;
-  float* fo = S.fld + (size_t)b * n2;
-  float* so = S.src + (size_t)b * n2;
   float* sp = S.srcp + (size_t)b * (n + 2) * (n + 2);
   const float* ps = S.ps + (size_t)b * 4;
   // zero border of the padded copy of s
@@ -883,19 +892,15 @@ __device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* s
     S.st[b * ST_WORDS + 2] = st;
     S.status[b] = 0u;             // the post roles OR their words into it
   }
+  if (gp_split(n)) return;   // the transform: three line-pass launches (gp_pass)
   const Matern mt = make_matern(ps);
   const float alpha = ps[3];
   const float inv_n2 = 1.f / (float)n2;
-  auto positivity = [&](int q, float f) {
-    fo[q] = f;
-    const float x = f * 100.f;   // f / s0, s0 = 0.01
-    const float s = __expf(alpha * (-4.605170186f + log_softplus_f(x)));
-    so[q] = s;
-    sp[((q >> logn) + 1) * (n + 2) + (q & (n - 1)) + 1] = s;
-  };
-  if (n <= 128) {
-    // the whole grid in LDS at row stride n + 1: rows, then columns, to split
-    // order; F kept in that layout; times sqrt(P); columns, then rows, back
+  auto positivity = [&](int q, float f) { gp_source(S, b, q, f, alpha); };
+  {
+    // grids below the split size: the whole grid in LDS at row stride n + 1:
+    // rows, then columns, to split order; F kept in that layout; times
+    // sqrt(P); columns, then rows, back
     float2* tw = lds + cap;
     for (int k = threadIdx.x; k < 128; k += blockDim.x) tw[k] = c_tw[k];
     const int ls = n + 1;
@@ -923,29 +928,7 @@ __device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* s
     fft_grid_dir(lds, tw, n, logn, false, 1.f, false);
     for (int q = threadIdx.x; q < n2; q += blockDim.x)
       positivity(q, lds[(q >> logn) * ls + (q & (n - 1))].x * inv_n2);
-    return;
   }
-  // larger grids: lines in chunks through the workspace T
-  // rows: forward transform of the real latent
-  fft_pass(lds, cap, n, logn, false, -1.f, false, 0.f,
-           [&](int r, int c) { return make_float2(w[r * n + c], 0.f); },
-           [&](int, int, float2 v) { return v; },
-           [&](int r, int c, float2 v) { T[r * n + c] = v; });
-  // columns: forward, keep F, multiply by sqrt(P), inverse
-  fft_pass(lds, cap, n, logn, true, -1.f, true, 1.f,
-           [&](int r, int c) { return T[r * n + c]; },
-           [&](int r, int c, float2 v) {
-             F[r * n + c] = v;
-             const float kx = fft_freq(c, n), ky = fft_freq(r, n);
-             const float sp = matern_sqrtP(mt, kx * kx + ky * ky);
-             return make_float2(v.x * sp, v.y * sp);
-           },
-           [&](int r, int c, float2 v) { T[r * n + c] = v; });
-  // rows: inverse, real part / n^2, positivity transform
-  fft_pass(lds, cap, n, logn, false, 1.f, false, 0.f,
-           [&](int r, int c) { return T[r * n + c]; },
-           [&](int, int, float2 v) { return v; },
-           [&](int r, int c, float2 v) { positivity(r * n + c, v.x * inv_n2); });
 }
 
 // Dynamic LDS of the prep kernels: the larger of the selection layout and the
@@ -1620,6 +1603,137 @@ __global__ void __launch_bounds__(PSF_THREADS) k_psf(SysDev S, int adjoint) {
 }
 
 // ====================================================================== k_post
+// The GP adjoint's pointwise steps (eqs. 1-4), shared by the one-workgroup
+// transform and the split line passes; the spectrum-parameter sums go into
+// pacc (sigma, n, zeta, alpha).
+struct GpAdj {
+  Matern mt;
+  float alpha, inv_n2, inv_sig, inv_zeta, dn_c;
+  int n;
+  __device__ __forceinline__ GpAdj(const float* ps, int n_) : mt(make_matern(ps)), alpha(ps[3]), n(n_) {
+    inv_n2 = 1.f / (float)(n * n);
+    inv_sig = 1.f / ps[0];
+    inv_zeta = 1.f / mt.zeta;
+    dn_c = (mt.n + 1.f) / (2.f * mt.n);
+  }
+  // fbar = sbar ds/df, ds/df = alpha s sigmoid(x)/(s0 softplus(x)), x = f/s0
+  __device__ __forceinline__ float fbar(float sbq, float f, float s, double (&pacc)[4]) const {
+    const SoftplusTerms sp = softplus_terms(f * 100.f);
+    pacc[3] += (double)(sbq * s * (-4.605170186f + sp.lsp));
+    return sbq * alpha * s * sp.ratio * 100.f;
+  }
+  // the spectrum: Re(F conj(Fbar)) sqrt(P) / n^2 times d log sqrt(P) / d (sigma, n, zeta):
+  //   1/sigma,  ((n+1)/(2n)) k^2/(a+k^2) + log(a/(a+k^2))/2,  (a - n k^2)/(zeta (a+k^2));
+  // returns Fbar sqrt(P)
+  __device__ __forceinline__ float2 spectrum(int r, int c, float2 v, float2 f0, double (&pacc)[4]) const {
+    const float kx = fft_freq(c, n), ky = fft_freq(r, n);
+    const float k2 = kx * kx + ky * ky;
+    const float sq = matern_sqrtP(mt, k2);
+    const float re = (f0.x * v.x + f0.y * v.y) * inv_n2 * sq;
+    const float iapk = 1.f / (mt.a + k2);
+    pacc[0] += (double)(re * inv_sig);
+    pacc[1] += (double)(re * (dn_c * k2 * iapk + 0.5f * __logf(mt.a * iapk)));
+    pacc[2] += (double)(re * ((mt.a - mt.n * k2) * iapk * inv_zeta));
+    return make_float2(v.x * sq, v.y * sq);
+  }
+};
+
+// ====================================================================== split GP transforms
+// Grids of at least GP_SPLIT_N per side: the 2-D transforms of the GP source
+// (prep) and of its adjoint (post) as three line passes through the
+// workspace T, each a launch of GP_LINES lines per workgroup, so that a
+// sample's transform is spread over n / GP_LINES workgroups:
+//   prep:    rows: T = DFT_x(w); columns: F = DFT_y(T), T = IDFT_y(sqrt(P) F);
+//            rows: f = Re IDFT_x(T) / n^2, then the source;
+//   adjoint: rows: T = DFT_x(fbar); columns: Fbar = DFT_y(T) with the
+//            spectrum sums, T = IDFT_y(sqrt(P) Fbar); rows: d loss / d w =
+//            Re IDFT_x(T) / n^2 + w.
+// The adjoint's spectrum sums are kept per workgroup (gpp) and added in
+// workgroup order by the last pass's first workgroup.
+template <bool ADJ>
+__device__ void gp_pass(const SysDev& S, int b, int pass, int part, unsigned char* smem, double* red) {
+  float2* lds = reinterpret_cast<float2*>(smem);
+  const int n = S.n_src, logn = S.log2_src, n2 = n * n;
+  const int cap = GP_LINES * (n + 1), l0 = part * GP_LINES, l1 = l0 + GP_LINES;
+  const int G = n / GP_LINES;
+  float2* T = S.tmp + (size_t)b * n2;
+  const float* ps = S.ps + (size_t)b * 4;
+  const float* w = S.latent + (size_t)b * n2;
+  auto same = [](int, int, float2 v) { return v; };
+  auto to_T = [&](int r, int c, float2 v) { T[r * n + c] = v; };
+  auto from_T = [&](int r, int c) { return T[r * n + c]; };
+  if (!ADJ) {
+    const Matern mt = make_matern(ps);
+    const float alpha = ps[3], inv_n2 = 1.f / (float)n2;
+    float2* F = S.F + (size_t)b * n2;
+    if (pass == 0)
+      fft_pass(lds, cap, n, logn, false, -1.f, false, 0.f, [&](int r, int c) { return make_float2(w[r * n + c], 0.f); },
+               same, to_T, l0, l1);
+    else if (pass == 1)
+      fft_pass(lds, cap, n, logn, true, -1.f, true, 1.f, from_T,
+               [&](int r, int c, float2 v) {
+                 F[r * n + c] = v;
+                 const float kx = fft_freq(c, n), ky = fft_freq(r, n);
+                 const float sq = matern_sqrtP(mt, kx * kx + ky * ky);
+                 return make_float2(v.x * sq, v.y * sq);
+               },
+               to_T, l0, l1);
+    else
+      fft_pass(lds, cap, n, logn, false, 1.f, false, 0.f, from_T, same,
+               [&](int r, int c, float2 v) { gp_source(S, b, r * n + c, v.x * inv_n2, alpha); }, l0, l1);
+    return;
+  }
+  const GpAdj ga(ps, n);
+  double pacc[4] = {0.0, 0.0, 0.0, 0.0};
+  double* gp = S.gpp + (size_t)b * (n / GP_LINES + 1) * 4;
+  if (pass == 0) {
+    const double* sb = S.sbar + (size_t)b * n2;
+    const float* fo = S.fld + (size_t)b * n2;
+    const float* so = S.src + (size_t)b * n2;
+    fft_pass<2>(lds, cap, n, logn, false, -1.f, false, 0.f,
+                [&](int r, int c) {
+                  const int q = r * n + c;
+                  return make_float2(ga.fbar((float)sb[q], fo[q], so[q], pacc), 0.f);
+                },
+                same, to_T, l0, l1);
+    block_sum<4>(pacc, red);
+    if (threadIdx.x == 0) gp[part * 4 + 3] = pacc[3];
+  } else if (pass == 1) {
+    const float2* F = S.F + (size_t)b * n2;
+    fft_pass<2>(lds, cap, n, logn, true, -1.f, true, 1.f, from_T,
+                [&](int r, int c, float2 v) { return ga.spectrum(r, c, v, F[r * n + c], pacc); }, to_T, l0, l1);
+    block_sum<4>(pacc, red);
+    if (threadIdx.x < 3) gp[part * 4 + threadIdx.x] = pacc[threadIdx.x];
+  } else {
+    uint32_t bad = 0;
+    fft_pass<2>(lds, cap, n, logn, false, 1.f, false, 0.f, from_T, same,
+                [&](int r, int c, float2 v) {
+                  const int q = r * n + c;
+                  const float g = v.x * ga.inv_n2 + w[q];
+                  if (S.g_lat) S.g_lat[(size_t)b * n2 + q] = g;
+                  if (!isfinite(g)) bad = 1;
+                },
+                l0, l1);
+    if (bad) atomicOr(&S.status[b], RTU_ST_NONFINITE);
+    if (part == 0 && threadIdx.x < 4) {
+      double v = 0.0;
+      for (int g = 0; g < G; ++g) v += gp[g * 4 + threadIdx.x];
+      if (S.g_ps) S.g_ps[(size_t)b * 4 + threadIdx.x] = (float)v;
+      if (!isfinite(v)) atomicOr(&S.status[b], RTU_ST_NONFINITE);
+    }
+  }
+}
+
+template <bool ADJ>
+__global__ void __launch_bounds__(GP_THREADS) k_gp(SysDev S, int pass) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[4 * (GP_THREADS / 64)];
+  if (ADJ && !S.want_grad) return;
+  const int G = S.n_src / GP_LINES;
+  const int b = blockIdx.x / G;
+  gp_pass<ADJ>(S, b, pass, blockIdx.x - b * G, smem, red);
+}
+
 struct PostLds {
   double red[16 * 16];
   double part[PREP_THREADS];
@@ -1769,48 +1883,26 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
       if (!isfinite(v)) atomicOr(&P.stat, RTU_ST_NONFINITE);
     }
   }
-  // ---- role 1: the GP adjoint
-  if (role == 1) {
+  // ---- role 1: the GP adjoint (split grids: three line-pass launches, gp_pass)
+  if (role == 1 && !gp_split(n)) {
     const float* ps = S.ps + (size_t)b * 4;
-    const Matern mt = make_matern(ps);
-    const float alpha = ps[3];
+    const GpAdj ga(ps, n);
     const double* sb = S.sbar + (size_t)b * n2;
     const float* fo = S.fld + (size_t)b * n2;
     const float* so = S.src + (size_t)b * n2;
     const float2* F = S.F + (size_t)b * n2;
-    float2* T = S.tmp + (size_t)b * n2;
     const float* w = S.latent + (size_t)b * n2;
     float2* lds = reinterpret_cast<float2*>(fft_smem);
     double pacc[4] = {0.0, 0.0, 0.0, 0.0};   // sigma, n, zeta, alpha
-    const float inv_n2 = 1.f / (float)n2;
-    const float inv_sig = 1.f / ps[0], inv_zeta = 1.f / mt.zeta, dn_c = (mt.n + 1.f) / (2.f * mt.n);
-    // fbar = sbar ds/df, ds/df = alpha s sigmoid(x)/(s0 softplus(x)), x = f/s0
-    auto fbar_of = [&](float sbq, float f, float s) {
-      const SoftplusTerms sp = softplus_terms(f * 100.f);
-      pacc[3] += (double)(sbq * s * (-4.605170186f + sp.lsp));
-      return sbq * alpha * s * sp.ratio * 100.f;
-    };
-    // the spectrum: Re(F conj(Fbar)) sqrt(P) / n^2 times d log sqrt(P) / d (sigma, n, zeta):
-    //   1/sigma,  ((n+1)/(2n)) k^2/(a+k^2) + log(a/(a+k^2))/2,  (a - n k^2)/(zeta (a+k^2));
-    // returns Fbar sqrt(P)
-    auto spectrum = [&](int r, int c, float2 v, float2 f0) {
-      const float kx = fft_freq(c, n), ky = fft_freq(r, n);
-      const float k2 = kx * kx + ky * ky;
-      const float sq = matern_sqrtP(mt, k2);
-      const float re = (f0.x * v.x + f0.y * v.y) * inv_n2 * sq;
-      const float iapk = 1.f / (mt.a + k2);
-      pacc[0] += (double)(re * inv_sig);
-      pacc[1] += (double)(re * (dn_c * k2 * iapk + 0.5f * __logf(mt.a * iapk)));
-      pacc[2] += (double)(re * ((mt.a - mt.n * k2) * iapk * inv_zeta));
-      return make_float2(v.x * sq, v.y * sq);
-    };
+    auto fbar_of = [&](float sbq, float f, float s) { return ga.fbar(sbq, f, s, pacc); };
+    auto spectrum = [&](int r, int c, float2 v, float2 f0) { return ga.spectrum(r, c, v, f0, pacc); };
     uint32_t bad = 0;
     auto latent_grad = [&](int q, float v, float wq) {
-      const float g = v * inv_n2 + wq;
+      const float g = v * ga.inv_n2 + wq;
       if (S.g_lat) S.g_lat[(size_t)b * n2 + q] = g;
       if (!isfinite(g)) bad = 1;
     };
-    if (n <= 128) {
+    {
       // the whole grid in LDS (as in the prep transform; F in split layout)
       float2* tw = lds + cap;
       for (int k = tid; k < 128; k += blockDim.x) tw[k] = c_tw[k];
@@ -1870,24 +1962,6 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
                         latent_grad(q + 2, a[2].x, v.z);
                         latent_grad(q + 3, a[3].x, v.w);
                       });
-    } else {
-      // larger grids: lines in chunks through the workspace T
-      fft_pass<2>(lds, cap, n, logn, false, -1.f, false, 0.f,
-               [&](int r, int c) {
-                 const int q = r * n + c;
-                 return make_float2(fbar_of((float)sb[q], fo[q], so[q]), 0.f);
-               },
-               [&](int, int, float2 v) { return v; },
-               [&](int r, int c, float2 v) { T[r * n + c] = v; });
-      // columns: forward -> Fbar; spectrum gradient; times sqrt(P); inverse
-      fft_pass<2>(lds, cap, n, logn, true, -1.f, true, 1.f,
-               [&](int r, int c) { return T[r * n + c]; },
-               [&](int r, int c, float2 v) { return spectrum(r, c, v, F[r * n + c]); },
-               [&](int r, int c, float2 v) { T[r * n + c] = v; });
-      fft_pass<2>(lds, cap, n, logn, false, 1.f, false, 0.f,
-               [&](int r, int c) { return T[r * n + c]; },
-               [&](int, int, float2 v) { return v; },
-               [&](int r, int c, float2 v) { latent_grad(r * n + c, v.x, w[r * n + c]); });
     }
     if (bad) atomicOr(&P.stat, RTU_ST_NONFINITE);
     block_sum<4>(pacc, P.red);
@@ -2075,7 +2149,8 @@ hipError_t upload_constants() {
 // The FFT keeps min(n, cap / (n + 1)) lines of the grid in LDS at a time:
 // every line of a grid up to 128 per side, 64-line chunks beyond.
 // The buffer holds the lines plus the 128-entry twiddle table.
-int fft_lds_cap(int n_src) { return n_src <= 128 ? n_src * (n_src + 1) : FFT_LDS_MAX; }
+int fft_lds_cap(int n_src) { return gp_split(n_src) ? 0 : n_src * (n_src + 1); }
+size_t gp_lds_bytes(int n_src) { return (size_t)(GP_LINES * (n_src + 1) + 128) * sizeof(float2); }
 size_t prep_lds_bytes(int n_src) {
   const size_t f = (size_t)(fft_lds_cap(n_src) + 128) * sizeof(float2);
   return f > sizeof(SelLds) ? f : sizeof(SelLds);
@@ -2091,6 +2166,10 @@ size_t post_lds_bytes(int n_src, int n_lens) {
 hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
   hipLaunchKernelGGL(k_prep, dim3(batch, 3), dim3(PREP_THREADS), prep_lds_bytes(h.n_src), s, h,
                      fft_lds_cap(h.n_src));
+  if (gp_split(h.n_src))
+    for (int pass = 0; pass < 3; ++pass)
+      hipLaunchKernelGGL(k_gp<false>, dim3(batch * (h.n_src / GP_LINES)), dim3(GP_THREADS), gp_lds_bytes(h.n_src), s,
+                         h, pass);
   return hipGetLastError();
 }
 
@@ -2158,6 +2237,10 @@ hipError_t launch_psf(const SysDev& h, int batch, bool adjoint, hipStream_t s) {
 hipError_t launch_post(const SysDev& h, int batch, hipStream_t s) {
   hipLaunchKernelGGL(k_post, dim3(batch, h.want_grad ? 2 : 1), dim3(PREP_THREADS), post_lds_bytes(h.n_src, h.n_lens), s, h,
                      fft_lds_cap(h.n_src));
+  if (h.want_grad && gp_split(h.n_src))
+    for (int pass = 0; pass < 3; ++pass)
+      hipLaunchKernelGGL(k_gp<true>, dim3(batch * (h.n_src / GP_LINES)), dim3(GP_THREADS), gp_lds_bytes(h.n_src), s,
+                         h, pass);
   return hipGetLastError();
 }
 
@@ -2178,6 +2261,17 @@ __global__ void __launch_bounds__(PREP_THREADS) kf_prep(const SysDev* __restrict
   if (!sys_active(S, round)) return;
   if (t.z < 2) prep_select(S, t.y, t.z, smem);
   else prep_gp(S, t.y, smem, fft_cap);
+}
+
+template <bool ADJ>
+__global__ void __launch_bounds__(GP_THREADS) kf_gp(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
+                                                    int round, int pass) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[4 * (GP_THREADS / 64)];
+  const Task t = tasks[blockIdx.x];
+  const SysDev S = sys[t.x];
+  if (!sys_active(S, round) || (ADJ && !S.want_grad)) return;
+  gp_pass<ADJ>(S, t.y, pass, t.z, smem, red);
 }
 
 template <bool EPL>
@@ -2229,6 +2323,9 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
       if (L.n_prep)
         hipLaunchKernelGGL(kf_prep, dim3(L.n_prep), dim3(PREP_THREADS), L.lds_prep, s, L.sys, L.t_prep, round,
                            (int)(L.lds_prep / sizeof(float2)) - 128);
+      if (L.n_gp)
+        for (int pass = 0; pass < 3; ++pass)
+          hipLaunchKernelGGL(kf_gp<false>, dim3(L.n_gp), dim3(GP_THREADS), L.lds_gp, s, L.sys, L.t_gp, round, pass);
       break;
     case RTU_STAGE_RAYS_FWD:
       if (L.n_fwd[0])
@@ -2262,6 +2359,9 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
       if (L.n_post)
         hipLaunchKernelGGL(kf_post, dim3(L.n_post), dim3(PREP_THREADS), L.lds_post, s, L.sys, L.t_post, round,
                            (int)(L.lds_post / sizeof(float2)) - 128);
+      if (L.n_gp)
+        for (int pass = 0; pass < 3; ++pass)
+          hipLaunchKernelGGL(kf_gp<true>, dim3(L.n_gp), dim3(GP_THREADS), L.lds_gp, s, L.sys, L.t_gp, round, pass);
       break;
     default:
       return launch_fleet_fit_stage(L, stage, round, eps, s);

@@ -141,6 +141,7 @@ size_t carve_workspace(SysDev& h, int B, char* base) {
   h.fld = c.take<float>(B * n2);
   h.F = c.take<float2>(B * n2);
   h.tmp = c.take<float2>(B * n2);
+  h.gpp = c.take<double>((size_t)B * (h.n_src / GP_LINES + 1) * 4);
   h.knots = c.take<float>((size_t)B * 4 * K);
   h.ktab = c.take<KnotTab>((size_t)B);
   h.sie = c.take<Sie>((size_t)B);

@@ -157,6 +157,8 @@ inline float __cosf(float x) { return cosf(x); }
 inline float __sinf(float x) { return sinf(x); }
 inline unsigned __umulhi(unsigned a, unsigned b) { return (unsigned)(((uint64_t)a * b) >> 32); }
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
+inline int __popc(unsigned v) { return __builtin_popcount(v); }
+inline int __ffs(unsigned v) { return __builtin_ffs((int)v); }
 inline int __clz(int v) { return v ? __builtin_clz((unsigned)v) : 32; }
 inline float __int_as_float(int v) { float f; memcpy(&f, &v, 4); return f; }
 inline float __uint_as_float(unsigned v) { float f; memcpy(&f, &v, 4); return f; }
