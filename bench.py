@@ -74,7 +74,7 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-KERNEL_OF_STAGE = {"rays_adj": "kf_rays_adj<true>", "rays_fwd": "kf_rays_fwd", "psf_fwd": "kf_psf",
+KERNEL_OF_STAGE = {"rays_adj": "kf_rays_adj<true, false>", "rays_fwd": "kf_rays_fwd<false>", "psf_fwd": "kf_psf",
                    "psf_adj": "kf_psf", "prep": "kf_prep", "post": "kf_post", "sample": "kf_sample",
                    "adam": "kf_adam"}
 
