@@ -80,7 +80,7 @@ __device__ __forceinline__ float grad_at(const FitDev& F, int s, int i) {
 
 // Adam on (mu, rho) with the gradient of -ELBO:
 //   d/dmu_i  = mean_s g_si,   d/drho_i = mean_s g_si exp(rho_i) eps_si - 1
-// A workgroup takes ADAM_P parameters; its ADAM_G groups of threads each sum
+// A workgroup takes ADAM_P parameters; its ADAM_G (16) groups of threads each sum
 // every ADAM_G-th sample of a parameter, and group 0 adds the group sums in
 // group order (so that more workgroups share the memory latency of the
 // S gradient and draw loads) and leaves the new mu and exp(rho) in nmu,
@@ -166,9 +166,9 @@ __global__ void __launch_bounds__(FIT_THREADS) kf_sample(const FitDev* __restric
 // 0 of each fit also writes the ELBO of this step from the rho sums taken
 // when this step's samples were drawn, the losses and the status words, each
 // summed in a fixed order.
-__global__ void __launch_bounds__(FIT_THREADS) kf_adam(const FitDev* __restrict__ fits,
-                                                       const Task* __restrict__ tasks, int round, int draw) {
-  __shared__ float red[2 * FIT_THREADS];
+__global__ void __launch_bounds__(ADAM_THREADS) kf_adam(const FitDev* __restrict__ fits,
+                                                        const Task* __restrict__ tasks, int round, int draw) {
+  __shared__ float red[2 * ADAM_THREADS];
   __shared__ float nmu[ADAM_P], nsig[ADAM_P];
   const Task t = tasks[blockIdx.x];      // x fit, y block of ADAM_P parameters
   const FitDev& F = fits[t.x];
@@ -213,7 +213,7 @@ hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, co
                                       round, eps);
   } else if (stage == RTU_STAGE_ADAM) {
     if (L.n_param)
-      hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(FIT_THREADS), 0, s, L.fit, L.t_param, round,
+      hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(ADAM_THREADS), 0, s, L.fit, L.t_param, round,
                          eps ? 0 : 1);
   }
   return hipGetLastError();

@@ -30,8 +30,9 @@ constexpr int GP_SPLIT_N = 256;
 constexpr int GP_THREADS = 256;
 __host__ __device__ constexpr bool gp_split(int n) { return n >= GP_SPLIT_N; }
 constexpr int FIT_THREADS = 256;        // fit kernels: sampling blocks of 256 parameters,
-constexpr int ADAM_P = 64;              // Adam blocks of 64 parameters x 4 sample groups
-constexpr int ADAM_G = FIT_THREADS / ADAM_P;
+constexpr int ADAM_P = 64;              // Adam blocks of 64 parameters
+constexpr int ADAM_THREADS = 1024;      // Adam blocks: ADAM_P parameters x ADAM_G sample groups
+constexpr int ADAM_G = ADAM_THREADS / ADAM_P;
 
 // PSF on the matrix cores: K-steps of 4 per PSF row for 16 output columns
 // (at least 15 + KP window columns), the padded weight-row length, and the
