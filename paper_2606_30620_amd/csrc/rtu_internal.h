@@ -45,6 +45,37 @@ __host__ __device__ constexpr int psf_row_stride(int KP) {
   return (PSF_TW - 16 + 4 * psf_nk(KP)) % 8 == 4 ? PSF_TW - 16 + 4 * psf_nk(KP) : PSF_TW - 12 + 4 * psf_nk(KP);
 }             // per axis pair: dX[K], dS[K]  (x: 0..2K, y: 2K..4K)
 
+// The order statistics the selection needs: ranks floor(h_k) and floor(h_k) + 1
+// of the 22 nodes (clamped to [0, M - 1]).  Each sequence is non-decreasing,
+// but with few masked rays neighbouring nodes share floor(h_k), so
+// floor(h_k) + 1 can exceed floor(h_{k+1}); the selections take the distinct
+// ranks in ascending order.  out[0, n): those ranks (the rest 0x7fffffff);
+// out[2K + t]: the place of rank t (node t / 2, + (t & 1)) in that list;
+// out[4K] = n.  It depends on the mask only, so it is made once per
+// observation.
+__host__ __device__ inline void target_list(const int* rank_j, int M, int* out) {
+  int r[2 * K];
+  for (int t = 0; t < 2 * K; ++t) {
+    const int v = rank_j[t >> 1] + (t & 1);
+    r[t] = v < 0 ? 0 : (v > M - 1 ? M - 1 : v);
+  }
+  int n = 0;
+  for (int t = 0; t < 2 * K; ++t) out[t] = 0x7fffffff;
+  for (int t = 0; t < 2 * K; ++t) {
+    bool first = true;
+    for (int s = 0; s < t; ++s) first = first && r[s] != r[t];
+    int below = 0;
+    for (int s = 0; s < 2 * K; ++s) {
+      bool fs = true;
+      for (int u = 0; u < s; ++u) fs = fs && r[u] != r[s];
+      below += (fs && r[s] < r[t]) ? 1 : 0;
+    }
+    if (first) { out[below] = r[t]; ++n; }
+    out[2 * K + t] = below;
+  }
+  out[4 * K] = n;
+}
+
 // Per-sample tables of the two smoothed-CDF splines, in the layout the ray
 // kernels keep in LDS; built once per sample by the selection workgroups (each
 // writes its axis).  For axis ax and interval k (0: below the first knot, K:
@@ -114,6 +145,7 @@ struct SysDev {
   const int* mask_idx;        // [M] row-major pixel index of each masked pixel
   const int* rank_j;          // [K] floor((M-1) u_k)
   const double* rank_t;       // [K] (M-1) u_k - rank_j
+  const int* tsel;            // [4K + 1] the selection's targets (target_list)
   // weighted RTU grid (ray_w non-null): per masked ray its weight, the total
   // W, per node floor((W-1) u_k) and its fraction, and sort scratch
   const float* ray_w;         // [M]
@@ -206,6 +238,7 @@ struct ObsHost {
   std::vector<int> idx;       // masked pixels, row-major
   int rank_j[K];
   double rank_t[K];
+  int tsel[4 * K + 1];
   std::vector<float> inv_var, wfwd, wadj;   // 1/sigma^2; padded PSF weight rows (forward, adjoint)
   std::vector<float> wsep;                  // rank-one factors [4][KP] (see SysDev::psf_sep)
   bool rank1 = false;

@@ -143,7 +143,8 @@ __device__ __forceinline__ float ord_value(unsigned k) {
 // The type-7 quantiles need the masked rays at 2K ranks of their sorted order
 // (ties by ray index): floor(h_k) and floor(h_k) + 1 for every node.  Both
 // selections below take the distinct ranks in ascending order (L.trank[0,
-// ntgt)); prep_select builds that list and the map from the nodes to it.  First a value-linear histogram over the finite range
+// ntgt)), made once per observation (target_list) with the map from the
+// nodes to it.  First a value-linear histogram over the finite range
 // [vmin, vmax] names the bin of every target rank.  When the target bins are
 // small, their rays are gathered into LDS and ranked by counting.  Otherwise
 // (rays clustered far below the histogram's resolution, many ties,
@@ -722,6 +723,9 @@ __device__ __forceinline__ void prep_select(const SysDev& S, int b, int axis, un
   if (M < (S.uniform ? 2 : K + 1)) st |= RTU_ST_MASK_SMALL;
   if (tid == 0) L.stat = 0;
   if (tid < 2 * K) { L.tval[tid] = 0.f; L.tidx[tid] = 0; }
+  // the selection's targets (read after the reductions' barriers)
+  if (tid < 2 * K) { L.trank[tid] = S.tsel[tid]; L.tmap[tid] = S.tsel[2 * K + tid]; }
+  if (tid == 0) L.ntgt = S.tsel[4 * K];
   __syncthreads();   // the EPL tables
 
   MaskedRays R;
@@ -762,34 +766,7 @@ __device__ __forceinline__ void prep_select(const SysDev& S, int b, int axis, un
   if (M > 0 && S.ray_w) {
     select_weighted(S, L, zb, M, b, axis);
   } else if (M > 0) {
-    // target ranks floor(h_k) and floor(h_k) + 1, h_k = (M-1) u_k.  Each of
-    // the two sequences is non-decreasing in k, but with few masked rays
-    // neighbouring nodes share floor(h_k), so floor(h_k) + 1 can exceed
-    // floor(h_{k+1}): merge them into one ascending list of distinct ranks
-    // (the selections need ascending targets) and record where each node's
-    // pair went.
-    // One wave, lane t for target t: a rank is kept at its first lane, and its
-    // place in the list is the number of kept ranks below it.
-    if (tid < 64) {
-      const int t = tid;
-      int r = t < 2 * K ? S.rank_j[t >> 1] + (t & 1) : 0x7fffffff;
-      r = t < 2 * K ? (r < 0 ? 0 : (r > M - 1 ? M - 1 : r)) : r;
-      bool first = t < 2 * K;
-      for (int s = 0; s < 2 * K; ++s) {
-        const int rs = lane_value(r, s);       // every lane reads every lane (no divergence)
-        first = first && !(s < t && rs == r);
-      }
-      const unsigned long long keep = __ballot(first);
-      int below = 0;
-      for (int s = 0; s < 2 * K; ++s) {
-        const int rs = lane_value(r, s);
-        below += (((keep >> s) & 1ull) && rs < r) ? 1 : 0;
-      }
-      if (first) L.trank[below] = r;
-      if (t < 2 * K) L.tmap[t] = below;
-      if (t == 0) L.ntgt = __popcll(keep);
-    }
-    __syncthreads();
+    // the targets (target_list, made with the observation) are in LDS
     if (S.sel_radix || !select_by_counting(L, zb, M, vmin, vmax)) select_by_radix(L, zb, M, umin, umax);
   }
   __syncthreads();
@@ -2099,6 +2076,9 @@ __global__ void __launch_bounds__(OBS_THREADS) k_observe(SysDev S, const float* 
   if (tid == 0) {
     dyn[0] = M;
     dyn[1] = rank1;
+    int rj[K];
+    for (int k = 0; k < K; ++k) rj[k] = (int)floor((double)(M > 0 ? M - 1 : 0) * c_ud[k]);
+    target_list(rj, M, const_cast<int*>(S.tsel));
   }
 }
 

@@ -174,6 +174,7 @@ size_t carve_observation(SysDev& h, int B, int M, char* base) {
   h.mask_idx = c.take<int>(M > 0 ? M : 1);
   h.rank_j = c.take<int>(K);
   h.rank_t = c.take<double>(K);
+  h.tsel = c.take<int>(4 * K + 1);
   h.zbuf = c.take<float>((size_t)B * 2 * (M > 0 ? M : 1));
   return c.off + 256;
 }
@@ -197,6 +198,7 @@ void prepare_observation(const rtu_geometry* g, const float* noise_sigma, const 
     o.rank_j[k] = (int)fl;
     o.rank_t[k] = hh - fl;
   }
+  target_list(o.rank_j, M, o.tsel);
   o.inv_var.resize(N2);
   for (size_t q = 0; q < N2; ++q) o.inv_var[q] = 1.f / (noise_sigma[q] * noise_sigma[q]);
   const int WS = psf_ws(KP);
@@ -256,6 +258,7 @@ hipError_t upload_observation(const SysDev& h, const float* image, const float* 
   cp(h.mask_idx, o.idx.data(), o.idx.size() * 4);
   cp(h.rank_j, o.rank_j, sizeof(o.rank_j));
   cp(h.rank_t, o.rank_t, sizeof(o.rank_t));
+  cp(h.tsel, o.tsel, sizeof(o.tsel));
   return e;
 }
 
@@ -460,6 +463,7 @@ int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma
   if (M) memcpy(const_cast<int*>(hs.mask_idx), o.idx.data(), (size_t)M * 4);
   memcpy(const_cast<int*>(hs.rank_j), o.rank_j, sizeof(o.rank_j));
   memcpy(const_cast<double*>(hs.rank_t), o.rank_t, sizeof(o.rank_t));
+  memcpy(const_cast<int*>(hs.tsel), o.tsel, sizeof(o.tsel));
   const size_t bytes = (size_t)(reinterpret_cast<const char*>(h.zbuf) - p->obs_pool);
   if (hipMemcpyAsync(p->obs_pool, p->stage, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return RTU_EHIP;
   if (hipEventRecord(p->stage_done, s) != hipSuccess) return RTU_EHIP;
