@@ -41,6 +41,9 @@ constexpr int ADAM_G = ADAM_THREADS / ADAM_P;
 // distinct banks).
 __host__ __device__ constexpr int psf_nk(int KP) { return (15 + KP + 3) / 4; }
 __host__ __device__ constexpr int psf_ws(int KP) { return 4 * psf_nk(KP) + 16; }
+// separable PSF: LDS row stride of the input tile (its 64 + KP - 1 columns
+// after a shift of up to 3 that aligns them to float4 groups)
+__host__ __device__ constexpr int psf_sep_stride(int KP) { return (PSF_TW + KP - 1 + 6) & ~3; }
 __host__ __device__ constexpr int psf_row_stride(int KP) {
   return (PSF_TW - 16 + 4 * psf_nk(KP)) % 8 == 4 ? PSF_TW - 16 + 4 * psf_nk(KP) : PSF_TW - 12 + 4 * psf_nk(KP);
 }             // per axis pair: dX[K], dS[K]  (x: 0..2K, y: 2K..4K)

@@ -1504,16 +1504,40 @@ __device__ void psf_body(const SysDev& S, int b, int tile, int adjoint, float* t
 template <int KPT>
 __device__ void psf_sep_body(const SysDev& S, int b, int tile, int adjoint, float* tilein, double* red) {
   const int KP = KPT ? KPT : S.psf_k;
-  const int LS = psf_row_stride(KP), HH = PSF_TH + KP - 1;
+  const int N = S.n_img, LS = psf_sep_stride(KP), HH = PSF_TH + KP - 1, h = KP / 2;
   const int ty0 = (tile / S.psf_tx) * PSF_TH, tx0 = (tile % S.psf_tx) * PSF_TW;
-  psf_load_tile(S, b, adjoint, KP, ty0, tx0, tilein, S.psf_sep + (adjoint ? 2 * KP : 0), 2 * KP);
+  // the tile's rows from column tx0 - h - sh (a multiple of 4): with N a
+  // multiple of 4 every row is read in aligned float4 groups, each wholly
+  // inside or wholly outside the image
+  const int sh = (4 - (h & 3)) & 3, gj0 = tx0 - h - sh, nq = LS / 4;
+  const float* in = (adjoint ? S.r : S.u) + (size_t)b * N * N;
+  if ((N & 3) == 0) {
+    batched_copy<4>(HH * nq,
+                    [&](int q) {
+                      const int rr = q / nq, gi = ty0 + rr - h, gj = gj0 + 4 * (q - rr * nq);
+                      return (gi >= 0 && gi < N && gj >= 0 && gj < N)
+                                 ? *reinterpret_cast<const float4*>(in + gi * N + gj)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+                    },
+                    [&](int q, float4 v) { reinterpret_cast<float4*>(tilein)[q] = v; });
+  } else {
+    batched_copy<8>(HH * LS,
+                    [&](int q) {
+                      const int rr = q / LS, gi = ty0 + rr - h, gj = gj0 + q - rr * LS;
+                      return (gi >= 0 && gi < N && gj >= 0 && gj < N) ? in[gi * N + gj] : 0.f;
+                    },
+                    [&](int q, float v) { tilein[q] = v; });
+  }
+  const float* W = S.psf_sep + (adjoint ? 2 * KP : 0);
+  for (int k = threadIdx.x; k < 2 * KP; k += blockDim.x) tilein[HH * LS + k] = W[k];
+  __syncthreads();
   const float* uf = tilein + HH * LS;
   const float* vf = uf + KP;
   float* tr = tilein + HH * LS + ((2 * KP + 3) & ~3);    // [HH][PSF_TW] row-pass sums
   for (int it = threadIdx.x; it < HH * (PSF_TW / 4); it += blockDim.x) {
     const int rr = it / (PSF_TW / 4), x = (it - rr * (PSF_TW / 4)) * 4;
     if (tx0 + x >= S.n_img) continue;
-    const float* row = tilein + rr * LS + x;
+    const float* row = tilein + rr * LS + x + sh;
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
     for (int c = 0; c < (KPT ? KPT : 1); ++c) {
@@ -2204,7 +2228,8 @@ hipError_t launch_rays_adj(const SysDev& h, int batch, hipStream_t s) {
 size_t psf_lds_bytes(int KP) {
   const size_t tile = (size_t)(PSF_TH + KP - 1) * psf_row_stride(KP);
   const size_t mfma = tile + (size_t)KP * psf_ws(KP);
-  const size_t sep = tile + (size_t)((2 * KP + 3) & ~3) + (size_t)(PSF_TH + KP - 1) * PSF_TW;
+  const size_t sep = (size_t)(PSF_TH + KP - 1) * psf_sep_stride(KP) + (size_t)((2 * KP + 3) & ~3) +
+                     (size_t)(PSF_TH + KP - 1) * PSF_TW;
   return (mfma > sep ? mfma : sep) * 4;
 }
 
