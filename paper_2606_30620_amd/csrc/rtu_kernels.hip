@@ -1406,9 +1406,41 @@ __global__ void __launch_bounds__(RAY_THREADS) k_rays_adj(SysDev S) {
 __device__ __forceinline__ void psf_epilogue(const SysDev& S, int b, int tile, int adjoint, int ty0, int tx0,
                                              int ly, int lx, const float (&acc)[4], double* red) {
   const int N = S.n_img;
-  const int gi = ty0 + ly;
+  const int gi = ty0 + ly, gj0 = tx0 + lx;
   double c2 = 0.0, c2m = 0.0;
-  if (gi < N) {
+  if ((N & 3) == 0 && gi < N && gj0 + 3 < N) {
+    // four whole columns, 16-byte aligned (N and gj0 multiples of 4): vector
+    // loads and stores, the same arithmetic in the same order
+    const int pi = gi * N + gj0;
+    const size_t p = (size_t)b * N * N + pi;
+    if (adjoint) {
+      *reinterpret_cast<float4*>(S.ubar + p) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    } else {
+      const float4 d = *reinterpret_cast<const float4*>(S.image + pi);
+      const float4 iv = *reinterpret_cast<const float4*>(S.inv_var + pi);
+      const uchar4 mk = *reinterpret_cast<const uchar4*>(S.mask + pi);
+      const float dd[4] = {d.x, d.y, d.z, d.w}, ivv[4] = {iv.x, iv.y, iv.z, iv.w};
+      const bool mm[4] = {mk.x != 0, mk.y != 0, mk.z != 0, mk.w != 0};
+      float rr[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float res = acc[q] - dd[q];
+        rr[q] = res * ivv[q];
+        const double e = (double)res * (double)res * (double)ivv[q];
+        c2 += e;
+        if (mm[q]) c2m += e;
+      }
+      *reinterpret_cast<float4*>(S.r + p) = make_float4(rr[0], rr[1], rr[2], rr[3]);
+      if (S.model) {
+        float* mo = S.model + p;
+        if ((reinterpret_cast<uintptr_t>(mo) & 15) == 0) {
+          *reinterpret_cast<float4*>(mo) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        } else {
+          mo[0] = acc[0]; mo[1] = acc[1]; mo[2] = acc[2]; mo[3] = acc[3];
+        }
+      }
+    }
+  } else if (gi < N) {
     for (int q = 0; q < 4; ++q) {
       const int gj = tx0 + lx + q;
       if (gj >= N) break;
