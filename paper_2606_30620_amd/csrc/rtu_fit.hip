@@ -80,32 +80,33 @@ __device__ __forceinline__ float grad_at(const FitDev& F, int s, int i) {
 
 // Adam on (mu, rho) with the gradient of -ELBO:
 //   d/dmu_i  = mean_s g_si,   d/drho_i = mean_s g_si exp(rho_i) eps_si - 1
-// A workgroup takes ADAM_P parameters; its ADAM_G (16) groups of threads each sum
-// every ADAM_G-th sample of a parameter, and group 0 adds the group sums in
+// A workgroup takes ADAM_P parameters; its G = blockDim / ADAM_P groups of
+// threads (as many as the launch's largest sample count needs, at most 16)
+// each sum every G-th sample of a parameter, and group 0 adds the group sums in
 // group order (so that more workgroups share the memory latency of the
 // S gradient and draw loads) and leaves the new mu and exp(rho) in nmu,
 // nsig.  Called by every thread of the workgroup.
 __device__ __forceinline__ void adam_body(const FitDev& F, int t, int i, int g, float* red, float* nmu,
                                           float* nsig) {
-  const int p = threadIdx.x % ADAM_P;
+  const int p = threadIdx.x % ADAM_P, G = blockDim.x / ADAM_P;
   float gm = 0.f, gr = 0.f;
   if (i < F.dim) {
 #pragma unroll 4
-    for (int s = g; s < F.S; s += ADAM_G) {
+    for (int s = g; s < F.S; s += G) {
       const float gs = grad_at(F, s, i);
       gm += gs;
       gr += gs * F.eps_s[(size_t)s * F.dim + i];
     }
   }
   red[g * ADAM_P + p] = gm;
-  red[(ADAM_G + g) * ADAM_P + p] = gr;
+  red[(G + g) * ADAM_P + p] = gr;
   __syncthreads();
   if (g != 0 || i >= F.dim) return;
   gm = red[p];
-  gr = red[ADAM_G * ADAM_P + p];
-  for (int k = 1; k < ADAM_G; ++k) {
+  gr = red[G * ADAM_P + p];
+  for (int k = 1; k < G; ++k) {
     gm += red[k * ADAM_P + p];
-    gr += red[(ADAM_G + k) * ADAM_P + p];
+    gr += red[(G + k) * ADAM_P + p];
   }
   const float sig = __expf(F.rho[i]);
   const float invS = 1.f / (float)F.S;
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(ADAM_THREADS) kf_adam(const FitDev* __restrict
   __syncthreads();
   if (draw) {
     if (i < F.dim)
-      for (int c = g; 4 * c < F.S; c += ADAM_G) {   // four samples per Philox block
+      for (int c = g; 4 * c < F.S; c += (int)(blockDim.x / ADAM_P)) {   // four samples per Philox block
         float z[4];
         normal_draw4(F, step + 1, c, i, z);
         for (int k = 0; k < 4 && 4 * c + k < F.S; ++k) sample_store(F, 4 * c + k, i, nmu[p], nsig[p], z[k]);
@@ -213,7 +214,7 @@ hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, co
                                       round, eps);
   } else if (stage == RTU_STAGE_ADAM) {
     if (L.n_param)
-      hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(ADAM_THREADS), 0, s, L.fit, L.t_param, round,
+      hipLaunchKernelGGL(kf_adam, dim3(L.n_param), dim3(L.adam_threads), 0, s, L.fit, L.t_param, round,
                          eps ? 0 : 1);
   }
   return hipGetLastError();

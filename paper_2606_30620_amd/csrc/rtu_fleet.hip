@@ -182,6 +182,12 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
   L.t_sample = d_tasks + off[4]; L.n_sample = (int)samp.size();
   L.t_fit = d_tasks + off[5];   L.n_fit = (int)fits.size();
   L.t_gp = d_tasks + off[12];   L.n_gp = (int)gp.size();
+  {
+    int smax = 1, g = 1;
+    for (size_t i = 0; i < n; ++i) smax = std::max(smax, fit[i].S);
+    while (g < smax && ADAM_P * g < ADAM_THREADS) g *= 2;
+    L.adam_threads = ADAM_P * g;
+  }
   L.lds_gp = lds_g;
   for (int k = 0; k < 2; ++k) {
     L.t_fwd[k] = d_tasks + off[6 + k]; L.n_fwd[k] = (int)fwd[k].size();

@@ -31,8 +31,7 @@ constexpr int GP_THREADS = 256;
 __host__ __device__ constexpr bool gp_split(int n) { return n >= GP_SPLIT_N; }
 constexpr int FIT_THREADS = 256;        // fit kernels: sampling blocks of 256 parameters,
 constexpr int ADAM_P = 64;              // Adam blocks of 64 parameters
-constexpr int ADAM_THREADS = 1024;      // Adam blocks: ADAM_P parameters x ADAM_G sample groups
-constexpr int ADAM_G = ADAM_THREADS / ADAM_P;
+constexpr int ADAM_THREADS = 1024;      // Adam blocks: ADAM_P parameters x up to 16 sample groups
 
 // PSF on the matrix cores: K-steps of 4 per PSF row for 16 output columns
 // (at least 15 + KP window columns), the padded weight-row length, and the
@@ -283,6 +282,7 @@ struct FleetLaunch {
   const Task* t_adj[2][2];
   int n_adj[2][2];
   size_t lds_rays_fwd, lds_rays_adj, lds_psf, lds_prep, lds_post, lds_gp;
+  int adam_threads;           // ADAM_P x the sample groups of the largest sample count (<= ADAM_THREADS)
 };
 // One stage (RTU_STAGE_*) of a shared launch; eps (device [S][dim] per fit,
 // only for a single-fit table) replaces the Philox draws when not null.
