@@ -47,6 +47,13 @@ __host__ __device__ constexpr int psf_row_stride(int KP) {
   return (PSF_TW - 16 + 4 * psf_nk(KP)) % 8 == 4 ? PSF_TW - 16 + 4 * psf_nk(KP) : PSF_TW - 12 + 4 * psf_nk(KP);
 }             // per axis pair: dX[K], dS[K]  (x: 0..2K, y: 2K..4K)
 
+// Pixel (i, j)'s centre ((j - (N-1)/2) d, (i - (N-1)/2) d), the same FP32
+// arithmetic on the host and the device.
+__host__ __device__ inline float2 pixel_centre(int p, int N, float pix) {
+  const int i = p / N, j = p - i * N;
+  return make_float2(((float)j - 0.5f * (float)(N - 1)) * pix, ((float)i - 0.5f * (float)(N - 1)) * pix);
+}
+
 // The order statistics the selection needs: ranks floor(h_k) and floor(h_k) + 1
 // of the 22 nodes (clamped to [0, M - 1]).  Each sequence is non-decreasing,
 // but with few masked rays neighbouring nodes share floor(h_k), so
@@ -145,6 +152,7 @@ struct SysDev {
                               // (these then replace the two fields above)
   const uint8_t* mask;        // [N*N]
   const int* mask_idx;        // [M] row-major pixel index of each masked pixel
+  const float2* mask_xy;      // [M] its image-plane position (the pixel centre)
   const int* rank_j;          // [K] floor((M-1) u_k)
   const double* rank_t;       // [K] (M-1) u_k - rank_j
   const int* tsel;            // [4K + 1] the selection's targets (target_list)
@@ -238,6 +246,7 @@ hipError_t launch_observe(const SysDev& h, const float* noise_sigma, const float
 // host helpers shared by plans, fits and the serving fleet (rtu_runtime.hip)
 struct ObsHost {
   std::vector<int> idx;       // masked pixels, row-major
+  std::vector<float2> xy;     // their pixel centres
   int rank_j[K];
   double rank_t[K];
   int tsel[4 * K + 1];

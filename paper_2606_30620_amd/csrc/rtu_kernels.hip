@@ -674,16 +674,14 @@ template <class MAIN>
 __device__ __forceinline__ void masked_rays(const SysDev& S, const MAIN& ML, const float* lensp, int nsub, int axis,
                                             int M, float* zb, MaskedRays& R) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  // the mask index of the iteration after next is loaded ahead
-  int p1 = tid < M ? S.mask_idx[tid] : 0;
-  int p2 = tid + nt < M ? S.mask_idx[tid + nt] : 0;
+  // the pixel centre of the iteration after next is loaded ahead
+  const float2 z2 = make_float2(0.f, 0.f);
+  float2 p1 = tid < M ? S.mask_xy[tid] : z2;
+  float2 p2 = tid + nt < M ? S.mask_xy[tid + nt] : z2;
   for (int m = tid; m < M; m += nt) {
-    const int p = p1;
+    const float x = p1.x, y = p1.y;
     p1 = p2;
-    if (m + 2 * nt < M) p2 = S.mask_idx[m + 2 * nt];
-    const int i = p / S.n_img, j = p - i * S.n_img;
-    const float x = ((float)j - 0.5f * (float)(S.n_img - 1)) * S.pix;
-    const float y = ((float)i - 0.5f * (float)(S.n_img - 1)) * S.pix;
+    if (m + 2 * nt < M) p2 = S.mask_xy[m + 2 * nt];
     float bx, by;
     shoot(S, ML, lensp, nsub, x, y, bx, by);
     if (S.ray_w) {   // weighted grid: weighted moments
@@ -2113,7 +2111,10 @@ __global__ void __launch_bounds__(OBS_THREADS) k_observe(SysDev S, const float* 
     __syncthreads();
     int off = s_off;
     for (int w = 0; w < wv; ++w) off += wcnt[w];
-    if (m) idx[off + below] = p;
+    if (m) {
+      idx[off + below] = p;
+      const_cast<float2*>(S.mask_xy)[off + below] = pixel_centre(p, S.n_img, S.pix);
+    }
     __syncthreads();
     if (tid == 0) {
       int t = 0;

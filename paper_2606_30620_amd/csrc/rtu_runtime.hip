@@ -172,6 +172,7 @@ size_t carve_observation(SysDev& h, int B, int M, char* base) {
   h.psf_sep = c.take<float>((size_t)4 * h.psf_k);
   h.mask = c.take<uint8_t>(N2);
   h.mask_idx = c.take<int>(M > 0 ? M : 1);
+  h.mask_xy = c.take<float2>(M > 0 ? M : 1);
   h.rank_j = c.take<int>(K);
   h.rank_t = c.take<double>(K);
   h.tsel = c.take<int>(4 * K + 1);
@@ -188,8 +189,12 @@ void prepare_observation(const rtu_geometry* g, const float* noise_sigma, const 
   const int N = g->n_img, KP = g->psf_size;
   const size_t N2 = (size_t)N * N;
   o.idx.clear();
+  o.xy.clear();
   for (size_t q = 0; q < N2; ++q)
-    if (arc_mask[q]) o.idx.push_back((int)q);
+    if (arc_mask[q]) {
+      o.idx.push_back((int)q);
+      o.xy.push_back(pixel_centre((int)q, N, g->pixel_scale));
+    }
   const int M = (int)o.idx.size();
   for (int k = 0; k < K; ++k) {
     const double u = 0.5 * (1.0 - cos((2.0 * (k + 1) - 1.0) * M_PI / (2.0 * K)));
@@ -256,6 +261,7 @@ hipError_t upload_observation(const SysDev& h, const float* image, const float* 
   cp(h.psf_sep, o.wsep.data(), o.wsep.size() * 4);
   cp(h.mask, arc_mask, N2);
   cp(h.mask_idx, o.idx.data(), o.idx.size() * 4);
+  cp(h.mask_xy, o.xy.data(), o.xy.size() * sizeof(float2));
   cp(h.rank_j, o.rank_j, sizeof(o.rank_j));
   cp(h.rank_t, o.rank_t, sizeof(o.rank_t));
   cp(h.tsel, o.tsel, sizeof(o.tsel));
@@ -461,6 +467,7 @@ int rtu_set_observation(rtu_plan p, const float* image, const float* noise_sigma
   memcpy(const_cast<float*>(hs.psf_sep), o.wsep.data(), o.wsep.size() * 4);
   memcpy(const_cast<uint8_t*>(hs.mask), arc_mask, N2);
   if (M) memcpy(const_cast<int*>(hs.mask_idx), o.idx.data(), (size_t)M * 4);
+  if (M) memcpy(const_cast<float2*>(hs.mask_xy), o.xy.data(), (size_t)M * sizeof(float2));
   memcpy(const_cast<int*>(hs.rank_j), o.rank_j, sizeof(o.rank_j));
   memcpy(const_cast<double*>(hs.rank_t), o.rank_t, sizeof(o.rank_t));
   memcpy(const_cast<int*>(hs.tsel), o.tsel, sizeof(o.tsel));
