@@ -675,13 +675,14 @@ __device__ __forceinline__ void masked_rays(const SysDev& S, const MAIN& ML, con
                                             int M, float* zb, MaskedRays& R) {
   const int tid = threadIdx.x, nt = blockDim.x;
   // the pixel centre of the iteration after next is loaded ahead
-  const float2 z2 = make_float2(0.f, 0.f);
-  float2 p1 = tid < M ? S.mask_xy[tid] : z2;
-  float2 p2 = tid + nt < M ? S.mask_xy[tid + nt] : z2;
+  const float* xy = reinterpret_cast<const float*>(S.mask_xy);
+  float p1x = 0.f, p1y = 0.f, p2x = 0.f, p2y = 0.f;
+  if (tid < M) { p1x = xy[2 * tid]; p1y = xy[2 * tid + 1]; }
+  if (tid + nt < M) { p2x = xy[2 * (tid + nt)]; p2y = xy[2 * (tid + nt) + 1]; }
   for (int m = tid; m < M; m += nt) {
-    const float x = p1.x, y = p1.y;
-    p1 = p2;
-    if (m + 2 * nt < M) p2 = S.mask_xy[m + 2 * nt];
+    const float x = p1x, y = p1y;
+    p1x = p2x; p1y = p2y;
+    if (m + 2 * nt < M) { p2x = xy[2 * (m + 2 * nt)]; p2y = xy[2 * (m + 2 * nt) + 1]; }
     float bx, by;
     shoot(S, ML, lensp, nsub, x, y, bx, by);
     if (S.ray_w) {   // weighted grid: weighted moments
@@ -1804,7 +1805,7 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
   if (role == 0 && S.want_grad) {
     const float* lensp = S.lens + (size_t)b * nl;
     const int nsub = n_sub_of(S, b);
-    const Sie L = make_sie(lensp);
+    const Sie L = S.epl ? make_sie(lensp) : S.sie[b];   // (the EPL path does not use it)
     if (S.epl && tid == 0) epl_table(make_epl(lensp), P.etab);   // read after the syncs below
     // ---- knot adjoint: sum the tile partials, then S_k = 1/p'_k with
     //      p'_k = sum_l D_kl X_l  ->  dX_l += sum_k (-S_k^2 dS_k) D_kl
@@ -1869,10 +1870,8 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
       const int M = obs_M(S);
       m = m < 0 ? 0 : (m >= M ? M - 1 : m);
       if (bb != 0.0 && M > 0) {
-        const int p = S.mask_idx[m];
-        const int i = p / S.n_img, j = p - i * S.n_img;
-        const float x = ((float)j - 0.5f * (float)(S.n_img - 1)) * S.pix;
-        const float y = ((float)i - 0.5f * (float)(S.n_img - 1)) * S.pix;
+        const float2 c = S.mask_xy[m];
+        const float x = c.x, y = c.y;
         const float abx = ax == 0 ? -(float)bb : 0.f, aby = ax == 1 ? -(float)bb : 0.f;
         if (S.epl) {     // the parameter gradients themselves (row 8 stays zero)
           float ea[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
