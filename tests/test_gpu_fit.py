@@ -53,17 +53,26 @@ def test_elbo_step_with_log_space_spectrum_matches_oracle():
                      log_params=[7, 9])
 
 
-def _elbo_step_check(p, groups, log_params=(), n_sub=0):
+@pytest.mark.parametrize("S", [5, 19])
+def test_elbo_step_sample_counts(S):
+    """Sample counts that leave some of the Adam update's sample groups
+    short or idle (5: eight groups; 19: sixteen groups, three of them with
+    two samples)."""
+    say(f"[gpu] fit: one ELBO+Adam step, C1, S={S}, eps given")
+    _elbo_step_check(c1_mock(), {"lens": slice(0, 7), "ps": slice(7, 11), "latent": slice(11, None)}, S=S)
+
+
+def _elbo_step_check(p, groups, log_params=(), n_sub=0, S=2):
     from paper_2606_30620_amd import _lib, api
-    plan = api.plan_for_problem(p, max_batch=2)
+    plan = api.plan_for_problem(p, max_batch=S)
     mu, rho = _guide(p)
     for i in log_params:
         mu[i] = math.log(mu[i])
         rho[i] = math.log(0.05)
     mu32, rho32 = mu.astype(np.float32), rho.astype(np.float32)
     rng = np.random.default_rng(21)
-    eps = rng.standard_normal((2, mu.size)).astype(np.float32)
-    fit = _lib.Fit(plan, 2, mu32, rho32, lr=1e-2, seed=1, max_steps=4, n_sub=n_sub, log_params=log_params)
+    eps = rng.standard_normal((S, mu.size)).astype(np.float32)
+    fit = _lib.Fit(plan, S, mu32, rho32, lr=1e-2, seed=1, max_steps=4, n_sub=n_sub, log_params=log_params)
     fit.step(1, eps=torch.from_numpy(eps).cuda())
     state, steps = fit.get_state()
     _, _, trace = fit.read()
