@@ -51,7 +51,7 @@ def _prepared_sources():
 
 
 def build() -> str:
-    """Compile (when any input changed) and return the driver's path."""
+    """Compile (when any input changed) and return the path of the emulation program."""
     srcs = _prepared_sources()
     own = {f: open(os.path.join(HERE, f)).read() for f in ("emu.cpp", "driver.cpp", os.path.join("hip", "hip_runtime.h"))}
     h = hashlib.sha256()
