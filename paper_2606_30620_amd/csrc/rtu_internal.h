@@ -19,7 +19,15 @@ constexpr int PSF_TW = 64;              // PSF kernels: 64 x 16 output tile,
 constexpr int PSF_TH = 16;              // 256 threads x 4 columns each
 constexpr int PSF_THREADS = 256;
 constexpr int ST_WORDS = 8;
-constexpr int PREP_THREADS = 512;       // quantile selection and FFT workgroups
+constexpr int PREP_THREADS = 512;       // quantile selection and FFT workgroups,
+constexpr int PREP_THREADS_WIDE = 1024; // twice as wide for masks of PREP_WIDE_M rays or more
+constexpr int PREP_WIDE_M = 12000;
+constexpr int POST_THREADS = 512;       // per-sample adjoint workgroups
+// Prep workgroup size for a mask of M rays (0: not known on the host).  The
+// selection's passes over the rays (shooting, histogram, gather) shorten
+// with more threads only when each thread has many rays; with fewer, the
+// barriers of sixteen waves cost more than the passes save.
+inline int prep_threads(int M) { return M >= PREP_WIDE_M ? PREP_THREADS_WIDE : PREP_THREADS; }
 constexpr int GRID_LDS_MAX = 64;        // n_src <= this: the ray adjoint keeps d loss / d s in LDS
 constexpr int KBAR = 4 * K;
 // GP transforms of source grids of at least GP_SPLIT_N per side run as three
@@ -292,6 +300,7 @@ struct FleetLaunch {
   int n_adj[2][2];
   size_t lds_rays_fwd, lds_rays_adj, lds_psf, lds_prep, lds_post, lds_gp;
   int adam_threads;           // ADAM_P x the sample groups of the largest sample count (<= ADAM_THREADS)
+  int prep_threads;           // prep workgroup size for the largest mask (prep_threads)
 };
 // One stage (RTU_STAGE_*) of a shared launch; eps (device [S][dim] per fit,
 // only for a single-fit table) replaces the Philox draws when not null.

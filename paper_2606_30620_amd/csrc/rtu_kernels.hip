@@ -194,6 +194,10 @@ struct SelLds {
   uint32_t stat;
   EplTab etab;                  // EPL deflector: the sample's series tables
 };
+// per-wave slots (red, fred, ured: 16 waves) and the weighted sort's per-wave
+// digit counts in rhist hold the widest prep workgroup
+static_assert(PREP_THREADS_WIDE / 64 <= 16 && 256 * (1 + PREP_THREADS_WIDE / 64) <= SEL_BINS + 1,
+              "prep workgroup wider than the selection's LDS");
 
 // Exclusive scan of h[0, n) by the whole workgroup; h[n] = total.
 __device__ __forceinline__ void block_exclusive_scan(int* h, int n, int* wsum) {
@@ -461,8 +465,8 @@ __device__ __forceinline__ double block_scan_f64(double v, double* wsum, double*
 // four passes of 8-bit digits between A and Bf; the result is in A.
 __device__ void weighted_sort(SelLds& L, uint2* A, uint2* Bf, int M) {
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-  int* hist = L.c.hist;             // [256] digit counts, then the running bases
-  int* cnt = L.c.hist + 256;        // [nw][256] per-wave digit counts of a chunk
+  int* hist = L.rhist;              // [256] digit counts, then the running bases
+  int* cnt = L.rhist + 256;         // [nw][256] per-wave digit counts of a chunk (nw <= 16)
   for (int pass = 0; pass < 4; ++pass) {
     const int sh = 8 * pass;
     for (int d = tid; d < 256; d += nt) hist[d] = 0;
@@ -909,7 +913,7 @@ __device__ __forceinline__ void prep_gp(const SysDev& S, int b, unsigned char* s
 
 // Dynamic LDS of the prep kernels: the larger of the selection layout and the
 // FFT buffer (fft_cap float2 line slots, then the twiddle table).
-__global__ void __launch_bounds__(PREP_THREADS) k_prep(SysDev S, int fft_cap) {
+__global__ void __launch_bounds__(PREP_THREADS_WIDE) k_prep(SysDev S, int fft_cap) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x, role = blockIdx.y;
   if (role < 2) prep_select(S, b, role, smem);
@@ -1768,7 +1772,7 @@ __global__ void __launch_bounds__(GP_THREADS) k_gp(SysDev S, int pass) {
 
 struct PostLds {
   double red[16 * 16];
-  double part[PREP_THREADS];
+  double part[POST_THREADS];
   double xbar[2][K];      // d loss / d X (beta units), after the slope chain
   double wk[2][K];        // -S_k^2 d loss / d S_k
   double lsum[RTU_MAX_LENS + 1];   // raw sums
@@ -2009,7 +2013,7 @@ __device__ __forceinline__ void post_body(const SysDev& S, int b, int role, unsi
   }
 }
 
-__global__ void __launch_bounds__(PREP_THREADS) k_post(SysDev S, int fft_cap) {
+__global__ void __launch_bounds__(POST_THREADS) k_post(SysDev S, int fft_cap) {
   extern __shared__ __align__(16) unsigned char fft_smem[];
   __shared__ PostLds P;
   // one inlined copy per role, so that each holds only its own code
@@ -2200,7 +2204,7 @@ size_t post_lds_bytes(int n_src, int n_lens) {
 }
 
 hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep, dim3(batch, 3), dim3(PREP_THREADS), prep_lds_bytes(h.n_src), s, h,
+  hipLaunchKernelGGL(k_prep, dim3(batch, 3), dim3(prep_threads(h.obs_dyn ? 0 : h.M)), prep_lds_bytes(h.n_src), s, h,
                      fft_lds_cap(h.n_src));
   if (gp_split(h.n_src))
     for (int pass = 0; pass < 3; ++pass)
@@ -2272,7 +2276,7 @@ hipError_t launch_psf(const SysDev& h, int batch, bool adjoint, hipStream_t s) {
 }
 
 hipError_t launch_post(const SysDev& h, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_post, dim3(batch, h.want_grad ? 2 : 1), dim3(PREP_THREADS), post_lds_bytes(h.n_src, h.n_lens), s, h,
+  hipLaunchKernelGGL(k_post, dim3(batch, h.want_grad ? 2 : 1), dim3(POST_THREADS), post_lds_bytes(h.n_src, h.n_lens), s, h,
                      fft_lds_cap(h.n_src));
   if (h.want_grad && gp_split(h.n_src))
     for (int pass = 0; pass < 3; ++pass)
@@ -2290,7 +2294,7 @@ __device__ __forceinline__ bool sys_active(const SysDev& S, int round) {
   return st >= 0 && st < S.nsteps;
 }
 
-__global__ void __launch_bounds__(PREP_THREADS) kf_prep(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
+__global__ void __launch_bounds__(PREP_THREADS_WIDE) kf_prep(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
                                                       int round, int fft_cap) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Task t = tasks[blockIdx.x];
@@ -2341,7 +2345,7 @@ __global__ void __launch_bounds__(PSF_THREADS) kf_psf(const SysDev* __restrict__
   psf_dispatch(S, t.y, t.z, adjoint, tilein, red);
 }
 
-__global__ void __launch_bounds__(PREP_THREADS) kf_post(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
+__global__ void __launch_bounds__(POST_THREADS) kf_post(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
                                                       int round, int fft_cap) {
   extern __shared__ __align__(16) unsigned char fft_smem[];
   __shared__ PostLds P;
@@ -2358,7 +2362,7 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
   switch (stage) {
     case RTU_STAGE_PREP:
       if (L.n_prep)
-        hipLaunchKernelGGL(kf_prep, dim3(L.n_prep), dim3(PREP_THREADS), L.lds_prep, s, L.sys, L.t_prep, round,
+        hipLaunchKernelGGL(kf_prep, dim3(L.n_prep), dim3(L.prep_threads), L.lds_prep, s, L.sys, L.t_prep, round,
                            (int)(L.lds_prep / sizeof(float2)) - 128);
       if (L.n_gp)
         for (int pass = 0; pass < 3; ++pass)
@@ -2394,7 +2398,7 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
       break;
     case RTU_STAGE_POST:
       if (L.n_post)
-        hipLaunchKernelGGL(kf_post, dim3(L.n_post), dim3(PREP_THREADS), L.lds_post, s, L.sys, L.t_post, round,
+        hipLaunchKernelGGL(kf_post, dim3(L.n_post), dim3(POST_THREADS), L.lds_post, s, L.sys, L.t_post, round,
                            (int)(L.lds_post / sizeof(float2)) - 128);
       if (L.n_gp)
         for (int pass = 0; pass < 3; ++pass)

@@ -244,15 +244,19 @@ def test_replay_is_deterministic():
         assert torch.equal(getattr(a, name), getattr(b, name)), name
 
 
-@pytest.mark.parametrize("case", ["c2", "subhalo", "ragged"])
+@pytest.mark.parametrize("case", ["c2", "subhalo", "ragged", "wide"])
 def test_radix_selection_matches_histogram_selection(case):
     """The bounded-pass radix select (the fallback for clustered or tied
     masked rays) picks exactly the rays of the histogram + counting select:
     forcing it for every sample leaves every output bit-identical, and the
-    forced run agrees with the oracle."""
+    forced run agrees with the oracle.  "wide": C3 seed 325, 29859 masked
+    rays, above the size from which the prep workgroups are 1024 wide."""
     from paper_2606_30620_amd import _lib
     if case == "c2":
         p = synth.make_problem("C2", batch=2)
+    elif case == "wide":
+        p = synth.make_problem("C3", batch=2, seed=325)
+        assert int(p.mask.sum()) >= 12000
     elif case == "subhalo":
         p = synth.make_problem("X", batch=2, seed=11,
                                geom=synth.Geometry(96, 0.05, 2, 64, 15, 1.0, n_sub_max=3, tnfw_tau=10.0))
