@@ -115,13 +115,14 @@ namespace rtu {
 
 int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDev>& fit, FleetLaunch& L) {
   const size_t n = sys.size();
-  std::vector<Task> prep, psf, post, param, samp, fits, gp, fwd[2], adj[2][2];
+  std::vector<Task> prep, psf, post, param, samp, fits, gp, mr, fwd[2], adj[2][2];
   size_t lds_f = 0, lds_a = 0, lds_p = 0, lds_pr = 0, lds_po = 0, lds_g = 0;
   for (size_t i = 0; i < n; ++i) {
     const SysDev& h = sys[i];
     const FitDev& F = fit[i];
     const int si = (int)i, S = h.batch;
     for (int b = 0; b < S; ++b) {
+      for (int c = 0; c < h.mr_nchunk; ++c) mr.push_back(make_int4(si, b, c, 0));
       for (int r = 0; r < 3; ++r) prep.push_back(make_int4(si, b, r, 0));
       if (gp_split(h.n_src))
         for (int g = 0; g < h.n_src / GP_LINES; ++g) gp.push_back(make_int4(si, b, g, 0));
@@ -146,10 +147,10 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
     if (gp_split(h.n_src)) lds_g = std::max(lds_g, gp_lds_bytes(h.n_src));
   }
   std::vector<Task> all;
-  size_t off[13];
-  std::vector<Task>* lists[13] = {&prep, &psf, &post, &param, &samp, &fits, &fwd[0], &fwd[1],
-                                  &adj[0][0], &adj[0][1], &adj[1][0], &adj[1][1], &gp};
-  for (int k = 0; k < 13; ++k) {
+  size_t off[14];
+  std::vector<Task>* lists[14] = {&prep, &psf, &post, &param, &samp, &fits, &fwd[0], &fwd[1],
+                                  &adj[0][0], &adj[0][1], &adj[1][0], &adj[1][1], &gp, &mr};
+  for (int k = 0; k < 14; ++k) {
     off[k] = all.size();
     all.insert(all.end(), lists[k]->begin(), lists[k]->end());
   }
@@ -182,6 +183,7 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
   L.t_sample = d_tasks + off[4]; L.n_sample = (int)samp.size();
   L.t_fit = d_tasks + off[5];   L.n_fit = (int)fits.size();
   L.t_gp = d_tasks + off[12];   L.n_gp = (int)gp.size();
+  L.t_mr = d_tasks + off[13];   L.n_mr = (int)mr.size();
   {
     int smax = 1, g = 1;
     for (size_t i = 0; i < n; ++i) smax = std::max(smax, fit[i].S);

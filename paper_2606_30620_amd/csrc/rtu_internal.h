@@ -28,6 +28,14 @@ constexpr int POST_THREADS = 512;       // per-sample adjoint workgroups
 // with more threads only when each thread has many rays; with fewer, the
 // barriers of sixteen waves cost more than the passes save.
 inline int prep_threads(int M) { return M >= PREP_WIDE_M ? PREP_THREADS_WIDE : PREP_THREADS; }
+// Masks of MR_MIN_M rays or more are shot before the selection by a launch
+// of its own, MR_CHUNK rays per workgroup of MR_THREADS, over many CUs
+// (the selection workgroup of a sample runs on one CU); the selection
+// then sums the chunks' moments and ranges in chunk order.
+constexpr int MR_THREADS = 256;
+constexpr int MR_CHUNK = 1024;
+constexpr int MR_MIN_M = 8192;
+inline int mr_chunks(int M) { return M >= MR_MIN_M ? (M + MR_CHUNK - 1) / MR_CHUNK : 0; }
 constexpr int GRID_LDS_MAX = 64;        // n_src <= this: the ray adjoint keeps d loss / d s in LDS
 constexpr int KBAR = 4 * K;
 // GP transforms of source grids of at least GP_SPLIT_N per side run as three
@@ -132,6 +140,17 @@ struct Sie {
 
 // Everything a kernel needs about one lens system and the samples of a call.
 // Sample b of a per-sample array starts at base + b * (its per-sample size).
+// Moments and ranges of one chunk of masked rays (both axes): the (weighted)
+// sums of beta_x, beta_y and their squares, the finite value range and the
+// order-key range per axis, the uniform grid's extreme keys (x min, x max,
+// y min, y max).
+struct MRayPart {
+  double s[4];
+  float vmin[2], vmax[2];
+  unsigned umin[2], umax[2];
+  unsigned long long k[4];
+};
+
 struct SysDev {
   // geometry
   int n_img, ss, n_src, log2_src, psf_k, n_sub_max, n_lens, M;
@@ -194,6 +213,8 @@ struct SysDev {
   float2* tmp;                // [B][n^2] FFT scratch
   double* gpp;                // [B][n / GP_LINES][4] split GP adjoint: spectrum-gradient partials per workgroup
   float* zbuf;                // [B][2][M] masked-ray beta per axis
+  MRayPart* mrp;              // [B][mr_nchunk] chunk partials of the masked-ray launch
+  int mr_nchunk;               // chunks of that launch per sample (0: the selection shoots the rays)
   float* knots;               // [B][2][2][K] per axis: X_k, S_k in beta units
   float* kdbg;                // [B][2][2][K] per axis: X_k, S_k standardised
   int* sel;                   // [B][2][2][K] per axis: ray index at rank j, j+1
@@ -291,6 +312,8 @@ struct FleetLaunch {
   const FitDev* fit;          // device [n_slots]
   const Task *t_prep, *t_psf, *t_post, *t_param, *t_sample, *t_fit, *t_gp;
   int n_prep, n_psf, n_post, n_param, n_sample, n_fit, n_gp;   // t_gp: split GP line groups
+  const Task* t_mr;           // masked-ray chunks (systems with mr_nchunk > 0)
+  int n_mr;
   // forward ray tiles by main deflector: [0] SIE, [1] EPL
   const Task* t_fwd[2];
   int n_fwd[2];

@@ -712,6 +712,101 @@ __device__ __forceinline__ void masked_rays(const SysDev& S, const MAIN& ML, con
   }
 }
 
+// Chunk c of the masked rays of sample b (a launch before the selection, for
+// large masks): the rays m in [c MR_CHUNK, (c + 1) MR_CHUNK), both axes'
+// values into zbuf and the chunk's moments and ranges into mrp, with the
+// arithmetic of masked_rays.
+struct MRayLds {
+  EplTab etab;
+  double red[4 * (MR_THREADS / 64)];
+  float fred[4 * (MR_THREADS / 64)];
+  unsigned ured[4 * (MR_THREADS / 64)];
+  unsigned long long kred[4];   // uniform grid: x min, x max, y min, y max keys
+};
+template <class MAIN>
+__device__ __forceinline__ void mrays_chunk(const SysDev& S, const MAIN& ML, const float* lensp, int nsub, int b,
+                                            int c, MRayLds& L) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  const int M = S.M, m0 = c * MR_CHUNK, m1 = min(M, m0 + MR_CHUNK);
+  float* zx = S.zbuf + (size_t)b * 2 * M;
+  float* zy = zx + M;
+  const float* xy = reinterpret_cast<const float*>(S.mask_xy);
+  double sx = 0.0, sy = 0.0, sxx = 0.0, syy = 0.0;
+  float v0x = INFINITY, v1x = -INFINITY, v0y = INFINITY, v1y = -INFINITY;
+  unsigned u0x = 0xffffffffu, u1x = 0u, u0y = 0xffffffffu, u1y = 0u;
+  unsigned long long kx0 = ~0ull, kx1 = 0ull, ky0 = ~0ull, ky1 = 0ull;
+  for (int m = m0 + tid; m < m1; m += nt) {
+    const float x = xy[2 * m], y = xy[2 * m + 1];
+    float bx, by;
+    shoot(S, ML, lensp, nsub, x, y, bx, by);
+    if (S.ray_w) {
+      const double wm = (double)S.ray_w[m];
+      sx += wm * bx; sy += wm * by; sxx += wm * bx * bx; syy += wm * by * by;
+    } else {
+      sx += bx; sy += by; sxx += (double)bx * bx; syy += (double)by * by;
+    }
+    const float vx = bx + 0.0f, vy = by + 0.0f;
+    zx[m] = vx;
+    zy[m] = vy;
+    if (isfinite(vx)) { v0x = fminf(v0x, vx); v1x = fmaxf(v1x, vx); }
+    if (isfinite(vy)) { v0y = fminf(v0y, vy); v1y = fmaxf(v1y, vy); }
+    const unsigned ux = ord_key(vx), uy = ord_key(vy);
+    u0x = min(u0x, ux); u1x = max(u1x, ux);
+    u0y = min(u0y, uy); u1y = max(u1y, uy);
+    if (S.uniform) {
+      const unsigned long long kx = sel_key(bx, m), ky = sel_key(by, m);
+      kx0 = min(kx0, kx); kx1 = max(kx1, kx);
+      ky0 = min(ky0, ky); ky1 = max(ky1, ky);
+    }
+  }
+  if (S.uniform) {
+    atomicMin(&L.kred[0], kx0); atomicMax(&L.kred[1], kx1);
+    atomicMin(&L.kred[2], ky0); atomicMax(&L.kred[3], ky1);
+  }
+  double v4[4] = {sx, sy, sxx, syy};
+  block_sum<4>(v4, L.red);
+  const float f[4] = {wave_min(v0x), wave_min(v0y), wave_max(v1x), wave_max(v1y)};
+  const unsigned u[4] = {wave_min(u0x), wave_min(u0y), wave_max(u1x), wave_max(u1y)};
+  if (lane == 0)
+    for (int q = 0; q < 4; ++q) { L.fred[4 * wv + q] = f[q]; L.ured[4 * wv + q] = u[q]; }
+  __syncthreads();
+  if (tid == 0) {
+    MRayPart P;
+    for (int q = 0; q < 4; ++q) P.s[q] = v4[q];
+    P.vmin[0] = P.vmin[1] = INFINITY; P.vmax[0] = P.vmax[1] = -INFINITY;
+    P.umin[0] = P.umin[1] = 0xffffffffu; P.umax[0] = P.umax[1] = 0u;
+    for (int q = 0; q < 4; ++q) P.k[q] = L.kred[q];
+    for (int w = 0; w < nw; ++w) {
+      const float* fw = L.fred + 4 * w;
+      const unsigned* uw = L.ured + 4 * w;
+      for (int a = 0; a < 2; ++a) {
+        P.vmin[a] = fminf(P.vmin[a], fw[a]); P.vmax[a] = fmaxf(P.vmax[a], fw[2 + a]);
+        P.umin[a] = min(P.umin[a], uw[a]); P.umax[a] = max(P.umax[a], uw[2 + a]);
+      }
+    }
+    S.mrp[(size_t)b * S.mr_nchunk + c] = P;
+  }
+}
+__device__ __forceinline__ void mrays_body(const SysDev& S, int b, int c, MRayLds& L) {
+  const float* lensp = S.lens + (size_t)b * S.n_lens;
+  const int nsub = n_sub_of(S, b);
+  if (threadIdx.x == 0) {
+    if (S.epl) epl_table(make_epl(lensp), L.etab);
+    L.kred[0] = L.kred[2] = ~0ull;
+    L.kred[1] = L.kred[3] = 0ull;
+  }
+  __syncthreads();
+  if (S.epl) {
+    mrays_chunk(S, Main<true>(lensp, &L.etab), lensp, nsub, b, c, L);
+  } else {
+    mrays_chunk(S, Main<false>(lensp, nullptr), lensp, nsub, b, c, L);
+  }
+}
+__global__ void __launch_bounds__(MR_THREADS) k_mrays(SysDev S) {
+  __shared__ MRayLds L;
+  mrays_body(S, blockIdx.y, blockIdx.x, L);
+}
+
 __device__ __forceinline__ void prep_select(const SysDev& S, int b, int axis, unsigned char* smem) {
   SelLds& L = *reinterpret_cast<SelLds*>(smem);
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -732,8 +827,21 @@ __device__ __forceinline__ void prep_select(const SysDev& S, int b, int axis, un
   __syncthreads();   // the EPL tables
 
   MaskedRays R;
-  if (S.epl) masked_rays(S, Main<true>(lensp, &L.etab), lensp, nsub, axis, M, zb, R);
-  else masked_rays(S, Main<false>(lensp, nullptr), lensp, nsub, axis, M, zb, R);
+  if (S.mr_nchunk) {
+    // shot by the masked-ray launch: this thread's chunks, in chunk order
+    for (int c = tid; c < S.mr_nchunk; c += nt) {
+      const MRayPart& P = S.mrp[(size_t)b * S.mr_nchunk + c];
+      R.sx += P.s[0]; R.sy += P.s[1]; R.sxx += P.s[2]; R.syy += P.s[3];
+      R.vmin = fminf(R.vmin, P.vmin[axis]); R.vmax = fmaxf(R.vmax, P.vmax[axis]);
+      R.umin = min(R.umin, P.umin[axis]); R.umax = max(R.umax, P.umax[axis]);
+      R.kx0 = min(R.kx0, P.k[0]); R.kx1 = max(R.kx1, P.k[1]);
+      R.ky0 = min(R.ky0, P.k[2]); R.ky1 = max(R.ky1, P.k[3]);
+    }
+  } else if (S.epl) {
+    masked_rays(S, Main<true>(lensp, &L.etab), lensp, nsub, axis, M, zb, R);
+  } else {
+    masked_rays(S, Main<false>(lensp, nullptr), lensp, nsub, axis, M, zb, R);
+  }
   double sx = R.sx, sy = R.sy, sxx = R.sxx, syy = R.syy;
   float vmin = R.vmin, vmax = R.vmax;
   unsigned umin = R.umin, umax = R.umax;
@@ -2204,6 +2312,7 @@ size_t post_lds_bytes(int n_src, int n_lens) {
 }
 
 hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
+  if (h.mr_nchunk) hipLaunchKernelGGL(k_mrays, dim3(h.mr_nchunk, batch), dim3(MR_THREADS), 0, s, h);
   hipLaunchKernelGGL(k_prep, dim3(batch, 3), dim3(prep_threads(h.obs_dyn ? 0 : h.M)), prep_lds_bytes(h.n_src), s, h,
                      fft_lds_cap(h.n_src));
   if (gp_split(h.n_src))
@@ -2304,6 +2413,15 @@ __global__ void __launch_bounds__(PREP_THREADS_WIDE) kf_prep(const SysDev* __res
   else prep_gp(S, t.y, smem, fft_cap);
 }
 
+__global__ void __launch_bounds__(MR_THREADS) kf_mrays(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
+                                                     int round) {
+  __shared__ MRayLds L;
+  const Task t = tasks[blockIdx.x];
+  const SysDev S = sys[t.x];
+  if (!sys_active(S, round)) return;
+  mrays_body(S, t.y, t.z, L);
+}
+
 template <bool ADJ>
 __global__ void __launch_bounds__(GP_THREADS) kf_gp(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
                                                     int round, int pass) {
@@ -2361,6 +2479,8 @@ hipError_t launch_fleet_fit_stage(const FleetLaunch& L, int stage, int round, co
 hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const float* eps, hipStream_t s) {
   switch (stage) {
     case RTU_STAGE_PREP:
+      if (L.n_mr)
+        hipLaunchKernelGGL(kf_mrays, dim3(L.n_mr), dim3(MR_THREADS), 0, s, L.sys, L.t_mr, round);
       if (L.n_prep)
         hipLaunchKernelGGL(kf_prep, dim3(L.n_prep), dim3(L.prep_threads), L.lds_prep, s, L.sys, L.t_prep, round,
                            (int)(L.lds_prep / sizeof(float2)) - 128);

@@ -177,6 +177,8 @@ size_t carve_observation(SysDev& h, int B, int M, char* base) {
   h.rank_t = c.take<double>(K);
   h.tsel = c.take<int>(4 * K + 1);
   h.zbuf = c.take<float>((size_t)B * 2 * (M > 0 ? M : 1));
+  h.mr_nchunk = mr_chunks(M);
+  h.mrp = c.take<MRayPart>((size_t)B * (h.mr_nchunk > 0 ? h.mr_nchunk : 1));
   return c.off + 256;
 }
 
@@ -573,6 +575,7 @@ int rtu_loss_grad_noalloc(const rtu_geometry* g, int32_t batch, const float* ima
   if (rc) return rc;
   carve_workspace(h, batch, base);
   carve_observation(h, batch, g->n_img * g->n_img, base + ws);
+  h.mr_nchunk = 0;   // M is known on the device only: the selection shoots the rays
   int* dyn = reinterpret_cast<int*>(base + ws + ob);
   // the kernels read the image and the mask where the caller keeps them
   h.image = image;
