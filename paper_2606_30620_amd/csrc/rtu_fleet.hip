@@ -189,9 +189,9 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
     for (size_t i = 0; i < n; ++i) smax = std::max(smax, fit[i].S);
     while (g < smax && ADAM_P * g < ADAM_THREADS) g *= 2;
     L.adam_threads = ADAM_P * g;
-    int mmax = 0;
-    for (size_t i = 0; i < n; ++i) mmax = std::max(mmax, sys[i].obs_dyn ? 0 : sys[i].M);
-    L.prep_threads = prep_threads(mmax);
+    L.prep_threads = PREP_THREADS;
+    for (size_t i = 0; i < n; ++i)
+      L.prep_threads = std::max(L.prep_threads, prep_threads(sys[i].obs_dyn ? 0 : sys[i].M, sys[i].n_src));
   }
   L.lds_gp = lds_g;
   for (int k = 0; k < 2; ++k) {

@@ -23,11 +23,6 @@ constexpr int PREP_THREADS = 512;       // quantile selection and FFT workgroups
 constexpr int PREP_THREADS_WIDE = 1024; // twice as wide for masks of PREP_WIDE_M rays or more
 constexpr int PREP_WIDE_M = 12000;
 constexpr int POST_THREADS = 512;       // per-sample adjoint workgroups
-// Prep workgroup size for a mask of M rays (0: not known on the host).  The
-// selection's passes over the rays (shooting, histogram, gather) shorten
-// with more threads only when each thread has many rays; with fewer, the
-// barriers of sixteen waves cost more than the passes save.
-inline int prep_threads(int M) { return M >= PREP_WIDE_M ? PREP_THREADS_WIDE : PREP_THREADS; }
 // Masks of MR_MIN_M rays or more are shot before the selection by a launch
 // of its own, MR_CHUNK rays per workgroup of MR_THREADS, over many CUs
 // (the selection workgroup of a sample runs on one CU); the selection
@@ -45,6 +40,15 @@ constexpr int GP_LINES = 16;
 constexpr int GP_SPLIT_N = 256;
 constexpr int GP_THREADS = 256;
 __host__ __device__ constexpr bool gp_split(int n) { return n >= GP_SPLIT_N; }
+// Prep workgroup size for a mask of M rays (0: not known on the host) and an
+// n_src grid.  The selection's passes over the rays (histogram, gather, and
+// the shooting below MR_MIN_M) shorten with more threads only when each
+// thread has many rays, and the GP role's one-workgroup transform only from
+// 128 x 128 on; otherwise the barriers of sixteen waves cost more than the
+// passes save.
+inline int prep_threads(int M, int n_src) {
+  return M >= PREP_WIDE_M || (n_src >= 128 && !gp_split(n_src)) ? PREP_THREADS_WIDE : PREP_THREADS;
+}
 constexpr int FIT_THREADS = 256;        // fit kernels: sampling blocks of 256 parameters,
 constexpr int ADAM_P = 64;              // Adam blocks of 64 parameters
 constexpr int ADAM_THREADS = 1024;      // Adam blocks: ADAM_P parameters x up to 16 sample groups

@@ -2313,7 +2313,7 @@ size_t post_lds_bytes(int n_src, int n_lens) {
 
 hipError_t launch_prep(const SysDev& h, int batch, hipStream_t s) {
   if (h.mr_nchunk) hipLaunchKernelGGL(k_mrays, dim3(h.mr_nchunk, batch), dim3(MR_THREADS), 0, s, h);
-  hipLaunchKernelGGL(k_prep, dim3(batch, 3), dim3(prep_threads(h.obs_dyn ? 0 : h.M)), prep_lds_bytes(h.n_src), s, h,
+  hipLaunchKernelGGL(k_prep, dim3(batch, 3), dim3(prep_threads(h.obs_dyn ? 0 : h.M, h.n_src)), prep_lds_bytes(h.n_src), s, h,
                      fft_lds_cap(h.n_src));
   if (gp_split(h.n_src))
     for (int pass = 0; pass < 3; ++pass)
