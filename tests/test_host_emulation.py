@@ -6,7 +6,8 @@ indices come from the data: the 24 x 24 image with 52 masked pixels, 3 x 3
 sub-rays, a 128 x 128 source in global memory, a rank-two PSF and lens light
 (once a GPU memory fault: the quantile selection's target ranks were out of
 order for few masked rays); masks of 10 and 52 pixels with both selections;
-the allocation-free entry point.  CPU only."""
+the allocation-free entry point; a mask large enough for the masked-ray
+chunk launch.  CPU only."""
 import os
 import struct
 import subprocess
@@ -200,3 +201,21 @@ def test_epl_deflector(driver, case):
         g = synth.Geometry(40, 0.08, 2, 16, 9, 1.0, n_sub_max=2, tnfw_tau=10.0)
         p = synth.with_epl(synth.make_problem("X", batch=2, seed=12, geom=g), slope_mean=1.85)
     _compare(_run(driver, p, flags=4), p)
+
+
+@pytest.mark.parametrize("case", ["sie", "uniform"])
+def test_large_mask_chunked_rays(driver, case):
+    """A mask of 8192 rays or more (9604: all but the border of a 100 x 100
+    image, a partial last chunk): the masked rays are shot by the chunk
+    launch before the selection, which sums the chunks' moments and ranges
+    (the uniform grid also their extreme keys)."""
+    g = synth.Geometry(100, 0.05, 1, 16, 9, 1.0)
+    p = synth.make_problem("X", batch=2, seed=5, geom=g)
+    m = np.zeros_like(p.mask)
+    m[1:99, 1:99] = 1
+    p.mask = m
+    assert int(m.sum()) == 9604
+    if case == "uniform":
+        import dataclasses
+        p = dataclasses.replace(p, geom=dataclasses.replace(p.geom, uniform=True))
+    _compare(_run(driver, p, flags=2 if case == "uniform" else 0), p)
