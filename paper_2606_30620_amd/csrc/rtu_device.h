@@ -598,6 +598,39 @@ __device__ __forceinline__ void nfw_vjp(const Nfw& N, float tau, float x, float 
   gys -= C * aby + Y * Cpr * dy;
 }
 
+// nfw_alpha that also keeps what nfw_vjp needs at the same point: r (or -1
+// where the deflection is skipped), h and h' (0 beyond the truncation), with
+// the arithmetic of both, so that the adjoint evaluates h once per sub-ray.
+__device__ __forceinline__ void nfw_alpha_keep(const Nfw& N, float tau, float x, float y, float& ax, float& ay,
+                                               float& r, float& H, float& dH) {
+  const float dx = x - N.xs, dy = y - N.ys;
+  const float r2 = dx * dx + dy * dy;
+  r = -1.f; H = 0.f; dH = 0.f;
+  if (!(r2 > 1e-30f)) return;
+  const float ir2 = rcp(r2);
+  r = fsqrt(r2);
+  const float X = r * N.irs;
+  if (tau > 0.f && X > tau) { H = N.htau; dH = 0.f; } else { nfw_h_dh(X, H, dH); }
+  const float C = 4.f * N.ks * N.rs * N.rs * H * ir2;
+  ax += C * dx;
+  ay += C * dy;
+}
+// nfw_vjp from the values nfw_alpha_keep kept.
+__device__ __forceinline__ void nfw_vjp_kept(const Nfw& N, float x, float y, float abx, float aby, float r, float H,
+                                             float dH, float& gks, float& grs, float& gxs, float& gys) {
+  if (!(r > 0.f)) return;
+  const float dx = x - N.xs, dy = y - N.ys;
+  const float ir = rcp(r), ir2 = ir * ir;
+  const float Y = abx * dx + aby * dy;
+  const float rs = N.rs;
+  gks += 4.f * rs * rs * H * Y * ir2;
+  grs += Y * 4.f * N.ks * (2.f * rs * H - r * dH) * ir2;
+  const float C = 4.f * N.ks * rs * rs * H * ir2;
+  const float Cpr = 4.f * N.ks * (rs * dH * ir - 2.f * rs * rs * H * ir2) * ir2;
+  gxs -= C * abx + Y * Cpr * dx;
+  gys -= C * aby + Y * Cpr * dy;
+}
+
 // ------------------------------------------------------------------ CDF spline
 // Number of knots <= z (0..K): the spline interval of z.
 // Knot adjoint of one axis, accumulated per interval as moments

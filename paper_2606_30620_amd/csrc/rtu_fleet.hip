@@ -116,11 +116,13 @@ namespace rtu {
 int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDev>& fit, FleetLaunch& L) {
   const size_t n = sys.size();
   std::vector<Task> prep, psf, post, param, samp, fits, gp, mr, fwd[2], adj[2][2];
+  int adj_sub[2][2] = {{0, 0}, {0, 0}};
   size_t lds_f = 0, lds_a = 0, lds_p = 0, lds_pr = 0, lds_po = 0, lds_g = 0;
   for (size_t i = 0; i < n; ++i) {
     const SysDev& h = sys[i];
     const FitDev& F = fit[i];
     const int si = (int)i, S = h.batch;
+    if (h.n_sub_max > 0) adj_sub[h.lds_adj ? 0 : 1][h.epl ? 1 : 0] = 1;
     for (int b = 0; b < S; ++b) {
       for (int c = 0; c < h.mr_nchunk; ++c) mr.push_back(make_int4(si, b, c, 0));
       for (int r = 0; r < 3; ++r) prep.push_back(make_int4(si, b, r, 0));
@@ -199,6 +201,7 @@ int DeviceTables::upload(const std::vector<SysDev>& sys, const std::vector<FitDe
     for (int e = 0; e < 2; ++e) {
       L.t_adj[k][e] = d_tasks + off[8 + 2 * k + e];
       L.n_adj[k][e] = (int)adj[k][e].size();
+      L.adj_sub[k][e] = adj_sub[k][e];
     }
   }
   L.lds_rays_fwd = lds_f;

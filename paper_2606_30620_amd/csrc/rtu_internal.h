@@ -325,6 +325,7 @@ struct FleetLaunch {
   // memory), then by main deflector
   const Task* t_adj[2][2];
   int n_adj[2][2];
+  int adj_sub[2][2];          // the list has a system with subhaloes
   size_t lds_rays_fwd, lds_rays_adj, lds_psf, lds_prep, lds_post, lds_gp;
   int adam_threads;           // ADAM_P x the sample groups of the largest sample count (<= ADAM_THREADS)
   int prep_threads;           // prep workgroup size for the largest mask (prep_threads)

@@ -1244,7 +1244,9 @@ __global__ void __launch_bounds__(RAY_THREADS) k_rays_fwd(SysDev S) {
   rays_fwd_body<EPL>(S, b, blockIdx.x - b * S.ray_tiles, smem);
 }
 
-template <bool LDSGRID, bool EPL>
+// SUB: the variant for systems with subhaloes, which keeps each subhalo's r,
+// h and h' in registers from the deflection to its vector-Jacobian product.
+template <bool LDSGRID, bool EPL, bool SUB = false>
 __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* smem) {
   RayLdsHead& H = *reinterpret_cast<RayLdsHead*>(smem);
   const int n = S.n_src, np = n + 2;
@@ -1356,7 +1358,14 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         float ax, ay;
         if constexpr (EPL) M.alpha(x, y, ax, ay);
         else sie_shear_alpha<true>(M.L, x, y, ax, ay, E);
-        for (int q = 0; q < nsub; ++q) nfw_alpha(H.nfw[q], S.tau, x, y, ax, ay);
+        float kr[SUB ? RTU_MAX_SUB : 1], kh[SUB ? RTU_MAX_SUB : 1], kdh[SUB ? RTU_MAX_SUB : 1];
+        if constexpr (SUB) {
+#pragma unroll
+          for (int q = 0; q < RTU_MAX_SUB; ++q)
+            if (q < nsub) nfw_alpha_keep(H.nfw[q], S.tau, x, y, ax, ay, kr[q], kh[q], kdh[q]);
+        } else {
+          for (int q = 0; q < nsub; ++q) nfw_alpha(H.nfw[q], S.tau, x, y, ax, ay);
+        }
         const float bx = x - ax, by = y - ay;
         kx = knot_find(H, 0, bx, kx);
         ky = knot_find(H, 1, by, ky);
@@ -1388,11 +1397,22 @@ __device__ void rays_adj_body(const SysDev& S, int b, int tile, unsigned char* s
         const float abx = -Tbx * dTx, aby = -Tby * dTy;
         if constexpr (EPL) epl_shear_vjp(M.L, *M.T, x, y, abx, aby, eacc);
         else sie_shear_vjp(M.L, E, x, y, abx, aby, acc);
-        for (int q = 0; q < nsub; ++q) {
-          float* sa = subacc + (4 * q) * RAY_THREADS + threadIdx.x;
-          float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
-          nfw_vjp(H.nfw[q], S.tau, x, y, abx, aby, g0, g1, g2, g3);
-          sa[0] += g0; sa[RAY_THREADS] += g1; sa[2 * RAY_THREADS] += g2; sa[3 * RAY_THREADS] += g3;
+        if constexpr (SUB) {
+#pragma unroll
+          for (int q = 0; q < RTU_MAX_SUB; ++q)
+            if (q < nsub) {
+              float* sa = subacc + (4 * q) * RAY_THREADS + threadIdx.x;
+              float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+              nfw_vjp_kept(H.nfw[q], x, y, abx, aby, kr[q], kh[q], kdh[q], g0, g1, g2, g3);
+              sa[0] += g0; sa[RAY_THREADS] += g1; sa[2 * RAY_THREADS] += g2; sa[3 * RAY_THREADS] += g3;
+            }
+        } else {
+          for (int q = 0; q < nsub; ++q) {
+            float* sa = subacc + (4 * q) * RAY_THREADS + threadIdx.x;
+            float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+            nfw_vjp(H.nfw[q], S.tau, x, y, abx, aby, g0, g1, g2, g3);
+            sa[0] += g0; sa[RAY_THREADS] += g1; sa[2 * RAY_THREADS] += g2; sa[3 * RAY_THREADS] += g3;
+          }
         }
       }
     }
@@ -1499,6 +1519,12 @@ __global__ void __launch_bounds__(RAY_THREADS) k_rays_adj(SysDev S) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x / S.ray_tiles;
   rays_adj_body<LDSGRID, EPL>(S, b, blockIdx.x - b * S.ray_tiles, smem);
+}
+template <bool LDSGRID, bool EPL>
+__global__ void __launch_bounds__(RAY_THREADS) k_rays_adj_sub(SysDev S) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x / S.ray_tiles;
+  rays_adj_body<LDSGRID, EPL, true>(S, b, blockIdx.x - b * S.ray_tiles, smem);
 }
 
 // ====================================================================== PSF
@@ -2361,7 +2387,12 @@ hipError_t launch_rays_adj(const SysDev& h, int batch, hipStream_t s) {
   const bool lg = adj_lds_grid(h);
   const size_t lds = ray_lds_bytes(h, true, lg);
   const dim3 g(batch * h.ray_tiles), t(RAY_THREADS);
-  if (lg && h.epl) hipLaunchKernelGGL((k_rays_adj<true, true>), g, t, lds, s, h);
+  if (h.n_sub_max > 0) {   // subhaloes: the variant that keeps their terms in registers
+    if (lg && h.epl) hipLaunchKernelGGL((k_rays_adj_sub<true, true>), g, t, lds, s, h);
+    else if (lg) hipLaunchKernelGGL((k_rays_adj_sub<true, false>), g, t, lds, s, h);
+    else if (h.epl) hipLaunchKernelGGL((k_rays_adj_sub<false, true>), g, t, lds, s, h);
+    else hipLaunchKernelGGL((k_rays_adj_sub<false, false>), g, t, lds, s, h);
+  } else if (lg && h.epl) hipLaunchKernelGGL((k_rays_adj<true, true>), g, t, lds, s, h);
   else if (lg) hipLaunchKernelGGL((k_rays_adj<true, false>), g, t, lds, s, h);
   else if (h.epl) hipLaunchKernelGGL((k_rays_adj<false, true>), g, t, lds, s, h);
   else hipLaunchKernelGGL((k_rays_adj<false, false>), g, t, lds, s, h);
@@ -2452,6 +2483,15 @@ __global__ void __launch_bounds__(RAY_THREADS) kf_rays_adj(const SysDev* __restr
   if (!sys_active(S, round)) return;
   rays_adj_body<LDSGRID, EPL>(S, t.y, t.z, smem);
 }
+template <bool LDSGRID, bool EPL>
+__global__ void __launch_bounds__(RAY_THREADS) kf_rays_adj_sub(const SysDev* __restrict__ sys,
+                                                               const Task* __restrict__ tasks, int round) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Task t = tasks[blockIdx.x];
+  const SysDev S = sys[t.x];
+  if (!sys_active(S, round)) return;
+  rays_adj_body<LDSGRID, EPL, true>(S, t.y, t.z, smem);
+}
 
 __global__ void __launch_bounds__(PSF_THREADS) kf_psf(const SysDev* __restrict__ sys, const Task* __restrict__ tasks,
                                                     int round, int adjoint) {
@@ -2503,18 +2543,22 @@ hipError_t launch_fleet_stage(const FleetLaunch& L, int stage, int round, const 
                            stage == RTU_STAGE_PSF_ADJ ? 1 : 0);
       break;
     case RTU_STAGE_RAYS_ADJ:
-      if (L.n_adj[0][0])
-        hipLaunchKernelGGL((kf_rays_adj<true, false>), dim3(L.n_adj[0][0]), dim3(RAY_THREADS), L.lds_rays_adj, s,
-                           L.sys, L.t_adj[0][0], round);
-      if (L.n_adj[0][1])
-        hipLaunchKernelGGL((kf_rays_adj<true, true>), dim3(L.n_adj[0][1]), dim3(RAY_THREADS), L.lds_rays_adj, s,
-                           L.sys, L.t_adj[0][1], round);
-      if (L.n_adj[1][0])
-        hipLaunchKernelGGL((kf_rays_adj<false, false>), dim3(L.n_adj[1][0]), dim3(RAY_THREADS), L.lds_rays_adj, s,
-                           L.sys, L.t_adj[1][0], round);
-      if (L.n_adj[1][1])
-        hipLaunchKernelGGL((kf_rays_adj<false, true>), dim3(L.n_adj[1][1]), dim3(RAY_THREADS), L.lds_rays_adj, s,
-                           L.sys, L.t_adj[1][1], round);
+      // lists with a system that has subhaloes take the variant that keeps
+      // their terms in registers
+#define RTU_ADJ_LAUNCH(G, E)                                                                              \
+      if (L.n_adj[G ? 0 : 1][E]) {                                                                        \
+        if (L.adj_sub[G ? 0 : 1][E])                                                                      \
+          hipLaunchKernelGGL((kf_rays_adj_sub<G, E>), dim3(L.n_adj[G ? 0 : 1][E]), dim3(RAY_THREADS),     \
+                             L.lds_rays_adj, s, L.sys, L.t_adj[G ? 0 : 1][E], round);                     \
+        else                                                                                              \
+          hipLaunchKernelGGL((kf_rays_adj<G, E>), dim3(L.n_adj[G ? 0 : 1][E]), dim3(RAY_THREADS),         \
+                             L.lds_rays_adj, s, L.sys, L.t_adj[G ? 0 : 1][E], round);                     \
+      }
+      RTU_ADJ_LAUNCH(true, false)
+      RTU_ADJ_LAUNCH(true, true)
+      RTU_ADJ_LAUNCH(false, false)
+      RTU_ADJ_LAUNCH(false, true)
+#undef RTU_ADJ_LAUNCH
       break;
     case RTU_STAGE_POST:
       if (L.n_post)
