@@ -532,9 +532,13 @@ __device__ __forceinline__ void nfw_h_dh(float X, float& h, float& dh) {
     dh = X * (F - 1.f) * ic * ic;
     return;
   }
+  // F = atanh(sqrt(1 - X^2))/sqrt(1 - X^2) (atan beyond X = 1) = T(1 - X^2)
+  // equals 2 T(v)/(1 + X), v = (1 - X)/(1 + X): with c = sqrt(1 - X^2),
+  // atanh(c) = ln((1 + c)/X) = 2 atanh(sqrt v), and sqrt(v)/c = 1/(1 + X)
   const float ix1 = rcp(1.f + X);
   const float v = (1.f - X) * ix1;
-  h = fln(0.5f * X) + 2.f * nfw_T(v) * ix1;
+  const float F = 2.f * nfw_T(v) * ix1;
+  h = fln(0.5f * X) + F;
   const float vp = (1.f - X) * (1.f + X);
   float G;
   if (fabsf(vp) < 0.2f) {
@@ -545,7 +549,7 @@ __device__ __forceinline__ void nfw_h_dh(float X, float& h, float& dh) {
     r = fmaf(r, vp, 1.f / 5.f);  r = fmaf(r, vp, 1.f / 3.f);
     G = r;
   } else {
-    G = (nfw_T(vp) - 1.f) * rcp(vp);
+    G = (F - 1.f) * rcp(vp);
   }
   dh = X * G;
 }
