@@ -205,16 +205,16 @@ def test_epl_deflector(driver, case):
 
 @pytest.mark.parametrize("case", ["sie", "uniform"])
 def test_large_mask_chunked_rays(driver, case):
-    """A mask of 8192 rays or more (9604: all but the border of a 100 x 100
+    """A mask of 8192 rays or more (8281: all but the border of a 93 x 93
     image, a partial last chunk): the masked rays are shot by the chunk
     launch before the selection, which sums the chunks' moments and ranges
     (the uniform grid also their extreme keys)."""
-    g = synth.Geometry(100, 0.05, 1, 16, 9, 1.0)
-    p = synth.make_problem("X", batch=2, seed=5, geom=g)
+    g = synth.Geometry(93, 0.054, 1, 16, 9, 1.0)
+    p = synth.make_problem("X", batch=1, seed=5, geom=g)
     m = np.zeros_like(p.mask)
-    m[1:99, 1:99] = 1
+    m[1:92, 1:92] = 1
     p.mask = m
-    assert int(m.sum()) == 9604
+    assert int(m.sum()) == 8281
     if case == "uniform":
         import dataclasses
         p = dataclasses.replace(p, geom=dataclasses.replace(p.geom, uniform=True))
