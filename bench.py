@@ -374,6 +374,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the RTU vs uniform grid N_src sweep")
     ap.add_argument("--c4-iters", type=int, default=500)
     ap.add_argument("--serve-only", action="store_true", help="only the serving section (for profiling)")
+    ap.add_argument("--c3-only", action="store_true", help="only the C3 section (for profiling)")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-steps", type=int, default=200)
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -392,6 +393,9 @@ def main():
 
     if args.serve_only:
         print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_steps)}), flush=True)
+        return
+    if args.c3_only:
+        print(json.dumps({"c3": c3_bench(args.steps, args.warmup)}), flush=True)
         return
 
     S = 32
