@@ -175,7 +175,9 @@ int rtu_set_ray_weights(rtu_plan p, const float* weights, void* stream);
 /* ---- allocation-free evaluation ----------------------------------------
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
- * evaluation as rtu_loss_grad with no plan.  The geometry comes by value
+ * evaluation as rtu_loss_grad with no plan (equal bit for bit below 8192
+ * masked pixels; above, a plan sums the masked rays' moments in another
+ * order, and the two agree to rounding).  The geometry comes by value
  * (host), the observation as device arrays in rtu_set_observation's layout
  * (image[N*N], noise_sigma[N*N], psf[K*K], arc_mask[N*N] uint8), and the
  * per-sample inputs and outputs as for rtu_loss_grad.  Every intermediate
