@@ -224,6 +224,42 @@ void DeviceTables::release() {
 
 }  // namespace rtu
 
+// Pinned host staging for the copies of a sync point (admitted fits'
+// observation tables and initial guide, retired fits' results): blocks of
+// 16 MiB (or one request's size), at most 64 MiB in all, handed out in order.
+// take() returns null when the pool is full: the caller then synchronises
+// the stream (every copy out of or into the pool has completed) and resets
+// it.  Each sync point starts from a reset pool.
+struct Staging {
+  static constexpr size_t BLOCK = (size_t)16 << 20, CAP = (size_t)64 << 20;
+  std::vector<std::pair<char*, size_t>> blocks;
+  size_t cur = 0, used = 0, total = 0;
+  char* take(size_t bytes) {
+    used = (used + 255) & ~(size_t)255;
+    while (cur < blocks.size() && used + bytes > blocks[cur].second) { ++cur; used = 0; }
+    if (cur == blocks.size()) {
+      const size_t cap = std::max(bytes, BLOCK);
+      char* p = nullptr;
+      if ((!blocks.empty() && total + cap > CAP) ||
+          hipHostMalloc(reinterpret_cast<void**>(&p), cap, hipHostMallocDefault) != hipSuccess)
+        return nullptr;
+      blocks.push_back({p, cap});
+      total += cap;
+      used = 0;
+    }
+    char* p = blocks[cur].first + used;
+    used += bytes;
+    return p;
+  }
+  void reset() { cur = 0; used = 0; }
+  void release() {
+    for (auto& b : blocks) (void)hipHostFree(b.first);
+    blocks.clear();
+    total = 0;
+    reset();
+  }
+};
+
 struct rtu_fleet_s {
   int device = 0;
   size_t budget = 0;
@@ -240,6 +276,7 @@ struct rtu_fleet_s {
   DeviceTables tables;
   FleetLaunch L{};
   bool dirty = true;
+  Staging stage;
 };
 
 namespace {
@@ -286,8 +323,57 @@ int admit_one(rtu_fleet f, hipStream_t s) {
   F.seed_hi = (uint32_t)(e.seed >> 32);
   for (int w = 0; w < RTU_LOG_MASK_WORDS; ++w) F.log_mask[w] = e.log_mask[w];
   F.elbo_const = elbo_constant(e.obs.inv_var, F.n_src2, F.dim);
-  if (upload_observation(h, e.image.data(), e.psf.data(), e.mask.data(), e.obs, s) != hipSuccess) return -1;
-  if (init_fit_state(F, e.mu0.data(), e.rho0.data(), e.n_sub, s) != hipSuccess) return -1;
+  // the observation region (carved first, from base, up to zbuf) and the
+  // initial fit state, staged in pinned memory laid out as on the device and
+  // sent in four asynchronous copies
+  {
+    const int M = (int)e.obs.idx.size();
+    const size_t ob = (size_t)(reinterpret_cast<const char*>(h.zbuf) - base);
+    const size_t fb = (size_t)(reinterpret_cast<const char*>(F.rho + F.dim) - reinterpret_cast<const char*>(F.mu));
+    // a full pool: the copies issued from it complete, then it is reused
+    auto stage = [&](size_t bytes) -> char* {
+      char* p = f->stage.take(bytes);
+      if (!p && hipStreamSynchronize(s) == hipSuccess) {
+        f->stage.reset();
+        p = f->stage.take(bytes);
+      }
+      return p;
+    };
+    char* so = stage(ob);
+    if (!so) return -1;
+    SysDev hs = h;
+    carve_observation(hs, e.S, M, so);
+    const size_t N2 = (size_t)h.n_img * h.n_img, kw = (size_t)h.psf_k * psf_ws(h.psf_k);
+    memcpy(const_cast<float*>(hs.image), e.image.data(), N2 * 4);
+    memcpy(const_cast<float*>(hs.inv_var), e.obs.inv_var.data(), N2 * 4);
+    memcpy(const_cast<float*>(hs.psf_flip), e.obs.wfwd.data(), kw * 4);
+    memcpy(const_cast<float*>(hs.psf), e.obs.wadj.data(), kw * 4);
+    memcpy(const_cast<float*>(hs.psf_sep), e.obs.wsep.data(), e.obs.wsep.size() * 4);
+    memcpy(const_cast<uint8_t*>(hs.mask), e.mask.data(), N2);
+    if (M) memcpy(const_cast<int*>(hs.mask_idx), e.obs.idx.data(), (size_t)M * 4);
+    if (M) memcpy(const_cast<float2*>(hs.mask_xy), e.obs.xy.data(), (size_t)M * sizeof(float2));
+    memcpy(const_cast<int*>(hs.rank_j), e.obs.rank_j, sizeof(e.obs.rank_j));
+    memcpy(const_cast<double*>(hs.rank_t), e.obs.rank_t, sizeof(e.obs.rank_t));
+    memcpy(const_cast<int*>(hs.tsel), e.obs.tsel, sizeof(e.obs.tsel));
+    if (hipMemcpyAsync(base, so, ob, hipMemcpyHostToDevice, s) != hipSuccess) return -1;
+    // mu and rho are carved one after the other, then the four Adam moments
+    // (zeroed on the device)
+    const size_t fb2 = (fb + 255) & ~(size_t)255;
+    char* sf = stage(fb2 + (size_t)F.S * 4 + 4);
+    if (!sf) return -1;
+    int* sn = reinterpret_cast<int*>(sf + fb2);
+    memcpy(sf, e.mu0.data(), (size_t)F.dim * 4);
+    memcpy(sf + (reinterpret_cast<const char*>(F.rho) - reinterpret_cast<const char*>(F.mu)), e.rho0.data(),
+           (size_t)F.dim * 4);
+    for (int q = 0; q < F.S; ++q) sn[q] = e.n_sub;
+    sn[F.S] = 0;
+    const size_t zb = (size_t)(reinterpret_cast<const char*>(F.v_rho + F.dim) - reinterpret_cast<const char*>(F.m_mu));
+    if (hipMemcpyAsync(F.mu, sf, fb, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemsetAsync(F.m_mu, 0, zb, s) != hipSuccess ||
+        hipMemcpyAsync(F.n_sub, sn, (size_t)F.S * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(F.status_acc, sn + F.S, 4, hipMemcpyHostToDevice, s) != hipSuccess)
+      return -1;
+  }
   // the host copies are no longer needed once on the device
   e.image.clear(); e.image.shrink_to_fit();
   e.sigma.clear(); e.sigma.shrink_to_fit();
@@ -298,27 +384,62 @@ int admit_one(rtu_fleet f, hipStream_t s) {
 
 int sync_point(rtu_fleet f, hipStream_t s) {
   if (hipStreamSynchronize(s) != hipSuccess) return RTU_EHIP;
-  // retire
-  std::vector<Entry> keep;
+  f->stage.reset();   // every copy of the previous sync point has completed
+  // retire: each finished fit's guide, ELBO trace and status into pinned
+  // staging (asynchronous copies), one synchronisation for all of them
+  std::vector<Entry> keep, gone;
+  std::vector<char*> at;
   bool changed = false;
+  // the staged results so far: wait for their copies, read them, reuse the pool
+  auto drain = [&]() -> int {
+    if (gone.empty()) return RTU_OK;
+    if (hipStreamSynchronize(s) != hipSuccess) return RTU_EHIP;
+    for (size_t i = 0; i < gone.size(); ++i) {
+      const Entry& e = gone[i];
+      const char* p = at[i];
+      const size_t d4 = (size_t)e.F.dim * 4;
+      Result r;
+      r.mu.resize(e.F.dim);
+      r.rho.resize(e.F.dim);
+      r.trace.resize(e.steps);
+      memcpy(r.mu.data(), p, d4);
+      memcpy(r.rho.data(), p + d4, d4);
+      memcpy(r.trace.data(), p + 2 * d4, (size_t)e.steps * 8);
+      memcpy(&r.status, p + 2 * d4 + (size_t)e.steps * 8, 4);
+      f->alloc.release(e.off, e.bytes);
+      f->results[e.ticket] = std::move(r);
+      f->done.push_back(e.ticket);
+    }
+    gone.clear();
+    at.clear();
+    f->stage.reset();
+    changed = true;
+    return RTU_OK;
+  };
   for (Entry& e : f->active) {
     if (!finished(f, e)) {
       keep.push_back(std::move(e));
       continue;
     }
-    Result r;
-    r.mu.resize(e.F.dim);
-    r.rho.resize(e.F.dim);
-    r.trace.resize(e.steps);
-    if (hipMemcpy(r.mu.data(), e.F.mu, (size_t)e.F.dim * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(r.rho.data(), e.F.rho, (size_t)e.F.dim * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(r.trace.data(), e.F.trace, (size_t)e.steps * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(&r.status, e.F.status_acc, 4, hipMemcpyDeviceToHost) != hipSuccess)
+    const size_t d4 = (size_t)e.F.dim * 4, bytes = 2 * d4 + (size_t)e.steps * 8 + 8;
+    char* p = f->stage.take(bytes);
+    if (!p) {
+      const int rc = drain();
+      if (rc) return rc;
+      p = f->stage.take(bytes);
+      if (!p) return RTU_ENOMEM;
+    }
+    if (hipMemcpyAsync(p, e.F.mu, d4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(p + d4, e.F.rho, d4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(p + 2 * d4, e.F.trace, (size_t)e.steps * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(p + 2 * d4 + (size_t)e.steps * 8, e.F.status_acc, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
       return RTU_EHIP;
-    f->alloc.release(e.off, e.bytes);
-    f->results[e.ticket] = std::move(r);
-    f->done.push_back(e.ticket);
-    changed = true;
+    at.push_back(p);
+    gone.push_back(std::move(e));
+  }
+  {
+    const int rc = drain();   // also resets the pool for the admissions below
+    if (rc) return rc;
   }
   f->active = std::move(keep);
   // admit, first come first served
@@ -374,6 +495,7 @@ int rtu_fleet_destroy(rtu_fleet f) {
   (void)hipDeviceSynchronize();
   if (f->arena) (void)hipFree(f->arena);
   f->tables.release();
+  f->stage.release();
   delete f;
   return RTU_OK;
 }

@@ -129,7 +129,9 @@ def serve_fleet(requests: List[Request], hbm_budget: int = 8 << 30, max_fits: in
     ticket_of = {}
     nxt = 0
     t0 = clock()
-    while len(done) < n:
+
+    def submit_arrived():
+        nonlocal nxt
         now = clock() - t0
         while nxt < n and reqs[nxt].arrival <= now:
             r = reqs[nxt]
@@ -139,12 +141,18 @@ def serve_fleet(requests: List[Request], hbm_budget: int = 8 << 30, max_fits: in
                              r.samples, r.steps, int(p.n_sub[0]), r.lr, r.seed, log_params(p))
             ticket_of[t] = r.rid
             nxt += 1
+
+    while len(done) < n:
+        submit_arrived()
         st = fleet.stats()
         if st["active"] + st["queued"] == 0:
             if nxt < n:
                 sleep(max(0.0, reqs[nxt].arrival - (clock() - t0)))
             continue
         fleet.run(sync_every)
+        # requests that arrived meanwhile are prepared on the host while the
+        # queued rounds run, and admitted at this sync point
+        submit_arrived()
         fleet.sync()
         for t in fleet.poll():
             rid = ticket_of.pop(t)
