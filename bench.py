@@ -321,11 +321,15 @@ def c4_bench(iters: int) -> dict:
 
 def serving_bench(n: int, steps: int, loads=(0.5, 0.8, 0.95), seq_load: float = 0.5) -> dict:
     """Fleet vs sequential plain fits on the serving mix (see module docstring)."""
-    from paper_2606_30620_amd import serve
+    from paper_2606_30620_amd import _lib, serve
 
-    # warm-up (kernel loading) on a few short requests
-    serve.serve_fleet(serve.make_requests(8, float("inf"), steps=10, first_id=900000))
-    cap = serve.serve_fleet(serve.make_requests(n, float("inf"), steps=steps, first_id=0), keep_results=True)
+    # one fleet for every run, as a serving process keeps it: its arena, its
+    # pinned staging pool and its work-list buffers are sized by a warm-up
+    # burst of short requests (which also loads the kernels)
+    fleet = _lib.Fleet(8 << 30, max_fits=512, sync_every=4)
+    serve.serve_fleet(serve.make_requests(600, float("inf"), steps=5, first_id=900000), fleet=fleet)
+    cap = serve.serve_fleet(serve.make_requests(n, float("inf"), steps=steps, first_id=0), fleet=fleet,
+                            keep_results=True)
     note(f"serving capacity {cap.summary()}")
     out = {"workload": f"{n} requests of the serving mix, {steps} ELBO + Adam steps each, 1 sample per step, "
                        "subhalo scales fitted in log space",
@@ -333,14 +337,14 @@ def serving_bench(n: int, steps: int, loads=(0.5, 0.8, 0.95), seq_load: float = 
     for lam in loads:
         rate = lam * cap.fits_per_s
         reqs = serve.make_requests(n, rate, steps=steps, first_id=10000, seed=505)
-        fleet = serve.serve_fleet(reqs, keep_results=True)
-        entry = {"arrival_rate_per_s": round(rate, 2), "fleet": fleet.summary()}
-        note(f"serving fleet at {lam} x capacity {fleet.summary()}")
+        res = serve.serve_fleet(reqs, fleet=fleet, keep_results=True)
+        entry = {"arrival_rate_per_s": round(rate, 2), "fleet": res.summary()}
+        note(f"serving fleet at {lam} x capacity {res.summary()}")
         if abs(lam - seq_load) < 1e-9:
             seq = serve.serve_sequential(reqs, keep_results=True)
             note(f"serving sequential on the same trace {seq.summary()}")
             entry["sequential"] = seq.summary()
-            entry["speedup_fits_per_s"] = round(fleet.fits_per_s / seq.fits_per_s, 2)
+            entry["speedup_fits_per_s"] = round(res.fits_per_s / seq.fits_per_s, 2)
         out["loads"][str(lam)] = entry
     return out
 
