@@ -226,10 +226,11 @@ void DeviceTables::release() {
 
 // Pinned host staging for the copies of a sync point (admitted fits'
 // observation tables and initial guide, retired fits' results): blocks of
-// 16 MiB (or one request's size), at most 64 MiB in all, handed out in order.
-// take() returns null when the pool is full: the caller then synchronises
-// the stream (every copy out of or into the pool has completed) and resets
-// it.  Each sync point starts from a reset pool.
+// 16 MiB, at most 64 MiB in all, handed out in order; a request larger than
+// a block gets a block of its own whatever the total.  take() returns null
+// when the pool is full: the caller then synchronises the stream (every copy
+// out of or into the pool has completed) and resets it.  Each sync point
+// starts from a reset pool.
 struct Staging {
   static constexpr size_t BLOCK = (size_t)16 << 20, CAP = (size_t)64 << 20;
   std::vector<std::pair<char*, size_t>> blocks;
@@ -240,7 +241,7 @@ struct Staging {
     if (cur == blocks.size()) {
       const size_t cap = std::max(bytes, BLOCK);
       char* p = nullptr;
-      if ((!blocks.empty() && total + cap > CAP) ||
+      if ((!blocks.empty() && bytes <= BLOCK && total + cap > CAP) ||
           hipHostMalloc(reinterpret_cast<void**>(&p), cap, hipHostMallocDefault) != hipSuccess)
         return nullptr;
       blocks.push_back({p, cap});
