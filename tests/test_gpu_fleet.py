@@ -133,3 +133,22 @@ def test_serve_loop_matches_sequential():
     assert np.all(a.latency > 0) and np.all(b.latency > 0)
     for rid in a.results:
         _same(a.results[rid], b.results[rid], f"request {rid}")
+
+
+def test_admissions_beyond_the_staging_pool():
+    """Ninety fits admitted at one sync point stage more observation data than
+    the 64 MiB pinned pool holds (the pool is drained and reused during the
+    admissions): each fit's result equals its result in a fleet of its own."""
+    from paper_2606_30620_amd import _lib
+    ids = [i for i in range(800) if synth.serving_request(i).geom.n_img == 300][:90]
+    reqs = [serve.Request(i, 0.0, synth.serving_request(i), 2, 1, lr=5e-3, seed=700 + i) for i in ids]
+    staged = sum(r.problem.image.nbytes * 2 + r.problem.mask.nbytes for r in reqs)
+    say(f"[gpu] fleet: {len(reqs)} fits of 300 x 300 admitted together ({staged / 2**20:.0f} MiB of image data)")
+    assert staged > 64 << 20
+    big = _lib.Fleet(6 << 30, max_fits=96, sync_every=4)
+    tickets = [_submit(big, r) for r in reqs]
+    mix = _drain(big, tickets)
+    for r, t in list(zip(reqs, tickets))[::18]:
+        own = _lib.Fleet(1 << 30, max_fits=1, sync_every=4)
+        alone = _drain(own, [_submit(own, r)])
+        _same(mix[t], next(iter(alone.values())), f"request {r.rid}")
