@@ -1,6 +1,7 @@
 """Serving fleet on the GPU: each fit's result is the same alone (plain fit
 calls) and in a mix of other fits sharing the launches, under admission by an
-HBM budget, with arrivals while others run, and with a faulty fit in the mix.
+HBM budget, with arrivals while others run, with a faulty fit in the mix,
+and with more admissions at once than the pinned staging pool holds.
 
 Tolerance: ELBO traces within 1e-5 relative, guides within 1e-4 absolute
 + 1e-4 relative (float atomics make any two runs differ at rounding level;
